@@ -1,0 +1,196 @@
+/*
+ * h2.h -- C ABI of the MI355X H^2-ULV dense solver.
+ *
+ * Solves A x = b for a dense symmetric positive definite kernel matrix
+ * A_ij = G(x_i, x_j) over points x_i, following Ma & Yokota, "An inherently
+ * parallel H^2-ULV factorization for solving dense linear systems on GPUs"
+ * (arXiv 2502.02395):
+ *   h2_build   -- H^2 construction with pre-factorization (Algorithm 1,
+ *                 Sections 3.4-3.5): cluster tree, shared bases whose span
+ *                 includes the Schur-complement fill-ins, couplings, dense
+ *                 near blocks;
+ *   h2_factor  -- the level-by-level ULV factorization (Algorithm 4,
+ *                 Section 4.4, Eq. 21, Eq. 32);
+ *   h2_solve   -- the inherently parallel forward and backward substitution
+ *                 (Section 3.7, Eq. 24-31), optionally followed by iterative
+ *                 refinement / PCG against the FP64 H^2 operator;
+ *   h2_matvec  -- the FP64 H^2 matrix-vector product.
+ *
+ * Conventions (all entry points):
+ *   - Every call returns an h2_status; no exception or abort crosses the ABI.
+ *   - Matrices are column-major.  Points are row-major (n x dim).
+ *   - "host" pointers are read during the call only; "device" pointers must be
+ *     HIP device allocations on the current device.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it; the call returns after the work that the
+ *     call needs to inspect on the host (ranks during build, the breakdown flag
+ *     after factor, residual norms during refinement) has completed.
+ *   - The handle owns every device buffer it allocates (hipMalloc) and frees
+ *     them in h2_destroy.  A handle must not be used from two threads or two
+ *     streams at once.
+ *   - After an error other than H2_ERR_ARG the handle may only be inspected
+ *     (h2_stats, getters) or destroyed.
+ */
+#ifndef H2_H
+#define H2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = 1,         /* invalid argument (synchronous, handle unchanged)   */
+  H2_ERR_ALLOC = 2,       /* device or host allocation failed                   */
+  H2_ERR_HIP = 3,         /* a HIP runtime call failed                          */
+  H2_ERR_NOT_SPD = 4,     /* Cholesky breakdown; h2_stats gives (level, box)    */
+  H2_ERR_STATE = 5,       /* call out of order (e.g. solve before factor)       */
+  H2_ERR_NOCONV = 6,      /* refinement did not reach the tolerance             */
+  H2_ERR_UNSUPPORTED = 7  /* option not available in this build                 */
+} h2_status;
+
+/* Kernel functions (Eq. 35, Eq. 36 regularised; covariance kernels). */
+typedef enum {
+  H2_K_LAPLACE_REG = 0,   /* 1/(r + delta)                                       */
+  H2_K_YUKAWA_REG = 1,    /* exp(-kappa r)/(r + delta)                           */
+  H2_K_GAUSSIAN = 2,      /* exp(-r^2/ell^2) + nugget [i == j]                   */
+  H2_K_MATERN32 = 3       /* (1 + sqrt3 r/ell) exp(-sqrt3 r/ell) + nugget [i==j] */
+} h2_kernel_id;
+
+typedef struct {
+  int32_t id;             /* h2_kernel_id */
+  double delta, kappa, ell, nugget;
+} h2_kernel;
+
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_BF16 = 2 } h2_prec;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3                                              */
+  int32_t leaf;           /* max points per leaf box (>= 2)                      */
+  double eta;             /* admissibility: far iff |c_a-c_b| > eta (rho_a+rho_b) */
+  double eps;             /* ID truncation: keep |R_jj| > eps |R_00|             */
+  int32_t max_rank;       /* 0 = no cap                                          */
+  int32_t s_far, s_near;  /* sample sizes per box; -1 = every candidate point    */
+  int32_t gemm_prec;      /* h2_prec of the basis-transform / Schur GEMMs        */
+  int32_t ir_max_iter;    /* 0 = plain direct solve                              */
+  double ir_tol;          /* relative residual target of refinement              */
+  int32_t use_pcg;        /* 1 = PCG instead of stationary refinement            */
+  int32_t use_graph;      /* 1 = capture factor launches in a hipGraph           */
+  const float* rank_model;/* host, 4801 MLP weights; NULL = plain pivoted QR    */
+  double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
+} h2_params;
+
+typedef struct h2_ctx* h2_handle;
+
+/* Per-handle statistics (h2_stats). */
+typedef struct {
+  int64_t n;              /* total points (all instances)                        */
+  int32_t n_inst, levels; /* instances, max tree depth L                         */
+  int64_t n_boxes;        /* boxes of levels 1..L over all instances             */
+  int64_t near_pairs;     /* unordered near pairs incl. diagonal, all levels     */
+  int64_t far_pairs;      /* unordered far pairs, all levels                     */
+  int64_t leaf_near_blocks; /* ordered dense near blocks at the leaves (N_NZB)   */
+  int32_t max_rank_seen, max_m_seen, root_n;
+  double flops_factor;    /* canonical algorithmic flops of one factorization    */
+  double flops_solve;     /* canonical flops of one solve, per right-hand side   */
+  double bytes_factors;   /* bytes of the stored factors                         */
+  double t_build, t_factor, t_solve; /* seconds of the last call (host clock)    */
+  int32_t ir_iters;       /* refinement iterations of the last solve             */
+  double ir_residual;     /* last relative residual against the H^2 operator     */
+  int32_t fail_level, fail_box, fail_inst; /* location of a Cholesky breakdown   */
+  int32_t rank_fallbacks; /* boxes whose predicted rank fell back to full QR     */
+} h2_stats_t;
+
+/* Build the H^2 representation of one kernel matrix (Algorithm 1).
+ *  pts:   host, n x dim row-major points (copied).
+ *  perm:  host, n int64, the sampling permutation pi of 0..n-1; S_F / S_C take
+ *         the candidates that come first in pi.  NULL = identity.
+ *  out:   receives the new handle.
+ * Errors: H2_ERR_ARG for n < 1, leaf < 2, dim not 2/3, bad kernel id, eps < 0;
+ *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD. */
+h2_status h2_build(const double* pts, int64_t n, const h2_kernel* kernel,
+                   const h2_params* params, const int64_t* perm, void* stream,
+                   h2_handle* out);
+
+/* Build many independent systems in one handle (same params, own points,
+ * kernel and permutation each); every level of every instance is processed in
+ * the same batched launches, instances aligned by height above the leaves.
+ * pts[t]: host n[t] x dim; perms[t]: host or NULL. */
+h2_status h2_build_batched(int32_t n_inst, const double* const* pts,
+                           const int64_t* n, const h2_kernel* kernels,
+                           const h2_params* params, const int64_t* const* perms,
+                           void* stream, h2_handle* out);
+
+/* Build with a prescribed skeleton selection instead of pivoted QR: for every
+ * box of levels L..1 (level-major from the leaves, box-minor), ranks[b] and
+ * skel[...] = the k_b skeleton positions into that box's active rows, in pivot
+ * order, concatenated.  The ID coefficients are then computed on the device.
+ * Single instance only.  Used to run the factorization on an identical H^2
+ * matrix as an external reference. */
+h2_status h2_build_fixed(const double* pts, int64_t n, const h2_kernel* kernel,
+                         const h2_params* params, const int64_t* perm,
+                         const int32_t* ranks, const int32_t* skel,
+                         void* stream, h2_handle* out);
+
+/* Factor (Algorithm 4).  Returns H2_ERR_NOT_SPD with the location in h2_stats
+ * if a redundant diagonal block or the root is not positive definite. */
+h2_status h2_factor(h2_handle h, void* stream);
+
+/* x = A~^{-1} b through the parallel substitution (Eq. 31 and its transpose);
+ * with ir_max_iter > 0 refined until max_col ||b - A~ x||/||b|| <= ir_tol
+ * (H2_ERR_NOCONV if not reached).  b, x: device, n x nrhs, leading dimension
+ * ld >= n, original point order (instances concatenated); b == x allowed.
+ * H2_ERR_STATE before a successful h2_factor. */
+h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs,
+                   int64_t ld, void* stream);
+
+/* y = A~ x, the FP64 H^2 operator (upward pass, couplings, downward pass,
+ * dense near field).  x, y: device, n x nrhs, ld >= n, original order; x != y. */
+h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs,
+                    int64_t ld, void* stream);
+
+h2_status h2_stats(h2_handle h, h2_stats_t* out);
+
+/* Structure export (host buffers, sizes from h2_stats / h2_get_counts).
+ *  perm:   n int64, the original index of each tree position (instances
+ *          concatenated, each instance's indices local to it).
+ *  ranks:  n_boxes int32, levels L..1 level-major, box-minor (instance-major
+ *          within a level when batched: instance t's boxes in order).
+ *  ms:     n_boxes int32, active sizes m in the same order.
+ *  skel:   sum(ranks) int64, skeleton point ids (instance-local) per box.   */
+h2_status h2_get_counts(h2_handle h, int64_t* n_boxes, int64_t* n_skel);
+h2_status h2_get_structure(h2_handle h, int64_t* perm, int32_t* ranks,
+                           int32_t* ms, int64_t* skel);
+/* Near / far pairs of one level of instance 0 (ordered pairs, both orders):
+ * pairs is 2*count int32; pass NULL to query count only. */
+h2_status h2_get_pairs(h2_handle h, int32_t level, int32_t far, int32_t* pairs,
+                       int64_t* count);
+/* The root matrix after factor: A_00 (before Cholesky) of instance t, n0 x n0
+ * column-major into host `a` (n0 from h2_stats.root_n for t == 0). */
+h2_status h2_get_root(h2_handle h, int32_t inst, double* a, int64_t* n0);
+
+/* Rank-predictor MLP 8 -> 64 -> 64 -> 1 (ReLU), FP32, hand-written kernels.
+ * Weights: 4801 floats W1(64x8) b1 W2(64x64) b2 W3(1x64) b3, row-major.
+ * All pointers device.  Not part of the paper: sizes buffers before
+ * compression; pivoted QR remains the fallback. */
+h2_status h2_mlp_forward(const float* w, const float* x, float* y, int64_t n,
+                         void* stream);
+/* One full-batch Adam step on mean((y - t)^2): updates w, m, v in place,
+ * writes the loss to *loss (device, 1 float) and the gradient to g (4801). */
+h2_status h2_mlp_train_step(float* w, float* m, float* v, float* g,
+                            const float* x, const float* t, int64_t n,
+                            int32_t step, float lr, float* loss, void* stream);
+/* Box features (8 per box, levels L..1 order as ranks) of a built handle. */
+h2_status h2_box_features(h2_handle h, float* feats /* device, n_boxes x 8 */,
+                          void* stream);
+
+void h2_destroy(h2_handle h);
+const char* h2_status_str(h2_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* H2_H */
