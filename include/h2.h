@@ -81,6 +81,7 @@ typedef struct {
   int32_t use_graph;      /* 1 = capture factor launches in a hipGraph           */
   const float* rank_model;/* host, 4801 MLP weights; NULL = plain pivoted QR    */
   double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
+  int32_t timing;         /* 1 = time the near-pair transform launches of factor */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -102,6 +103,11 @@ typedef struct {
   double ir_residual;     /* last relative residual against the H^2 operator     */
   int32_t fail_level, fail_box, fail_inst; /* location of a Cholesky breakdown   */
   int32_t rank_fallbacks; /* boxes whose predicted rank fell back to full QR     */
+  double t_pair_gemm;     /* seconds in the near-pair transform launches of the
+                             last factor (HIP events; params.timing = 1)         */
+  double flops_pair_gemm; /* canonical flops of those launches: sum over
+                             unordered near pairs of 2 m_i m_j (m_i + m_j)      */
+  int32_t pair_launches;  /* number of those launches per factor                */
 } h2_stats_t;
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).

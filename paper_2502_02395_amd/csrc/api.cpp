@@ -1,0 +1,349 @@
+// The extern "C" entry points declared in include/h2.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "h2_ctx.hpp"
+
+namespace h2 {
+h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
+                     const h2_kernel* kerns, const h2_params* prm, const int64_t* const* perms,
+                     const int32_t* fixed_ranks, const int32_t* fixed_skel, hipStream_t st,
+                     h2_handle* out);
+}  // namespace h2
+
+using namespace h2;
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return H2_ERR_HIP;      \
+  } while (0)
+
+static hipStream_t S(void* p) { return static_cast<hipStream_t>(p); }
+
+static double geqrf(double m, double k) { return 2.0 * m * k * k - 2.0 / 3.0 * k * k * k; }
+static double orgqr_full(double m, double k) {
+  return 4.0 * m * m * k - 4.0 * m * k * k + 4.0 / 3.0 * k * k * k;
+}
+
+// Canonical algorithmic flop counts (unpadded sizes); see include/h2.h.
+static void count_flops(Ctx& c) {
+  double ff = 0.0, fs = 0.0, bytes = 0.0;
+  int64_t nboxes = 0, npairs = 0, nfar = 0, nnzb = 0;
+  int maxk = 0, maxm = 0;
+  c.st.flops_pair_gemm = 0.0;
+  c.st.pair_launches = 0;
+  for (auto& S : c.steps) {
+    if (S.g_pair1.count > 0) c.st.pair_launches += 2;
+    nboxes += S.nbox;
+    for (int b = 0; b < S.nbox; ++b) {
+      const double m = S.m[b], k = S.k[b], r = m - k;
+      ff += geqrf(m, k) + orgqr_full(m, k) + 4.0 * m * m * m;
+      ff += r * r * r / 3.0 + k * r * r + k * k * r + m * r * r;
+      fs += 4.0 * m * m + 4.0 * r * r;
+      maxk = std::max(maxk, S.k[b]);
+      maxm = std::max(maxm, S.m[b]);
+      bytes += 8.0 * m * m;  // P
+    }
+    for (size_t p = 0; p < S.np_i.size(); ++p) {
+      const int i = S.np_i[p], j = S.np_j[p];
+      const double mi = S.m[i], mj = S.m[j], ki = S.k[i], kj = S.k[j], ri = mi - ki, rj = mj - kj;
+      bytes += 8.0 * mi * mj;
+      ++npairs;
+      if (i == j) {
+        fs += 4.0 * ki * ri;
+        if (S.h == 0) ++nnzb;
+        continue;
+      }
+      if (S.h == 0) nnzb += 2;
+      ff += ki * rj * rj + kj * ri * ri;
+      ff += 2.0 * mi * mj * (mi + mj) + ri * rj * rj;
+      c.st.flops_pair_gemm += 2.0 * mi * mj * (mi + mj);
+      fs += 4.0 * ki * rj + 4.0 * kj * ri + 4.0 * ri * rj;
+    }
+    for (size_t f = 0; f < S.fp_i.size(); ++f) {
+      const double ki = S.k[S.fp_i[f]], kj = S.k[S.fp_j[f]];
+      ff += ki * kj * (ki + kj);
+      ++nfar;
+    }
+  }
+  for (auto& in : c.ins) {
+    ff += (double)in.n0 * in.n0 * in.n0 / 3.0;
+    fs += 2.0 * (double)in.n0 * in.n0;
+    bytes += 8.0 * (double)in.n0 * in.n0;
+    if (in.tree.L == 0) ++nnzb;
+  }
+  c.st.n = c.N;
+  c.st.n_inst = c.n_inst;
+  c.st.levels = c.H;
+  c.st.n_boxes = nboxes;
+  c.st.near_pairs = npairs;
+  c.st.far_pairs = nfar;
+  c.st.leaf_near_blocks = nnzb;
+  c.st.max_rank_seen = maxk;
+  c.st.max_m_seen = maxm;
+  c.st.root_n = c.ins.empty() ? 0 : c.ins[0].n0;
+  c.st.flops_factor = ff;
+  c.st.flops_solve = fs;
+  c.st.bytes_factors = bytes;
+}
+
+extern "C" {
+
+const char* h2_status_str(h2_status s) {
+  switch (s) {
+    case H2_OK: return "ok";
+    case H2_ERR_ARG: return "invalid argument";
+    case H2_ERR_ALLOC: return "allocation failed";
+    case H2_ERR_HIP: return "HIP runtime error";
+    case H2_ERR_NOT_SPD: return "Cholesky breakdown (matrix not positive definite)";
+    case H2_ERR_STATE: return "call out of order";
+    case H2_ERR_NOCONV: return "refinement did not converge";
+    case H2_ERR_UNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+h2_status h2_build(const double* pts, int64_t n, const h2_kernel* kernel, const h2_params* params,
+                   const int64_t* perm, void* stream, h2_handle* out) {
+  const double* p[1] = {pts};
+  const int64_t* q[1] = {perm};
+  h2_status s = build_impl(1, p, &n, kernel, params, q, nullptr, nullptr, S(stream), out);
+  if (s == H2_OK) count_flops(*(*out)->c);
+  return s;
+}
+
+h2_status h2_build_batched(int32_t n_inst, const double* const* pts, const int64_t* n,
+                           const h2_kernel* kernels, const h2_params* params,
+                           const int64_t* const* perms, void* stream, h2_handle* out) {
+  h2_status s = build_impl(n_inst, pts, n, kernels, params, perms, nullptr, nullptr, S(stream), out);
+  if (s == H2_OK) count_flops(*(*out)->c);
+  return s;
+}
+
+h2_status h2_build_fixed(const double* pts, int64_t n, const h2_kernel* kernel,
+                         const h2_params* params, const int64_t* perm, const int32_t* ranks,
+                         const int32_t* skel, void* stream, h2_handle* out) {
+  if (!ranks || !skel) return H2_ERR_ARG;
+  const double* p[1] = {pts};
+  const int64_t* q[1] = {perm};
+  h2_status s = build_impl(1, p, &n, kernel, params, q, ranks, skel, S(stream), out);
+  if (s == H2_OK) count_flops(*(*out)->c);
+  return s;
+}
+
+h2_status h2_factor(h2_handle h, void* stream) {
+  if (!h || !h->c) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (c.failed) return H2_ERR_STATE;
+  hipStream_t st = S(stream);
+  const double t0 = now_seconds();
+  if (c.prm.use_graph) {
+    if (!c.graph) {
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      h2_status e = do_factor(c, st);
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(st, &g);
+      if (e != H2_OK) return e;
+      HIPCHK(ce);
+      c.graph_def = g;
+      HIPCHK(hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0));
+    }
+    HIPCHK(hipGraphLaunch(c.graph, st));
+  } else {
+    h2_status e = do_factor(c, st);
+    if (e != H2_OK) { c.failed = true; return e; }
+  }
+  int fail = INT_MAX;
+  HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c.st.t_factor = now_seconds() - t0;
+  if (fail != INT_MAX) {
+    const int hstep = fail >> 20, b = fail & ((1 << 20) - 1);
+    if (hstep == 1023) {
+      c.st.fail_level = 0;
+      c.st.fail_box = 0;
+      c.st.fail_inst = b;
+    } else {
+      const Step& Sx = c.steps[hstep];
+      c.st.fail_level = Sx.lvl[b];
+      c.st.fail_box = Sx.idx[b];
+      c.st.fail_inst = Sx.inst[b];
+    }
+    c.failed = true;
+    c.factored = false;
+    return H2_ERR_NOT_SPD;
+  }
+  c.factored = true;
+  return H2_OK;
+}
+
+static h2_status solve_plain(Ctx& c, const double* b, double* x, int nc, hipStream_t st) {
+  return do_solve_chunk(c, b, c.N, x, c.N, nc, st);
+}
+
+static h2_status colnorms(Ctx& c, const double* a, int nc, double* out, hipStream_t st) {
+  HIPCHK(launch_coldot(a, c.N, a, c.N, c.N, nc, c.dWs, out, st));
+  return H2_OK;
+}
+
+h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_t ld, void* stream) {
+  if (!h || !h->c || !b || !x) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
+  if (!c.factored || c.failed) return H2_ERR_STATE;
+  hipStream_t st = S(stream);
+  const double t0 = now_seconds();
+  const int maxit = c.prm.ir_max_iter;
+  int iters_total = 0;
+  double worst = 0.0;
+  bool noconv = false;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += NRHS_MAX) {
+    const int nc = (int)std::min<int64_t>(NRHS_MAX, nrhs - c0);
+    const double* bb = b + c0 * ld;
+    double* xx = x + c0 * ld;
+    // keep b (x may alias it)
+    HIPCHK(launch_axpby(c.w_t, c.N, bb, ld, bb, ld, c.N, nc, nullptr, nullptr, 0.0, st));
+    if (maxit <= 0) {
+      h2_status e = solve_plain(c, c.w_t, c.w_x, nc, st);
+      if (e != H2_OK) return e;
+    } else {
+      double* sc = c.dScal;  // [0,16): r.r  [16,32): b.b  [32,48): rz  [48,64): pq  [64,80): rz_new
+      std::vector<double> hr(NRHS_MAX), hb(NRHS_MAX);
+      h2_status e = colnorms(c, c.w_t, nc, sc + 16, st);
+      if (e != H2_OK) return e;
+      HIPCHK(hipMemcpyAsync(hb.data(), sc + 16, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+      if ((e = solve_plain(c, c.w_t, c.w_x, nc, st)) != H2_OK) return e;
+      // r = b - A x
+      if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+      HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
+      const bool pcg = c.prm.use_pcg != 0;
+      if (pcg) {
+        if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+        HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
+        HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 32, st));
+      }
+      int it = 0;
+      double res = 0.0;
+      for (;;) {
+        if ((e = colnorms(c, c.w_r, nc, sc, st)) != H2_OK) return e;
+        HIPCHK(hipMemcpyAsync(hr.data(), sc, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        res = 0.0;
+        for (int q = 0; q < nc; ++q) {
+          const double rel = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
+          res = std::max(res, rel);
+        }
+        if (res <= c.prm.ir_tol || !(res == res)) break;
+        if (it >= maxit) { noconv = true; break; }
+        ++it;
+        if (!pcg) {
+          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 1.0, st));
+          if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
+        } else {
+          if ((e = do_matvec_chunk(c, c.w_p, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          HIPCHK(launch_coldot(c.w_p, c.N, c.w_q, c.N, c.N, nc, c.dWs, sc + 48, st));
+          HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_p, c.N, c.N, nc, sc + 32, sc + 48, 1.0, st));
+          HIPCHK(launch_axpby(c.w_r, c.N, c.w_r, c.N, c.w_q, c.N, c.N, nc, sc + 32, sc + 48, -1.0, st));
+          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 64, st));
+          HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_p, c.N, c.N, nc, sc + 64, sc + 32, 1.0, st));
+          HIPCHK(hipMemcpyAsync(sc + 32, sc + 64, nc * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+      }
+      iters_total = std::max(iters_total, it);
+      worst = std::max(worst, res);
+    }
+    HIPCHK(launch_axpby(xx, ld, c.w_x, c.N, c.w_x, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  c.st.t_solve = now_seconds() - t0;
+  c.st.ir_iters = iters_total;
+  c.st.ir_residual = worst;
+  return noconv ? H2_ERR_NOCONV : H2_OK;
+}
+
+h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs, int64_t ld, void* stream) {
+  if (!h || !h->c || !x || !y || x == y) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
+  hipStream_t st = S(stream);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += NRHS_MAX) {
+    const int nc = (int)std::min<int64_t>(NRHS_MAX, nrhs - c0);
+    h2_status e = do_matvec_chunk(c, x + c0 * ld, ld, y + c0 * ld, ld, nc, st);
+    if (e != H2_OK) return e;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+h2_status h2_stats(h2_handle h, h2_stats_t* out) {
+  if (!h || !h->c || !out) return H2_ERR_ARG;
+  *out = h->c->st;
+  return H2_OK;
+}
+
+h2_status h2_get_counts(h2_handle h, int64_t* n_boxes, int64_t* n_skel) {
+  if (!h || !h->c) return H2_ERR_ARG;
+  int64_t nb = 0, ns = 0;
+  for (auto& Sx : h->c->steps) {
+    nb += Sx.nbox;
+    ns += Sx.sum_k;
+  }
+  if (n_boxes) *n_boxes = nb;
+  if (n_skel) *n_skel = ns;
+  return H2_OK;
+}
+
+h2_status h2_get_structure(h2_handle h, int64_t* perm, int32_t* ranks, int32_t* ms, int64_t* skel) {
+  if (!h || !h->c) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (perm)
+    for (auto& in : c.ins) std::memcpy(perm + in.pbase, in.tree.perm.data(), in.n * sizeof(int64_t));
+  int64_t bo = 0, so = 0;
+  for (auto& Sx : c.steps) {
+    for (int b = 0; b < Sx.nbox; ++b) {
+      if (ranks) ranks[bo + b] = Sx.k[b];
+      if (ms) ms[bo + b] = Sx.m[b];
+    }
+    if (skel)
+      for (int64_t q = 0; q < Sx.sum_k; ++q) {
+        int b = (int)(std::upper_bound(Sx.koff.begin(), Sx.koff.end(), q) - Sx.koff.begin()) - 1;
+        skel[so + q] = Sx.SK[q] - c.ins[Sx.inst[b]].pbase;
+      }
+    bo += Sx.nbox;
+    so += Sx.sum_k;
+  }
+  return H2_OK;
+}
+
+h2_status h2_get_pairs(h2_handle h, int32_t level, int32_t far, int32_t* pairs, int64_t* count) {
+  if (!h || !h->c || !count) return H2_ERR_ARG;
+  const Tree& t = h->c->ins[0].tree;
+  if (level < 0 || level > t.L) return H2_ERR_ARG;
+  const auto& v = far ? t.far[level] : t.near[level];
+  *count = (int64_t)v.size();
+  if (pairs)
+    for (size_t q = 0; q < v.size(); ++q) {
+      pairs[2 * q] = v[q].first;
+      pairs[2 * q + 1] = v[q].second;
+    }
+  return H2_OK;
+}
+
+h2_status h2_get_root(h2_handle h, int32_t inst, double* a, int64_t* n0) {
+  if (!h || !h->c || inst < 0 || inst >= h->c->n_inst) return H2_ERR_ARG;
+  Instance& in = h->c->ins[inst];
+  if (n0) *n0 = in.n0;
+  if (a && in.n0 > 0) {
+    if (!h->c->factored) return H2_ERR_STATE;
+    HIPCHK(hipMemcpy(a, in.dRootA, sizeof(double) * in.n0 * in.n0, hipMemcpyDeviceToHost));
+  }
+  return H2_OK;
+}
+
+void h2_destroy(h2_handle h) { delete h; }
+
+}  // extern "C"

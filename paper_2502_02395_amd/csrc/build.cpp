@@ -1,0 +1,716 @@
+// h2_build: H^2 construction with pre-factorization (Algorithm 1) on the
+// device, level by level from the leaves, batched over every box of every
+// instance at the same height.  The host keeps the index bookkeeping (tree,
+// lists, sample selection, parent active sets); kernel evaluation, the
+// near-sample Cholesky solves, the interpolative decompositions, couplings and
+// near blocks run in the kernels of k_vec.hip, k_dense.hip and k_gemm.hip.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <thread>
+#include <unordered_map>
+
+#include "h2_ctx.hpp"
+
+namespace h2 {
+
+double now_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+Ctx::~Ctx() {
+  if (ev_a) (void)hipEventDestroy(ev_a);
+  if (ev_b) (void)hipEventDestroy(ev_b);
+  if (graph) (void)hipGraphExecDestroy(graph);
+  if (graph_def) (void)hipGraphDestroy(graph_def);
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
+  return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag);
+}
+hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
+  return launch_thin(b.d, b.count, b.max_rows, ncols, st);
+}
+hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
+  return launch_copy(b.d, b.count, st);
+}
+hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int nrhs,
+                      hipStream_t st) {
+  return launch_gather(b.d, b.count, b.max_rows, n.d, nrhs, st);
+}
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return H2_ERR_HIP;      \
+  } while (0)
+#define ALLOCHK(p)                                 \
+  do {                                             \
+    if (!(p)) return H2_ERR_ALLOC;                 \
+  } while (0)
+
+static constexpr int ID_MMAX = 4096;    // cpqr_id_kernel LDS capacity
+static constexpr int CHOL_NMAX = 2048;  // chol_inv rows per workgroup
+static constexpr int QR_KMAX = 4096;
+
+// Temporary device buffer freed at scope exit.
+struct TmpBuf {
+  void* p = nullptr;
+  ~TmpBuf() { if (p) (void)hipFree(p); }
+  template <class T> T* get(size_t n) {
+    if (n == 0) n = 1;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) p = nullptr;
+    return static_cast<T*>(p);
+  }
+};
+
+template <class T>
+static bool upload_tmp(TmpBuf& tb, T*& dst, const std::vector<T>& v, hipStream_t st) {
+  dst = tb.get<T>(v.size());
+  if (!dst) return false;
+  if (v.empty()) return true;
+  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) == hipSuccess;
+}
+
+static h2_status run_eval(Ctx& c, const std::vector<EvalDesc>& ev, hipStream_t st) {
+  if (ev.empty()) return H2_OK;
+  TmpBuf tb1, tb2;
+  EvalDesc* d = nullptr;
+  int* t = nullptr;
+  auto toff = eval_tiles(ev);
+  if (!upload_tmp(tb1, d, ev, st) || !upload_tmp(tb2, t, toff, st)) return H2_ERR_ALLOC;
+  HIPCHK(launch_eval(d, t, (int)ev.size(), toff.back(), c.dX, c.dim, c.dKern, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st) {
+  if (g.empty()) return H2_OK;
+  TmpBuf tb1, tb2;
+  GemmDesc* d = nullptr;
+  int* t = nullptr;
+  auto toff = gemm_tiles(g);
+  if (!upload_tmp(tb1, d, g, st) || !upload_tmp(tb2, t, toff, st)) return H2_ERR_ALLOC;
+  HIPCHK(launch_gemm(d, t, (int)g.size(), toff.back(), st));
+  HIPCHK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
+                     const h2_kernel* kerns, const h2_params* prm, const int64_t* const* perms,
+                     const int32_t* fixed_ranks, const int32_t* fixed_skel, hipStream_t st,
+                     h2_handle* out) {
+  if (!out || !prm || !pts || !ns || !kerns || n_inst < 1) return H2_ERR_ARG;
+  *out = nullptr;
+  if (prm->dim != 2 && prm->dim != 3) return H2_ERR_ARG;
+  if (prm->leaf < 2 || !(prm->eps >= 0.0) || !(prm->eta >= 0.0)) return H2_ERR_ARG;
+  if (prm->s_far < -1 || prm->s_near < -1 || prm->max_rank < 0) return H2_ERR_ARG;
+  if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
+      prm->gemm_prec != H2_PREC_BF16)
+    return H2_ERR_ARG;
+  for (int t = 0; t < n_inst; ++t) {
+    if (!pts[t] || ns[t] < 1) return H2_ERR_ARG;
+    const h2_kernel& k = kerns[t];
+    if (k.id < 0 || k.id > 3) return H2_ERR_ARG;
+    if ((k.id <= 1 && !(k.delta > 0.0)) || (k.id >= 2 && !(k.ell > 0.0))) return H2_ERR_ARG;
+    if (k.nugget < 0.0) return H2_ERR_ARG;
+  }
+  if (fixed_ranks && n_inst != 1) return H2_ERR_ARG;
+
+  const double t_begin = now_seconds();
+  auto ctx = std::make_unique<Ctx>();
+  Ctx& c = *ctx;
+  c.prm = *prm;
+  c.n_inst = n_inst;
+  c.dim = prm->dim;
+  c.ins.resize(n_inst);
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+
+  int64_t N = 0;
+  for (int t = 0; t < n_inst; ++t) {
+    Instance& in = c.ins[t];
+    in.n = ns[t];
+    in.pbase = N;
+    N += ns[t];
+    const h2_kernel& k = kerns[t];
+    in.kern = KernelDev{k.id, k.delta, k.kappa, k.ell, k.nugget};
+    in.rank.assign(in.n, 0);
+    if (perms && perms[t]) {
+      std::vector<char> seen(in.n, 0);
+      for (int64_t q = 0; q < in.n; ++q) {
+        const int64_t v = perms[t][q];
+        if (v < 0 || v >= in.n || seen[v]) return H2_ERR_ARG;
+        seen[v] = 1;
+        in.rank[v] = q;
+      }
+    } else {
+      for (int64_t q = 0; q < in.n; ++q) in.rank[q] = q;
+    }
+  }
+  c.N = N;
+  // trees in parallel over instances
+  {
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (unsigned w = 0; w < std::min<unsigned>(hw, n_inst); ++w)
+      th.emplace_back([&]() {
+        for (int t; (t = next.fetch_add(1)) < n_inst;)
+          build_tree(pts[t], c.ins[t].n, c.dim, prm->leaf, prm->eta, c.ins[t].tree);
+      });
+    for (auto& x : th) x.join();
+  }
+  c.H = 0;
+  for (auto& in : c.ins) c.H = std::max(c.H, in.tree.L);
+
+  // points (global ids: pbase + local index), kernels, global tree permutation
+  {
+    std::vector<double> X((size_t)N * c.dim);
+    for (int t = 0; t < n_inst; ++t)
+      std::memcpy(&X[(size_t)c.ins[t].pbase * c.dim], pts[t], sizeof(double) * c.ins[t].n * c.dim);
+    c.dX = c.alloc<double>(X.size());
+    ALLOCHK(c.dX);
+    HIPCHK(hipMemcpy(c.dX, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<KernelDev> kd(n_inst);
+    for (int t = 0; t < n_inst; ++t) kd[t] = c.ins[t].kern;
+    c.dKern = c.alloc<KernelDev>(n_inst);
+    ALLOCHK(c.dKern);
+    HIPCHK(hipMemcpy(c.dKern, kd.data(), n_inst * sizeof(KernelDev), hipMemcpyHostToDevice));
+    std::vector<int64_t> pg(N);
+    for (int t = 0; t < n_inst; ++t)
+      for (int64_t q = 0; q < c.ins[t].n; ++q) pg[c.ins[t].pbase + q] = c.ins[t].pbase + c.ins[t].tree.perm[q];
+    c.dPermG = c.alloc<int64_t>(N);
+    ALLOCHK(c.dPermG);
+    HIPCHK(hipMemcpy(c.dPermG, pg.data(), N * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
+  c.dFail = c.alloc<int>(4);
+  c.dWs = c.alloc<double>(256 * NRHS_MAX * 4);
+  c.dScal = c.alloc<double>(NRHS_MAX * 8);
+  ALLOCHK(c.dFail);
+  ALLOCHK(c.dWs);
+  ALLOCHK(c.dScal);
+
+  // active sets of the current level per instance (global ids)
+  std::vector<std::vector<std::vector<int64_t>>> curB(n_inst);
+  for (int t = 0; t < n_inst; ++t) {
+    const Tree& tr = c.ins[t].tree;
+    const int L = tr.L;
+    curB[t].resize((size_t)1 << L);
+    for (int i = 0; i < (1 << L); ++i)
+      for (int64_t q = tr.start[L][i]; q < tr.start[L][i + 1]; ++q)
+        curB[t][i].push_back(c.ins[t].pbase + tr.perm[q]);
+  }
+  size_t fixed_pos = 0, fixed_box = 0;
+
+  c.steps.resize(c.H);
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    S.h = h;
+    std::vector<int> base(n_inst, -1);
+    for (int t = 0; t < n_inst; ++t) {
+      const int l = c.ins[t].tree.L - h;
+      if (l < 1) continue;
+      base[t] = S.nbox;
+      for (int i = 0; i < (1 << l); ++i) {
+        S.inst.push_back(t);
+        S.idx.push_back(i);
+        S.lvl.push_back(l);
+        S.m.push_back((int)curB[t][i].size());
+        ++S.nbox;
+      }
+    }
+    const int nb = S.nbox;
+    S.boff.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) S.boff[b + 1] = S.boff[b] + S.m[b];
+    S.sum_m = S.boff[nb];
+    for (int b = 0; b < nb; ++b)
+      if (S.m[b] > ID_MMAX) return H2_ERR_UNSUPPORTED;
+    // pairs and per-box near lists
+    std::vector<std::vector<int>> near_loc(nb);
+    for (int t = 0; t < n_inst; ++t) {
+      if (base[t] < 0) continue;
+      const int l = c.ins[t].tree.L - h;
+      for (auto& pr : c.ins[t].tree.near[l]) {
+        near_loc[base[t] + pr.first].push_back(pr.second);
+        if (pr.first >= pr.second) {
+          S.np_i.push_back(base[t] + pr.first);
+          S.np_j.push_back(base[t] + pr.second);
+        }
+      }
+      for (auto& pr : c.ins[t].tree.far[l])
+        if (pr.first > pr.second) {
+          S.fp_i.push_back(base[t] + pr.first);
+          S.fp_j.push_back(base[t] + pr.second);
+        }
+    }
+    S.diag_pair.assign(nb, -1);
+    for (size_t p = 0; p < S.np_i.size(); ++p)
+      if (S.np_i[p] == S.np_j[p]) S.diag_pair[S.np_i[p]] = (int)p;
+    // active ids
+    S.B.reserve(S.sum_m);
+    for (int b = 0; b < nb; ++b)
+      S.B.insert(S.B.end(), curB[S.inst[b]][S.idx[b]].begin(), curB[S.inst[b]][S.idx[b]].end());
+    S.dB = c.alloc<int64_t>(S.sum_m);
+    ALLOCHK(S.dB);
+    HIPCHK(hipMemcpy(S.dB, S.B.data(), S.sum_m * sizeof(int64_t), hipMemcpyHostToDevice));
+
+    // ---- sample selection (host)
+    std::vector<std::vector<int64_t>> SF(nb), SC(nb);
+    for (int t = 0; t < n_inst; ++t) {
+      if (base[t] < 0) continue;
+      const int l = c.ins[t].tree.L - h;
+      const int nbt = 1 << l;
+      std::vector<std::vector<int>> nl(near_loc.begin() + base[t], near_loc.begin() + base[t] + nbt);
+      std::vector<std::vector<int64_t>> sf, sc;
+      sample_level(curB[t], nl, c.ins[t].rank.data(), c.ins[t].pbase, prm->s_far, prm->s_near, sf,
+                   sc, (int)hw);
+      for (int i = 0; i < nbt; ++i) {
+        SF[base[t] + i] = std::move(sf[i]);
+        SC[base[t] + i] = std::move(sc[i]);
+      }
+    }
+    std::vector<int> sf(nb), sc(nb), s(nb);
+    std::vector<int64_t> sfo(nb + 1, 0), sco(nb + 1, 0), acco(nb + 1, 0), t1o(nb + 1, 0),
+        xo(nb + 1, 0), qo(nb + 1, 0);
+    std::vector<int64_t> ids_f, ids_c;
+    for (int b = 0; b < nb; ++b) {
+      sf[b] = (int)SF[b].size();
+      sc[b] = (int)SC[b].size();
+      s[b] = sf[b] + sc[b];
+      if (sc[b] > CHOL_NMAX) return H2_ERR_UNSUPPORTED;
+      sfo[b + 1] = sfo[b] + sf[b];
+      sco[b + 1] = sco[b] + sc[b];
+      acco[b + 1] = acco[b] + (int64_t)sc[b] * sc[b];
+      t1o[b + 1] = t1o[b] + (int64_t)sc[b] * S.m[b];
+      xo[b + 1] = xo[b] + (int64_t)s[b] * S.m[b];
+      qo[b + 1] = qo[b] + (int64_t)S.m[b] * S.m[b];
+      ids_f.insert(ids_f.end(), SF[b].begin(), SF[b].end());
+      ids_c.insert(ids_c.end(), SC[b].begin(), SC[b].end());
+    }
+    S.qoff = qo;
+    // forced skeletons for this step
+    std::vector<int32_t> fk(nb, 0), fsk;
+    if (fixed_ranks) {
+      for (int b = 0; b < nb; ++b) {
+        const int kk = fixed_ranks[fixed_box + b];
+        if (kk < 0 || kk > S.m[b] || kk > s[b]) return H2_ERR_ARG;
+        fk[b] = kk;
+        std::vector<char> seen(S.m[b], 0);
+        for (int q = 0; q < kk; ++q) {
+          const int pos = fixed_skel[fixed_pos + q];
+          if (pos < 0 || pos >= S.m[b] || seen[pos]) return H2_ERR_ARG;
+          seen[pos] = 1;
+          fsk.push_back(pos);
+        }
+        fixed_pos += kk;
+      }
+      fixed_box += nb;
+    }
+    TmpBuf tf, tc, tacc, tlc, tt1, tt2, tx, tpiv, tk, tfs;
+    int64_t *dF = nullptr, *dC = nullptr;
+    if (!upload_tmp(tf, dF, ids_f, st) || !upload_tmp(tc, dC, ids_c, st)) return H2_ERR_ALLOC;
+    double* dAcc = tacc.get<double>(acco[nb]);
+    double* dLc = tlc.get<double>(acco[nb]);
+    double* dT1 = tt1.get<double>(t1o[nb]);
+    double* dT2 = tt2.get<double>(t1o[nb]);
+    double* dXid = tx.get<double>(xo[nb]);
+    int32_t* dPiv = tpiv.get<int32_t>(S.sum_m);
+    int32_t* dK = tk.get<int32_t>(nb);
+    int32_t* dFs = nullptr;
+    if (fixed_ranks && !upload_tmp(tfs, dFs, fsk, st)) return H2_ERR_ALLOC;
+    S.dU = c.alloc<double>(qo[nb]);
+    ALLOCHK(S.dU);
+    ALLOCHK(dAcc); ALLOCHK(dLc); ALLOCHK(dT1); ALLOCHK(dT2); ALLOCHK(dXid); ALLOCHK(dPiv); ALLOCHK(dK);
+
+    // ---- kernel blocks: A_cc, G(S_C, B_i), G(S_F, B_i) into the ID matrix
+    std::vector<EvalDesc> ev;
+    for (int b = 0; b < nb; ++b) {
+      const int64_t* Bb = S.dB + S.boff[b];
+      const int t = S.inst[b];
+      if (sc[b] > 0) {
+        ev.push_back({dC + sco[b], dC + sco[b], dAcc + acco[b], sc[b], sc[b], sc[b], t});
+        ev.push_back({dC + sco[b], Bb, dT1 + t1o[b], sc[b], S.m[b], sc[b], t});
+      }
+      if (sf[b] > 0) ev.push_back({dF + sfo[b], Bb, dXid + xo[b], sf[b], S.m[b], s[b], t});
+    }
+    h2_status e = run_eval(c, ev, st);
+    if (e != H2_OK) return e;
+    // ---- A_Close^T = A_cc^{-1} G(S_C, B_i) = Lc^{-T} (Lc^{-1} G(S_C, B_i))
+    {
+      std::vector<CholDesc> cd;
+      for (int b = 0; b < nb; ++b)
+        if (sc[b] > 0) cd.push_back({dAcc + acco[b], dLc + acco[b], sc[b], sc[b], b});
+      TmpBuf tcd;
+      CholDesc* dcd = nullptr;
+      if (!upload_tmp(tcd, dcd, cd, st)) return H2_ERR_ALLOC;
+      HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
+      HIPCHK(launch_chol_inv(dcd, (int)cd.size(), c.dFail, st));
+      int fail = INT_MAX;
+      HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (fail != INT_MAX) {
+        c.st.fail_level = c.ins[S.inst[fail]].tree.L - h;
+        c.st.fail_box = S.idx[fail];
+        c.st.fail_inst = S.inst[fail];
+        return H2_ERR_NOT_SPD;
+      }
+      std::vector<GemmDesc> g1, g2;
+      for (int b = 0; b < nb; ++b) {
+        if (sc[b] == 0) continue;
+        g1.push_back(gd(dLc + acco[b], sc[b], 0, dT1 + t1o[b], sc[b], 0, nullptr, 1, dT2 + t1o[b],
+                        sc[b], sc[b], S.m[b], sc[b], 1.0, 0.0));
+        g2.push_back(gd(dLc + acco[b], sc[b], 1, dT2 + t1o[b], sc[b], 0, nullptr, 1,
+                        dXid + xo[b] + sf[b], s[b], sc[b], S.m[b], sc[b], 1.0, 0.0));
+      }
+      if ((e = run_gemm_tmp(g1, st)) != H2_OK) return e;
+      if ((e = run_gemm_tmp(g2, st)) != H2_OK) return e;
+    }
+    // ---- interpolative decomposition
+    {
+      std::vector<IdDesc> idd(nb);
+      int64_t fsp = 0;
+      for (int b = 0; b < nb; ++b) {
+        idd[b] = IdDesc{dXid + xo[b], S.dU + qo[b], dPiv + S.boff[b], dK + b,
+                        fixed_ranks ? dFs + fsp : nullptr, s[b], S.m[b], fk[b], 0};
+        fsp += fk[b];
+      }
+      TmpBuf tid;
+      IdDesc* did = nullptr;
+      if (!upload_tmp(tid, did, idd, st)) return H2_ERR_ALLOC;
+      HIPCHK(launch_cpqr_id(did, nb, prm->eps, prm->max_rank, nullptr, st));
+      S.k.assign(nb, 0);
+      std::vector<int32_t> piv(S.sum_m);
+      HIPCHK(hipMemcpyAsync(S.k.data(), dK, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(piv.data(), dPiv, S.sum_m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      S.koff.assign(nb + 1, 0);
+      S.roff.assign(nb + 1, 0);
+      for (int b = 0; b < nb; ++b) {
+        S.koff[b + 1] = S.koff[b] + S.k[b];
+        S.roff[b + 1] = S.roff[b] + (S.m[b] - S.k[b]);
+        for (int q = 0; q < S.k[b]; ++q) S.SK.push_back(S.B[S.boff[b] + piv[S.boff[b] + q]]);
+      }
+      S.sum_k = S.koff[nb];
+      S.sum_r = S.roff[nb];
+      S.dSK = c.alloc<int64_t>(S.sum_k);
+      ALLOCHK(S.dSK);
+      HIPCHK(hipMemcpy(S.dSK, S.SK.data(), S.sum_k * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    // ---- couplings S_ij = G(SK_i, SK_j) (far, i > j) and leaf near blocks
+    {
+      const size_t nf = S.fp_i.size();
+      S.soff.assign(nf + 1, 0);
+      for (size_t f = 0; f < nf; ++f)
+        S.soff[f + 1] = S.soff[f] + (int64_t)S.k[S.fp_i[f]] * S.k[S.fp_j[f]];
+      S.dS = c.alloc<double>(S.soff[nf]);
+      ALLOCHK(S.dS);
+      std::vector<EvalDesc> ev2;
+      for (size_t f = 0; f < nf; ++f) {
+        const int i = S.fp_i[f], j = S.fp_j[f];
+        ev2.push_back({S.dSK + S.koff[i], S.dSK + S.koff[j], S.dS + S.soff[f], S.k[i], S.k[j],
+                       std::max(1, S.k[i]), S.inst[i]});
+      }
+      const size_t np = S.np_i.size();
+      S.poff.assign(np + 1, 0);
+      for (size_t p = 0; p < np; ++p)
+        S.poff[p + 1] = S.poff[p] + (int64_t)S.m[S.np_i[p]] * S.m[S.np_j[p]];
+      if (h == 0) {
+        S.dD = c.alloc<double>(S.poff[np]);
+        ALLOCHK(S.dD);
+        for (size_t p = 0; p < np; ++p) {
+          const int i = S.np_i[p], j = S.np_j[p];
+          ev2.push_back({S.dB + S.boff[i], S.dB + S.boff[j], S.dD + S.poff[p], S.m[i], S.m[j],
+                         S.m[i], S.inst[i]});
+        }
+      }
+      if ((e = run_eval(c, ev2, st)) != H2_OK) return e;
+    }
+    // ---- parents' active sets
+    for (int t = 0; t < n_inst; ++t) {
+      if (base[t] < 0) continue;
+      const int l = c.ins[t].tree.L - h;
+      std::vector<std::vector<int64_t>> nbp((size_t)1 << (l - 1));
+      for (int I = 0; I < (1 << (l - 1)); ++I)
+        for (int ch = 0; ch < 2; ++ch) {
+          const int b = base[t] + 2 * I + ch;
+          nbp[I].insert(nbp[I].end(), S.SK.begin() + S.koff[b], S.SK.begin() + S.koff[b + 1]);
+        }
+      curB[t] = std::move(nbp);
+    }
+  }
+  // roots
+  for (int t = 0; t < n_inst; ++t) {
+    Instance& in = c.ins[t];
+    in.root_ids = curB[t][0];
+    in.n0 = (int)in.root_ids.size();
+    if (in.n0 > 65536) return H2_ERR_UNSUPPORTED;
+  }
+  h2_status e = plan_factor(c, st);
+  if (e != H2_OK) return e;
+  e = plan_solve(c, st);
+  if (e != H2_OK) return e;
+  if (hipEventCreate(&c.ev_a) != hipSuccess || hipEventCreate(&c.ev_b) != hipSuccess)
+    return H2_ERR_HIP;
+  c.st.t_build = now_seconds() - t_begin;
+  auto* hnd = new h2_ctx;
+  hnd->c = std::move(ctx);
+  *out = hnd;
+  return H2_OK;
+}
+
+// ------------------------------------------------------------- factor plan
+h2_status plan_factor(Ctx& c, hipStream_t st) {
+  // root buffers
+  int max_n0 = 0;
+  for (auto& in : c.ins) {
+    const int n0 = std::max(in.n0, 1);
+    in.dRoot = c.alloc<double>((size_t)n0 * n0);
+    in.dRootA = c.alloc<double>((size_t)n0 * n0);
+    in.dDinv = c.alloc<double>((size_t)((n0 + 63) / 64) * 4096);
+    in.dPan = c.alloc<double>((size_t)n0 * 64);
+    ALLOCHK(in.dRoot); ALLOCHK(in.dRootA); ALLOCHK(in.dDinv); ALLOCHK(in.dPan);
+    max_n0 = std::max(max_n0, in.n0);
+  }
+  // L == 0 instances: the dense kernel block is the whole matrix
+  {
+    std::vector<EvalDesc> ev;
+    std::vector<int64_t> ids;
+    std::vector<int64_t> io(c.n_inst + 1, 0);
+    for (int t = 0; t < c.n_inst; ++t) {
+      if (c.ins[t].tree.L == 0) ids.insert(ids.end(), c.ins[t].root_ids.begin(), c.ins[t].root_ids.end());
+      io[t + 1] = ids.size();
+    }
+    if (!ids.empty()) {
+      int64_t* dids = c.alloc<int64_t>(ids.size());
+      ALLOCHK(dids);
+      HIPCHK(hipMemcpy(dids, ids.data(), ids.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+      for (int t = 0; t < c.n_inst; ++t) {
+        Instance& in = c.ins[t];
+        if (in.tree.L != 0) continue;
+        in.dRootOrig = c.alloc<double>((size_t)in.n0 * in.n0);
+        ALLOCHK(in.dRootOrig);
+        ev.push_back({dids + io[t], dids + io[t], in.dRootOrig, in.n0, in.n0, in.n0, t});
+      }
+      h2_status e = run_eval(c, ev, st);
+      if (e != H2_OK) return e;
+    }
+  }
+  // per-step storage
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    const int nb = S.nbox;
+    S.rkoff.assign(nb + 1, 0);
+    S.lioff.assign(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+      const int r = S.m[b] - S.k[b];
+      S.rkoff[b + 1] = S.rkoff[b] + (int64_t)S.k[b] * S.k[b];
+      S.lioff[b + 1] = S.lioff[b] + (int64_t)r * r;
+      if (S.k[b] > QR_KMAX || r > CHOL_NMAX) return H2_ERR_UNSUPPORTED;
+    }
+    const int64_t q = S.qoff[nb];
+    S.dQ = c.alloc<double>(q); S.dP = c.alloc<double>(q); S.dTA = c.alloc<double>(q);
+    S.dTB = c.alloc<double>(q); S.dW = c.alloc<double>(q);
+    S.dR = c.alloc<double>(S.rkoff[nb]); S.dLi = c.alloc<double>(S.lioff[nb]);
+    ALLOCHK(S.dQ); ALLOCHK(S.dP); ALLOCHK(S.dTA); ALLOCHK(S.dTB); ALLOCHK(S.dW);
+    ALLOCHK(S.dR); ALLOCHK(S.dLi);
+    // near blocks of upper steps (m = k_2I + k_2I+1 is known now)
+    const size_t np = S.np_i.size();
+    S.poff.assign(np + 1, 0);
+    for (size_t p = 0; p < np; ++p) S.poff[p + 1] = S.poff[p] + (int64_t)S.m[S.np_i[p]] * S.m[S.np_j[p]];
+    if (h > 0) { S.dD = c.alloc<double>(S.poff[np]); ALLOCHK(S.dD); }
+    S.dF = c.alloc<double>(S.poff[np]);
+    S.dT2 = c.alloc<double>(S.poff[np]);
+    S.dT3 = c.alloc<double>(S.soff.back());
+    ALLOCHK(S.dF); ALLOCHK(S.dT2); ALLOCHK(S.dT3);
+  }
+  // index of (instance, level-local box) in each step
+  auto local = [&](int h, int t, int i) -> int {
+    const Step& S = c.steps[h];
+    // boxes of an instance are contiguous; find its first box
+    int lo = 0, hi = S.nbox - 1, first = -1;
+    while (lo <= hi) {  // first b with inst[b] >= t
+      const int mid = (lo + hi) / 2;
+      if (S.inst[mid] >= t) { first = mid; hi = mid - 1; } else lo = mid + 1;
+    }
+    return first + i;
+  };
+  // pair maps
+  std::vector<std::unordered_map<int64_t, int>> pmap(c.H);
+  for (int h = 0; h < c.H; ++h) {
+    const Step& S = c.steps[h];
+    for (size_t p = 0; p < S.np_i.size(); ++p)
+      pmap[h][(int64_t)S.np_i[p] * S.nbox + S.np_j[p]] = (int)p;
+  }
+  // parent block of child pair (a, b), a >= b, at step h: pointer, ld
+  auto parent_block = [&](int h, int a, int b, double*& ptr, int& ld) {
+    const Step& S = c.steps[h];
+    const int t = S.inst[a];
+    const int l = S.lvl[a];
+    const int ia = S.idx[a], ib = S.idx[b];
+    const int ro = (ia & 1) ? S.k[a - 1] : 0;
+    const int co = (ib & 1) ? S.k[b - 1] : 0;
+    if (l == 1) {
+      ld = c.ins[t].n0;
+      ptr = c.ins[t].dRoot + ro + (int64_t)co * ld;
+      return;
+    }
+    const Step& P = c.steps[h + 1];
+    const int pI = local(h + 1, t, ia / 2), pJ = local(h + 1, t, ib / 2);
+    const int pp = pmap[h + 1].at((int64_t)pI * P.nbox + pJ);
+    ld = P.m[pI];
+    ptr = P.dD + P.poff[pp] + ro + (int64_t)co * ld;
+  };
+
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    const int nb = S.nbox;
+    std::vector<GemmDesc> gw, gd1, gd2, gv, gs, gp1, gp2, gf1, gf2;
+    std::vector<CopyDesc> cw, cps, cm;
+    std::vector<BoxDev> qr(nb);
+    std::vector<CholDesc> ch;
+    for (int b = 0; b < nb; ++b) {
+      const int m = S.m[b], k = S.k[b], r = m - k;
+      double* U = S.dU + S.qoff[b];
+      double* W = S.dW + S.qoff[b];
+      double* Q = S.dQ + S.qoff[b];
+      double* P = S.dP + S.qoff[b];
+      double* TA = S.dTA + S.qoff[b];
+      double* TB = S.dTB + S.qoff[b];
+      double* R = S.dR + S.rkoff[b];
+      double* Li = S.dLi + S.lioff[b];
+      double* Dii = S.dD + S.poff[S.diag_pair[b]];
+      double* Fii = S.dF + S.poff[S.diag_pair[b]];
+      if (h == 0) {
+        if (m * k > 0) cw.push_back({U, W, m, k, m, m, 0});
+      } else {
+        const Step& C = c.steps[h - 1];
+        const int a = local(h - 1, S.inst[b], 2 * S.idx[b]);
+        const int ka = C.k[a], kb = C.k[a + 1];
+        gw.push_back(gd(C.dR + C.rkoff[a], ka, 0, U, m, 0, nullptr, 1, W, m, ka, k, ka, 1.0, 0.0));
+        gw.push_back(gd(C.dR + C.rkoff[a + 1], kb, 0, U + ka, m, 0, nullptr, 1, W + ka, m, kb, k, kb,
+                        1.0, 0.0));
+      }
+      qr[b] = BoxDev{m, k, S.inst[b], Q, P, R, Li, TA, TB, W};
+      gd1.push_back(gd(Dii, m, 0, Q, m, 0, nullptr, 1, TA, m, m, m, m, 1.0, 0.0));
+      gd2.push_back(gd(Q, m, 1, TA, m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
+      if (r > 0) ch.push_back({TB + k + (int64_t)k * m, Li, r, m, h * (1 << 20) + b});
+      if (m * k > 0) cps.push_back({Q, P, m, k, m, m, 0});
+      if (r > 0) {
+        gv.push_back(gd(Q + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, P + (int64_t)k * m, m, m, r,
+                        r, 1.0, 0.0));
+        if (k > 0)
+          gv.push_back(gd(TB + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, Fii + (int64_t)k * m, m, k,
+                          r, r, 1.0, 0.0));
+      }
+      if (k > 0)
+        gs.push_back(gd(Fii + (int64_t)k * m, m, 0, Fii + (int64_t)k * m, m, 1, TB, m, Fii, m, k, k, r,
+                        -1.0, 1.0));
+    }
+    for (size_t p = 0; p < S.np_i.size(); ++p) {
+      const int i = S.np_i[p], j = S.np_j[p];
+      if (i == j) continue;
+      const int mi = S.m[i], mj = S.m[j];
+      gp1.push_back(gd(S.dD + S.poff[p], mi, 0, S.dP + S.qoff[j], mj, 0, nullptr, 1,
+                       S.dT2 + S.poff[p], mi, mi, mj, mj, 1.0, 0.0));
+      gp2.push_back(gd(S.dP + S.qoff[i], mi, 1, S.dT2 + S.poff[p], mi, 0, nullptr, 1,
+                       S.dF + S.poff[p], mi, mi, mj, mi, 1.0, 0.0));
+    }
+    for (size_t f = 0; f < S.fp_i.size(); ++f) {
+      const int i = S.fp_i[f], j = S.fp_j[f];
+      const int ki = S.k[i], kj = S.k[j];
+      double* dst;
+      int ldp;
+      parent_block(h, i, j, dst, ldp);
+      gf1.push_back(gd(S.dR + S.rkoff[i], ki, 0, S.dS + S.soff[f], ki, 0, nullptr, 1,
+                       S.dT3 + S.soff[f], ki, ki, kj, ki, 1.0, 0.0));
+      gf2.push_back(gd(S.dT3 + S.soff[f], ki, 0, S.dR + S.rkoff[j], kj, 1, nullptr, 1, dst, ldp, ki,
+                       kj, kj, 1.0, 0.0));
+      const bool sib = (S.idx[i] >> 1) == (S.idx[j] >> 1);
+      if (sib && ki * kj > 0) {
+        // transposed copy inside the parent's diagonal block
+        cm.push_back({dst, dst - S.k[j] + (int64_t)S.k[j] * ldp, kj, ki, ldp, ldp, 1});
+      }
+    }
+    for (size_t p = 0; p < S.np_i.size(); ++p) {
+      const int a = S.np_i[p], b = S.np_j[p];
+      const int ka = S.k[a], kb = S.k[b];
+      if (ka * kb == 0) continue;
+      double* dst;
+      int ldp;
+      parent_block(h, a, b, dst, ldp);
+      cm.push_back({S.dF + S.poff[p], dst, ka, kb, S.m[a], ldp, 0});
+      if (a != b && (S.idx[a] >> 1) == (S.idx[b] >> 1)) {
+        // sibling block (2I+1, 2I): also write (2I, 2I+1) = transpose
+        double* base = dst - kb;  // row offset of a is k_b; back to the parent origin row
+        cm.push_back({S.dF + S.poff[p], base + (int64_t)kb * ldp, kb, ka, S.m[a], ldp, 1});
+      }
+    }
+    {
+      auto to = gemm_tiles(gw);
+      if (!gw.empty() && !upload(c, S.g_w, gw, st, &to)) return H2_ERR_ALLOC;
+    }
+    auto up_g = [&](Batch<GemmDesc>& B, const std::vector<GemmDesc>& v) {
+      auto to = gemm_tiles(v);
+      return v.empty() ? true : upload(c, B, v, st, &to);
+    };
+    if (!up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
+        !up_g(S.g_schur, gs) || !up_g(S.g_pair1, gp1) || !up_g(S.g_pair2, gp2) ||
+        !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2))
+      return H2_ERR_ALLOC;
+    if (!upload(c, S.c_w, cw, st) || !upload(c, S.c_ps, cps, st) || !upload(c, S.c_merge, cm, st) ||
+        !upload(c, S.qr, qr, st) || !upload(c, S.chol, ch, st))
+      return H2_ERR_ALLOC;
+  }
+  // root plan: save, then blocked Cholesky panels
+  {
+    // L == 0: root <- dense block; all: keep a copy of the assembled root
+    std::vector<CopyDesc> sv;
+    for (auto& in : c.ins)
+      if (in.n0 > 0) {
+        if (in.tree.L == 0) {
+          sv.push_back({in.dRootOrig, in.dRoot, in.n0, in.n0, in.n0, in.n0, 0});
+          sv.push_back({in.dRootOrig, in.dRootA, in.n0, in.n0, in.n0, in.n0, 0});
+        } else {
+          sv.push_back({in.dRoot, in.dRootA, in.n0, in.n0, in.n0, in.n0, 0});
+        }
+      }
+    if (!upload(c, c.r_save, sv, st)) return H2_ERR_ALLOC;
+    const int np = (max_n0 + 63) / 64;
+    c.r_panel.resize(np);
+    c.r_trsm.resize(np);
+    c.r_syrk.resize(np);
+    c.r_back.resize(np);
+    for (int pi = 0; pi < np; ++pi) {
+      const int p = pi * 64;
+      std::vector<PanelDesc> pd;
+      std::vector<GemmDesc> tr, sy;
+      std::vector<CopyDesc> bk;
+      for (int t = 0; t < c.n_inst; ++t) {
+        Instance& in = c.ins[t];
+        const int n = in.n0;
+        if (n <= p) continue;
+        const int nbk = std::min(64, n - p);
+        double* A = in.dRoot;
+        pd.push_back({A + p + (int64_t)p * n, n, nbk, in.dDinv + (int64_t)pi * 4096, (1023 << 20) + t});
+        const int rows = n - p - nbk;
+        if (rows > 0) {
+          double* A21 = A + (p + nbk) + (int64_t)p * n;
+          double* A22 = A + (p + nbk) + (int64_t)(p + nbk) * n;
+          tr.push_back(gd(A21, n, 0, in.dDinv + (int64_t)pi * 4096, 64, 1, nullptr, 1, in.dPan, n,
+                          rows, nbk, nbk, 1.0, 0.0));
+          sy.push_back(gd(in.dPan, n, 0, in.dPan, n, 1, A22, n, A22, n, rows, rows, nbk, -1.0, 1.0));
+          bk.push_back({in.dPan, A21, rows, nbk, n, n, 0});
+        }
+      }
+      auto to1 = gemm_tiles(tr), to2 = gemm_tiles(sy);
+      if (!upload(c, c.r_panel[pi], pd, st) || (!tr.empty() && !upload(c, c.r_trsm[pi], tr, st, &to1)) ||
+          (!sy.empty() && !upload(c, c.r_syrk[pi], sy, st, &to2)) || !upload(c, c.r_back[pi], bk, st))
+        return H2_ERR_ALLOC;
+    }
+  }
+  return H2_OK;
+}
+
+}  // namespace h2

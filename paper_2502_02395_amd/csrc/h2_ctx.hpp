@@ -1,0 +1,221 @@
+// The handle behind h2_handle: host structure, device arenas and the
+// precomputed work lists of every launch of factor, solve and matvec.
+#pragma once
+
+#include <climits>
+#include <memory>
+
+#include "h2_internal.hpp"
+#include "tree.hpp"
+
+namespace h2 {
+
+// A launch-ready batch of descriptors living in device memory.
+template <class T>
+struct Batch {
+  T* d = nullptr;          // descriptors
+  int* toff = nullptr;     // tile prefix (GEMM / eval), count + 1 entries
+  int count = 0;
+  int tiles = 0;
+  int max_rows = 0;        // thin / gather: row extent for the grid
+};
+
+// One height step h above the leaves: level L_t - h of every instance t with
+// L_t - h >= 1.  Boxes are ordered instance-major, box-minor.
+struct Step {
+  int h = 0;
+  int nbox = 0;
+  std::vector<int> inst, idx, lvl, m, k;
+  std::vector<int64_t> boff;               // prefix of m  (active ids, vectors)
+  std::vector<int64_t> koff;               // prefix of k  (skeleton ids, skeleton vectors)
+  std::vector<int64_t> roff;               // prefix of r = m - k
+  int64_t sum_m = 0, sum_k = 0, sum_r = 0;
+  // unordered near pairs (i >= j) and far pairs (i > j), step-local indices
+  std::vector<int> np_i, np_j, fp_i, fp_j;
+  std::vector<int> diag_pair;              // near-pair index of (b, b)
+  std::vector<int64_t> poff;               // near-pair block offsets (m_i m_j prefix)
+  std::vector<int64_t> soff;               // far-pair coupling offsets (k_i k_j prefix)
+  std::vector<int64_t> qoff, rkoff, lioff; // m^2, k^2, r^2 prefixes
+  std::vector<int64_t> voff;               // box offsets in the level vectors
+  int64_t vld = 0;                         // their leading dimension
+  // host copies of ids
+  std::vector<int64_t> B;                  // active ids, sum_m
+  std::vector<int64_t> SK;                 // skeleton ids, sum_k
+  // device buffers
+  int64_t* dB = nullptr;
+  int64_t* dSK = nullptr;
+  double* dU = nullptr;                    // U_i at qoff (capacity m^2, used m x k)
+  double* dS = nullptr;                    // couplings at soff
+  double* dD = nullptr;                    // input near blocks at poff
+  double* dF = nullptr;                    // transformed near blocks at poff
+  double* dT2 = nullptr;                   // pair scratch at poff
+  double* dT3 = nullptr;                   // far scratch at soff
+  double *dQ = nullptr, *dP = nullptr, *dTA = nullptr, *dTB = nullptr;  // at qoff
+  double* dW = nullptr;                    // QR workspace at qoff
+  double* dR = nullptr;                    // at rkoff
+  double* dLi = nullptr;                   // at lioff
+  // factor work lists
+  Batch<GemmDesc> g_w;                     // W = D_i U_i (upper steps)
+  Batch<CopyDesc> c_w;                     // W = U (leaf step)
+  Batch<BoxDev> qr;
+  Batch<GemmDesc> g_diag1, g_diag2;        // D_ii Q, Q^T (.)
+  Batch<CholDesc> chol;
+  Batch<CopyDesc> c_ps;                    // P^S = Q^S
+  Batch<GemmDesc> g_v;                     // V = Q^R Linv^T, L(s)_ii
+  Batch<GemmDesc> g_schur;                 // SS_ii -= L(s) L(s)^T
+  Batch<GemmDesc> g_pair1, g_pair2;        // D_ij P_j, P_i^T (.)
+  Batch<GemmDesc> g_far1, g_far2;          // R_i S_ij, (.) R_j^T into the parent
+  Batch<CopyDesc> c_merge;
+  // solve / matvec work lists (built for NRHS_MAX columns)
+  Batch<GemmDesc> t_fwd, t_bwd;            // P^T b, P [xS; s]
+  Batch<GatherBox> gb_yr, gb_cs, gb_t, gb_s;
+  Batch<GatherNbr> gn_yr, gn_cs, gn_t, gn_s;
+  Batch<GemmDesc> t_up, t_down;            // U^T x, U y
+  Batch<GatherBox> gb_cpl, gb_near;
+  Batch<GatherNbr> gn_cpl, gn_near;
+  // solve vectors (ld = sum_m or sum_r), NRHS_MAX columns
+  double *v_in = nullptr, *v_d = nullptr, *v_out = nullptr, *v_yr = nullptr, *v_t = nullptr;
+  double *v_xh = nullptr, *v_yh = nullptr;  // matvec skeleton vectors (ld sum_k)
+};
+
+struct Instance {
+  int64_t n = 0, pbase = 0;                // points, global id base
+  KernelDev kern{};
+  Tree tree;
+  std::vector<int64_t> rank;               // position of each local point in pi
+  int n0 = 0;                              // root size
+  std::vector<int64_t> root_ids;
+  double* dRoot = nullptr;                 // n0 x n0 (factored in place)
+  double* dRootA = nullptr;                // copy of the assembled root block
+  double* dRootOrig = nullptr;             // L == 0: the dense kernel block
+  double* dDinv = nullptr;                 // ceil(n0/64) x 64 x 64
+  double* dPan = nullptr;                  // n0 x 64 panel scratch
+  double* v_root = nullptr;                // n0 x NRHS_MAX
+};
+
+constexpr int NRHS_MAX = 16;
+
+struct Ctx {
+  h2_params prm{};
+  int n_inst = 0;
+  int dim = 3;
+  int64_t N = 0;
+  int H = 0;                               // max levels
+  std::vector<Instance> ins;
+  std::vector<Step> steps;                 // h = 0 .. H-1
+  double* dX = nullptr;                    // N x dim points (original order per instance)
+  KernelDev* dKern = nullptr;
+  int64_t* dPermG = nullptr;               // global tree position -> global id
+  int* dFail = nullptr;
+  double* dWs = nullptr;                   // reduction workspace
+  double* dScal = nullptr;                 // small scalars
+  // root work lists (per panel step p)
+  std::vector<Batch<PanelDesc>> r_panel;
+  std::vector<Batch<GemmDesc>> r_trsm, r_syrk;
+  std::vector<Batch<CopyDesc>> r_back;
+  Batch<CopyDesc> r_save;
+  Batch<RootDesc> r_solve;
+  bool factored = false;
+  bool failed = false;
+  h2_stats_t st{};
+  std::vector<void*> allocs;               // everything hipMalloc'd
+  // tree-ordered input / output vectors (N x NRHS_MAX, ld N); the leaf step
+  // and root-only instances read and write them directly
+  double *vt_in = nullptr, *vt_out = nullptr;
+  Batch<CopyDesc> r_in, r_out;             // root-only instances <-> v_root
+  Batch<GemmDesc> t_root;                  // root-only instances: matvec
+  // refinement vectors (N x NRHS_MAX)
+  double *w_x = nullptr, *w_r = nullptr, *w_z = nullptr, *w_p = nullptr, *w_q = nullptr, *w_t = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;  // pair-transform timing
+  double pair_flops = 0.0;                 // canonical flops of all pair transforms
+  int pair_launches = 0;
+  hipGraphExec_t graph = nullptr;
+  hipGraph_t graph_def = nullptr;
+  hipStream_t graph_stream = nullptr;
+
+  ~Ctx();
+  template <class T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    allocs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+// Upload a host descriptor vector (and tile prefix for tiled batches).
+template <class T>
+bool upload(Ctx& c, Batch<T>& b, const std::vector<T>& v, hipStream_t st,
+            const std::vector<int>* toff = nullptr) {
+  b.count = (int)v.size();
+  if (v.empty()) return true;
+  b.d = c.alloc<T>(v.size());
+  if (!b.d) return false;
+  if (hipMemcpyAsync(b.d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess)
+    return false;
+  if (toff) {
+    b.toff = c.alloc<int>(toff->size());
+    if (!b.toff) return false;
+    if (hipMemcpyAsync(b.toff, toff->data(), toff->size() * sizeof(int), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return false;
+    b.tiles = toff->back();
+  }
+  // the host vectors may die after return: wait for the copies
+  return hipStreamSynchronize(st) == hipSuccess;
+}
+
+// Tile prefix for GEMM items (64 x 64 tiles).
+inline std::vector<int> gemm_tiles(const std::vector<GemmDesc>& v) {
+  std::vector<int> off(v.size() + 1, 0);
+  for (size_t i = 0; i < v.size(); ++i) {
+    const int tm = (v[i].M + 63) / 64, tn = (v[i].N + 63) / 64;
+    off[i + 1] = off[i] + ((v[i].M > 0 && v[i].N > 0) ? tm * tn : 0);
+  }
+  return off;
+}
+inline std::vector<int> eval_tiles(const std::vector<EvalDesc>& v) {
+  std::vector<int> off(v.size() + 1, 0);
+  for (size_t i = 0; i < v.size(); ++i) {
+    const int tm = (v[i].nr + 63) / 64, tn = (v[i].nc + 63) / 64;
+    off[i + 1] = off[i] + ((v[i].nr > 0 && v[i].nc > 0) ? tm * tn : 0);
+  }
+  return off;
+}
+
+inline GemmDesc gd(const double* A, int lda, int tA, const double* B, int ldb, int tB,
+                   const double* C, int ldc, double* D, int ldd, int M, int N, int K,
+                   double alpha, double beta) {
+  GemmDesc g;
+  g.A = A; g.B = B; g.C = C; g.D = D;
+  g.M = M; g.N = N; g.K = K;
+  g.lda = lda < 1 ? 1 : lda; g.ldb = ldb < 1 ? 1 : ldb;
+  g.ldc = ldc < 1 ? 1 : ldc; g.ldd = ldd < 1 ? 1 : ldd;
+  g.tA = tA; g.tB = tB; g.alpha = alpha; g.beta = beta;
+  return g;
+}
+
+hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag = 0);
+hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st);
+hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st);
+hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int nrhs,
+                      hipStream_t st);
+
+// defined in the orchestration sources
+h2_status plan_factor(Ctx& c, hipStream_t st);
+h2_status plan_solve(Ctx& c, hipStream_t st);
+h2_status do_factor(Ctx& c, hipStream_t st);
+h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                         hipStream_t st);
+h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs,
+                          hipStream_t st);
+double now_seconds();
+
+hipError_t launch_set_int(int* p, int v, hipStream_t st);
+
+}  // namespace h2
+
+struct h2_ctx {
+  std::unique_ptr<h2::Ctx> c;
+};

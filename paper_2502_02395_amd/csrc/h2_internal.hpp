@@ -1,0 +1,188 @@
+// Internal declarations shared by the host orchestration (*.cpp) and the HIP
+// kernels (*.hip) of the H^2-ULV library.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/h2.h"
+
+namespace h2 {
+
+// ---------------------------------------------------------------- device types
+
+struct KernelDev {          // kernel function parameters of one instance
+  int id;
+  double delta, kappa, ell, nugget;
+};
+
+// One item of a batched GEMM:  D = alpha * op(A) op(B) + beta * C
+// (column-major; op(A) is M x K, op(B) is K x N; C may alias D).
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  const double* C;
+  double* D;
+  int M, N, K;
+  int lda, ldb, ldc, ldd;
+  int tA, tB;
+  double alpha, beta;
+};
+
+// One item of a batched kernel-matrix evaluation: out(r, c) = G(x_rows[r], x_cols[c])
+struct EvalDesc {
+  const int64_t* rows;      // global point ids
+  const int64_t* cols;
+  double* out;
+  int nr, nc, ld;
+  int inst;
+};
+
+// One item of a batched block copy: dst = src (or src^T)
+struct CopyDesc {
+  const double* src;
+  double* dst;
+  int rows, cols;           // of dst
+  int lds, ldd;
+  int trans;                // 1: dst(r, c) = src(c, r)
+};
+
+// Factor blocks of one box (pointers into the handle's arenas).
+struct BoxDev {
+  int m, k;                 // active size, rank
+  int inst;
+  double* Q;                // m x m orthogonal completion
+  double* P;                // m x m [Q^S | Q^R L(r)^{-T}]
+  double* Rf;               // k x k triangular factor of D_i U_i
+  double* Linv;             // r x r inverse Cholesky factor of the RR block
+  double* tmpA;             // m x m scratch
+  double* tmpB;             // m x m transformed diagonal block
+  double* W;                // m x k QR workspace
+};
+
+// ------------------------------------------------------------- launch wrappers
+// All wrappers enqueue on `st`; they return hipSuccess or the launch error.
+
+// tag 1 launches the same kernel under the symbol gemm_f64_pair_kernel
+hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
+                       int tiles, hipStream_t st, int tag = 0);
+hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
+                       int tiles, const double* X, int dim, const KernelDev* kern,
+                       hipStream_t st);
+hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st);
+
+// QR of W (m x k) into the full Q (m x m) and R (k x k), one workgroup per box.
+hipError_t launch_qr_complete(const BoxDev* boxes, int nbox, hipStream_t st);
+// Cholesky + explicit inverse of n x n SPD blocks: A (ld lda, destroyed),
+// Linv (n x n dense, zero upper triangle).  Breakdown: *fail = min(code).
+struct CholDesc {
+  double* A;
+  double* Linv;
+  int n, lda;
+  int code;                 // reported through *fail when this block breaks down
+};
+hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail,
+                           hipStream_t st);
+// Column-pivoted QR interpolative decomposition of X (s x m, ld s), one box
+// per workgroup.  Free mode: rank by eps; forced mode: skel[] given.
+struct IdDesc {
+  double* X;                // s x m workspace, destroyed
+  double* U;                // m x kcap output basis (written m x k, ld m)
+  int32_t* piv;             // m pivot positions (output)
+  int32_t* k_out;           // rank (output)
+  const int32_t* skel;      // forced skeleton positions (NULL = free)
+  int s, m, kforced, kcap;
+};
+hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps,
+                          int max_rank, double* norm_ws, hipStream_t st);
+
+// Thin products y = alpha op(A) x + beta y for N <= 16 columns; ncols > 0
+// overrides every item's N.
+hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols,
+                       hipStream_t st);
+
+// Neighbour gathers of the substitution and the matvec:
+//   y_i = base_i + alpha * sum_nbr op(B_nbr) x_nbr
+// with op(B) = B ("direct": B is rows x cols, ld ldB) or B^T ("trans": B is
+// cols x rows).  Direct neighbours are summed by one thread per output row
+// (coalesced down columns of B), transposed ones by one wave per output row
+// (coalesced down columns of B^T); the direct pass always runs first and
+// writes y, the transposed pass adds to it.  base == NULL means zero; base may
+// alias y.
+struct GatherBox {
+  double* y;
+  const double* base;
+  int rows, ldy, ldbase;
+  double alpha;
+  int d0, d1;               // direct neighbour range
+  int t0, t1;               // transposed neighbour range
+};
+struct GatherNbr {
+  const double* B;
+  const double* x;
+  int ldB, ldx, cols;       // cols: summation length
+};
+hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows,
+                         const GatherNbr* nb, int nrhs, hipStream_t st);
+
+// Root blocked Cholesky panel: factor nb x nb diagonal block in place and
+// write its inverse (64 x 64, zero padded) to dinv.
+struct PanelDesc {
+  double* A;                // diagonal block pointer
+  int lda, nb;
+  double* dinv;             // 64 x 64
+  int code;
+};
+hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st);
+// Root triangular solves with blocked diagonal inverses, one workgroup per
+// instance: b (n x nrhs, ld n) overwritten by L^{-T} L^{-1} b.
+struct RootDesc {
+  const double* L;          // n x n lower Cholesky factor (ld n)
+  const double* dinv;       // ceil(n/64) blocks of 64 x 64
+  double* b;
+  int n;
+};
+hipError_t launch_root_solve(const RootDesc* d, int count, int nrhs, hipStream_t st);
+
+// Vector permutations: dst[r + c*ldd] = src[idx[r] + c*lds]  (gather)
+hipError_t launch_gather_rows(const int64_t* idx, int64_t n, int nrhs,
+                              const double* src, int64_t lds, double* dst,
+                              int64_t ldd, hipStream_t st);
+// dst[idx[r] + c*ldd] = src[r + c*lds]  (scatter)
+hipError_t launch_scatter_rows(const int64_t* idx, int64_t n, int nrhs,
+                               const double* src, int64_t lds, double* dst,
+                               int64_t ldd, hipStream_t st);
+// out[c] = sum_i a[i, c] b[i, c] (deterministic two-stage sum; ws holds
+// 256 * nrhs doubles)
+hipError_t launch_coldot(const double* a, int64_t lda, const double* b, int64_t ldb,
+                         int64_t n, int nrhs, double* ws, double* out, hipStream_t st);
+// z = x + sgn * (alphas[c] / alphas_den[c]) * y  (NULL alpha arrays mean 1)
+hipError_t launch_axpby(double* z, int64_t ldz, const double* x, int64_t ldx,
+                        const double* y, int64_t ldy, int64_t n, int nrhs,
+                        const double* alphas, const double* alphas_den, double sgn,
+                        hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+
+// MLP (FP32)
+hipError_t launch_mlp_forward(const float* w, const float* x, float* y,
+                              int64_t n, hipStream_t st);
+hipError_t launch_mlp_grad(const float* w, const float* x, const float* t,
+                           int64_t n, float* g, float* loss, hipStream_t st);
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, int np,
+                       int step, float lr, hipStream_t st);
+
+// ------------------------------------------------------------------- helpers
+
+// A device array of descriptors with its tile prefix (for GEMM / eval).
+template <class T>
+struct DevBatch {
+  T* desc = nullptr;
+  int* tile_off = nullptr;
+  int count = 0;
+  int tiles = 0;
+};
+
+}  // namespace h2

@@ -1,0 +1,433 @@
+// Per-box dense factorizations, one 256-thread workgroup per box:
+//   * qr_complete  -- Householder QR of D_i U_i with the full square Q_i
+//                     (basis completion, first step of each level of the
+//                     ULV sweep; skeleton columns first);
+//   * cpqr_id      -- column-pivoted Householder QR of M^T for the row
+//                     interpolative decomposition of Algorithm 1, rank by the
+//                     leading |R_jj| > eps |R_00|, then T = R_11^{-1} R_12;
+//   * chol_inv     -- Cholesky of an SPD block and the explicit inverse of its
+//                     factor (redundant diagonal blocks, near-sample matrices);
+//   * panel        -- the same on the 64-wide diagonal panels of the root;
+//   * root_solve   -- forward and backward triangular solves at the root.
+// Householder vectors follow LAPACK's convention (beta = -sign(alpha)||x||,
+// v_0 = 1, tau = (beta - alpha)/beta).
+#include "h2_internal.hpp"
+
+namespace h2 {
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the 256 threads; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// Householder reflector for x = col[j..n) (col has stride 1).  Overwrites
+// col[j] with beta and col[j+1..n) with v (v_0 = 1 implicit); returns tau.
+__device__ double householder(double* col, int j, int n, double* sh, double* beta_out) {
+  double p = 0.0;
+  for (int i = j + 1 + (int)threadIdx.x; i < n; i += 256) p += col[i] * col[i];
+  const double sigma = block_sum(p, sh);
+  const double alpha = col[j];
+  double tau = 0.0, beta = alpha;
+  if (sigma != 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+    tau = (beta - alpha) / beta;
+    const double scal = 1.0 / (alpha - beta);
+    for (int i = j + 1 + (int)threadIdx.x; i < n; i += 256) col[i] *= scal;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) col[j] = beta;
+  __syncthreads();
+  *beta_out = beta;
+  return tau;
+}
+
+// Apply H = I - tau v v^T (v in vcol[j..n), v_j = 1) to column c[j..n) with a
+// single wave; returns nothing.  If norm_out != NULL, also returns the sum of
+// squares of c[j+1..n) after the update (for pivoting).
+__device__ __forceinline__ double apply_reflector_wave(const double* vcol, double* c, int j,
+                                                       int n, double tau, bool want_norm) {
+  const int lane = threadIdx.x & 63;
+  double w = 0.0;
+  for (int i = j + lane; i < n; i += 64) w += (i == j ? 1.0 : vcol[i]) * c[i];
+  w = wave_sum(w) * tau;
+  double s = 0.0;
+  for (int i = j + lane; i < n; i += 64) {
+    const double nv = c[i] - w * (i == j ? 1.0 : vcol[i]);
+    c[i] = nv;
+    if (want_norm && i > j) s += nv * nv;
+  }
+  return want_norm ? wave_sum(s) : 0.0;
+}
+
+// ------------------------------------------------------------------ QR + Q
+__global__ __launch_bounds__(256) void qr_complete_kernel(const BoxDev* __restrict__ boxes) {
+  extern __shared__ double tau_s[];
+  __shared__ double sh[4];
+  const BoxDev b = boxes[blockIdx.x];
+  const int m = b.m, k = b.k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* W = b.W;
+  for (int j = 0; j < k; ++j) {
+    double beta;
+    const double tau = householder(W + (int64_t)j * m, j, m, sh, &beta);
+    if (threadIdx.x == 0) tau_s[j] = tau;
+    if (tau != 0.0)
+      for (int c = j + 1 + wave; c < k; c += 4)
+        apply_reflector_wave(W + (int64_t)j * m, W + (int64_t)c * m, j, m, tau, false);
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < k * k; e += 256) {
+    const int r = e % k, c = e / k;
+    b.Rf[e] = (r <= c) ? W[r + (int64_t)c * m] : 0.0;
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += 256)
+    b.Q[e] = (e % m == e / m) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    if (tau != 0.0)
+      for (int c = j + wave; c < m; c += 4)
+        apply_reflector_wave(W + (int64_t)j * m, b.Q + (int64_t)c * m, j, m, tau, false);
+    __syncthreads();
+  }
+  (void)lane;
+}
+
+hipError_t launch_qr_complete(const BoxDev* boxes, int nbox, hipStream_t st) {
+  if (nbox <= 0) return hipSuccess;
+  // tau for up to QR_KMAX reflectors (host checks k <= QR_KMAX)
+  hipLaunchKernelGGL(qr_complete_kernel, dim3(nbox), dim3(256), 4096 * sizeof(double), st, boxes);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- pivoted QR ID
+constexpr int ID_MMAX = 4096;
+
+__global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__ descs, double eps,
+                                                      int max_rank) {
+  __shared__ double sh[4];
+  __shared__ double norms[ID_MMAX];
+  __shared__ int piv[ID_MMAX];
+  __shared__ double bestv[4];
+  __shared__ int besti[4];
+  __shared__ int kfinal;
+  const IdDesc d = descs[blockIdx.x];
+  const int s = d.s, m = d.m;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* X = d.X;
+  const bool forced = d.skel != nullptr;
+
+  for (int c = threadIdx.x; c < m; c += 256) piv[c] = c;
+  for (int c = wave; c < m; c += 4) {
+    double p = 0.0;
+    for (int i = lane; i < s; i += 64) p += X[i + (int64_t)c * s] * X[i + (int64_t)c * s];
+    p = wave_sum(p);
+    if (lane == 0) norms[c] = p;
+  }
+  int kmax = s < m ? s : m;
+  if (d.kcap > 0 && d.kcap < kmax) kmax = d.kcap;
+  if (max_rank > 0 && max_rank < kmax) kmax = max_rank;
+  if (forced) kmax = d.kforced;
+  if (threadIdx.x == 0) kfinal = kmax;
+  __syncthreads();
+
+  double r00 = 0.0;
+  for (int j = 0; j < kmax; ++j) {
+    // ---- choose the pivot column
+    int p = -1;
+    if (forced) {
+      if (threadIdx.x == 0) besti[0] = -1;
+      __syncthreads();
+      const int want = d.skel[j];
+      for (int c = j + threadIdx.x; c < m; c += 256)
+        if (piv[c] == want) besti[0] = c;
+      __syncthreads();
+      p = besti[0];
+      if (p < 0) p = j;  // invalid input: keep order (host validates)
+    } else {
+      double bv = -1.0;
+      int bi = m;
+      for (int c = j + threadIdx.x; c < m; c += 256) {
+        const double v = norms[c];
+        if (v > bv || (v == bv && c < bi)) { bv = v; bi = c; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(bv, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { bestv[wave] = bv; besti[wave] = bi; }
+      __syncthreads();
+      bv = bestv[0]; bi = besti[0];
+      for (int w = 1; w < 4; ++w)
+        if (bestv[w] > bv || (bestv[w] == bv && besti[w] < bi)) { bv = bestv[w]; bi = besti[w]; }
+      p = bi;
+      __syncthreads();
+    }
+    if (p != j) {
+      for (int i = threadIdx.x; i < s; i += 256) {
+        const double t = X[i + (int64_t)j * s];
+        X[i + (int64_t)j * s] = X[i + (int64_t)p * s];
+        X[i + (int64_t)p * s] = t;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const double tn = norms[j]; norms[j] = norms[p]; norms[p] = tn;
+        const int ti = piv[j]; piv[j] = piv[p]; piv[p] = ti;
+      }
+      __syncthreads();
+    }
+    // ---- reflector on column j
+    double beta;
+    const double tau = householder(X + (int64_t)j * s, j, s, sh, &beta);
+    if (j == 0) {
+      r00 = fabs(beta);
+      if (r00 == 0.0) { if (threadIdx.x == 0) kfinal = 0; break; }
+    }
+    if (!forced && !(fabs(beta) > eps * r00)) {
+      if (threadIdx.x == 0) kfinal = j;
+      break;
+    }
+    for (int c = j + 1 + wave; c < m; c += 4) {
+      const double nn = (tau != 0.0)
+          ? apply_reflector_wave(X + (int64_t)j * s, X + (int64_t)c * s, j, s, tau, true)
+          : 0.0;
+      if (tau == 0.0) {
+        double q = 0.0;
+        for (int i = j + 1 + lane; i < s; i += 64) q += X[i + (int64_t)c * s] * X[i + (int64_t)c * s];
+        q = wave_sum(q);
+        if (lane == 0) norms[c] = q;
+      } else if (lane == 0) {
+        norms[c] = nn;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  const int k = kfinal;
+  const int nr = m - k;
+  // ---- T = R11^{-1} R12, in place in rows 0..k-1 of columns k..m-1
+  for (int t = k - 1; t >= 0; --t) {
+    const double rtt = X[t + (int64_t)t * s];
+    for (int c = threadIdx.x; c < nr; c += 256) X[t + (int64_t)(k + c) * s] /= rtt;
+    __syncthreads();
+    for (int e = threadIdx.x; e < t * nr; e += 256) {
+      const int q = e % t, c = e / t;
+      X[q + (int64_t)(k + c) * s] -= X[q + (int64_t)t * s] * X[t + (int64_t)(k + c) * s];
+    }
+    __syncthreads();
+  }
+  // ---- U (m x k, ld m): identity rows at the skeleton, T^T elsewhere
+  for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += 256) {
+    const int t = (int)(e / m), r = (int)(e % m);
+    (void)r;
+    d.U[e] = 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += 256) d.U[piv[t] + (int64_t)t * m] = 1.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)nr * k; e += 256) {
+    const int q = (int)(e % nr), t = (int)(e / nr);
+    d.U[piv[k + q] + (int64_t)t * m] = X[t + (int64_t)(k + q) * s];
+  }
+  for (int c = threadIdx.x; c < m; c += 256) d.piv[c] = piv[c];
+  if (threadIdx.x == 0) *d.k_out = k;
+}
+
+hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps, int max_rank,
+                          double* norm_ws, hipStream_t st) {
+  (void)norm_ws;
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cpqr_id_kernel, dim3(count), dim3(256), 0, st, d_desc, eps, max_rank);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ Cholesky + inv
+// n <= 256 * CHOL_ROWS_PER_THREAD (the host rejects larger blocks).
+constexpr int CHOL_ROWS_PER_THREAD = 8;
+// Right-looking Cholesky of the n x n lower part of a (ld lda), then the
+// explicit inverse of the factor into li (ld ldl), zero upper triangle.
+// a and li may live in LDS or global memory (flat addressing).
+__device__ void chol_inv_impl(double* a, int lda, double* li, int ldl, int n, int* fail,
+                              int code) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double piv_s;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double dj = a[j + (int64_t)j * lda];
+      if (!(dj > 0.0)) {
+        atomicMin(fail, code);
+        dj = 1.0;
+      }
+      dj = sqrt(dj);
+      a[j + (int64_t)j * lda] = dj;
+      piv_s = 1.0 / dj;
+    }
+    __syncthreads();
+    const double inv = piv_s;
+    for (int i = j + 1 + (int)threadIdx.x; i < n; i += 256) a[i + (int64_t)j * lda] *= inv;
+    __syncthreads();
+    for (int c = j + 1 + wave; c < n; c += 4) {
+      const double acj = a[c + (int64_t)j * lda];
+      for (int i = c + lane; i < n; i += 64) a[i + (int64_t)c * lda] -= a[i + (int64_t)j * lda] * acj;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
+    const int r = (int)(e % n), c = (int)(e / n);
+    li[r + (int64_t)c * ldl] = (r >= c) ? a[r + (int64_t)c * lda] : 0.0;
+  }
+  __syncthreads();
+  // in-place inversion of the lower-triangular li, last column first
+  for (int j = n - 1; j >= 0; --j) {
+    const double djj = 1.0 / li[j + (int64_t)j * ldl];
+    double y = 0.0;
+    const int i = j + 1 + (int)threadIdx.x;
+    // y_i = sum_{q=j+1..i} Linv[i, q] x_q, x_q = L[q, j] (column j, not yet overwritten)
+    double yv[CHOL_ROWS_PER_THREAD];
+    int cnt = 0;
+    for (int ii = i; ii < n; ii += 256) {
+      y = 0.0;
+      for (int q = j + 1; q <= ii; ++q) y += li[ii + (int64_t)q * ldl] * li[q + (int64_t)j * ldl];
+      if (cnt < CHOL_ROWS_PER_THREAD) yv[cnt] = y;
+      ++cnt;
+    }
+    __syncthreads();
+    cnt = 0;
+    for (int ii = i; ii < n; ii += 256) {
+      if (cnt < CHOL_ROWS_PER_THREAD) li[ii + (int64_t)j * ldl] = -djj * yv[cnt];
+      ++cnt;
+    }
+    if (threadIdx.x == 0) li[j + (int64_t)j * ldl] = djj;
+    __syncthreads();
+  }
+}
+
+constexpr int CHOL_LDS_N = 88;  // n*n doubles fit in 62 KB of LDS
+
+__global__ __launch_bounds__(256) void chol_inv_kernel(const CholDesc* __restrict__ descs, int* fail) {
+  __shared__ double buf[CHOL_LDS_N * CHOL_LDS_N];
+  const CholDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  if (n <= 0) return;
+  if (n <= CHOL_LDS_N) {
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+      const int r = e % n, c = e / n;
+      buf[e] = d.A[r + (int64_t)c * d.lda];
+    }
+    __syncthreads();
+    chol_inv_impl(buf, n, d.Linv, n, n, fail, d.code);
+  } else {
+    chol_inv_impl(d.A, d.lda, d.Linv, n, n, fail, d.code);
+  }
+}
+
+hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(count), dim3(256), 0, st, d_desc, fail);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- root panels
+__global__ __launch_bounds__(256) void panel_kernel(const PanelDesc* __restrict__ descs, int* fail) {
+  __shared__ double buf[64 * 64];
+  const PanelDesc d = descs[blockIdx.x];
+  const int n = d.nb;
+  if (n <= 0) return;
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    buf[e] = d.A[r + (int64_t)c * d.lda];
+  }
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) d.dinv[e] = 0.0;
+  __syncthreads();
+  chol_inv_impl(buf, n, d.dinv, 64, n, fail, d.code);
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    d.A[r + (int64_t)c * d.lda] = (r >= c) ? buf[e] : 0.0;
+  }
+}
+
+hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(panel_kernel, dim3(count), dim3(256), 0, st, d, fail);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- root solves
+// b <- L^{-T} L^{-1} b with L blocked in 64-wide panels whose diagonal
+// inverses are in dinv.  One workgroup per instance, columns one at a time.
+__global__ __launch_bounds__(256) void root_solve_kernel(const RootDesc* __restrict__ descs, int nrhs) {
+  __shared__ double xb[64];
+  __shared__ double part[4][64];
+  const RootDesc d = descs[blockIdx.x];
+  const int n = d.n;
+  const int nblk = (n + 63) / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = 0; c < nrhs; ++c) {
+    double* b = d.b + (int64_t)c * n;
+    // forward: x_p = Dinv_p b_p ; b_rest -= L_{rest,p} x_p
+    for (int p = 0; p < nblk; ++p) {
+      const int p0 = p * 64, nb = min(64, n - p0);
+      const double* Di = d.dinv + (int64_t)p * 4096;
+      // xb[r] = sum_q Di[r, q] b[p0+q]
+      {
+        double v = 0.0;
+        const int r = lane;
+        for (int q = wave; q < nb; q += 4) v += Di[r + q * 64] * b[p0 + q];
+        part[wave][lane] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        xb[lane] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+      }
+      __syncthreads();
+      if (threadIdx.x < nb) b[p0 + threadIdx.x] = xb[threadIdx.x];
+      for (int i = p0 + nb + threadIdx.x; i < n; i += 256) {
+        double v = 0.0;
+        for (int q = 0; q < nb; ++q) v += d.L[i + (int64_t)(p0 + q) * n] * xb[q];
+        b[i] -= v;
+      }
+      __syncthreads();
+    }
+    // backward: x_p = Dinv_p^T (b_p - sum_{i > p block} L_{i,p}^T x_i)
+    for (int p = nblk - 1; p >= 0; --p) {
+      const int p0 = p * 64, nb = min(64, n - p0);
+      // w_q = b[p0+q] - sum_{i >= p0+nb} L[i, p0+q] x_i   (wave per q)
+      for (int q = wave; q < nb; q += 4) {
+        double v = 0.0;
+        const double* col = d.L + (int64_t)(p0 + q) * n;
+        for (int i = p0 + nb + lane; i < n; i += 64) v += col[i] * b[i];
+        v = wave_sum(v);
+        if (lane == 0) xb[q] = b[p0 + q] - v;
+      }
+      __syncthreads();
+      const double* Di = d.dinv + (int64_t)p * 4096;
+      double out = 0.0;
+      if (threadIdx.x < nb) {
+        const int r = threadIdx.x;
+        for (int q = 0; q < nb; ++q) out += Di[q + r * 64] * xb[q];  // (Dinv^T)[r, q]
+      }
+      __syncthreads();
+      if (threadIdx.x < nb) b[p0 + threadIdx.x] = out;
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t launch_root_solve(const RootDesc* d, int count, int nrhs, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(root_solve_kernel, dim3(count), dim3(256), 0, st, d, nrhs);
+  return hipGetLastError();
+}
+
+}  // namespace h2

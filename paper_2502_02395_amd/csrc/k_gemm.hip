@@ -1,0 +1,266 @@
+// Batched variable-size FP64 GEMM on CDNA4 matrix cores, thin products for
+// the substitution, and batched block copies.
+//
+// The basis transforms of the ULV sweep (Algorithm 4: U_i^T A_ij V_j, the
+// diagonal transform and the Schur update of Eq. 21) are many independent
+// small dense products of uneven shape.  Instead of padding them to a common
+// size (the paper's choice for its vendor batched calls, Section 4.1), every
+// launch takes a work list of items of their own M, N, K, strides and
+// transposes; each workgroup computes one 64 x 64 tile of one item, found by a
+// binary search over the per-item tile prefix.
+#include "h2_internal.hpp"
+
+namespace h2 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 64, TN = 64, TK = 16, LPAD = 1;
+
+__device__ __forceinline__ int find_item(const int* off, int count, int t) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {  // largest i with off[i] <= t
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that
+// consecutive logical tiles (the tiles of one item, which share operands) run
+// on the same XCD and hit the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int per = (nb + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs,
+                                              const int* __restrict__ toff, int count, int tiles) {
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  if (logical >= tiles) return;
+  const int item = find_item(toff, count, logical);
+  const GemmDesc d = descs[item];
+  const int t = logical - toff[item];
+  const int tiles_m = (d.M + TM - 1) / TM;
+  const int m0 = (t % tiles_m) * TM;
+  const int n0 = (t / tiles_m) * TN;
+
+  __shared__ double As[TK][TM + LPAD];
+  __shared__ double Bs[TK][TN + LPAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+  d4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int m, k;
+      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; }
+      else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
+      const int gm = m0 + m, gk = k0 + k;
+      double v = 0.0;
+      if (gm < d.M && gk < d.K)
+        v = d.tA ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int n, k;
+      if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
+      else       { n = tid & 63; k = (tid >> 6) + 4 * q; }
+      const int gn = n0 + n, gk = k0 + k;
+      double v = 0.0;
+      if (gn < d.N && gk < d.K)
+        v = d.tB ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
+      rb[q] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int m, k;
+      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; }
+      else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
+      As[k][m] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int n, k;
+      if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
+      else       { n = tid & 63; k = (tid >> 6) + 4 * q; }
+      Bs[k][n] = rb[q];
+    }
+  };
+
+  const int nk = (d.K + TK - 1) / TK;
+  if (nk > 0) load(0);
+  for (int kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (kt + 1 < nk) load((kt + 1) * TK);
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const int c = lane & 15;
+      double a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
+      double b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  }
+
+  // Accumulator layout of the 16x16x4 f64 MFMA (measured on gfx950): element e
+  // of lane l holds row 4*e + l/16, column l%16.
+  const int col = lane & 15;
+  const int rg = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gm = m0 + wm + 16 * i + 4 * e + rg;
+        const int gn = n0 + wn + 16 * j + col;
+        if (gm < d.M && gn < d.N) {
+          double v = d.alpha * acc[i][j][e];
+          if (d.beta != 0.0) v += d.beta * d.C[gm + (int64_t)gn * d.ldc];
+          d.D[gm + (int64_t)gn * d.ldd] = v;
+        }
+      }
+}
+
+// Two symbols with the same body so that profiles separate the near-pair
+// basis transforms (the dominant cost) from every other product.
+__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
+                                                       const int* __restrict__ toff, int count,
+                                                       int tiles) {
+  gemm_f64_body(descs, toff, count, tiles);
+}
+__global__ __launch_bounds__(256) void gemm_f64_pair_kernel(const GemmDesc* __restrict__ descs,
+                                                            const int* __restrict__ toff,
+                                                            int count, int tiles) {
+  gemm_f64_body(descs, toff, count, tiles);
+}
+
+hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
+                       int tiles, hipStream_t st, int tag) {
+  if (count <= 0 || tiles <= 0) return hipSuccess;
+  const int grid = (tiles + 7) & ~7;
+  if (tag == 1)
+    hipLaunchKernelGGL(gemm_f64_pair_kernel, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off,
+                       count, tiles);
+  else
+    hipLaunchKernelGGL(gemm_f64_kernel, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off,
+                       count, tiles);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Thin products y = alpha op(A) x + beta y, x with N <= 16 columns.  Each
+// workgroup owns 64 output rows of one item and reads its part of A once.
+constexpr int THIN_NMAX = 16;
+
+__global__ __launch_bounds__(256) void thin_kernel(const GemmDesc* __restrict__ descs, int ncols) {
+  const GemmDesc d = descs[blockIdx.y];
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= d.M) return;
+  const int tid = threadIdx.x;
+  __shared__ double red[4][64][THIN_NMAX + 1];
+  double acc[THIN_NMAX];
+#pragma unroll
+  for (int c = 0; c < THIN_NMAX; ++c) acc[c] = 0.0;
+  const int N = ncols > 0 ? ncols : d.N;
+  if (!d.tA) {
+    const int r = r0 + (tid & 63);
+    const int kq = tid >> 6;
+    if (r < d.M) {
+      for (int k = kq; k < d.K; k += 4) {
+        const double a = d.A[r + (int64_t)k * d.lda];
+#pragma unroll
+        for (int c = 0; c < THIN_NMAX; ++c)
+          if (c < N) acc[c] += a * d.B[k + (int64_t)c * d.ldb];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < THIN_NMAX; ++c)
+      if (c < N) red[kq][tid & 63][c] = acc[c];
+    __syncthreads();
+    if (tid < 64 && r < d.M) {
+      for (int c = 0; c < N; ++c) {
+        double v = d.alpha * (red[0][tid][c] + red[1][tid][c] + red[2][tid][c] + red[3][tid][c]);
+        if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
+        d.D[r + (int64_t)c * d.ldd] = v;
+      }
+    }
+  } else {
+    // row r of op(A) is column r of A: a wave reduces over k
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int rr = wave; rr < 64; rr += 4) {
+      const int r = r0 + rr;
+      if (r >= d.M) break;
+      double p[THIN_NMAX];
+#pragma unroll
+      for (int c = 0; c < THIN_NMAX; ++c) p[c] = 0.0;
+      const double* col = d.A + (int64_t)r * d.lda;
+      for (int k = lane; k < d.K; k += 64) {
+        const double a = col[k];
+#pragma unroll
+        for (int c = 0; c < THIN_NMAX; ++c)
+          if (c < N) p[c] += a * d.B[k + (int64_t)c * d.ldb];
+      }
+#pragma unroll
+      for (int c = 0; c < THIN_NMAX; ++c) {
+        if (c < N) {
+          double v = p[c];
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+          p[c] = v;
+        }
+      }
+      if (lane == 0) {
+        for (int c = 0; c < N; ++c) {
+          double v = d.alpha * p[c];
+          if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
+          d.D[r + (int64_t)c * d.ldd] = v;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, hipStream_t st) {
+  if (count <= 0 || max_m <= 0) return hipSuccess;
+  if (ncols > THIN_NMAX) return hipErrorInvalidValue;
+  dim3 grid((max_m + 63) / 64, count);
+  hipLaunchKernelGGL(thin_kernel, grid, dim3(256), 0, st, d_desc, ncols);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void copy_kernel(const CopyDesc* __restrict__ descs) {
+  const CopyDesc d = descs[blockIdx.x];
+  const int64_t total = (int64_t)d.rows * d.cols;
+  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < total; e += 256 * (int64_t)gridDim.y) {
+    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
+    const double v = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
+    d.dst[r + (int64_t)c * d.ldd] = v;
+  }
+}
+
+hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_kernel, dim3(count, 8), dim3(256), 0, st, d_desc);
+  return hipGetLastError();
+}
+
+}  // namespace h2

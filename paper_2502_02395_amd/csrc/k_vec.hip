@@ -1,0 +1,258 @@
+// Kernel-matrix evaluation, the neighbour gathers of the substitution and of
+// the H^2 matrix-vector product, and vector utilities.
+#include "h2_internal.hpp"
+
+namespace h2 {
+
+// ---------------------------------------------------------- kernel function
+// Eq. 35 / Eq. 36 with the regularisation 1/(r + delta) (value 1/delta on the
+// diagonal) and the covariance kernels with a nugget added where the two
+// point indices coincide.
+__device__ __forceinline__ double kernel_value(const KernelDev& k, double r, bool same) {
+  switch (k.id) {
+    case 0: return 1.0 / (r + k.delta);
+    case 1: return exp(-k.kappa * r) / (r + k.delta);
+    case 2: return exp(-(r * r) / (k.ell * k.ell)) + (same ? k.nugget : 0.0);
+    default: {
+      const double a = 1.7320508075688772 * r / k.ell;
+      return (1.0 + a) * exp(-a) + (same ? k.nugget : 0.0);
+    }
+  }
+}
+
+__device__ __forceinline__ int find_item_v(const int* off, int count, int t) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One 64 x 64 output tile per workgroup; thread t owns row t%64 and 16 of the
+// columns.
+__global__ __launch_bounds__(256) void eval_kernel(const EvalDesc* __restrict__ descs,
+                                                   const int* __restrict__ toff, int count,
+                                                   const double* __restrict__ X, int dim,
+                                                   const KernelDev* __restrict__ kern) {
+  const int item = find_item_v(toff, count, blockIdx.x);
+  const EvalDesc d = descs[item];
+  const int t = blockIdx.x - toff[item];
+  const int tiles_r = (d.nr + 63) / 64;
+  const int r0 = (t % tiles_r) * 64, c0 = (t / tiles_r) * 64;
+  const int r = r0 + (threadIdx.x & 63);
+  if (r >= d.nr) return;
+  const KernelDev k = kern[d.inst];
+  const int64_t pr = d.rows[r];
+  double xr[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < dim; ++a) xr[a] = X[pr * dim + a];
+  for (int cc = threadIdx.x >> 6; cc < 64; cc += 4) {
+    const int c = c0 + cc;
+    if (c >= d.nc) break;
+    const int64_t pc = d.cols[c];
+    double s = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      const double df = xr[a] - X[pc * dim + a];
+      s += df * df;
+    }
+    d.out[r + (int64_t)c * d.ld] = kernel_value(k, sqrt(s), pr == pc);
+  }
+}
+
+hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count, int tiles,
+                       const double* X, int dim, const KernelDev* kern, hipStream_t st) {
+  if (count <= 0 || tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(eval_kernel, dim3(tiles), dim3(256), 0, st, d_desc, d_tile_off, count, X,
+                     dim, kern);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gathers
+constexpr int GNR = 16;  // max right-hand sides per pass
+
+__global__ __launch_bounds__(256) void gather_direct_kernel(const GatherBox* __restrict__ boxes,
+                                                            const GatherNbr* __restrict__ nbrs,
+                                                            int nrhs) {
+  const GatherBox b = boxes[blockIdx.x];
+  const int r = blockIdx.y * 256 + threadIdx.x;
+  if (r >= b.rows) return;
+  double acc[GNR];
+#pragma unroll
+  for (int c = 0; c < GNR; ++c) acc[c] = 0.0;
+  for (int q = b.d0; q < b.d1; ++q) {
+    const GatherNbr nb = nbrs[q];
+    const double* col = nb.B + r;
+    for (int s = 0; s < nb.cols; ++s) {
+      const double bv = col[(int64_t)s * nb.ldB];
+#pragma unroll
+      for (int c = 0; c < GNR; ++c)
+        if (c < nrhs) acc[c] += bv * nb.x[s + (int64_t)c * nb.ldx];
+    }
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    const double base = b.base ? b.base[r + (int64_t)c * b.ldbase] : 0.0;
+    b.y[r + (int64_t)c * b.ldy] = base + b.alpha * acc[c];
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_trans_kernel(const GatherBox* __restrict__ boxes,
+                                                           const GatherNbr* __restrict__ nbrs,
+                                                           int nrhs) {
+  const GatherBox b = boxes[blockIdx.x];
+  if (b.t1 <= b.t0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int rr = wave; rr < 64; rr += 4) {
+    const int r = blockIdx.y * 64 + rr;
+    if (r >= b.rows) break;
+    double acc[GNR];
+#pragma unroll
+    for (int c = 0; c < GNR; ++c) acc[c] = 0.0;
+    for (int q = b.t0; q < b.t1; ++q) {
+      const GatherNbr nb = nbrs[q];
+      const double* col = nb.B + (int64_t)r * nb.ldB;  // row r of B^T
+      for (int s = lane; s < nb.cols; s += 64) {
+        const double bv = col[s];
+#pragma unroll
+        for (int c = 0; c < GNR; ++c)
+          if (c < nrhs) acc[c] += bv * nb.x[s + (int64_t)c * nb.ldx];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < GNR; ++c) {
+      if (c < nrhs) {
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[c] = v;
+      }
+    }
+    if (lane == 0)
+      for (int c = 0; c < nrhs; ++c) b.y[r + (int64_t)c * b.ldy] += b.alpha * acc[c];
+  }
+}
+
+hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows, const GatherNbr* nb,
+                         int nrhs, hipStream_t st) {
+  if (nbox <= 0 || max_rows <= 0) return hipSuccess;
+  if (nrhs > GNR) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_direct_kernel, dim3(nbox, (max_rows + 255) / 256), dim3(256), 0, st,
+                     bx, nb, nrhs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gather_trans_kernel, dim3(nbox, (max_rows + 63) / 64), dim3(256), 0, st, bx,
+                     nb, nrhs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ vector utilities
+__global__ void gather_rows_kernel(const int64_t* idx, int64_t n, int nrhs, const double* src,
+                                   int64_t lds, double* dst, int64_t ldd) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % n, c = e / n;
+    dst[r + c * ldd] = src[idx[r] + c * lds];
+  }
+}
+
+__global__ void scatter_rows_kernel(const int64_t* idx, int64_t n, int nrhs, const double* src,
+                                    int64_t lds, double* dst, int64_t ldd) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % n, c = e / n;
+    dst[idx[r] + c * ldd] = src[r + c * lds];
+  }
+}
+
+static int grid_for(int64_t work) {
+  int64_t g = (work + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_gather_rows(const int64_t* idx, int64_t n, int nrhs, const double* src,
+                              int64_t lds, double* dst, int64_t ldd, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, idx, n, nrhs,
+                     src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(const int64_t* idx, int64_t n, int nrhs, const double* src,
+                               int64_t lds, double* dst, int64_t ldd, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_rows_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, idx, n,
+                     nrhs, src, lds, dst, ldd);
+  return hipGetLastError();
+}
+
+// Column partial sums: ws[c*NCH + chunk]; then fold (deterministic order).
+constexpr int NCH = 256;
+
+__global__ __launch_bounds__(256) void coldot_partial(const double* a, int64_t lda, const double* b,
+                                                      int64_t ldb, int64_t n, double* ws) {
+  __shared__ double sh[4];
+  const int c = blockIdx.y;
+  double s = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)NCH * 256)
+    s += a[i + c * lda] * b[i + c * ldb];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) ws[c * NCH + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+__global__ void coldot_fold(const double* ws, int nrhs, double* out) {
+  const int c = threadIdx.x;
+  if (c >= nrhs) return;
+  double s = 0.0;
+  for (int q = 0; q < NCH; ++q) s += ws[c * NCH + q];
+  out[c] = s;
+}
+
+hipError_t launch_coldot(const double* a, int64_t lda, const double* b, int64_t ldb, int64_t n,
+                         int nrhs, double* ws, double* out, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(coldot_partial, dim3(NCH, nrhs), dim3(256), 0, st, a, lda, b, ldb, n, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(coldot_fold, dim3(1), dim3(256), 0, st, ws, nrhs, out);
+  return hipGetLastError();
+}
+
+// z = x + alpha[c] * y  (alpha per column from device memory if alphas != NULL,
+// scaled by sgn), all n x nrhs with their own leading dimensions.
+__global__ void axpby_kernel(double* z, int64_t ldz, const double* x, int64_t ldx, const double* y,
+                             int64_t ldy, int64_t n, int nrhs, const double* alphas,
+                             const double* alphas_den, double sgn) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % n, c = e / n;
+    double a = sgn;
+    if (alphas) a *= alphas[c];
+    if (alphas_den) a /= alphas_den[c];
+    z[r + c * ldz] = x[r + c * ldx] + a * y[r + c * ldy];
+  }
+}
+
+hipError_t launch_axpby(double* z, int64_t ldz, const double* x, int64_t ldx, const double* y,
+                        int64_t ldy, int64_t n, int nrhs, const double* alphas,
+                        const double* alphas_den, double sgn, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n * nrhs)), dim3(256), 0, st, z, ldz, x, ldx, y,
+                     ldy, n, nrhs, alphas, alphas_den, sgn);
+  return hipGetLastError();
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace h2

@@ -1,0 +1,405 @@
+// Work lists and launch sequences of the factorization (Algorithm 4), the
+// parallel substitution (Section 3.7) and the H^2 matrix-vector product.
+//
+// Substitution in the two-sided basis P_i = [Q_i^S | Q_i^R L(r)_ii^{-T}]:
+// the transformed block F_ij = P_i^T A_ij P_j holds, in S-first order,
+//   [ SS_ij          L(s)_ij                           ]
+//   [ L(s)_ji^T      L(r)_ii^{-1} L(r)_ij  (i > j)      ]
+// so with d_i = P_i^T b_i = [c_i^S; z_i], z_i = L(r)_ii^{-1} c_i^R, Eq. 31 reads
+//   y_i^R = z_i - sum_{j<i} (L(r)_ii^{-1} L(r)_ij) z_j,
+//   c_i^S -= sum_j L(s)_ij y_j^R                        (forward), and
+//   t_j   = y_j^R - sum_i L(s)_ij^T x_i^S,
+//   s_j   = t_j - sum_{i>j} (L(r)_ii^{-1} L(r)_ij)^T t_i,
+//   x_j   = P_j [x_j^S; s_j]                           (backward),
+// which is the transpose of Eq. 31 since Q_j^R L(r)_jj^{-T} s_j = Q_j^R x_j^R.
+// Every step is a batched product or neighbour gather; only the root keeps
+// triangular solves.
+#include <algorithm>
+#include <unordered_map>
+
+#include "h2_ctx.hpp"
+
+namespace h2 {
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    if ((x) != hipSuccess) return H2_ERR_HIP;      \
+  } while (0)
+#define ALLOCHK(p)                                 \
+  do {                                             \
+    if (!(p)) return H2_ERR_ALLOC;                 \
+  } while (0)
+
+static int local_box(const Step& S, int t, int i) {
+  int lo = 0, hi = S.nbox - 1, first = -1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) / 2;
+    if (S.inst[mid] >= t) { first = mid; hi = mid - 1; } else lo = mid + 1;
+  }
+  return first + i;
+}
+
+static bool up_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, hipStream_t st) {
+  auto to = gemm_tiles(v);
+  return v.empty() ? true : upload(c, b, v, st, &to);
+}
+static bool up_thin(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, hipStream_t st) {
+  int mx = 0;
+  for (auto& g : v) mx = std::max(mx, g.M);
+  b.max_rows = mx;
+  return upload(c, b, v, st);
+}
+static bool up_gather(Ctx& c, Batch<GatherBox>& bb, Batch<GatherNbr>& nb,
+                      const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
+                      hipStream_t st) {
+  int mx = 0;
+  for (auto& g : B) mx = std::max(mx, g.rows);
+  bb.max_rows = mx;
+  return upload(c, bb, B, st) && upload(c, nb, Nv, st);
+}
+
+h2_status plan_solve(Ctx& c, hipStream_t st) {
+  const int NR = NRHS_MAX;
+  c.vt_in = c.alloc<double>((size_t)c.N * NR);
+  c.vt_out = c.alloc<double>((size_t)c.N * NR);
+  c.w_x = c.alloc<double>((size_t)c.N * NR);
+  c.w_r = c.alloc<double>((size_t)c.N * NR);
+  c.w_z = c.alloc<double>((size_t)c.N * NR);
+  c.w_p = c.alloc<double>((size_t)c.N * NR);
+  c.w_q = c.alloc<double>((size_t)c.N * NR);
+  c.w_t = c.alloc<double>((size_t)c.N * NR);
+  ALLOCHK(c.vt_in); ALLOCHK(c.vt_out); ALLOCHK(c.w_x); ALLOCHK(c.w_r);
+  ALLOCHK(c.w_z); ALLOCHK(c.w_p); ALLOCHK(c.w_q); ALLOCHK(c.w_t);
+  for (auto& in : c.ins) {
+    in.v_root = c.alloc<double>((size_t)std::max(in.n0, 1) * NR);
+    ALLOCHK(in.v_root);
+  }
+  // vectors of every step
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    S.voff.assign(S.nbox, 0);
+    if (h == 0) {
+      S.vld = c.N;
+      for (int b = 0; b < S.nbox; ++b) {
+        const Instance& in = c.ins[S.inst[b]];
+        S.voff[b] = in.pbase + in.tree.start[in.tree.L][S.idx[b]];
+      }
+      S.v_in = c.vt_in;
+      S.v_out = c.vt_out;
+      S.v_d = c.alloc<double>((size_t)c.N * NR);
+      ALLOCHK(S.v_d);
+    } else {
+      S.vld = S.sum_m;
+      for (int b = 0; b < S.nbox; ++b) S.voff[b] = S.boff[b];
+      S.v_in = c.alloc<double>((size_t)S.sum_m * NR);
+      S.v_out = c.alloc<double>((size_t)S.sum_m * NR);
+      S.v_d = c.alloc<double>((size_t)S.sum_m * NR);
+      ALLOCHK(S.v_in); ALLOCHK(S.v_out); ALLOCHK(S.v_d);
+    }
+    S.v_yr = c.alloc<double>((size_t)std::max<int64_t>(S.sum_r, 1) * NR);
+    S.v_t = c.alloc<double>((size_t)std::max<int64_t>(S.sum_r, 1) * NR);
+    S.v_xh = c.alloc<double>((size_t)std::max<int64_t>(S.sum_k, 1) * NR);
+    S.v_yh = c.alloc<double>((size_t)std::max<int64_t>(S.sum_k, 1) * NR);
+    ALLOCHK(S.v_yr); ALLOCHK(S.v_t); ALLOCHK(S.v_xh); ALLOCHK(S.v_yh);
+  }
+  // parent vector slice of box b at step h (forward: in, backward: out)
+  auto parent_slice = [&](int h, int b, bool out, double*& p, int& ld) {
+    const Step& S = c.steps[h];
+    const int t = S.inst[b];
+    const int off = (S.idx[b] & 1) ? S.k[b - 1] : 0;
+    if (S.lvl[b] == 1) {
+      Instance& in = c.ins[t];
+      p = in.v_root + off;
+      ld = std::max(in.n0, 1);
+      return;
+    }
+    const Step& P = c.steps[h + 1];
+    const int pb = local_box(P, t, S.idx[b] / 2);
+    p = (out ? P.v_out : P.v_in) + P.voff[pb] + off;
+    ld = (int)P.vld;
+  };
+
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    const int nb = S.nbox;
+    const int vld = (int)S.vld;
+    const int rld = (int)std::max<int64_t>(S.sum_r, 1);
+    const int kld = (int)std::max<int64_t>(S.sum_k, 1);
+    // neighbour lists from the unordered near pairs
+    std::vector<std::vector<std::pair<int, int>>> lower(nb), upper(nb);  // (other, pair)
+    for (size_t p = 0; p < S.np_i.size(); ++p) {
+      const int i = S.np_i[p], j = S.np_j[p];
+      if (i == j) continue;
+      lower[i].push_back({j, (int)p});
+      upper[j].push_back({i, (int)p});
+    }
+    std::vector<std::vector<std::pair<int, int>>> flo(nb), fup(nb);
+    for (size_t f = 0; f < S.fp_i.size(); ++f) {
+      flo[S.fp_i[f]].push_back({S.fp_j[f], (int)f});
+      fup[S.fp_j[f]].push_back({S.fp_i[f], (int)f});
+    }
+    auto F = [&](int p) { return S.dF + S.poff[p]; };
+    std::vector<GemmDesc> tf, tb, tu, td;
+    std::vector<GatherBox> b1, b2, b3, b4, bc, bn;
+    std::vector<GatherNbr> n1, n2, n3, n4, nc, nn;
+    for (int b = 0; b < nb; ++b) {
+      const int m = S.m[b], k = S.k[b], r = m - k;
+      const double* P = S.dP + S.qoff[b];
+      double* vin = S.v_in + S.voff[b];
+      double* vd = S.v_d + S.voff[b];
+      double* vout = S.v_out + S.voff[b];
+      double* yr = S.v_yr + S.roff[b];
+      double* tv = S.v_t + S.roff[b];
+      // forward: d = P^T b
+      tf.push_back(gd(P, m, 1, vin, vld, 0, nullptr, 1, vd, vld, m, NR, m, 1.0, 0.0));
+      // y^R = z - sum_{j<i} Lt_ij z_j
+      {
+        GatherBox g{yr, vd + k, r, rld, vld, -1.0, (int)n1.size(), 0, 0, 0};
+        for (auto& jp : lower[b]) {
+          const int j = jp.first;
+          n1.push_back({F(jp.second) + k + (int64_t)S.k[j] * m, S.v_d + S.voff[j] + S.k[j], m, vld,
+                        S.m[j] - S.k[j]});
+        }
+        g.d1 = (int)n1.size();
+        g.t0 = g.t1 = (int)n1.size();
+        if (r > 0) b1.push_back(g);
+      }
+      // c^S -= sum_j L(s)_ij y_j^R, written into the parent vector
+      if (k > 0) {
+        double* py;
+        int pld;
+        parent_slice(h, b, false, py, pld);
+        GatherBox g{py, vd, k, pld, vld, -1.0, (int)n2.size(), 0, 0, 0};
+        const double* Fii = S.dF + S.poff[S.diag_pair[b]];
+        if (r > 0) n2.push_back({Fii + (int64_t)k * m, yr, m, rld, r});
+        for (auto& jp : lower[b]) {
+          const int j = jp.first, rj = S.m[j] - S.k[j];
+          if (rj > 0) n2.push_back({F(jp.second) + (int64_t)S.k[j] * m, S.v_yr + S.roff[j], m, rld, rj});
+        }
+        g.d1 = (int)n2.size();
+        g.t0 = (int)n2.size();
+        for (auto& jp : upper[b]) {
+          const int j = jp.first, rj = S.m[j] - S.k[j];
+          if (rj > 0) n2.push_back({F(jp.second) + S.k[j], S.v_yr + S.roff[j], S.m[j], rld, rj});
+        }
+        g.t1 = (int)n2.size();
+        b2.push_back(g);
+      }
+      // backward: t_j = y_j^R - sum_i L(s)_ij^T x_i^S  (+ copy x_j^S into d_j)
+      {
+        double* xs;
+        int xld;
+        parent_slice(h, b, true, xs, xld);
+        if (r > 0) {
+          GatherBox g{tv, yr, r, rld, rld, -1.0, (int)n3.size(), 0, 0, 0};
+          for (auto& ip : upper[b]) {  // i > j stored as (i, j): direct? no: L(s)_ij^T from F_ij
+            (void)ip;
+          }
+          // direct: i < j, block F_ji (ji stored since j > i): rows k_j.., cols 0..k_i
+          for (auto& ip : lower[b]) {
+            const int i = ip.first, ki = S.k[i];
+            if (ki == 0) continue;
+            double* xsi;
+            int xldi;
+            parent_slice(h, i, true, xsi, xldi);
+            n3.push_back({F(ip.second) + k, xsi, m, xldi, ki});
+          }
+          g.d1 = (int)n3.size();
+          g.t0 = (int)n3.size();
+          const double* Fjj = S.dF + S.poff[S.diag_pair[b]];
+          if (k > 0) n3.push_back({Fjj + (int64_t)k * m, xs, m, xld, k});
+          for (auto& ip : upper[b]) {
+            const int i = ip.first, ki = S.k[i];
+            if (ki == 0) continue;
+            double* xsi;
+            int xldi;
+            parent_slice(h, i, true, xsi, xldi);
+            n3.push_back({F(ip.second) + (int64_t)k * S.m[i], xsi, S.m[i], xldi, ki});
+          }
+          g.t1 = (int)n3.size();
+          b3.push_back(g);
+        }
+        if (k > 0) {
+          GatherBox g{vd, xs, k, vld, xld, 0.0, (int)n3.size(), (int)n3.size(), (int)n3.size(),
+                      (int)n3.size()};
+          b3.push_back(g);
+        }
+      }
+      // s_j = t_j - sum_{i>j} Lt_ij^T t_i, into d_j[k:]
+      if (r > 0) {
+        GatherBox g{vd + k, tv, r, vld, rld, -1.0, (int)n4.size(), (int)n4.size(), (int)n4.size(), 0};
+        for (auto& ip : upper[b]) {
+          const int i = ip.first, ri = S.m[i] - S.k[i];
+          if (ri > 0)
+            n4.push_back({F(ip.second) + S.k[i] + (int64_t)k * S.m[i], S.v_t + S.roff[i], S.m[i], rld, ri});
+        }
+        g.t1 = (int)n4.size();
+        b4.push_back(g);
+      }
+      // x_j = P_j d_j
+      tb.push_back(gd(P, m, 0, vd, vld, 0, nullptr, 1, vout, vld, m, NR, m, 1.0, 0.0));
+
+      // ---- matvec: upward U^T x
+      const double* U = S.dU + S.qoff[b];
+      if (k > 0) {
+        if (h == 0) {
+          tu.push_back(gd(U, m, 1, c.vt_in + S.voff[b], vld, 0, nullptr, 1, S.v_xh + S.koff[b], kld, k,
+                          NR, m, 1.0, 0.0));
+        } else {
+          const Step& C = c.steps[h - 1];
+          const int a = local_box(C, S.inst[b], 2 * S.idx[b]);
+          tu.push_back(gd(U, m, 1, C.v_xh + C.koff[a], (int)std::max<int64_t>(C.sum_k, 1), 0, nullptr,
+                          1, S.v_xh + S.koff[b], kld, k, NR, m, 1.0, 0.0));
+        }
+      }
+      // couplings y^_i = sum_j S_ij x^_j
+      if (k > 0) {
+        GatherBox g{S.v_yh + S.koff[b], nullptr, k, kld, kld, 1.0, (int)nc.size(), 0, 0, 0};
+        for (auto& jf : flo[b]) {
+          const int j = jf.first;
+          if (S.k[j] > 0) nc.push_back({S.dS + S.soff[jf.second], S.v_xh + S.koff[j], k, kld, S.k[j]});
+        }
+        g.d1 = (int)nc.size();
+        g.t0 = (int)nc.size();
+        for (auto& jf : fup[b]) {
+          const int j = jf.first;
+          if (S.k[j] > 0)
+            nc.push_back({S.dS + S.soff[jf.second], S.v_xh + S.koff[j], S.k[j], kld, S.k[j]});
+        }
+        g.t1 = (int)nc.size();
+        bc.push_back(g);
+      }
+      // downward U y^
+      if (h == 0) {
+        td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, nullptr, 1, c.vt_out + S.voff[b], vld, m,
+                        NR, k, 1.0, 0.0));
+        // near field y_i += sum_j D_ij x_j
+        GatherBox g{c.vt_out + S.voff[b], c.vt_out + S.voff[b], m, vld, vld, 1.0, (int)nn.size(), 0, 0,
+                    0};
+        nn.push_back({S.dD + S.poff[S.diag_pair[b]], c.vt_in + S.voff[b], m, vld, m});
+        for (auto& jp : lower[b]) {
+          const int j = jp.first;
+          nn.push_back({S.dD + S.poff[jp.second], c.vt_in + S.voff[j], m, vld, S.m[j]});
+        }
+        g.d1 = (int)nn.size();
+        g.t0 = (int)nn.size();
+        for (auto& jp : upper[b]) {
+          const int j = jp.first;
+          nn.push_back({S.dD + S.poff[jp.second], c.vt_in + S.voff[j], S.m[j], vld, S.m[j]});
+        }
+        g.t1 = (int)nn.size();
+        bn.push_back(g);
+      } else if (k > 0) {
+        const Step& C = c.steps[h - 1];
+        const int a = local_box(C, S.inst[b], 2 * S.idx[b]);
+        double* dst = C.v_yh + C.koff[a];
+        const int cld = (int)std::max<int64_t>(C.sum_k, 1);
+        td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, dst, cld, dst, cld, m, NR, k, 1.0, 1.0));
+      }
+    }
+    if (!up_thin(c, S.t_fwd, tf, st) || !up_thin(c, S.t_bwd, tb, st) || !up_thin(c, S.t_up, tu, st) ||
+        !up_thin(c, S.t_down, td, st) || !up_gather(c, S.gb_yr, S.gn_yr, b1, n1, st) ||
+        !up_gather(c, S.gb_cs, S.gn_cs, b2, n2, st) || !up_gather(c, S.gb_t, S.gn_t, b3, n3, st) ||
+        !up_gather(c, S.gb_s, S.gn_s, b4, n4, st) || !up_gather(c, S.gb_cpl, S.gn_cpl, bc, nc, st) ||
+        !up_gather(c, S.gb_near, S.gn_near, bn, nn, st))
+      return H2_ERR_ALLOC;
+  }
+  // root solves and root-only instances
+  {
+    std::vector<RootDesc> rd;
+    std::vector<CopyDesc> ri, ro;
+    std::vector<GemmDesc> tr;
+    for (auto& in : c.ins) {
+      if (in.n0 == 0) continue;
+      rd.push_back({in.dRoot, in.dDinv, in.v_root, in.n0});
+      if (in.tree.L == 0) {
+        ri.push_back({c.vt_in + in.pbase, in.v_root, in.n0, NR, (int)c.N, in.n0, 0});
+        ro.push_back({in.v_root, c.vt_out + in.pbase, in.n0, NR, in.n0, (int)c.N, 0});
+        tr.push_back(gd(in.dRootOrig, in.n0, 0, c.vt_in + in.pbase, (int)c.N, 0, nullptr, 1,
+                        c.vt_out + in.pbase, (int)c.N, in.n0, NR, in.n0, 1.0, 0.0));
+      }
+    }
+    if (!upload(c, c.r_solve, rd, st) || !upload(c, c.r_in, ri, st) || !upload(c, c.r_out, ro, st) ||
+        !up_thin(c, c.t_root, tr, st))
+      return H2_ERR_ALLOC;
+  }
+  return H2_OK;
+}
+
+// ------------------------------------------------------------------ factor
+h2_status do_factor(Ctx& c, hipStream_t st) {
+  HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
+  const bool timing = c.prm.timing != 0 && !c.prm.use_graph;
+  double t_pair = 0.0;
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    if (h == 0) HIPCHK(run_copy(S.c_w, st));
+    else HIPCHK(run_gemm(S.g_w, st));
+    HIPCHK(launch_qr_complete(S.qr.d, S.qr.count, st));
+    HIPCHK(run_gemm(S.g_diag1, st));
+    HIPCHK(run_gemm(S.g_diag2, st));
+    HIPCHK(launch_chol_inv(S.chol.d, S.chol.count, c.dFail, st));
+    HIPCHK(run_copy(S.c_ps, st));
+    HIPCHK(run_gemm(S.g_v, st));
+    HIPCHK(run_gemm(S.g_schur, st));
+    if (timing && S.g_pair1.count > 0) HIPCHK(hipEventRecord(c.ev_a, st));
+    HIPCHK(run_gemm(S.g_pair1, st, 1));
+    HIPCHK(run_gemm(S.g_pair2, st, 1));
+    if (timing && S.g_pair1.count > 0) {
+      HIPCHK(hipEventRecord(c.ev_b, st));
+      HIPCHK(hipEventSynchronize(c.ev_b));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+      t_pair += 1e-3 * ms;
+    }
+    HIPCHK(run_gemm(S.g_far1, st));
+    HIPCHK(run_gemm(S.g_far2, st));
+    HIPCHK(run_copy(S.c_merge, st));
+  }
+  HIPCHK(run_copy(c.r_save, st));
+  for (size_t p = 0; p < c.r_panel.size(); ++p) {
+    HIPCHK(launch_panel(c.r_panel[p].d, c.r_panel[p].count, c.dFail, st));
+    HIPCHK(run_gemm(c.r_trsm[p], st));
+    HIPCHK(run_gemm(c.r_syrk[p], st));
+    HIPCHK(run_copy(c.r_back[p], st));
+  }
+  if (timing) c.st.t_pair_gemm = t_pair;
+  return H2_OK;
+}
+
+// ------------------------------------------------------------------- solve
+h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                         hipStream_t st) {
+  HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, b, ldb, c.vt_in, c.N, st));
+  for (int h = 0; h < c.H; ++h) {
+    Step& S = c.steps[h];
+    HIPCHK(run_thin(S.t_fwd, nrhs, st));
+    HIPCHK(run_gather(S.gb_yr, S.gn_yr, nrhs, st));
+    HIPCHK(run_gather(S.gb_cs, S.gn_cs, nrhs, st));
+  }
+  HIPCHK(run_copy(c.r_in, st));
+  HIPCHK(launch_root_solve(c.r_solve.d, c.r_solve.count, nrhs, st));
+  HIPCHK(run_copy(c.r_out, st));
+  for (int h = c.H - 1; h >= 0; --h) {
+    Step& S = c.steps[h];
+    HIPCHK(run_gather(S.gb_t, S.gn_t, nrhs, st));
+    HIPCHK(run_gather(S.gb_s, S.gn_s, nrhs, st));
+    HIPCHK(run_thin(S.t_bwd, nrhs, st));
+  }
+  HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, x, ldx, st));
+  return H2_OK;
+}
+
+h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs,
+                          hipStream_t st) {
+  HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, x, ldx, c.vt_in, c.N, st));
+  for (int h = 0; h < c.H; ++h) HIPCHK(run_thin(c.steps[h].t_up, nrhs, st));
+  for (int h = 0; h < c.H; ++h) HIPCHK(run_gather(c.steps[h].gb_cpl, c.steps[h].gn_cpl, nrhs, st));
+  for (int h = c.H - 1; h >= 0; --h) HIPCHK(run_thin(c.steps[h].t_down, nrhs, st));
+  if (c.H > 0) HIPCHK(run_gather(c.steps[0].gb_near, c.steps[0].gn_near, nrhs, st));
+  HIPCHK(run_thin(c.t_root, nrhs, st));
+  HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, y, ldy, st));
+  return H2_OK;
+}
+
+}  // namespace h2

@@ -1,0 +1,305 @@
+"""Python binding of the HIP H^2-ULV library (include/h2.h), argument
+marshalling only: every step of build, factor, solve and matvec runs in the
+library's kernels.  PyTorch provides device memory and the current stream.
+
+Matrices cross the ABI column-major: an (n x nrhs) right-hand side is held
+here as a torch tensor of shape (nrhs, n) (row-major storage of the transpose).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libh2.so")
+
+OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_SPD, ERR_STATE, ERR_NOCONV, ERR_UNSUPPORTED = range(8)
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+SYMBOLS = ["h2_build", "h2_build_batched", "h2_build_fixed", "h2_factor", "h2_solve", "h2_matvec",
+           "h2_stats", "h2_get_counts", "h2_get_structure", "h2_get_pairs", "h2_get_root",
+           "h2_mlp_forward", "h2_mlp_train_step", "h2_box_features", "h2_destroy", "h2_status_str"]
+
+
+class H2Error(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_status_str(status)} ({status})")
+        self.status = status
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int32), ("delta", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("ell", ctypes.c_double), ("nugget", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("leaf", ctypes.c_int32), ("eta", ctypes.c_double),
+                ("eps", ctypes.c_double), ("max_rank", ctypes.c_int32), ("s_far", ctypes.c_int32),
+                ("s_near", ctypes.c_int32), ("gemm_prec", ctypes.c_int32),
+                ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
+                ("use_pcg", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
+                ("timing", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_inst", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("n_boxes", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+                ("far_pairs", ctypes.c_int64), ("leaf_near_blocks", ctypes.c_int64),
+                ("max_rank_seen", ctypes.c_int32), ("max_m_seen", ctypes.c_int32),
+                ("root_n", ctypes.c_int32), ("flops_factor", ctypes.c_double),
+                ("flops_solve", ctypes.c_double), ("bytes_factors", ctypes.c_double),
+                ("t_build", ctypes.c_double), ("t_factor", ctypes.c_double),
+                ("t_solve", ctypes.c_double), ("ir_iters", ctypes.c_int32),
+                ("ir_residual", ctypes.c_double), ("fail_level", ctypes.c_int32),
+                ("fail_box", ctypes.c_int32), ("fail_inst", ctypes.c_int32),
+                ("rank_fallbacks", ctypes.c_int32), ("t_pair_gemm", ctypes.c_double),
+                ("flops_pair_gemm", ctypes.c_double), ("pair_launches", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libh2.so; raises if it has not been built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2502_02395_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.h2_status_str.restype = ctypes.c_char_p
+    L.h2_status_str.argtypes = [ctypes.c_int]
+    L.h2_build.argtypes = [vp, i64, P(Kernel), P(Params), vp, vp, P(vp)]
+    L.h2_build_batched.argtypes = [i32, vp, vp, P(Kernel), P(Params), vp, vp, P(vp)]
+    L.h2_build_fixed.argtypes = [vp, i64, P(Kernel), P(Params), vp, vp, vp, vp, P(vp)]
+    L.h2_factor.argtypes = [vp, vp]
+    L.h2_solve.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.h2_matvec.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.h2_stats.argtypes = [vp, P(Stats)]
+    L.h2_get_counts.argtypes = [vp, P(i64), P(i64)]
+    L.h2_get_structure.argtypes = [vp, vp, vp, vp, vp]
+    L.h2_get_pairs.argtypes = [vp, i32, i32, vp, P(i64)]
+    L.h2_get_root.argtypes = [vp, i32, vp, P(i64)]
+    L.h2_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
+    L.h2_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, ctypes.c_float, vp, vp]
+    L.h2_box_features.argtypes = [vp, vp, vp]
+    L.h2_destroy.argtypes = [vp]
+    L.h2_destroy.restype = None
+    for name in SYMBOLS:
+        if name not in ("h2_status_str", "h2_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _status_str(s: int) -> str:
+    try:
+        return load().h2_status_str(s).decode()
+    except Exception:  # library unavailable while formatting an error
+        return "status"
+
+
+def _check(s: int, what: str):
+    if s != OK:
+        raise H2Error(s, what)
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_kernel(k) -> Kernel:
+    return Kernel(int(k.id), float(k.delta), float(k.kappa), float(k.ell), float(k.nugget))
+
+
+def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_near: int = -1,
+                max_rank: int = 0, gemm_prec: int = PREC_FP64, ir_max_iter: int = 0,
+                ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
+                timing: bool = False) -> Params:
+    return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
+                  int(use_pcg), int(use_graph), None, 0.25, int(timing))
+
+
+def _as_cols(t, n):
+    """(n,) or (n, nrhs) tensor -> contiguous (nrhs, n) float64 on the device."""
+    import torch
+    if t.dim() == 1:
+        t = t[:, None]
+    assert t.shape[0] == n
+    return t.to(dtype=torch.float64).t().contiguous()
+
+
+class Handle:
+    """An H^2 matrix built on the device (one instance or a batch)."""
+
+    def __init__(self, ptr: ctypes.c_void_p, n: int):
+        self._h = ptr
+        self.n = n
+
+    def close(self):
+        if self._h:
+            load().h2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def factor(self, stream=None):
+        _check(load().h2_factor(self._h, _stream(stream)), "h2_factor")
+
+    def solve(self, b, stream=None):
+        """b: device tensor (n,) or (n, nrhs); returns x of the same shape."""
+        import torch
+        cols = _as_cols(b, self.n)
+        x = torch.empty_like(cols)
+        s = load().h2_solve(self._h, ctypes.c_void_p(cols.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            cols.shape[0], self.n, _stream(stream))
+        if s not in (OK, ERR_NOCONV):
+            _check(s, "h2_solve")
+        self.last_solve_status = s
+        out = x.t()
+        return out[:, 0] if b.dim() == 1 else out
+
+    def solve_into(self, cols_b, cols_x, stream=None) -> int:
+        """Raw form: (nrhs, n) contiguous tensors, no copies; returns the status."""
+        return load().h2_solve(self._h, ctypes.c_void_p(cols_b.data_ptr()),
+                               ctypes.c_void_p(cols_x.data_ptr()), cols_b.shape[0], self.n,
+                               _stream(stream))
+
+    def matvec(self, x, stream=None):
+        import torch
+        cols = _as_cols(x, self.n)
+        y = torch.empty_like(cols)
+        _check(load().h2_matvec(self._h, ctypes.c_void_p(cols.data_ptr()),
+                                ctypes.c_void_p(y.data_ptr()), cols.shape[0], self.n,
+                                _stream(stream)), "h2_matvec")
+        out = y.t()
+        return out[:, 0] if x.dim() == 1 else out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().h2_stats(self._h, ctypes.byref(s)), "h2_stats")
+        return s.as_dict()
+
+    def structure(self):
+        """(perm, ranks, ms, skeleton ids) as numpy arrays, boxes in levels L..1."""
+        L = load()
+        nb, nsk = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.h2_get_counts(self._h, ctypes.byref(nb), ctypes.byref(nsk)), "h2_get_counts")
+        perm = np.zeros(self.n, dtype=np.int64)
+        ranks = np.zeros(nb.value, dtype=np.int32)
+        ms = np.zeros(nb.value, dtype=np.int32)
+        skel = np.zeros(nsk.value, dtype=np.int64)
+        _check(L.h2_get_structure(self._h, perm.ctypes.data, ranks.ctypes.data, ms.ctypes.data,
+                                  skel.ctypes.data), "h2_get_structure")
+        return perm, ranks, ms, skel
+
+    def pairs(self, level: int, far: bool) -> list:
+        L = load()
+        cnt = ctypes.c_int64()
+        _check(L.h2_get_pairs(self._h, level, int(far), None, ctypes.byref(cnt)), "h2_get_pairs")
+        buf = np.zeros(2 * cnt.value, dtype=np.int32)
+        _check(L.h2_get_pairs(self._h, level, int(far), buf.ctypes.data, ctypes.byref(cnt)),
+               "h2_get_pairs")
+        return [(int(buf[2 * q]), int(buf[2 * q + 1])) for q in range(cnt.value)]
+
+    def root(self, inst: int = 0) -> np.ndarray:
+        L = load()
+        n0 = ctypes.c_int64()
+        _check(L.h2_get_root(self._h, inst, None, ctypes.byref(n0)), "h2_get_root")
+        a = np.zeros((n0.value, n0.value))
+        _check(L.h2_get_root(self._h, inst, a.ctypes.data, ctypes.byref(n0)), "h2_get_root")
+        return a.T.copy()  # column-major -> row-major
+
+    def box_features(self):
+        import torch
+        nb = ctypes.c_int64()
+        _check(load().h2_get_counts(self._h, ctypes.byref(nb), None), "h2_get_counts")
+        f = torch.empty((nb.value, 8), dtype=torch.float32, device="cuda")
+        _check(load().h2_box_features(self._h, ctypes.c_void_p(f.data_ptr()), _stream(None)),
+               "h2_box_features")
+        return f
+
+
+def build(points: np.ndarray, kernel, leaf: int, eta: float, eps: float, perm=None,
+          s_far: int = -1, s_near: int = -1, stream=None, **kw) -> Handle:
+    L = load()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, dim = pts.shape
+    prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
+    k = make_kernel(kernel)
+    pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    out = ctypes.c_void_p()
+    _check(L.h2_build(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm),
+                      None if pp is None else pp.ctypes.data, _stream(stream), ctypes.byref(out)),
+           "h2_build")
+    return Handle(out, n)
+
+
+def build_fixed(points: np.ndarray, kernel, leaf: int, eta: float, eps: float, perm, ranks,
+                skel, s_far: int = -1, s_near: int = -1, stream=None, **kw) -> Handle:
+    """Build with a prescribed skeleton selection (ranks per box in levels
+    L..1 order, skeleton positions concatenated)."""
+    L = load()
+    pts = np.ascontiguousarray(points, dtype=np.float64)
+    n, dim = pts.shape
+    prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
+    k = make_kernel(kernel)
+    pp = np.ascontiguousarray(perm, dtype=np.int64)
+    rk = np.ascontiguousarray(ranks, dtype=np.int32)
+    sk = np.ascontiguousarray(skel, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _check(L.h2_build_fixed(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm), pp.ctypes.data,
+                            rk.ctypes.data, sk.ctypes.data, _stream(stream), ctypes.byref(out)),
+           "h2_build_fixed")
+    return Handle(out, n)
+
+
+def build_batched(point_sets, kernels, leaf: int, eta: float, eps: float, perms=None,
+                  s_far: int = -1, s_near: int = -1, stream=None, **kw) -> Handle:
+    L = load()
+    pts = [np.ascontiguousarray(p, dtype=np.float64) for p in point_sets]
+    ns = np.array([p.shape[0] for p in pts], dtype=np.int64)
+    dim = pts[0].shape[1]
+    prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
+    ks = (Kernel * len(pts))(*[make_kernel(k) for k in kernels])
+    pptr = (ctypes.c_void_p * len(pts))(*[p.ctypes.data for p in pts])
+    if perms is not None:
+        perms = [np.ascontiguousarray(q, dtype=np.int64) for q in perms]
+        qptr = (ctypes.c_void_p * len(pts))(*[q.ctypes.data for q in perms])
+    else:
+        qptr = None
+    out = ctypes.c_void_p()
+    _check(L.h2_build_batched(len(pts), pptr, ns.ctypes.data, ks, ctypes.byref(prm), qptr,
+                              _stream(stream), ctypes.byref(out)), "h2_build_batched")
+    h = Handle(out, int(ns.sum()))
+    h._keep = (pts, perms)
+    return h
+
+
+def mlp_forward(w, x, stream=None):
+    import torch
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(load().h2_mlp_forward(ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                 ctypes.c_void_p(y.data_ptr()), x.shape[0], _stream(stream)),
+           "h2_mlp_forward")
+    return y
+
+
+def mlp_train_step(w, m, v, g, x, t, step: int, lr: float, loss, stream=None):
+    _check(load().h2_mlp_train_step(*(ctypes.c_void_p(a.data_ptr()) for a in (w, m, v, g, x, t)),
+                                    x.shape[0], step, lr, ctypes.c_void_p(loss.data_ptr()),
+                                    _stream(stream)), "h2_mlp_train_step")
