@@ -74,6 +74,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (the reference for "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU H^2-ULV path "
@@ -83,6 +86,12 @@ def main():
     import torch
     from paper_2502_02395_amd import h2
     torch.cuda.set_device(0)
+    if a.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = workload(a.n, a.kernel, a.eps, a.leaf, a.s)
     t0 = time.perf_counter()
     H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,

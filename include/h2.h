@@ -82,6 +82,7 @@ typedef struct {
   const float* rank_model;/* host, 4801 MLP weights; NULL = plain pivoted QR    */
   double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
   int32_t timing;         /* 1 = time the near-pair transform launches of factor */
+  int32_t no_autotune;    /* 1 = skip the tile-shape autotuner (64x64 tiles)     */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -108,6 +109,10 @@ typedef struct {
   double flops_pair_gemm; /* canonical flops of those launches: sum over
                              unordered near pairs of 2 m_i m_j (m_i + m_j)      */
   int32_t pair_launches;  /* number of those launches per factor                */
+  double bytes_basis;     /* bytes allocated for the bases U_i (predicted
+                             capacities plus fallbacks, or m_i^2 per box)       */
+  int32_t tuned_lists;    /* GEMM work lists timed by the autotuner             */
+  int32_t tuned_cfg_hist[3]; /* how many chose 64x64, 128x64, 128x128 tiles     */
 } h2_stats_t;
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).

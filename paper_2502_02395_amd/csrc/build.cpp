@@ -30,7 +30,7 @@ Ctx::~Ctx() {
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
-  return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag);
+  return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg);
 }
 hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
   return launch_thin(b.d, b.count, b.max_rows, ncols, st);
@@ -204,6 +204,42 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   }
   size_t fixed_pos = 0, fixed_box = 0;
 
+  // rank prediction for every box of every level, before any compression:
+  // one network launch over the tree geometry
+  std::vector<std::vector<float>> pred(c.H);
+  if (prm->rank_model) {
+    std::vector<float> feats;
+    std::vector<int> cnt(c.H, 0);
+    for (int h = 0; h < c.H; ++h)
+      for (int t = 0; t < n_inst; ++t) {
+        const int l = c.ins[t].tree.L - h;
+        if (l < 1) continue;
+        for (int i = 0; i < (1 << l); ++i) {
+          float f[8];
+          box_features_host(c, t, l, i, f);
+          feats.insert(feats.end(), f, f + 8);
+          ++cnt[h];
+        }
+      }
+    const int64_t nb_all = (int64_t)feats.size() / 8;
+    TmpBuf tw, tfe, ty;
+    float* dw = tw.get<float>(4801);
+    float* df = tfe.get<float>(feats.size());
+    float* dy = ty.get<float>(nb_all);
+    if (!dw || !df || !dy) return H2_ERR_ALLOC;
+    HIPCHK(hipMemcpy(dw, prm->rank_model, 4801 * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(df, feats.data(), feats.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (h2_mlp_forward(dw, df, dy, nb_all, st) != H2_OK) return H2_ERR_HIP;
+    std::vector<float> y(nb_all);
+    HIPCHK(hipMemcpyAsync(y.data(), dy, nb_all * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int64_t o = 0;
+    for (int h = 0; h < c.H; ++h) {
+      pred[h].assign(y.begin() + o, y.begin() + o + cnt[h]);
+      o += cnt[h];
+    }
+  }
+
   c.steps.resize(c.H);
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
@@ -320,8 +356,24 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     int32_t* dK = tk.get<int32_t>(nb);
     int32_t* dFs = nullptr;
     if (fixed_ranks && !upload_tmp(tfs, dFs, fsk, st)) return H2_ERR_ALLOC;
-    S.dU = c.alloc<double>(qo[nb]);
+    // U capacity: the predicted rank with a margin, else the full m
+    S.kcap.assign(nb, 0);
+    std::vector<int64_t> uo(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+      int cap = S.m[b];
+      if (prm->rank_model) {
+        const double kp = std::max(0.0, std::exp2((double)pred[h][b]) - 1.0);
+        const double margin = prm->rank_margin > 0 ? prm->rank_margin : 0.0;
+        cap = std::min<int64_t>(S.m[b], (int64_t)std::ceil(kp * (1.0 + margin)) + 4);
+      }
+      S.kcap[b] = cap;
+      uo[b + 1] = uo[b] + (int64_t)S.m[b] * cap;
+    }
+    S.dU = c.alloc<double>(uo[nb]);
     ALLOCHK(S.dU);
+    S.Uptr.assign(nb, nullptr);
+    for (int b = 0; b < nb; ++b) S.Uptr[b] = S.dU + uo[b];
+    c.st.bytes_basis += 8.0 * (double)uo[nb];
     ALLOCHK(dAcc); ALLOCHK(dLc); ALLOCHK(dT1); ALLOCHK(dT2); ALLOCHK(dXid); ALLOCHK(dPiv); ALLOCHK(dK);
 
     // ---- kernel blocks: A_cc, G(S_C, B_i), G(S_F, B_i) into the ID matrix
@@ -372,8 +424,8 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       std::vector<IdDesc> idd(nb);
       int64_t fsp = 0;
       for (int b = 0; b < nb; ++b) {
-        idd[b] = IdDesc{dXid + xo[b], S.dU + qo[b], dPiv + S.boff[b], dK + b,
-                        fixed_ranks ? dFs + fsp : nullptr, s[b], S.m[b], fk[b], 0};
+        idd[b] = IdDesc{dXid + xo[b], S.Uptr[b], dPiv + S.boff[b], dK + b,
+                        fixed_ranks ? dFs + fsp : nullptr, s[b], S.m[b], fk[b], S.kcap[b]};
         fsp += fk[b];
       }
       TmpBuf tid;
@@ -385,6 +437,33 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       HIPCHK(hipMemcpyAsync(S.k.data(), dK, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(piv.data(), dPiv, S.sum_m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      // fallback: ranks above the predicted capacity get a buffer of their own
+      {
+        std::vector<int> over;
+        int64_t extra = 0;
+        for (int b = 0; b < nb; ++b)
+          if (S.k[b] > S.kcap[b]) { over.push_back(b); extra += (int64_t)S.m[b] * S.k[b]; }
+        if (!over.empty()) {
+          double* dx = c.alloc<double>(extra);
+          ALLOCHK(dx);
+          std::vector<IdDesc> od;
+          int64_t o = 0;
+          for (int b : over) {
+            S.Uptr[b] = dx + o;
+            o += (int64_t)S.m[b] * S.k[b];
+            IdDesc q = idd[b];
+            q.U = S.Uptr[b];
+            od.push_back(q);
+          }
+          TmpBuf tod;
+          IdDesc* dod = nullptr;
+          if (!upload_tmp(tod, dod, od, st)) return H2_ERR_ALLOC;
+          HIPCHK(launch_id_write_u(dod, (int)od.size(), st));
+          HIPCHK(hipStreamSynchronize(st));
+          c.st.rank_fallbacks += (int)over.size();
+          c.st.bytes_basis += 8.0 * (double)extra;
+        }
+      }
       S.koff.assign(nb + 1, 0);
       S.roff.assign(nb + 1, 0);
       for (int b = 0; b < nb; ++b) {
@@ -453,6 +532,10 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   if (e != H2_OK) return e;
   if (hipEventCreate(&c.ev_a) != hipSuccess || hipEventCreate(&c.ev_b) != hipSuccess)
     return H2_ERR_HIP;
+  if (!prm->no_autotune) {
+    e = autotune(c, st);
+    if (e != H2_OK) return e;
+  }
   c.st.t_build = now_seconds() - t_begin;
   auto* hnd = new h2_ctx;
   hnd->c = std::move(ctx);
@@ -572,7 +655,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     std::vector<CholDesc> ch;
     for (int b = 0; b < nb; ++b) {
       const int m = S.m[b], k = S.k[b], r = m - k;
-      double* U = S.dU + S.qoff[b];
+      double* U = S.Uptr[b];
       double* W = S.dW + S.qoff[b];
       double* Q = S.dQ + S.qoff[b];
       double* P = S.dP + S.qoff[b];
@@ -647,15 +730,10 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         cm.push_back({S.dF + S.poff[p], base + (int64_t)kb * ldp, kb, ka, S.m[a], ldp, 1});
       }
     }
-    {
-      auto to = gemm_tiles(gw);
-      if (!gw.empty() && !upload(c, S.g_w, gw, st, &to)) return H2_ERR_ALLOC;
-    }
     auto up_g = [&](Batch<GemmDesc>& B, const std::vector<GemmDesc>& v) {
-      auto to = gemm_tiles(v);
-      return v.empty() ? true : upload(c, B, v, st, &to);
+      return upload_gemm(c, B, v, st);
     };
-    if (!up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
+    if (!up_g(S.g_w, gw) || !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
         !up_g(S.g_schur, gs) || !up_g(S.g_pair1, gp1) || !up_g(S.g_pair2, gp2) ||
         !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2))
       return H2_ERR_ALLOC;
@@ -704,9 +782,8 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
           bk.push_back({in.dPan, A21, rows, nbk, n, n, 0});
         }
       }
-      auto to1 = gemm_tiles(tr), to2 = gemm_tiles(sy);
-      if (!upload(c, c.r_panel[pi], pd, st) || (!tr.empty() && !upload(c, c.r_trsm[pi], tr, st, &to1)) ||
-          (!sy.empty() && !upload(c, c.r_syrk[pi], sy, st, &to2)) || !upload(c, c.r_back[pi], bk, st))
+      if (!upload(c, c.r_panel[pi], pd, st) || !upload_gemm(c, c.r_trsm[pi], tr, st) ||
+          !upload_gemm(c, c.r_syrk[pi], sy, st) || !upload(c, c.r_back[pi], bk, st))
         return H2_ERR_ALLOC;
     }
   }

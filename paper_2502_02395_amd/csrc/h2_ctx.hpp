@@ -18,6 +18,11 @@ struct Batch {
   int count = 0;
   int tiles = 0;
   int max_rows = 0;        // thin / gather: row extent for the grid
+  // GEMM batches: tile prefix of every tile shape, and the one in use
+  int* toffs[GEMM_NCFG] = {nullptr, nullptr, nullptr};
+  int tiles_c[GEMM_NCFG] = {0, 0, 0};
+  int cfg = 0;
+  void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 
 // One height step h above the leaves: level L_t - h of every instance t with
@@ -44,7 +49,9 @@ struct Step {
   // device buffers
   int64_t* dB = nullptr;
   int64_t* dSK = nullptr;
-  double* dU = nullptr;                    // U_i at qoff (capacity m^2, used m x k)
+  double* dU = nullptr;                    // U arena: box b at U capacity m_b x kcap_b
+  std::vector<double*> Uptr;               // U_i (m x k, ld m) of every box
+  std::vector<int> kcap;                   // predicted U capacity (columns)
   double* dS = nullptr;                    // couplings at soff
   double* dD = nullptr;                    // input near blocks at poff
   double* dF = nullptr;                    // transformed near blocks at poff
@@ -166,15 +173,19 @@ bool upload(Ctx& c, Batch<T>& b, const std::vector<T>& v, hipStream_t st,
   return hipStreamSynchronize(st) == hipSuccess;
 }
 
-// Tile prefix for GEMM items (64 x 64 tiles).
-inline std::vector<int> gemm_tiles(const std::vector<GemmDesc>& v) {
+// Tile prefix for GEMM items (BM x BN tiles).
+inline std::vector<int> gemm_tiles(const std::vector<GemmDesc>& v, int BM = 64, int BN = 64) {
   std::vector<int> off(v.size() + 1, 0);
   for (size_t i = 0; i < v.size(); ++i) {
-    const int tm = (v[i].M + 63) / 64, tn = (v[i].N + 63) / 64;
+    const int tm = (v[i].M + BM - 1) / BM, tn = (v[i].N + BN - 1) / BN;
     off[i + 1] = off[i] + ((v[i].M > 0 && v[i].N > 0) ? tm * tn : 0);
   }
   return off;
 }
+
+// Upload a GEMM batch with the tile prefix of every tile shape (shape 0 in use).
+inline bool upload_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v,
+                        hipStream_t st);
 inline std::vector<int> eval_tiles(const std::vector<EvalDesc>& v) {
   std::vector<int> off(v.size() + 1, 0);
   for (size_t i = 0; i < v.size(); ++i) {
@@ -197,6 +208,8 @@ inline GemmDesc gd(const double* A, int lda, int tA, const double* B, int ldb, i
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag = 0);
+// Time every tile shape on every factor GEMM batch and keep the fastest.
+h2_status autotune(Ctx& c, hipStream_t st);
 hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st);
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st);
 hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int nrhs,
@@ -213,6 +226,27 @@ h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64
 double now_seconds();
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
+// The eight geometry features of box i at level l of instance t (see mlp.hip).
+void box_features_host(const Ctx& c, int t, int l, int i, float* f);
+
+inline bool upload_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v,
+                        hipStream_t st) {
+  if (v.empty()) { b.count = 0; return true; }
+  auto t0 = gemm_tiles(v, GEMM_BM[0], GEMM_BN[0]);
+  if (!upload(c, b, v, st, &t0)) return false;
+  b.toffs[0] = b.toff;
+  b.tiles_c[0] = b.tiles;
+  for (int q = 1; q < GEMM_NCFG; ++q) {
+    auto tq = gemm_tiles(v, GEMM_BM[q], GEMM_BN[q]);
+    b.toffs[q] = c.alloc<int>(tq.size());
+    if (!b.toffs[q]) return false;
+    if (hipMemcpy(b.toffs[q], tq.data(), tq.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+      return false;
+    b.tiles_c[q] = tq.back();
+  }
+  b.use(0);
+  return true;
+}
 
 }  // namespace h2
 

@@ -66,9 +66,18 @@ struct BoxDev {
 // ------------------------------------------------------------- launch wrappers
 // All wrappers enqueue on `st`; they return hipSuccess or the launch error.
 
-// tag 1 launches the same kernel under the symbol gemm_f64_pair_kernel
+// tag 1 launches the same kernel under the symbol gemm_f64_pair_kernel;
+// cfg selects the tile shape: 0 = 64x64, 1 = 128x64, 2 = 128x128 (the tile
+// prefix d_tile_off must have been computed for that shape).
+constexpr int GEMM_NCFG = 3;
+constexpr int GEMM_BM[GEMM_NCFG] = {64, 128, 128};
+constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128};
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
-                       int tiles, hipStream_t st, int tag = 0);
+                       int tiles, hipStream_t st, int tag = 0, int cfg = 0);
+// Same work lists in reduced precision (prec = H2_PREC_FP32 or H2_PREC_BF16,
+// FP32 accumulation, FP64 in and out); H2_PREC_FP64 forwards to launch_gemm.
+hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count,
+                          int tiles, int prec, hipStream_t st, int tag = 0);
 hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
                        int tiles, const double* X, int dim, const KernelDev* kern,
                        hipStream_t st);
@@ -89,15 +98,18 @@ hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail,
 // Column-pivoted QR interpolative decomposition of X (s x m, ld s), one box
 // per workgroup.  Free mode: rank by eps; forced mode: skel[] given.
 struct IdDesc {
-  double* X;                // s x m workspace, destroyed
-  double* U;                // m x kcap output basis (written m x k, ld m)
+  double* X;                // s x m workspace; on exit T = R_11^{-1} R_12 in rows 0..k-1
+  double* U;                // output basis m x k (ld m), written only if k <= kcap
   int32_t* piv;             // m pivot positions (output)
   int32_t* k_out;           // rank (output)
   const int32_t* skel;      // forced skeleton positions (NULL = free)
-  int s, m, kforced, kcap;
+  int s, m, kforced;
+  int kcap;                 // U capacity in columns (0 = unlimited)
 };
 hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps,
                           int max_rank, double* norm_ws, hipStream_t st);
+// Write U for IDs whose rank exceeded the capacity given to cpqr_id.
+hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 
 // Thin products y = alpha op(A) x + beta y for N <= 16 columns; ncols > 0
 // overrides every item's N.

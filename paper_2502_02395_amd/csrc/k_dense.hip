@@ -114,6 +114,19 @@ hipError_t launch_qr_complete(const BoxDev* boxes, int nbox, hipStream_t st) {
 // ------------------------------------------------------------- pivoted QR ID
 constexpr int ID_MMAX = 4096;
 
+// U (m x k, ld m) from T = R_11^{-1} R_12 stored in rows 0..k-1 of columns
+// k..m-1 of X (ld s) and the pivot order piv (LDS or global).
+__device__ void write_u(const double* X, int s, int m, int k, const int* piv, double* U) {
+  const int nr = m - k;
+  for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += 256) U[e] = 0.0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < k; t += 256) U[piv[t] + (int64_t)t * m] = 1.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)nr * k; e += 256) {
+    const int q = (int)(e % nr), t = (int)(e / nr);
+    U[piv[k + q] + (int64_t)t * m] = X[t + (int64_t)(k + q) * s];
+  }
+}
+
 __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__ descs, double eps,
                                                       int max_rank) {
   __shared__ double sh[4];
@@ -136,7 +149,6 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__
     if (lane == 0) norms[c] = p;
   }
   int kmax = s < m ? s : m;
-  if (d.kcap > 0 && d.kcap < kmax) kmax = d.kcap;
   if (max_rank > 0 && max_rank < kmax) kmax = max_rank;
   if (forced) kmax = d.kforced;
   if (threadIdx.x == 0) kfinal = kmax;
@@ -228,20 +240,23 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__
     }
     __syncthreads();
   }
-  // ---- U (m x k, ld m): identity rows at the skeleton, T^T elsewhere
-  for (int64_t e = threadIdx.x; e < (int64_t)m * k; e += 256) {
-    const int t = (int)(e / m), r = (int)(e % m);
-    (void)r;
-    d.U[e] = 0.0;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < k; t += 256) d.U[piv[t] + (int64_t)t * m] = 1.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)nr * k; e += 256) {
-    const int q = (int)(e % nr), t = (int)(e / nr);
-    d.U[piv[k + q] + (int64_t)t * m] = X[t + (int64_t)(k + q) * s];
-  }
+  // ---- U (m x k, ld m) if it fits the caller's capacity; otherwise the
+  // caller writes it later from X and piv (id_write_u_kernel)
   for (int c = threadIdx.x; c < m; c += 256) d.piv[c] = piv[c];
   if (threadIdx.x == 0) *d.k_out = k;
+  if (d.kcap <= 0 || k <= d.kcap) write_u(X, s, m, k, piv, d.U);
+}
+
+// U = identity rows at the skeleton, T^T elsewhere, from a finished ID.
+__global__ __launch_bounds__(256) void id_write_u_kernel(const IdDesc* __restrict__ descs) {
+  const IdDesc d = descs[blockIdx.x];
+  write_u(d.X, d.s, d.m, *d.k_out, d.piv, d.U);
+}
+
+hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(id_write_u_kernel, dim3(count), dim3(256), 0, st, d_desc);
+  return hipGetLastError();
 }
 
 hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps, int max_rank,

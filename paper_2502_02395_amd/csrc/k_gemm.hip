@@ -14,7 +14,7 @@ namespace h2 {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64, TN = 64, TK = 16, LPAD = 1;
+constexpr int TK = 16, LPAD = 1;
 
 __device__ __forceinline__ int find_item(const int* off, int count, int t) {
   int lo = 0, hi = count - 1;
@@ -33,38 +33,52 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b & 7) * per + (b >> 3);
 }
 
+// One BM x BN output tile per 256-thread workgroup; the four waves form a 2x2
+// grid, each wave accumulating (BM/32) x (BN/32) 16x16 MFMA tiles.  Operand
+// tiles of TK = 16 are staged through LDS; the next one is prefetched into
+// registers while the current one is multiplied.
+template <int BM, int BN>
 __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs,
                                               const int* __restrict__ toff, int count, int tiles) {
+  constexpr int MI = BM / 32, NJ = BN / 32;
+  constexpr int QA = BM / 16, QB = BN / 16;  // operand elements per thread per tile
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
   const int item = find_item(toff, count, logical);
   const GemmDesc d = descs[item];
   const int t = logical - toff[item];
-  const int tiles_m = (d.M + TM - 1) / TM;
-  const int m0 = (t % tiles_m) * TM;
-  const int n0 = (t / tiles_m) * TN;
+  const int tiles_m = (d.M + BM - 1) / BM;
+  const int m0 = (t % tiles_m) * BM;
+  const int n0 = (t / tiles_m) * BN;
 
-  __shared__ double As[TK][TM + LPAD];
-  __shared__ double Bs[TK][TN + LPAD];
+  __shared__ double As[TK][BM + LPAD];
+  __shared__ double Bs[TK][BN + LPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
 
-  d4 acc[2][2];
+  d4 acc[MI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NJ; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
-  double ra[4], rb[4];
+  double ra[QA], rb[QB];
+  auto amap = [&](int q, int& m, int& k) {
+    if (!d.tA) { m = tid % BM; k = tid / BM + (256 / BM) * q; }
+    else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
+  };
+  auto bmap = [&](int q, int& n, int& k) {
+    if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
+    else       { n = tid % BN; k = tid / BN + (256 / BN) * q; }
+  };
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; }
-      else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
+      amap(q, m, k);
       const int gm = m0 + m, gk = k0 + k;
       double v = 0.0;
       if (gm < d.M && gk < d.K)
@@ -72,10 +86,9 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
       ra[q] = v;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QB; ++q) {
       int n, k;
-      if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
-      else       { n = tid & 63; k = (tid >> 6) + 4 * q; }
+      bmap(q, n, k);
       const int gn = n0 + n, gk = k0 + k;
       double v = 0.0;
       if (gn < d.N && gk < d.K)
@@ -85,17 +98,15 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
   };
   auto store = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QA; ++q) {
       int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; }
-      else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
+      amap(q, m, k);
       As[k][m] = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < QB; ++q) {
       int n, k;
-      if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
-      else       { n = tid & 63; k = (tid >> 6) + 4 * q; }
+      bmap(q, n, k);
       Bs[k][n] = rb[q];
     }
   };
@@ -111,12 +122,16 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
       const int c = lane & 15;
-      double a0 = As[kr][wm + c], a1 = As[kr][wm + 16 + c];
-      double b0 = Bs[kr][wn + c], b1 = Bs[kr][wn + 16 + c];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double a[MI], b[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) a[i] = As[kr][wm + 16 * i + c];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) b[j] = Bs[kr][wn + 16 * j + c];
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
 
@@ -125,9 +140,9 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
   const int col = lane & 15;
   const int rg = lane >> 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gm = m0 + wm + 16 * i + 4 * e + rg;
@@ -140,29 +155,41 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
       }
 }
 
-// Two symbols with the same body so that profiles separate the near-pair
-// basis transforms (the dominant cost) from every other product.
+// Two symbols per tile shape with the same body so that profiles separate
+// the near-pair basis transforms (the dominant cost) from every other product.
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
                                                        const int* __restrict__ toff, int count,
                                                        int tiles) {
-  gemm_f64_body(descs, toff, count, tiles);
+  gemm_f64_body<BM, BN>(descs, toff, count, tiles);
 }
+template <int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_f64_pair_kernel(const GemmDesc* __restrict__ descs,
                                                             const int* __restrict__ toff,
                                                             int count, int tiles) {
-  gemm_f64_body(descs, toff, count, tiles);
+  gemm_f64_body<BM, BN>(descs, toff, count, tiles);
+}
+
+template <int BM, int BN>
+static void launch_cfg(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
+                       hipStream_t st, int tag) {
+  const int grid = (tiles + 7) & ~7;
+  if (tag == 1)
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN>), dim3(grid), dim3(256), 0, st, d_desc,
+                       d_tile_off, count, tiles);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), dim3(grid), dim3(256), 0, st, d_desc,
+                       d_tile_off, count, tiles);
 }
 
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
-                       int tiles, hipStream_t st, int tag) {
+                       int tiles, hipStream_t st, int tag, int cfg) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
-  const int grid = (tiles + 7) & ~7;
-  if (tag == 1)
-    hipLaunchKernelGGL(gemm_f64_pair_kernel, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off,
-                       count, tiles);
-  else
-    hipLaunchKernelGGL(gemm_f64_kernel, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off,
-                       count, tiles);
+  switch (cfg) {
+    case 1: launch_cfg<128, 64>(d_desc, d_tile_off, count, tiles, st, tag); break;
+    case 2: launch_cfg<128, 128>(d_desc, d_tile_off, count, tiles, st, tag); break;
+    default: launch_cfg<64, 64>(d_desc, d_tile_off, count, tiles, st, tag); break;
+  }
   return hipGetLastError();
 }
 

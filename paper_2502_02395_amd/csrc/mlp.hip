@@ -4,6 +4,7 @@
 // buffers can be sized before compression.  Gradients are reduced in a fixed
 // order (per-block partials, then a serial sum per parameter), so training is
 // bitwise reproducible.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -184,6 +185,37 @@ hipError_t launch_set_int(int* p, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Features of box i at level l (instance t), in the order the predictor was
+// trained on: level/L, log2(points), log(radius/ell), middle/largest and
+// smallest/largest bounding-box side, near boxes (j != i), log2(1 + points of
+// the boxes that are not near), -log10(eps).
+void box_features_host(const Ctx& c, int t, int l, int i, float* f) {
+  const Instance& in = c.ins[t];
+  const Tree& tr = in.tree;
+  const double sz = (double)(tr.start[l][i + 1] - tr.start[l][i]);
+  double ext[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < tr.dim; ++a) ext[a] = tr.extent[l][(size_t)i * tr.dim + a];
+  std::sort(ext, ext + 3);
+  const double emax = ext[2] > 0 ? ext[2] : 1.0;
+  const double ell = (in.kern.id >= 2) ? in.kern.ell : 1.0;
+  int nnear = 0;
+  double near_pts = 0.0;
+  for (auto& pr : tr.near[l])
+    if (pr.first == i) {
+      ++nnear;
+      near_pts += (double)(tr.start[l][pr.second + 1] - tr.start[l][pr.second]);
+    }
+  const double rad = std::max(tr.radius[l][i], 1e-300);
+  f[0] = (float)((double)l / tr.L);
+  f[1] = (float)std::log2(sz);
+  f[2] = (float)std::log(rad / ell);
+  f[3] = (float)(ext[1] / emax);
+  f[4] = (float)(ext[0] / emax);
+  f[5] = (float)(nnear - 1);
+  f[6] = (float)std::log2(1.0 + (double)in.n - near_pts);
+  f[7] = (float)(-std::log10(c.prm.eps > 0 ? c.prm.eps : 1e-300));
+}
+
 }  // namespace h2
 
 using namespace h2;
@@ -223,35 +255,12 @@ h2_status h2_box_features(h2_handle h, float* feats, void* stream) {
   if (!h || !h->c || !feats) return H2_ERR_ARG;
   Ctx& c = *h->c;
   std::vector<float> f;
-  for (auto& S : c.steps) {
+  for (auto& S : c.steps)
     for (int b = 0; b < S.nbox; ++b) {
-      const Instance& in = c.ins[S.inst[b]];
-      const Tree& tr = in.tree;
-      const int l = S.lvl[b], i = S.idx[b];
-      const double sz = (double)(tr.start[l][i + 1] - tr.start[l][i]);
-      double ext[3] = {0.0, 0.0, 0.0};
-      for (int a = 0; a < tr.dim; ++a) ext[a] = tr.extent[l][(size_t)i * tr.dim + a];
-      std::sort(ext, ext + 3);
-      const double emax = ext[2] > 0 ? ext[2] : 1.0;
-      const double ell = (in.kern.id >= 2) ? in.kern.ell : 1.0;
-      int nnear = 0;
-      double near_pts = 0.0;
-      for (auto& pr : tr.near[l])
-        if (pr.first == i) {
-          ++nnear;
-          near_pts += (double)(tr.start[l][pr.second + 1] - tr.start[l][pr.second]);
-        }
-      const double rad = std::max(tr.radius[l][i], 1e-300);
-      f.push_back((float)((double)l / tr.L));
-      f.push_back((float)std::log2(sz));
-      f.push_back((float)std::log(rad / ell));
-      f.push_back((float)(ext[1] / emax));
-      f.push_back((float)(ext[0] / emax));
-      f.push_back((float)(nnear - 1));
-      f.push_back((float)std::log2(1.0 + (double)in.n - near_pts));
-      f.push_back((float)(-std::log10(c.prm.eps > 0 ? c.prm.eps : 1e-300)));
+      float v[8];
+      box_features_host(c, S.inst[b], S.lvl[b], S.idx[b], v);
+      f.insert(f.end(), v, v + 8);
     }
-  }
   if (f.empty()) return H2_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (hipMemcpyAsync(feats, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, st) != hipSuccess)

@@ -39,10 +39,6 @@ static int local_box(const Step& S, int t, int i) {
   return first + i;
 }
 
-static bool up_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, hipStream_t st) {
-  auto to = gemm_tiles(v);
-  return v.empty() ? true : upload(c, b, v, st, &to);
-}
 static bool up_thin(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, hipStream_t st) {
   int mx = 0;
   for (auto& g : v) mx = std::max(mx, g.M);
@@ -240,7 +236,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       tb.push_back(gd(P, m, 0, vd, vld, 0, nullptr, 1, vout, vld, m, NR, m, 1.0, 0.0));
 
       // ---- matvec: upward U^T x
-      const double* U = S.dU + S.qoff[b];
+      const double* U = S.Uptr[b];
       if (k > 0) {
         if (h == 0) {
           tu.push_back(gd(U, m, 1, c.vt_in + S.voff[b], vld, 0, nullptr, 1, S.v_xh + S.koff[b], kld, k,
@@ -327,6 +323,57 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ factor
+// Basis transforms and Schur update in the handle's GEMM precision.
+static hipError_t run_gemm_p(const Ctx& c, const Batch<GemmDesc>& b, hipStream_t st, int tag = 0) {
+  if (c.prm.gemm_prec == H2_PREC_FP64) return run_gemm(b, st, tag);
+  return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], c.prm.gemm_prec, st, tag);
+}
+
+// Autotuner: every factor GEMM work list is timed with every tile shape (one
+// warm-up launch, then the best of two timed launches, HIP events on the
+// build stream) and the fastest shape is kept.  Running a work list on buffers
+// that the first factorization has not yet filled is safe: the kernels have no
+// data-dependent control flow and write only the list's own outputs.
+h2_status autotune(Ctx& c, hipStream_t st) {
+  if (c.prm.gemm_prec != H2_PREC_FP64) return H2_OK;
+  auto tune = [&](Batch<GemmDesc>& b, int tag) -> h2_status {
+    if (b.count == 0) return H2_OK;
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int q = 0; q < GEMM_NCFG; ++q) {
+      b.use(q);
+      HIPCHK(run_gemm(b, st, tag));
+      float ms_q = 1e30f;
+      for (int r = 0; r < 2; ++r) {
+        HIPCHK(hipEventRecord(c.ev_a, st));
+        HIPCHK(run_gemm(b, st, tag));
+        HIPCHK(hipEventRecord(c.ev_b, st));
+        HIPCHK(hipEventSynchronize(c.ev_b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
+        ms_q = std::min(ms_q, ms);
+      }
+      if (ms_q < best_ms) { best_ms = ms_q; best = q; }
+    }
+    b.use(best);
+    ++c.st.tuned_lists;
+    c.st.tuned_cfg_hist[best] += 1;
+    return H2_OK;
+  };
+  for (auto& S : c.steps) {
+    for (Batch<GemmDesc>* b : {&S.g_w, &S.g_diag1, &S.g_diag2, &S.g_v, &S.g_schur, &S.g_far1,
+                               &S.g_far2}) {
+      h2_status e = tune(*b, 0);
+      if (e != H2_OK) return e;
+    }
+    for (Batch<GemmDesc>* b : {&S.g_pair1, &S.g_pair2}) {
+      h2_status e = tune(*b, 1);
+      if (e != H2_OK) return e;
+    }
+  }
+  return H2_OK;
+}
+
 h2_status do_factor(Ctx& c, hipStream_t st) {
   HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
   const bool timing = c.prm.timing != 0 && !c.prm.use_graph;
@@ -336,15 +383,15 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     if (h == 0) HIPCHK(run_copy(S.c_w, st));
     else HIPCHK(run_gemm(S.g_w, st));
     HIPCHK(launch_qr_complete(S.qr.d, S.qr.count, st));
-    HIPCHK(run_gemm(S.g_diag1, st));
-    HIPCHK(run_gemm(S.g_diag2, st));
+    HIPCHK(run_gemm_p(c, S.g_diag1, st));
+    HIPCHK(run_gemm_p(c, S.g_diag2, st));
     HIPCHK(launch_chol_inv(S.chol.d, S.chol.count, c.dFail, st));
     HIPCHK(run_copy(S.c_ps, st));
     HIPCHK(run_gemm(S.g_v, st));
-    HIPCHK(run_gemm(S.g_schur, st));
+    HIPCHK(run_gemm_p(c, S.g_schur, st));
     if (timing && S.g_pair1.count > 0) HIPCHK(hipEventRecord(c.ev_a, st));
-    HIPCHK(run_gemm(S.g_pair1, st, 1));
-    HIPCHK(run_gemm(S.g_pair2, st, 1));
+    HIPCHK(run_gemm_p(c, S.g_pair1, st, 1));
+    HIPCHK(run_gemm_p(c, S.g_pair2, st, 1));
     if (timing && S.g_pair1.count > 0) {
       HIPCHK(hipEventRecord(c.ev_b, st));
       HIPCHK(hipEventSynchronize(c.ev_b));
@@ -352,8 +399,8 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
       HIPCHK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
       t_pair += 1e-3 * ms;
     }
-    HIPCHK(run_gemm(S.g_far1, st));
-    HIPCHK(run_gemm(S.g_far2, st));
+    HIPCHK(run_gemm_p(c, S.g_far1, st));
+    HIPCHK(run_gemm_p(c, S.g_far2, st));
     HIPCHK(run_copy(S.c_merge, st));
   }
   HIPCHK(run_copy(c.r_save, st));

@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
                 ("use_pcg", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -55,10 +55,15 @@ class Stats(ctypes.Structure):
                 ("ir_residual", ctypes.c_double), ("fail_level", ctypes.c_int32),
                 ("fail_box", ctypes.c_int32), ("fail_inst", ctypes.c_int32),
                 ("rank_fallbacks", ctypes.c_int32), ("t_pair_gemm", ctypes.c_double),
-                ("flops_pair_gemm", ctypes.c_double), ("pair_launches", ctypes.c_int32)]
+                ("flops_pair_gemm", ctypes.c_double), ("pair_launches", ctypes.c_int32),
+                ("bytes_basis", ctypes.c_double), ("tuned_lists", ctypes.c_int32),
+                ("tuned_cfg_hist", ctypes.c_int32 * 3)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["tuned_cfg_hist"] = list(self.tuned_cfg_hist)
+        return d
+
 
 
 _lib = None
@@ -125,9 +130,17 @@ def make_kernel(k) -> Kernel:
 def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_near: int = -1,
                 max_rank: int = 0, gemm_prec: int = PREC_FP64, ir_max_iter: int = 0,
                 ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
-                timing: bool = False) -> Params:
+                timing: bool = False, rank_model=None, rank_margin: float = 0.25,
+                autotune: bool = True) -> Params:
+    """rank_model: numpy float32 array of the 4801 predictor weights (kept alive
+    by the caller for the duration of the build call)."""
+    ptr = None
+    if rank_model is not None:
+        assert rank_model.dtype == np.float32 and rank_model.size == 4801
+        assert rank_model.flags["C_CONTIGUOUS"]
+        ptr = rank_model.ctypes.data
     return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
-                  int(use_pcg), int(use_graph), None, 0.25, int(timing))
+                  int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune))
 
 
 def _as_cols(t, n):
