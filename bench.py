@@ -25,6 +25,8 @@ HBM_PEAK_GBS = 8000.0
 
 def workload(n: int, kernel: str, eps: float, leaf: int, s: int):
     import workloads as W
+    if kernel == "gaussian_batch":
+        return W.gaussian_batch(n_inst=64, leaf=leaf, eps=eps, s=s)
     if kernel == "yukawa":
         return W.yukawa_cube(n=n, leaf=leaf, eps=eps, nrhs=1, s=s)
     if kernel == "laplace":
@@ -67,7 +69,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 20)
-    ap.add_argument("--kernel", default="yukawa")
+    ap.add_argument("--kernel", default="yukawa",
+                    help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="precision of the basis-transform and Schur-update GEMMs")
+    ap.add_argument("--rank-model", action="store_true",
+                    help="train the rank predictor on smaller seeded builds first (untimed) "
+                         "and size the basis buffers with it")
+    ap.add_argument("--graph", action="store_true", help="capture the factorization in a hipGraph")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--s", type=int, default=512)
@@ -92,16 +101,43 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    prec = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16}[a.prec]
+    model = None
+    if a.rank_model:
+        import numpy as np
+        import workloads as W
+        from paper_2502_02395_amd import rank_model
+        train_ps = []
+        for sd in (100, 101, 102):
+            q = workload(1 << 16, a.kernel, a.eps, a.leaf, a.s)
+            q.points = W.cube_points(1 << 16, 3, sd)
+            train_ps.append(q)
+        X, y = rank_model.collect(train_ps)
+        model, hist = rank_model.train(X, y, steps=2000, lr=3e-3)
+        print(f"[bench] rank model trained on {len(y)} boxes, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
+              file=sys.stderr, flush=True)
     p = workload(a.n, a.kernel, a.eps, a.leaf, a.s)
     t0 = time.perf_counter()
-    H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
-                 s_near=p.s_near, ir_max_iter=50, ir_tol=a.tol, timing=True)
+    if a.kernel == "gaussian_batch":
+        import numpy as np
+        H = h2.build_batched([q.points for q in p], [q.kernel for q in p], a.leaf, 1.0, a.eps,
+                             perms=[q.perm() for q in p], s_far=a.s, s_near=a.s, gemm_prec=prec,
+                             ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=not a.graph,
+                             use_graph=a.graph)
+        bnp = np.concatenate([q.b() for q in p], axis=0)
+        n_total = sum(q.n for q in p)
+    else:
+        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                     s_near=p.s_near, ir_max_iter=50, ir_tol=a.tol, timing=not a.graph,
+                     gemm_prec=prec, rank_model=model, use_graph=a.graph)
+        bnp = p.b()
+        n_total = p.n
     t_build = time.perf_counter() - t0
-    b = torch.from_numpy(p.b()).cuda()
+    b = torch.from_numpy(bnp).cuda()
     cols_b = b.t().contiguous()
     cols_x = torch.empty_like(cols_b)
-    print(f"[bench] built N={p.n} in {t_build:.1f}s: {H.stats()['levels']} levels", file=sys.stderr,
-          flush=True)
+    print(f"[bench] built N={n_total} in {t_build:.1f}s: {H.stats()['levels']} levels",
+          file=sys.stderr, flush=True)
 
     def step():
         H.factor()
@@ -136,13 +172,19 @@ def main():
     flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
     value = flops_step * K / dt / 1e12
     pair_tflops = st["flops_pair_gemm"] * K / max(t_pair, 1e-30) / 1e12
+    st_all = H.stats()
     out = {
         "metric": "H2-ULV factor+solve TFLOP/s at N=2^20 (rel. residual <= 1e-8 vs FP64 H2 operator)",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{a.kernel}_cube", "n": p.n, "dim": 3, "leaf": a.leaf,
-                   "eta": p.eta, "eps": a.eps, "s_far": a.s, "s_near": a.s, "nrhs": 1,
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[a.prec],
+        "data": "synthetic",
+        "config": {"workload": a.kernel if a.kernel == "gaussian_batch" else f"{a.kernel}_cube",
+                   "n": n_total, "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
+                   "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s, "nrhs": 1,
+                   "gemm_prec": a.prec, "rank_model": a.rank_model, "graph": a.graph,
+                   "rank_fallbacks": st_all["rank_fallbacks"], "basis_bytes": st_all["bytes_basis"],
+                   "autotuned_lists": st_all["tuned_lists"], "tile_choice": st_all["tuned_cfg_hist"],
                    "ir_tol": a.tol, "levels": st["levels"], "root_n": st["root_n"],
                    "max_rank": st["max_rank_seen"], "near_pairs": st["near_pairs"]},
         "factor_s": t_fac / K, "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
@@ -154,7 +196,7 @@ def main():
                      "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1)},
     }
     H.close()
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.kernel != "gaussian_batch":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.kernel, a.eps, a.leaf, a.s, a.cpu_sample)
     print(json.dumps(out), flush=True)

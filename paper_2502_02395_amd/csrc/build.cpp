@@ -30,7 +30,7 @@ Ctx::~Ctx() {
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
-  return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg);
+  return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
 }
 hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
   return launch_thin(b.d, b.count, b.max_rows, ncols, st);
@@ -94,7 +94,7 @@ static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st) {
   int* t = nullptr;
   auto toff = gemm_tiles(g);
   if (!upload_tmp(tb1, d, g, st) || !upload_tmp(tb2, t, toff, st)) return H2_ERR_ALLOC;
-  HIPCHK(launch_gemm(d, t, (int)g.size(), toff.back(), st));
+  HIPCHK(launch_gemm(d, t, (int)g.size(), toff.back(), st, 0, 0, g[0].tA, g[0].tB));
   HIPCHK(hipStreamSynchronize(st));
   return H2_OK;
 }

@@ -22,6 +22,7 @@ struct Batch {
   int* toffs[GEMM_NCFG] = {nullptr, nullptr, nullptr};
   int tiles_c[GEMM_NCFG] = {0, 0, 0};
   int cfg = 0;
+  int tA = 0, tB = 0;      // transposes shared by every item of the list
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 
@@ -232,6 +233,10 @@ void box_features_host(const Ctx& c, int t, int l, int i, float* f);
 inline bool upload_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v,
                         hipStream_t st) {
   if (v.empty()) { b.count = 0; return true; }
+  b.tA = v[0].tA;
+  b.tB = v[0].tB;
+  for (auto& g : v)
+    if (g.tA != b.tA || g.tB != b.tB) return false;  // lists are built uniform
   auto t0 = gemm_tiles(v, GEMM_BM[0], GEMM_BN[0]);
   if (!upload(c, b, v, st, &t0)) return false;
   b.toffs[0] = b.toff;

@@ -72,12 +72,13 @@ struct BoxDev {
 constexpr int GEMM_NCFG = 3;
 constexpr int GEMM_BM[GEMM_NCFG] = {64, 128, 128};
 constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128};
+// Every item of one launch must have the transposes tA, tB.
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
-                       int tiles, hipStream_t st, int tag = 0, int cfg = 0);
+                       int tiles, hipStream_t st, int tag, int cfg, int tA, int tB);
 // Same work lists in reduced precision (prec = H2_PREC_FP32 or H2_PREC_BF16,
 // FP32 accumulation, FP64 in and out); H2_PREC_FP64 forwards to launch_gemm.
 hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count,
-                          int tiles, int prec, hipStream_t st, int tag = 0);
+                          int tiles, int prec, hipStream_t st, int tag, int tA, int tB);
 hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
                        int tiles, const double* X, int dim, const KernelDev* kern,
                        hipStream_t st);

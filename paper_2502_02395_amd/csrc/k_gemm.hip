@@ -36,12 +36,13 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // One BM x BN output tile per 256-thread workgroup; the four waves form a 2x2
 // grid, each wave accumulating (BM/32) x (BN/32) 16x16 MFMA tiles.  Operand
 // tiles of TK = 16 are staged through LDS; the next one is prefetched into
-// registers while the current one is multiplied.
-template <int BM, int BN>
+// registers while the current one is multiplied.  TA / TB (transposed
+// operands) are compile-time so that every index is plain arithmetic.
+template <int BM, int BN, int TA, int TB>
 __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs,
                                               const int* __restrict__ toff, int count, int tiles) {
   constexpr int MI = BM / 32, NJ = BN / 32;
-  constexpr int QA = BM / 16, QB = BN / 16;  // operand elements per thread per tile
+  constexpr int QA = BM / 16, QB = BN / 16;  // operand elements per thread per K tile
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
   const int item = find_item(toff, count, logical);
@@ -59,6 +60,15 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
   const int wave = tid >> 6;
   const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
 
+  // this thread's operand elements: A(m, k) and B(k, n) of the tile
+  //   A not transposed: m fixed, k steps by 256/BM;  transposed: k fixed, m steps by 16
+  const int am = TA ? (tid >> 4) : (tid % BM);
+  const int ak = TA ? (tid & 15) : (tid / BM);
+  const int bn = TB ? (tid % BN) : (tid >> 4);
+  const int bk = TB ? (tid / BN) : (tid & 15);
+  constexpr int ASTEP = TA ? 16 : 256 / BM;   // along m (TA) or k (!TA)
+  constexpr int BSTEP = TB ? 256 / BN : 16;   // along k (TB) or n (!TB)
+
   d4 acc[MI][NJ];
 #pragma unroll
   for (int i = 0; i < MI; ++i)
@@ -66,58 +76,35 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
     for (int j = 0; j < NJ; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
   double ra[QA], rb[QB];
-  auto amap = [&](int q, int& m, int& k) {
-    if (!d.tA) { m = tid % BM; k = tid / BM + (256 / BM) * q; }
-    else       { k = tid & 15; m = (tid >> 4) + 16 * q; }
-  };
-  auto bmap = [&](int q, int& n, int& k) {
-    if (!d.tB) { k = tid & 15; n = (tid >> 4) + 16 * q; }
-    else       { n = tid % BN; k = tid / BN + (256 / BN) * q; }
-  };
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      int m, k;
-      amap(q, m, k);
-      const int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < d.M && gk < d.K)
-        v = d.tA ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
-      ra[q] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      int n, k;
-      bmap(q, n, k);
-      const int gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < d.N && gk < d.K)
-        v = d.tB ? d.B[gn + (int64_t)gk * d.ldb] : d.B[gk + (int64_t)gn * d.ldb];
-      rb[q] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int q = 0; q < QA; ++q) {
-      int m, k;
-      amap(q, m, k);
-      As[k][m] = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < QB; ++q) {
-      int n, k;
-      bmap(q, n, k);
-      Bs[k][n] = rb[q];
-    }
-  };
+  const int M = d.M, N = d.N, K = d.K;
+  const double* __restrict__ Ap = d.A;
+  const double* __restrict__ Bp = d.B;
+  const int64_t lda = d.lda, ldb = d.ldb;
 
-  const int nk = (d.K + TK - 1) / TK;
-  if (nk > 0) load(0);
+#define H2_LOAD(k0)                                                              \
+  {                                                                              \
+    _Pragma("unroll") for (int q = 0; q < QA; ++q) {                             \
+      const int gm = m0 + am + (TA ? ASTEP * q : 0);                             \
+      const int gk = (k0) + ak + (TA ? 0 : ASTEP * q);                           \
+      ra[q] = (gm < M && gk < K) ? (TA ? Ap[gk + gm * lda] : Ap[gm + gk * lda]) : 0.0; \
+    }                                                                            \
+    _Pragma("unroll") for (int q = 0; q < QB; ++q) {                             \
+      const int gn = n0 + bn + (TB ? 0 : BSTEP * q);                             \
+      const int gk = (k0) + bk + (TB ? BSTEP * q : 0);                           \
+      rb[q] = (gn < N && gk < K) ? (TB ? Bp[gn + gk * ldb] : Bp[gk + gn * ldb]) : 0.0; \
+    }                                                                            \
+  }
+
+  const int nk = (K + TK - 1) / TK;
+  if (nk > 0) H2_LOAD(0);
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
-    store();
+#pragma unroll
+    for (int q = 0; q < QA; ++q) As[ak + (TA ? 0 : ASTEP * q)][am + (TA ? ASTEP * q : 0)] = ra[q];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Bs[bk + (TB ? BSTEP * q : 0)][bn + (TB ? 0 : BSTEP * q)] = rb[q];
     __syncthreads();
-    if (kt + 1 < nk) load((kt + 1) * TK);
+    if (kt + 1 < nk) H2_LOAD((kt + 1) * TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -134,6 +121,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+#undef H2_LOAD
 
   // Accumulator layout of the 16x16x4 f64 MFMA (measured on gfx950): element e
   // of lane l holds row 4*e + l/16, column l%16.
@@ -147,7 +135,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
       for (int e = 0; e < 4; ++e) {
         const int gm = m0 + wm + 16 * i + 4 * e + rg;
         const int gn = n0 + wn + 16 * j + col;
-        if (gm < d.M && gn < d.N) {
+        if (gm < M && gn < N) {
           double v = d.alpha * acc[i][j][e];
           if (d.beta != 0.0) v += d.beta * d.C[gm + (int64_t)gn * d.ldc];
           d.D[gm + (int64_t)gn * d.ldd] = v;
@@ -155,40 +143,49 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
       }
 }
 
-// Two symbols per tile shape with the same body so that profiles separate
+// Two symbols per instantiation with the same body so that profiles separate
 // the near-pair basis transforms (the dominant cost) from every other product.
-template <int BM, int BN>
+template <int BM, int BN, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
                                                        const int* __restrict__ toff, int count,
                                                        int tiles) {
-  gemm_f64_body<BM, BN>(descs, toff, count, tiles);
+  gemm_f64_body<BM, BN, TA, TB>(descs, toff, count, tiles);
 }
-template <int BM, int BN>
+template <int BM, int BN, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_pair_kernel(const GemmDesc* __restrict__ descs,
                                                             const int* __restrict__ toff,
                                                             int count, int tiles) {
-  gemm_f64_body<BM, BN>(descs, toff, count, tiles);
+  gemm_f64_body<BM, BN, TA, TB>(descs, toff, count, tiles);
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int TA, int TB>
 static void launch_cfg(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
                        hipStream_t st, int tag) {
   const int grid = (tiles + 7) & ~7;
   if (tag == 1)
-    hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN>), dim3(grid), dim3(256), 0, st, d_desc,
-                       d_tile_off, count, tiles);
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st,
+                       d_desc, d_tile_off, count, tiles);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN>), dim3(grid), dim3(256), 0, st, d_desc,
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d_desc,
                        d_tile_off, count, tiles);
 }
 
+template <int BM, int BN>
+static void launch_t(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
+                     hipStream_t st, int tag, int tA, int tB) {
+  if (!tA && !tB) launch_cfg<BM, BN, 0, 0>(d_desc, d_tile_off, count, tiles, st, tag);
+  else if (!tA && tB) launch_cfg<BM, BN, 0, 1>(d_desc, d_tile_off, count, tiles, st, tag);
+  else if (tA && !tB) launch_cfg<BM, BN, 1, 0>(d_desc, d_tile_off, count, tiles, st, tag);
+  else launch_cfg<BM, BN, 1, 1>(d_desc, d_tile_off, count, tiles, st, tag);
+}
+
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
-                       int tiles, hipStream_t st, int tag, int cfg) {
+                       int tiles, hipStream_t st, int tag, int cfg, int tA, int tB) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: launch_cfg<128, 64>(d_desc, d_tile_off, count, tiles, st, tag); break;
-    case 2: launch_cfg<128, 128>(d_desc, d_tile_off, count, tiles, st, tag); break;
-    default: launch_cfg<64, 64>(d_desc, d_tile_off, count, tiles, st, tag); break;
+    case 1: launch_t<128, 64>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
+    case 2: launch_t<128, 128>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
+    default: launch_t<64, 64>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
   }
   return hipGetLastError();
 }

@@ -37,7 +37,7 @@ __device__ __forceinline__ unsigned short to_bf16(double x) {
 #define ACC_ROW(e, l) (4 * ((l) >> 4) + (e))
 
 // ---------------------------------------------------------------- FP32 MFMA
-template <int TAG>
+template <int TAG, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restrict__ descs,
                                                        const int* __restrict__ toff, int count,
                                                        int tiles) {
@@ -59,32 +59,25 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restric
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
   float ra[4], rb[4];
+  // operand element q of this thread: A(am + ..., ak + ...), B(bk + ..., bn + ...)
+  const int am = TA ? (tid >> 4) : (tid & 63), ak = TA ? (tid & 15) : (tid >> 6);
+  const int bn = TB ? (tid & 63) : (tid >> 4), bk = TB ? (tid >> 6) : (tid & 15);
+  const int M = d.M, N = d.N, K = d.K;
+  const int64_t lda = d.lda, ldb = d.ldb;
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; } else { k = tid & 15; m = (tid >> 4) + 16 * q; }
-      const int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < d.M && gk < d.K) v = d.tA ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
-      ra[q] = (float)v;
-      int n, k2;
-      if (!d.tB) { k2 = tid & 15; n = (tid >> 4) + 16 * q; } else { n = tid & 63; k2 = (tid >> 6) + 4 * q; }
-      const int gn = n0 + n, gk2 = k0 + k2;
-      double w = 0.0;
-      if (gn < d.N && gk2 < d.K) w = d.tB ? d.B[gn + (int64_t)gk2 * d.ldb] : d.B[gk2 + (int64_t)gn * d.ldb];
-      rb[q] = (float)w;
+      const int gm = m0 + am + (TA ? 16 * q : 0), gk = k0 + ak + (TA ? 0 : 4 * q);
+      ra[q] = (gm < M && gk < K) ? (float)(TA ? d.A[gk + gm * lda] : d.A[gm + gk * lda]) : 0.f;
+      const int gn = n0 + bn + (TB ? 0 : 16 * q), gk2 = k0 + bk + (TB ? 4 * q : 0);
+      rb[q] = (gn < N && gk2 < K) ? (float)(TB ? d.B[gn + gk2 * ldb] : d.B[gk2 + gn * ldb]) : 0.f;
     }
   };
   auto store = [&]() {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; } else { k = tid & 15; m = (tid >> 4) + 16 * q; }
-      As[k][m] = ra[q];
-      int n, k2;
-      if (!d.tB) { k2 = tid & 15; n = (tid >> 4) + 16 * q; } else { n = tid & 63; k2 = (tid >> 6) + 4 * q; }
-      Bs[k2][n] = rb[q];
+      As[ak + (TA ? 0 : 4 * q)][am + (TA ? 16 * q : 0)] = ra[q];
+      Bs[bk + (TB ? 4 * q : 0)][bn + (TB ? 0 : 16 * q)] = rb[q];
     }
   };
   const int nk = (d.K + TK - 1) / TK;
@@ -125,7 +118,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restric
 // ---------------------------------------------------------------- BF16 MFMA
 // Tiles are stored row-major in LDS (k contiguous) so that each lane fetches
 // its four consecutive k values of one row with a single 8-byte read.
-template <int TAG>
+template <int TAG, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmDesc* __restrict__ descs,
                                                         const int* __restrict__ toff, int count,
                                                         int tiles) {
@@ -147,32 +140,24 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmDesc* __restri
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
   unsigned short ra[8], rb[8];
+  const int am = TA ? (tid >> 5) : (tid & 63), ak = TA ? (tid & 31) : (tid >> 6);
+  const int bn = TB ? (tid & 63) : (tid >> 5), bk = TB ? (tid >> 6) : (tid & 31);
+  const int M = d.M, N = d.N, K = d.K;
+  const int64_t lda = d.lda, ldb = d.ldb;
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; } else { k = tid & 31; m = (tid >> 5) + 8 * q; }
-      const int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < d.M && gk < d.K) v = d.tA ? d.A[gk + (int64_t)gm * d.lda] : d.A[gm + (int64_t)gk * d.lda];
-      ra[q] = to_bf16(v);
-      int n, k2;
-      if (!d.tB) { k2 = tid & 31; n = (tid >> 5) + 8 * q; } else { n = tid & 63; k2 = (tid >> 6) + 4 * q; }
-      const int gn = n0 + n, gk2 = k0 + k2;
-      double w = 0.0;
-      if (gn < d.N && gk2 < d.K) w = d.tB ? d.B[gn + (int64_t)gk2 * d.ldb] : d.B[gk2 + (int64_t)gn * d.ldb];
-      rb[q] = to_bf16(w);
+      const int gm = m0 + am + (TA ? 8 * q : 0), gk = k0 + ak + (TA ? 0 : 4 * q);
+      ra[q] = to_bf16((gm < M && gk < K) ? (TA ? d.A[gk + gm * lda] : d.A[gm + gk * lda]) : 0.0);
+      const int gn = n0 + bn + (TB ? 0 : 8 * q), gk2 = k0 + bk + (TB ? 4 * q : 0);
+      rb[q] = to_bf16((gn < N && gk2 < K) ? (TB ? d.B[gn + gk2 * ldb] : d.B[gk2 + gn * ldb]) : 0.0);
     }
   };
   auto store = [&]() {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      int m, k;
-      if (!d.tA) { m = tid & 63; k = (tid >> 6) + 4 * q; } else { k = tid & 31; m = (tid >> 5) + 8 * q; }
-      As[m][k] = ra[q];
-      int n, k2;
-      if (!d.tB) { k2 = tid & 31; n = (tid >> 5) + 8 * q; } else { n = tid & 63; k2 = (tid >> 6) + 4 * q; }
-      Bs[n][k2] = rb[q];
+      As[am + (TA ? 8 * q : 0)][ak + (TA ? 0 : 4 * q)] = ra[q];
+      Bs[bn + (TB ? 0 : 8 * q)][bk + (TB ? 4 * q : 0)] = rb[q];
     }
   };
   const int nk = (d.K + TK - 1) / TK;
@@ -212,22 +197,35 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmDesc* __restri
       }
 }
 
-hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
-                          int prec, hipStream_t st, int tag) {
-  if (count <= 0 || tiles <= 0) return hipSuccess;
+template <int P, int TAG, int TA, int TB>
+static void launch_lp(const GemmDesc* d, const int* o, int count, int tiles, hipStream_t st) {
   const int grid = (tiles + 7) & ~7;
+  if (P == H2_PREC_FP32)
+    hipLaunchKernelGGL((gemm_f32_kernel<TAG, TA, TB>), dim3(grid), dim3(256), 0, st, d, o, count, tiles);
+  else
+    hipLaunchKernelGGL((gemm_bf16_kernel<TAG, TA, TB>), dim3(grid), dim3(256), 0, st, d, o, count, tiles);
+}
+
+template <int P, int TAG>
+static void launch_lp_t(const GemmDesc* d, const int* o, int count, int tiles, hipStream_t st,
+                        int tA, int tB) {
+  if (!tA && !tB) launch_lp<P, TAG, 0, 0>(d, o, count, tiles, st);
+  else if (!tA && tB) launch_lp<P, TAG, 0, 1>(d, o, count, tiles, st);
+  else if (tA && !tB) launch_lp<P, TAG, 1, 0>(d, o, count, tiles, st);
+  else launch_lp<P, TAG, 1, 1>(d, o, count, tiles, st);
+}
+
+hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
+                          int prec, hipStream_t st, int tag, int tA, int tB) {
+  if (count <= 0 || tiles <= 0) return hipSuccess;
   if (prec == H2_PREC_FP32) {
-    if (tag == 1)
-      hipLaunchKernelGGL(gemm_f32_kernel<1>, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off, count, tiles);
-    else
-      hipLaunchKernelGGL(gemm_f32_kernel<0>, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off, count, tiles);
+    if (tag == 1) launch_lp_t<H2_PREC_FP32, 1>(d_desc, d_tile_off, count, tiles, st, tA, tB);
+    else launch_lp_t<H2_PREC_FP32, 0>(d_desc, d_tile_off, count, tiles, st, tA, tB);
   } else if (prec == H2_PREC_BF16) {
-    if (tag == 1)
-      hipLaunchKernelGGL(gemm_bf16_kernel<1>, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off, count, tiles);
-    else
-      hipLaunchKernelGGL(gemm_bf16_kernel<0>, dim3(grid), dim3(256), 0, st, d_desc, d_tile_off, count, tiles);
+    if (tag == 1) launch_lp_t<H2_PREC_BF16, 1>(d_desc, d_tile_off, count, tiles, st, tA, tB);
+    else launch_lp_t<H2_PREC_BF16, 0>(d_desc, d_tile_off, count, tiles, st, tA, tB);
   } else {
-    return launch_gemm(d_desc, d_tile_off, count, tiles, st, tag);
+    return launch_gemm(d_desc, d_tile_off, count, tiles, st, tag, 0, tA, tB);
   }
   return hipGetLastError();
 }

@@ -326,7 +326,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
 // Basis transforms and Schur update in the handle's GEMM precision.
 static hipError_t run_gemm_p(const Ctx& c, const Batch<GemmDesc>& b, hipStream_t st, int tag = 0) {
   if (c.prm.gemm_prec == H2_PREC_FP64) return run_gemm(b, st, tag);
-  return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], c.prm.gemm_prec, st, tag);
+  return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], c.prm.gemm_prec, st, tag, b.tA, b.tB);
 }
 
 // Autotuner: every factor GEMM work list is timed with every tile shape (one
