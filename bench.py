@@ -77,6 +77,8 @@ def main():
                     help="train the rank predictor on smaller seeded builds first (untimed) "
                          "and size the basis buffers with it")
     ap.add_argument("--graph", action="store_true", help="capture the factorization in a hipGraph")
+    ap.add_argument("--stationary", action="store_true",
+                    help="stationary iterative refinement instead of PCG")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--s", type=int, default=512)
@@ -128,8 +130,9 @@ def main():
         n_total = sum(q.n for q in p)
     else:
         H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
-                     s_near=p.s_near, ir_max_iter=50, ir_tol=a.tol, timing=not a.graph,
-                     gemm_prec=prec, rank_model=model, use_graph=a.graph)
+                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=not a.graph,
+                     gemm_prec=prec, rank_model=model, use_graph=a.graph,
+                     use_pcg=not a.stationary)
         bnp = p.b()
         n_total = p.n
     t_build = time.perf_counter() - t0
@@ -147,7 +150,10 @@ def main():
 
     for w in range(a.warmup):
         step()
-        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+        st = H.stats()
+        print(f"[bench] warmup {w}: factor {st['t_factor']:.3f}s solve {st['t_solve']:.3f}s "
+              f"({st['ir_iters']} iterations, residual {st['ir_residual']:.1e})", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t_fac = t_sol = t_pair = 0.0
     iters = 0

@@ -33,7 +33,7 @@ hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
   return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
 }
 hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
-  return launch_thin(b.d, b.count, b.max_rows, ncols, st);
+  return launch_thin(b.d, b.count, b.max_rows, ncols, b.tA, st);
 }
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
   return launch_copy(b.d, b.count, st);
@@ -54,7 +54,6 @@ hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int 
 
 static constexpr int ID_MMAX = 4096;    // cpqr_id_kernel LDS capacity
 static constexpr int CHOL_NMAX = 2048;  // chol_inv rows per workgroup
-static constexpr int QR_KMAX = 4096;
 
 // Temporary device buffer freed at scope exit.
 struct TmpBuf {
@@ -554,6 +553,8 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     in.dDinv = c.alloc<double>((size_t)((n0 + 63) / 64) * 4096);
     in.dPan = c.alloc<double>((size_t)n0 * 64);
     ALLOCHK(in.dRoot); ALLOCHK(in.dRootA); ALLOCHK(in.dDinv); ALLOCHK(in.dPan);
+    // the panels write only their nb x nb corner: keep the padding zero
+    HIPCHK(hipMemsetAsync(in.dDinv, 0, (size_t)((n0 + 63) / 64) * 4096 * sizeof(double), st));
     max_n0 = std::max(max_n0, in.n0);
   }
   // L == 0 instances: the dense kernel block is the whole matrix
@@ -590,13 +591,14 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       const int r = S.m[b] - S.k[b];
       S.rkoff[b + 1] = S.rkoff[b] + (int64_t)S.k[b] * S.k[b];
       S.lioff[b + 1] = S.lioff[b] + (int64_t)r * r;
-      if (S.k[b] > QR_KMAX || r > CHOL_NMAX) return H2_ERR_UNSUPPORTED;
+      if (S.k[b] > QR_KMAX || S.m[b] > QR_MMAX) return H2_ERR_UNSUPPORTED;
     }
     const int64_t q = S.qoff[nb];
     S.dQ = c.alloc<double>(q); S.dP = c.alloc<double>(q); S.dTA = c.alloc<double>(q);
     S.dTB = c.alloc<double>(q); S.dW = c.alloc<double>(q);
     S.dR = c.alloc<double>(S.rkoff[nb]); S.dLi = c.alloc<double>(S.lioff[nb]);
-    ALLOCHK(S.dQ); ALLOCHK(S.dP); ALLOCHK(S.dTA); ALLOCHK(S.dTB); ALLOCHK(S.dW);
+    S.dTau = c.alloc<double>(std::max<int64_t>(S.koff[nb], 1));
+    ALLOCHK(S.dQ); ALLOCHK(S.dP); ALLOCHK(S.dTA); ALLOCHK(S.dTB); ALLOCHK(S.dW); ALLOCHK(S.dTau);
     ALLOCHK(S.dR); ALLOCHK(S.dLi);
     // near blocks of upper steps (m = k_2I + k_2I+1 is known now)
     const size_t np = S.np_i.size();
@@ -649,10 +651,9 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
     const int nb = S.nbox;
-    std::vector<GemmDesc> gw, gd1, gd2, gv, gs, gp1, gp2, gf1, gf2;
+    std::vector<GemmDesc> gw, gq1, gq2, gq3, gd1, gd2, gv, gs, gp1, gp2, gf1, gf2;
     std::vector<CopyDesc> cw, cps, cm;
     std::vector<BoxDev> qr(nb);
-    std::vector<CholDesc> ch;
     for (int b = 0; b < nb; ++b) {
       const int m = S.m[b], k = S.k[b], r = m - k;
       double* U = S.Uptr[b];
@@ -675,10 +676,15 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gw.push_back(gd(C.dR + C.rkoff[a + 1], kb, 0, U + ka, m, 0, nullptr, 1, W + ka, m, kb, k, kb,
                         1.0, 0.0));
       }
-      qr[b] = BoxDev{m, k, S.inst[b], Q, P, R, Li, TA, TB, W};
+      qr[b] = BoxDev{m, k, S.inst[b], Q, P, R, Li, TA, TB, W, S.dTau + S.koff[b]};
+      if (m * k > 0) {
+        // G = V^T V -> P (k x k); T V^T -> TB (k x m); Q = -V (T V^T)
+        gq1.push_back(gd(TA, m, 1, TA, m, 0, nullptr, 1, P, k, k, k, m, 1.0, 0.0));
+        gq2.push_back(gd(P, k, 0, TA, m, 1, nullptr, 1, TB, k, k, m, k, 1.0, 0.0));
+        gq3.push_back(gd(TA, m, 0, TB, k, 0, nullptr, 1, Q, m, m, m, k, -1.0, 0.0));
+      }
       gd1.push_back(gd(Dii, m, 0, Q, m, 0, nullptr, 1, TA, m, m, m, m, 1.0, 0.0));
       gd2.push_back(gd(Q, m, 1, TA, m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
-      if (r > 0) ch.push_back({TB + k + (int64_t)k * m, Li, r, m, h * (1 << 20) + b});
       if (m * k > 0) cps.push_back({Q, P, m, k, m, m, 0});
       if (r > 0) {
         gv.push_back(gd(Q + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, P + (int64_t)k * m, m, m, r,
@@ -733,13 +739,54 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     auto up_g = [&](Batch<GemmDesc>& B, const std::vector<GemmDesc>& v) {
       return upload_gemm(c, B, v, st);
     };
-    if (!up_g(S.g_w, gw) || !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
+    if (!up_g(S.g_w, gw) || !up_g(S.g_qr1, gq1) || !up_g(S.g_qr2, gq2) || !up_g(S.g_qr3, gq3) ||
+        !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
         !up_g(S.g_schur, gs) || !up_g(S.g_pair1, gp1) || !up_g(S.g_pair2, gp2) ||
         !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2))
       return H2_ERR_ALLOC;
     if (!upload(c, S.c_w, cw, st) || !upload(c, S.c_ps, cps, st) || !upload(c, S.c_merge, cm, st) ||
-        !upload(c, S.qr, qr, st) || !upload(c, S.chol, ch, st))
+        !upload(c, S.qr, qr, st))
       return H2_ERR_ALLOC;
+    // blocked Cholesky + inverse of the RR blocks (A at TB + k + k m, ld m;
+    // L^{-1} at Li, ld r; panel scratch in TA)
+    int rmax = 0;
+    for (int b = 0; b < nb; ++b) rmax = std::max(rmax, S.m[b] - S.k[b]);
+    const int npan = (rmax + 63) / 64;
+    S.ch_panel.assign(npan, {}); S.ch_trsm.assign(npan, {}); S.ch_syrk.assign(npan, {});
+    S.ch_back.assign(npan, {}); S.ch_inv1.assign(npan, {}); S.ch_inv2.assign(npan, {});
+    for (int pi = 0; pi < npan; ++pi) {
+      const int p0 = 64 * pi;
+      std::vector<PanelDesc> pd;
+      std::vector<GemmDesc> tr, sy, i1, i2;
+      std::vector<CopyDesc> bk;
+      for (int b = 0; b < nb; ++b) {
+        const int m = S.m[b], k = S.k[b], r = m - k;
+        if (r <= p0) continue;
+        const int w = std::min(64, r - p0), rows = r - p0 - w;
+        double* A = S.dTB + S.qoff[b] + k + (int64_t)k * m;
+        double* TA = S.dTA + S.qoff[b];
+        double* Li = S.dLi + S.lioff[b];
+        double* Dp = Li + p0 + (int64_t)p0 * r;
+        pd.push_back({A + p0 + (int64_t)p0 * m, m, w, Dp, r, h * (1 << 20) + b});
+        if (rows > 0) {
+          double* A21 = A + p0 + w + (int64_t)p0 * m;
+          double* A22 = A + p0 + w + (int64_t)(p0 + w) * m;
+          tr.push_back(gd(A21, m, 0, Dp, r, 1, nullptr, 1, TA, r, rows, w, w, 1.0, 0.0));
+          sy.push_back(gd(TA, r, 0, TA, r, 1, A22, m, A22, m, rows, rows, w, -1.0, 1.0));
+          bk.push_back({TA, A21, rows, w, r, m, 0});
+        }
+        if (p0 > 0) {
+          i1.push_back(gd(A + p0, m, 0, Li, r, 0, nullptr, 1, TA, 64, w, p0, p0, 1.0, 0.0));
+          i2.push_back(gd(Dp, r, 0, TA, 64, 0, nullptr, 1, Li + p0, r, w, p0, w, -1.0, 0.0));
+        }
+      }
+      if (!upload(c, S.ch_panel[pi], pd, st) || !up_g(S.ch_trsm[pi], tr) ||
+          !up_g(S.ch_syrk[pi], sy) || !upload(c, S.ch_back[pi], bk, st) ||
+          !up_g(S.ch_inv1[pi], i1) || !up_g(S.ch_inv2[pi], i2))
+        return H2_ERR_ALLOC;
+    }
+    S.qr.max_rows = 0;
+    for (auto& q : qr) S.qr.max_rows = std::max(S.qr.max_rows, q.m);
   }
   // root plan: save, then blocked Cholesky panels
   {
@@ -771,7 +818,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         if (n <= p) continue;
         const int nbk = std::min(64, n - p);
         double* A = in.dRoot;
-        pd.push_back({A + p + (int64_t)p * n, n, nbk, in.dDinv + (int64_t)pi * 4096, (1023 << 20) + t});
+        pd.push_back({A + p + (int64_t)p * n, n, nbk, in.dDinv + (int64_t)pi * 4096, 64, (1023 << 20) + t});
         const int rows = n - p - nbk;
         if (rows > 0) {
           double* A21 = A + (p + nbk) + (int64_t)p * n;

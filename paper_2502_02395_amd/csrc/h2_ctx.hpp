@@ -60,14 +60,21 @@ struct Step {
   double* dT3 = nullptr;                   // far scratch at soff
   double *dQ = nullptr, *dP = nullptr, *dTA = nullptr, *dTB = nullptr;  // at qoff
   double* dW = nullptr;                    // QR workspace at qoff
+  double* dTau = nullptr;                  // Householder scalars at koff
   double* dR = nullptr;                    // at rkoff
   double* dLi = nullptr;                   // at lioff
   // factor work lists
   Batch<GemmDesc> g_w;                     // W = D_i U_i (upper steps)
+  Batch<GemmDesc> g_qr1, g_qr2, g_qr3;     // compact-WY Q: V^T V, T V^T, -V (T V^T)
   Batch<CopyDesc> c_w;                     // W = U (leaf step)
   Batch<BoxDev> qr;
   Batch<GemmDesc> g_diag1, g_diag2;        // D_ii Q, Q^T (.)
-  Batch<CholDesc> chol;
+  // blocked Cholesky of the RR blocks and the explicit inverse of the factor,
+  // per 64-wide panel: diagonal panel, TRSM, trailing update, write-back;
+  // then inverse block rows X_p = -D_p (L_p,<p X_<p)
+  std::vector<Batch<PanelDesc>> ch_panel;
+  std::vector<Batch<GemmDesc>> ch_trsm, ch_syrk, ch_inv1, ch_inv2;
+  std::vector<Batch<CopyDesc>> ch_back;
   Batch<CopyDesc> c_ps;                    // P^S = Q^S
   Batch<GemmDesc> g_v;                     // V = Q^R Linv^T, L(s)_ii
   Batch<GemmDesc> g_schur;                 // SS_ii -= L(s) L(s)^T

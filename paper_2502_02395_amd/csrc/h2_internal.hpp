@@ -58,10 +58,14 @@ struct BoxDev {
   double* P;                // m x m [Q^S | Q^R L(r)^{-T}]
   double* Rf;               // k x k triangular factor of D_i U_i
   double* Linv;             // r x r inverse Cholesky factor of the RR block
-  double* tmpA;             // m x m scratch
+  double* tmpA;             // m x m scratch (the QR's explicit V first)
   double* tmpB;             // m x m transformed diagonal block
-  double* W;                // m x k QR workspace
+  double* W;                // m x k QR input, overwritten
+  double* tau;              // k Householder scalars
 };
+
+constexpr int QR_KMAX = 4096;  // rank limit of the QR kernels
+constexpr int QR_MMAX = 7680;  // row limit of the QR panel kernel
 
 // ------------------------------------------------------------- launch wrappers
 // All wrappers enqueue on `st`; they return hipSuccess or the launch error.
@@ -84,8 +88,13 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
                        hipStream_t st);
 hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st);
 
-// QR of W (m x k) into the full Q (m x m) and R (k x k), one workgroup per box.
-hipError_t launch_qr_complete(const BoxDev* boxes, int nbox, hipStream_t st);
+// QR of W (m x k) with R (k x k) and the full Q (m x m) in compact WY form:
+// qr_panel writes V (tmpA), tau and R; a GEMM writes G = V^T V into P;
+// qr_tbuild turns G into T in place; GEMMs write Q = -V (T V^T); qr_diag adds
+// the identity.  One workgroup per box.
+hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t st);
+hipError_t launch_qr_tbuild(const BoxDev* boxes, int nbox, hipStream_t st);
+hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st);
 // Cholesky + explicit inverse of n x n SPD blocks: A (ld lda, destroyed),
 // Linv (n x n dense, zero upper triangle).  Breakdown: *fail = min(code).
 struct CholDesc {
@@ -112,9 +121,9 @@ hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps,
 // Write U for IDs whose rank exceeded the capacity given to cpqr_id.
 hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 
-// Thin products y = alpha op(A) x + beta y for N <= 16 columns; ncols > 0
-// overrides every item's N.
-hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols,
+// Thin products y = alpha op(A) x + beta y for ncols <= 16 columns (every
+// item's N is ignored); every item of one launch has the transpose tA.
+hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
                        hipStream_t st);
 
 // Neighbour gathers of the substitution and the matvec:
@@ -146,7 +155,8 @@ hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows,
 struct PanelDesc {
   double* A;                // diagonal block pointer
   int lda, nb;
-  double* dinv;             // 64 x 64
+  double* dinv;             // nb x nb inverse of the panel's factor
+  int ldd;                  // leading dimension of dinv
   int code;
 };
 hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st);

@@ -1,7 +1,8 @@
 // Per-box dense factorizations, one 256-thread workgroup per box:
-//   * qr_complete  -- Householder QR of D_i U_i with the full square Q_i
-//                     (basis completion, first step of each level of the
-//                     ULV sweep; skeleton columns first);
+//   * qr_panel / qr_tbuild / qr_diag -- Householder QR of D_i U_i and the
+//                     full square Q_i in compact WY form (basis completion,
+//                     first step of each level of the ULV sweep; skeleton
+//                     columns first);
 //   * cpqr_id      -- column-pivoted Householder QR of M^T for the row
 //                     interpolative decomposition of Algorithm 1, rank by the
 //                     leading |R_jj| > eps |R_00|, then T = R_11^{-1} R_12;
@@ -71,43 +72,182 @@ __device__ __forceinline__ double apply_reflector_wave(const double* vcol, doubl
 }
 
 // ------------------------------------------------------------------ QR + Q
-__global__ __launch_bounds__(256) void qr_complete_kernel(const BoxDev* __restrict__ boxes) {
-  extern __shared__ double tau_s[];
+// Householder QR of W = D_i U_i (m x k) and the full square Q_i in compact
+// WY form, Q = H_0 H_1 ... H_{k-1} = I - V T V^T (V unit lower trapezoidal,
+// T upper triangular):
+//   qr_panel   -- blocked right-looking factorization, one workgroup per box,
+//                 panels of up to QR_NB columns resident in LDS; writes V
+//                 explicitly (tmpA), tau, and R (Rf);
+//   qr_tbuild  -- T from G = V^T V (a batched GEMM writes G into P):
+//                 T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j];
+//   qr_diag    -- after the GEMMs Q = -V (T V^T): add the identity (k = 0
+//                 boxes get Q = I outright).
+constexpr int QR_PAN = 7680;  // LDS doubles holding one panel (60 KiB)
+
+// Panel width NB is fixed per launch (NB * max m <= QR_PAN); only the last
+// panel of a box is narrower, and it has no trailing columns.
+template <int NB>
+__global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict__ boxes) {
+  __shared__ double pan[QR_PAN];
+  __shared__ double Tp[NB * NB];
+  __shared__ double taup[NB];
   __shared__ double sh[4];
   const BoxDev b = boxes[blockIdx.x];
   const int m = b.m, k = b.k;
+  if (k == 0 || m == 0) return;
+  constexpr int nb = NB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* W = b.W;
-  for (int j = 0; j < k; ++j) {
-    double beta;
-    const double tau = householder(W + (int64_t)j * m, j, m, sh, &beta);
-    if (threadIdx.x == 0) tau_s[j] = tau;
-    if (tau != 0.0)
-      for (int c = j + 1 + wave; c < k; c += 4)
-        apply_reflector_wave(W + (int64_t)j * m, W + (int64_t)c * m, j, m, tau, false);
+  for (int J = 0; J < k; J += nb) {
+    const int w = min(nb, k - J), L = m - J;
+    for (int e = threadIdx.x; e < L * w; e += 256) {
+      const int r = e % L, c = e / L;
+      pan[e] = W[J + r + (int64_t)(J + c) * m];
+    }
+    __syncthreads();
+    // unblocked factorization of the panel
+    for (int jj = 0; jj < w; ++jj) {
+      double beta;
+      const double tau = householder(pan + jj * L, jj, L, sh, &beta);
+      if (threadIdx.x == 0) taup[jj] = tau;
+      if (tau != 0.0)
+        for (int c = jj + 1 + wave; c < w; c += 4)
+          apply_reflector_wave(pan + jj * L, pan + c * L, jj, L, tau, false);
+      __syncthreads();
+    }
+    // R columns J..J+w-1 (rows above the panel are final in W), tau
+    for (int e = threadIdx.x; e < k * w; e += 256) {
+      const int r = e % k, c = e / k;
+      double v = 0.0;
+      if (r < J) v = W[r + (int64_t)(J + c) * m];
+      else if (r <= J + c) v = pan[c * L + (r - J)];
+      b.Rf[r + (int64_t)(J + c) * k] = v;
+    }
+    if (threadIdx.x < w) b.tau[J + threadIdx.x] = taup[threadIdx.x];
+    __syncthreads();
+    // make V explicit in the panel: zeros above the diagonal, ones on it
+    for (int e = threadIdx.x; e < w * w; e += 256) {
+      const int r = e % w, c = e / w;
+      if (r <= c) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // V into tmpA (all m rows)
+    for (int e = threadIdx.x; e < m * w; e += 256) {
+      const int r = e % m, c = e / m;
+      b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
+    }
+    if (J + w < k) {
+      // here w == NB.  Panel T: dots of V columns, then the triangular
+      // recurrence.
+      for (int pq = wave; pq < NB * NB; pq += 4) {
+        const int i = pq % NB, jj = pq / NB;
+        if (i >= jj) continue;
+        double d = 0.0;
+        for (int r = jj + lane; r < L; r += 64) d += pan[i * L + r] * pan[jj * L + r];
+        d = wave_sum(d);
+        if (lane == 0) Tp[i + jj * NB] = d;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int jj = 0; jj < NB; ++jj) {
+          const double tj = taup[jj];
+          for (int i = 0; i < jj; ++i) {
+            double t = 0.0;
+            for (int q = i; q < jj; ++q) t += Tp[i + q * NB] * Tp[q + jj * NB];
+            Tp[i + jj * NB] = -tj * t;
+          }
+          Tp[jj + jj * NB] = tj;
+        }
+      }
+      __syncthreads();
+      // trailing columns: c <- (I - V T^T V^T) c, one wave per column
+      for (int c = J + NB + wave; c < k; c += 4) {
+        double* col = W + J + (int64_t)c * m;
+        double y[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = 0.0;
+        for (int r = lane; r < L; r += 64) {
+          const double x = col[r];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) y[i] += pan[i * L + r] * x;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) y[i] = wave_sum(y[i]);
+        // z = T^T y, computed in place from the last entry down
+#pragma unroll
+        for (int i = NB - 1; i >= 0; --i) {
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q <= i; ++q) t += Tp[q + i * NB] * y[q];
+          y[i] = t;
+        }
+        for (int r = lane; r < L; r += 64) {
+          double x = col[r];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) x -= pan[i * L + r] * y[i];
+          col[r] = x;
+        }
+      }
+    }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < k * k; e += 256) {
-    const int r = e % k, c = e / k;
-    b.Rf[e] = (r <= c) ? W[r + (int64_t)c * m] : 0.0;
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += 256)
-    b.Q[e] = (e % m == e / m) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = k - 1; j >= 0; --j) {
-    const double tau = tau_s[j];
-    if (tau != 0.0)
-      for (int c = j + wave; c < m; c += 4)
-        apply_reflector_wave(W + (int64_t)j * m, b.Q + (int64_t)c * m, j, m, tau, false);
-    __syncthreads();
-  }
-  (void)lane;
 }
 
-hipError_t launch_qr_complete(const BoxDev* boxes, int nbox, hipStream_t st) {
+__global__ __launch_bounds__(256) void qr_tbuild_kernel(const BoxDev* __restrict__ boxes) {
+  __shared__ double g[QR_KMAX];
+  const BoxDev b = boxes[blockIdx.x];
+  const int k = b.k;
+  if (k == 0 || b.m == 0) return;
+  double* T = b.P;  // k x k, ld k, holds G on entry
+  for (int j = 0; j < k; ++j) {
+    for (int i = threadIdx.x; i < j; i += 256) g[i] = T[i + (int64_t)j * k];
+    const double tj = b.tau[j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += 256) {
+      double v = (i == j) ? tj : 0.0;
+      if (i < j) {
+        double s = 0.0;
+        for (int q = i; q < j; ++q) s += T[i + (int64_t)q * k] * g[q];
+        v = -tj * s;
+      }
+      T[i + (int64_t)j * k] = v;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void qr_diag_kernel(const BoxDev* __restrict__ boxes) {
+  const BoxDev b = boxes[blockIdx.x];
+  const int m = b.m;
+  if (b.k == 0) {
+    for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += 256)
+      b.Q[e] = (e % m == e / m) ? 1.0 : 0.0;
+  } else {
+    for (int i = threadIdx.x; i < m; i += 256) b.Q[i + (int64_t)i * m] += 1.0;
+  }
+}
+
+hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t st) {
+  if (nbox <= 0 || max_m <= 0) return hipSuccess;
+  if (max_m > QR_PAN) return hipErrorInvalidValue;
+  const int nb = QR_PAN / max_m;
+  if (nb >= 16) hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(nbox), dim3(256), 0, st, boxes);
+  else if (nb >= 8) hipLaunchKernelGGL(qr_panel_kernel<8>, dim3(nbox), dim3(256), 0, st, boxes);
+  else if (nb >= 4) hipLaunchKernelGGL(qr_panel_kernel<4>, dim3(nbox), dim3(256), 0, st, boxes);
+  else if (nb >= 2) hipLaunchKernelGGL(qr_panel_kernel<2>, dim3(nbox), dim3(256), 0, st, boxes);
+  else hipLaunchKernelGGL(qr_panel_kernel<1>, dim3(nbox), dim3(256), 0, st, boxes);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_tbuild(const BoxDev* boxes, int nbox, hipStream_t st) {
   if (nbox <= 0) return hipSuccess;
-  // tau for up to QR_KMAX reflectors (host checks k <= QR_KMAX)
-  hipLaunchKernelGGL(qr_complete_kernel, dim3(nbox), dim3(256), 4096 * sizeof(double), st, boxes);
+  hipLaunchKernelGGL(qr_tbuild_kernel, dim3(nbox), dim3(256), 0, st, boxes);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st) {
+  if (nbox <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qr_diag_kernel, dim3(nbox), dim3(256), 0, st, boxes);
   return hipGetLastError();
 }
 
@@ -363,9 +503,8 @@ __global__ __launch_bounds__(256) void panel_kernel(const PanelDesc* __restrict_
     const int r = e % n, c = e / n;
     buf[e] = d.A[r + (int64_t)c * d.lda];
   }
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) d.dinv[e] = 0.0;
   __syncthreads();
-  chol_inv_impl(buf, n, d.dinv, 64, n, fail, d.code);
+  chol_inv_impl(buf, n, d.dinv, d.ldd, n, fail, d.code);
   for (int e = threadIdx.x; e < n * n; e += 256) {
     const int r = e % n, c = e / n;
     d.A[r + (int64_t)c * d.lda] = (r >= c) ? buf[e] : 0.0;

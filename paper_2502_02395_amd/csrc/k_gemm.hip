@@ -191,82 +191,125 @@ hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
 }
 
 // ---------------------------------------------------------------------------
-// Thin products y = alpha op(A) x + beta y, x with N <= 16 columns.  Each
-// workgroup owns 64 output rows of one item and reads its part of A once.
-constexpr int THIN_NMAX = 16;
+// Thin products y = alpha op(A) x + beta y, x with at most 16 columns.  Each
+// item's A is read exactly once; eight loads per thread are kept in flight.
+//   op(A) = A   : one thread per output row, x staged through LDS;
+//   op(A) = A^T : one wave per output row (a column of A), lanes along it.
+constexpr int THIN_NMAX = 16, THIN_XCH = 256;
 
-__global__ __launch_bounds__(256) void thin_kernel(const GemmDesc* __restrict__ descs, int ncols) {
+template <int NR>
+__global__ __launch_bounds__(256) void thin_n_kernel(const GemmDesc* __restrict__ descs, int ncols) {
+  __shared__ double xs[THIN_XCH * NR];
+  const GemmDesc d = descs[blockIdx.y];
+  if ((int)blockIdx.x * 256 >= d.M) return;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const bool live = r < d.M;
+  double acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+  const int64_t lda = d.lda;
+  for (int k0 = 0; k0 < d.K; k0 += THIN_XCH) {
+    const int len = min(THIN_XCH, d.K - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < len * NR; e += 256) {
+      const int kv = e / NR, c = e % NR;
+      xs[e] = (c < ncols) ? d.B[k0 + kv + (int64_t)c * d.ldb] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      const double* col = d.A + r + (int64_t)k0 * lda;
+      int kv = 0;
+      for (; kv + 8 <= len; kv += 8) {
+        double av[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) av[u] = col[(int64_t)(kv + u) * lda];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[c] += av[u] * xs[(kv + u) * NR + c];
+      }
+      for (; kv < len; ++kv) {
+        const double av = col[(int64_t)kv * lda];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[c] += av * xs[kv * NR + c];
+      }
+    }
+  }
+  if (live)
+    for (int c = 0; c < ncols; ++c) {
+      double v = d.alpha * acc[c];
+      if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
+      d.D[r + (int64_t)c * d.ldd] = v;
+    }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void thin_t_kernel(const GemmDesc* __restrict__ descs, int ncols) {
   const GemmDesc d = descs[blockIdx.y];
   const int r0 = blockIdx.x * 64;
   if (r0 >= d.M) return;
-  const int tid = threadIdx.x;
-  __shared__ double red[4][64][THIN_NMAX + 1];
-  double acc[THIN_NMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int rr = wave; rr < 64; rr += 4) {
+    const int r = r0 + rr;
+    if (r >= d.M) break;
+    double p[NR];
 #pragma unroll
-  for (int c = 0; c < THIN_NMAX; ++c) acc[c] = 0.0;
-  const int N = ncols > 0 ? ncols : d.N;
-  if (!d.tA) {
-    const int r = r0 + (tid & 63);
-    const int kq = tid >> 6;
-    if (r < d.M) {
-      for (int k = kq; k < d.K; k += 4) {
-        const double a = d.A[r + (int64_t)k * d.lda];
+    for (int c = 0; c < NR; ++c) p[c] = 0.0;
+    const double* col = d.A + (int64_t)r * d.lda;
+    const int64_t ldb = d.ldb;
+    int k = lane;
+    for (; k + 192 < d.K; k += 256) {
+      double av[4];
 #pragma unroll
-        for (int c = 0; c < THIN_NMAX; ++c)
-          if (c < N) acc[c] += a * d.B[k + (int64_t)c * d.ldb];
-      }
+      for (int u = 0; u < 4; ++u) av[u] = col[k + 64 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < ncols) p[c] += av[u] * d.B[k + 64 * u + c * ldb];
+    }
+    for (; k < d.K; k += 64) {
+      const double av = col[k];
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < ncols) p[c] += av * d.B[k + c * ldb];
     }
 #pragma unroll
-    for (int c = 0; c < THIN_NMAX; ++c)
-      if (c < N) red[kq][tid & 63][c] = acc[c];
-    __syncthreads();
-    if (tid < 64 && r < d.M) {
-      for (int c = 0; c < N; ++c) {
-        double v = d.alpha * (red[0][tid][c] + red[1][tid][c] + red[2][tid][c] + red[3][tid][c]);
+    for (int c = 0; c < NR; ++c) {
+      double v = p[c];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      p[c] = v;
+    }
+    if (lane == 0) {
+      for (int c = 0; c < ncols; ++c) {
+        double v = d.alpha * p[c];
         if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
         d.D[r + (int64_t)c * d.ldd] = v;
-      }
-    }
-  } else {
-    // row r of op(A) is column r of A: a wave reduces over k
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int rr = wave; rr < 64; rr += 4) {
-      const int r = r0 + rr;
-      if (r >= d.M) break;
-      double p[THIN_NMAX];
-#pragma unroll
-      for (int c = 0; c < THIN_NMAX; ++c) p[c] = 0.0;
-      const double* col = d.A + (int64_t)r * d.lda;
-      for (int k = lane; k < d.K; k += 64) {
-        const double a = col[k];
-#pragma unroll
-        for (int c = 0; c < THIN_NMAX; ++c)
-          if (c < N) p[c] += a * d.B[k + (int64_t)c * d.ldb];
-      }
-#pragma unroll
-      for (int c = 0; c < THIN_NMAX; ++c) {
-        if (c < N) {
-          double v = p[c];
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-          p[c] = v;
-        }
-      }
-      if (lane == 0) {
-        for (int c = 0; c < N; ++c) {
-          double v = d.alpha * p[c];
-          if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
-          d.D[r + (int64_t)c * d.ldd] = v;
-        }
       }
     }
   }
 }
 
-hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, hipStream_t st) {
+template <int NR>
+static void launch_thin_nr(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
+                           hipStream_t st) {
+  if (tA)
+    hipLaunchKernelGGL(thin_t_kernel<NR>, dim3((max_m + 63) / 64, count), dim3(256), 0, st, d_desc,
+                       ncols);
+  else
+    hipLaunchKernelGGL(thin_n_kernel<NR>, dim3((max_m + 255) / 256, count), dim3(256), 0, st,
+                       d_desc, ncols);
+}
+
+hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
+                       hipStream_t st) {
   if (count <= 0 || max_m <= 0) return hipSuccess;
-  if (ncols > THIN_NMAX) return hipErrorInvalidValue;
-  dim3 grid((max_m + 63) / 64, count);
-  hipLaunchKernelGGL(thin_kernel, grid, dim3(256), 0, st, d_desc, ncols);
+  if (ncols > THIN_NMAX || ncols < 1) return hipErrorInvalidValue;
+  if (ncols == 1) launch_thin_nr<1>(d_desc, count, max_m, ncols, tA, st);
+  else if (ncols <= 2) launch_thin_nr<2>(d_desc, count, max_m, ncols, tA, st);
+  else if (ncols <= 4) launch_thin_nr<4>(d_desc, count, max_m, ncols, tA, st);
+  else if (ncols <= 8) launch_thin_nr<8>(d_desc, count, max_m, ncols, tA, st);
+  else launch_thin_nr<16>(d_desc, count, max_m, ncols, tA, st);
   return hipGetLastError();
 }
 

@@ -68,33 +68,63 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
 }
 
 // ------------------------------------------------------------------ gathers
-constexpr int GNR = 16;  // max right-hand sides per pass
+// The substitution and the matvec stream every factor block once per sweep:
+// these kernels are HBM-bound, so each thread keeps eight block loads in
+// flight and the right-hand-side slices are staged through LDS.
+constexpr int GNR = 16;   // max right-hand sides per pass
+constexpr int XCH = 256;  // x values staged per chunk
 
+template <int NR>
 __global__ __launch_bounds__(256) void gather_direct_kernel(const GatherBox* __restrict__ boxes,
                                                             const GatherNbr* __restrict__ nbrs,
                                                             int nrhs) {
+  __shared__ double xs[XCH * NR];
   const GatherBox b = boxes[blockIdx.x];
+  if ((int)blockIdx.y * 256 >= b.rows) return;
   const int r = blockIdx.y * 256 + threadIdx.x;
-  if (r >= b.rows) return;
-  double acc[GNR];
+  const bool live = r < b.rows;
+  double acc[NR];
 #pragma unroll
-  for (int c = 0; c < GNR; ++c) acc[c] = 0.0;
+  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
   for (int q = b.d0; q < b.d1; ++q) {
     const GatherNbr nb = nbrs[q];
-    const double* col = nb.B + r;
-    for (int s = 0; s < nb.cols; ++s) {
-      const double bv = col[(int64_t)s * nb.ldB];
+    const int64_t ldB = nb.ldB;
+    for (int s0 = 0; s0 < nb.cols; s0 += XCH) {
+      const int len = min(XCH, nb.cols - s0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < len * NR; e += 256) {
+        const int sv = e / NR, c = e % NR;
+        xs[e] = (c < nrhs) ? nb.x[s0 + sv + (int64_t)c * nb.ldx] : 0.0;
+      }
+      __syncthreads();
+      if (live) {
+        const double* col = nb.B + r + (int64_t)s0 * ldB;
+        int sv = 0;
+        for (; sv + 8 <= len; sv += 8) {
+          double bv[8];
 #pragma unroll
-      for (int c = 0; c < GNR; ++c)
-        if (c < nrhs) acc[c] += bv * nb.x[s + (int64_t)c * nb.ldx];
+          for (int u = 0; u < 8; ++u) bv[u] = col[(int64_t)(sv + u) * ldB];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] += bv[u] * xs[(sv + u) * NR + c];
+        }
+        for (; sv < len; ++sv) {
+          const double bv = col[(int64_t)sv * ldB];
+#pragma unroll
+          for (int c = 0; c < NR; ++c) acc[c] += bv * xs[sv * NR + c];
+        }
+      }
     }
   }
-  for (int c = 0; c < nrhs; ++c) {
-    const double base = b.base ? b.base[r + (int64_t)c * b.ldbase] : 0.0;
-    b.y[r + (int64_t)c * b.ldy] = base + b.alpha * acc[c];
-  }
+  if (live)
+    for (int c = 0; c < nrhs; ++c) {
+      const double base = b.base ? b.base[r + (int64_t)c * b.ldbase] : 0.0;
+      b.y[r + (int64_t)c * b.ldy] = base + b.alpha * acc[c];
+    }
 }
 
+template <int NR>
 __global__ __launch_bounds__(256) void gather_trans_kernel(const GatherBox* __restrict__ boxes,
                                                            const GatherNbr* __restrict__ nbrs,
                                                            int nrhs) {
@@ -104,42 +134,61 @@ __global__ __launch_bounds__(256) void gather_trans_kernel(const GatherBox* __re
   for (int rr = wave; rr < 64; rr += 4) {
     const int r = blockIdx.y * 64 + rr;
     if (r >= b.rows) break;
-    double acc[GNR];
+    double acc[NR];
 #pragma unroll
-    for (int c = 0; c < GNR; ++c) acc[c] = 0.0;
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
     for (int q = b.t0; q < b.t1; ++q) {
       const GatherNbr nb = nbrs[q];
       const double* col = nb.B + (int64_t)r * nb.ldB;  // row r of B^T
-      for (int s = lane; s < nb.cols; s += 64) {
-        const double bv = col[s];
+      const double* x = nb.x;
+      const int64_t ldx = nb.ldx;
+      int sv = lane;
+      for (; sv + 192 < nb.cols; sv += 256) {
+        double bv[4];
 #pragma unroll
-        for (int c = 0; c < GNR; ++c)
-          if (c < nrhs) acc[c] += bv * nb.x[s + (int64_t)c * nb.ldx];
+        for (int u = 0; u < 4; ++u) bv[u] = col[sv + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < NR; ++c)
+            if (c < nrhs) acc[c] += bv[u] * x[sv + 64 * u + c * ldx];
+      }
+      for (; sv < nb.cols; sv += 64) {
+        const double bv = col[sv];
+#pragma unroll
+        for (int c = 0; c < NR; ++c)
+          if (c < nrhs) acc[c] += bv * x[sv + c * ldx];
       }
     }
 #pragma unroll
-    for (int c = 0; c < GNR; ++c) {
-      if (c < nrhs) {
-        double v = acc[c];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        acc[c] = v;
-      }
+    for (int c = 0; c < NR; ++c) {
+      double v = acc[c];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[c] = v;
     }
     if (lane == 0)
       for (int c = 0; c < nrhs; ++c) b.y[r + (int64_t)c * b.ldy] += b.alpha * acc[c];
   }
 }
 
+template <int NR>
+static void launch_gather_nr(const GatherBox* bx, int nbox, int max_rows, const GatherNbr* nb,
+                             int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(gather_direct_kernel<NR>, dim3(nbox, (max_rows + 255) / 256), dim3(256), 0,
+                     st, bx, nb, nrhs);
+  hipLaunchKernelGGL(gather_trans_kernel<NR>, dim3(nbox, (max_rows + 63) / 64), dim3(256), 0, st,
+                     bx, nb, nrhs);
+}
+
 hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows, const GatherNbr* nb,
                          int nrhs, hipStream_t st) {
   if (nbox <= 0 || max_rows <= 0) return hipSuccess;
-  if (nrhs > GNR) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gather_direct_kernel, dim3(nbox, (max_rows + 255) / 256), dim3(256), 0, st,
-                     bx, nb, nrhs);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(gather_trans_kernel, dim3(nbox, (max_rows + 63) / 64), dim3(256), 0, st, bx,
-                     nb, nrhs);
+  if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
+  if (nrhs == 1) launch_gather_nr<1>(bx, nbox, max_rows, nb, nrhs, st);
+  else if (nrhs <= 2) launch_gather_nr<2>(bx, nbox, max_rows, nb, nrhs, st);
+  else if (nrhs <= 4) launch_gather_nr<4>(bx, nbox, max_rows, nb, nrhs, st);
+  else if (nrhs <= 8) launch_gather_nr<8>(bx, nbox, max_rows, nb, nrhs, st);
+  else launch_gather_nr<16>(bx, nbox, max_rows, nb, nrhs, st);
   return hipGetLastError();
 }
 

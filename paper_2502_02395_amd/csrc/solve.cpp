@@ -43,6 +43,9 @@ static bool up_thin(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, 
   int mx = 0;
   for (auto& g : v) mx = std::max(mx, g.M);
   b.max_rows = mx;
+  b.tA = v.empty() ? 0 : v[0].tA;
+  for (auto& g : v)
+    if (g.tA != b.tA) return false;  // lists are built uniform
   return upload(c, b, v, st);
 }
 static bool up_gather(Ctx& c, Batch<GatherBox>& bb, Batch<GatherNbr>& nb,
@@ -361,11 +364,16 @@ h2_status autotune(Ctx& c, hipStream_t st) {
     return H2_OK;
   };
   for (auto& S : c.steps) {
-    for (Batch<GemmDesc>* b : {&S.g_w, &S.g_diag1, &S.g_diag2, &S.g_v, &S.g_schur, &S.g_far1,
-                               &S.g_far2}) {
+    for (Batch<GemmDesc>* b : {&S.g_w, &S.g_qr1, &S.g_qr2, &S.g_qr3, &S.g_diag1, &S.g_diag2,
+                               &S.g_v, &S.g_schur, &S.g_far1, &S.g_far2}) {
       h2_status e = tune(*b, 0);
       if (e != H2_OK) return e;
     }
+    for (size_t p = 0; p < S.ch_trsm.size(); ++p)
+      for (Batch<GemmDesc>* b : {&S.ch_trsm[p], &S.ch_syrk[p], &S.ch_inv1[p], &S.ch_inv2[p]}) {
+        h2_status e = tune(*b, 0);
+        if (e != H2_OK) return e;
+      }
     for (Batch<GemmDesc>* b : {&S.g_pair1, &S.g_pair2}) {
       h2_status e = tune(*b, 1);
       if (e != H2_OK) return e;
@@ -382,10 +390,25 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     Step& S = c.steps[h];
     if (h == 0) HIPCHK(run_copy(S.c_w, st));
     else HIPCHK(run_gemm(S.g_w, st));
-    HIPCHK(launch_qr_complete(S.qr.d, S.qr.count, st));
+    HIPCHK(launch_qr_panel(S.qr.d, S.qr.count, S.qr.max_rows, st));
+    HIPCHK(run_gemm(S.g_qr1, st));
+    HIPCHK(launch_qr_tbuild(S.qr.d, S.qr.count, st));
+    HIPCHK(run_gemm(S.g_qr2, st));
+    HIPCHK(run_gemm(S.g_qr3, st));
+    HIPCHK(launch_qr_diag(S.qr.d, S.qr.count, st));
     HIPCHK(run_gemm_p(c, S.g_diag1, st));
     HIPCHK(run_gemm_p(c, S.g_diag2, st));
-    HIPCHK(launch_chol_inv(S.chol.d, S.chol.count, c.dFail, st));
+    HIPCHK(launch_fill(S.dLi, S.lioff.back(), 0.0, st));
+    for (size_t p = 0; p < S.ch_panel.size(); ++p) {
+      HIPCHK(launch_panel(S.ch_panel[p].d, S.ch_panel[p].count, c.dFail, st));
+      HIPCHK(run_gemm(S.ch_trsm[p], st));
+      HIPCHK(run_gemm(S.ch_syrk[p], st));
+      HIPCHK(run_copy(S.ch_back[p], st));
+    }
+    for (size_t p = 1; p < S.ch_panel.size(); ++p) {
+      HIPCHK(run_gemm(S.ch_inv1[p], st));
+      HIPCHK(run_gemm(S.ch_inv2[p], st));
+    }
     HIPCHK(run_copy(S.c_ps, st));
     HIPCHK(run_gemm(S.g_v, st));
     HIPCHK(run_gemm_p(c, S.g_schur, st));
