@@ -113,6 +113,13 @@ typedef struct {
                              capacities plus fallbacks, or m_i^2 per box)       */
   int32_t tuned_lists;    /* GEMM work lists timed by the autotuner             */
   int32_t tuned_cfg_hist[3]; /* how many chose 64x64, 128x64, 128x128 tiles     */
+  double t_gather[2];     /* seconds in the neighbour-gather launches of the last
+                             solve: [0] block products, [1] per-box reductions
+                             (HIP events around each launch; params.timing = 1) */
+  double bytes_gather[2]; /* algorithmic bytes of those launches: [0] every
+                             stored block once plus x slices and partial
+                             products, [1] partials, base and y once          */
+  int32_t gather_launches[2]; /* number of timed launches of each kind           */
 } h2_stats_t;
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).

@@ -139,17 +139,33 @@ h2_status h2_factor(h2_handle h, void* stream) {
   hipStream_t st = S(stream);
   const double t0 = now_seconds();
   if (c.prm.use_graph) {
+    // The caller's stream may be the null stream, which cannot be captured:
+    // capture and replay on a stream of our own (default priority), ordered
+    // after and before the caller's work by events.
+    if (!c.graph_stream) {
+      HIPCHK(hipStreamCreateWithFlags(&c.graph_stream, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&c.ev_g0, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&c.ev_g1, hipEventDisableTiming));
+    }
+    hipStream_t gs = c.graph_stream;
+    HIPCHK(hipEventRecord(c.ev_g0, st));
+    HIPCHK(hipStreamWaitEvent(gs, c.ev_g0, 0));
     if (!c.graph) {
-      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      h2_status e = do_factor(c, st);
+      HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+      h2_status e = do_factor(c, gs);
       hipGraph_t g = nullptr;
-      const hipError_t ce = hipStreamEndCapture(st, &g);
-      if (e != H2_OK) return e;
+      const hipError_t ce = hipStreamEndCapture(gs, &g);
+      if (e != H2_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+      }
       HIPCHK(ce);
       c.graph_def = g;
       HIPCHK(hipGraphInstantiate(&c.graph, g, nullptr, nullptr, 0));
     }
-    HIPCHK(hipGraphLaunch(c.graph, st));
+    HIPCHK(hipGraphLaunch(c.graph, gs));
+    HIPCHK(hipEventRecord(c.ev_g1, gs));
+    HIPCHK(hipStreamWaitEvent(st, c.ev_g1, 0));
   } else {
     h2_status e = do_factor(c, st);
     if (e != H2_OK) { c.failed = true; return e; }
@@ -195,6 +211,19 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
   hipStream_t st = S(stream);
   const double t0 = now_seconds();
   const int maxit = c.prm.ir_max_iter;
+  {
+    h2_status e = ensure_partials(c, (int)std::min<int64_t>(NRHS_MAX, nrhs));
+    if (e != H2_OK) return e;
+  }
+  if (c.prm.timing) {
+    if (c.gev.empty()) {
+      c.gev.resize(3 * 2048, nullptr);
+      for (auto& e : c.gev) HIPCHK(hipEventCreate(&e));
+    }
+    c.gtime = true;
+    c.gev_used = 0;
+    c.gbytes.clear();
+  }
   int iters_total = 0;
   double worst = 0.0;
   bool noconv = false;
@@ -260,6 +289,23 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
   }
   HIPCHK(hipStreamSynchronize(st));
   c.st.t_solve = now_seconds() - t0;
+  if (c.gtime) {
+    c.gtime = false;
+    double tt[2] = {0.0, 0.0}, bb[2] = {0.0, 0.0};
+    int nl[2] = {0, 0};
+    for (size_t q = 0; q + 3 <= c.gev_used; q += 3) {
+      float ms0 = 0.f, ms1 = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms0, c.gev[q], c.gev[q + 1]));
+      HIPCHK(hipEventElapsedTime(&ms1, c.gev[q + 1], c.gev[q + 2]));
+      tt[0] += 1e-3 * ms0; bb[0] += c.gbytes[2 * (q / 3)]; ++nl[0];
+      tt[1] += 1e-3 * ms1; bb[1] += c.gbytes[2 * (q / 3) + 1]; ++nl[1];
+    }
+    for (int q = 0; q < 2; ++q) {
+      c.st.t_gather[q] = tt[q];
+      c.st.bytes_gather[q] = bb[q];
+      c.st.gather_launches[q] = nl[q];
+    }
+  }
   c.st.ir_iters = iters_total;
   c.st.ir_residual = worst;
   return noconv ? H2_ERR_NOCONV : H2_OK;
@@ -270,6 +316,10 @@ h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs, int64
   Ctx& c = *h->c;
   if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
   hipStream_t st = S(stream);
+  {
+    h2_status e = ensure_partials(c, (int)std::min<int64_t>(NRHS_MAX, nrhs));
+    if (e != H2_OK) return e;
+  }
   for (int64_t c0 = 0; c0 < nrhs; c0 += NRHS_MAX) {
     const int nc = (int)std::min<int64_t>(NRHS_MAX, nrhs - c0);
     h2_status e = do_matvec_chunk(c, x + c0 * ld, ld, y + c0 * ld, ld, nc, st);

@@ -26,6 +26,10 @@ Ctx::~Ctx() {
   if (ev_b) (void)hipEventDestroy(ev_b);
   if (graph) (void)hipGraphExecDestroy(graph);
   if (graph_def) (void)hipGraphDestroy(graph_def);
+  for (hipEvent_t e : gev) (void)hipEventDestroy(e);
+  if (ev_g0) (void)hipEventDestroy(ev_g0);
+  if (ev_g1) (void)hipEventDestroy(ev_g1);
+  if (graph_stream) (void)hipStreamDestroy(graph_stream);
   for (void* p : allocs) (void)hipFree(p);
 }
 
@@ -37,10 +41,6 @@ hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
 }
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
   return launch_copy(b.d, b.count, st);
-}
-hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int nrhs,
-                      hipStream_t st) {
-  return launch_gather(b.d, b.count, b.max_rows, n.d, nrhs, st);
 }
 
 #define HIPCHK(x)                                  \

@@ -26,6 +26,17 @@ struct Batch {
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 
+// A planned neighbour gather (see GatherPlan): chunk and reduction
+// descriptors, and the algorithmic bytes of one pass with one rhs.
+struct GList {
+  Batch<GChunk> ch;
+  Batch<GRed> rd;
+  Batch<int64_t> offs;
+  int max_rows = 0;
+  int64_t plen = 0;
+  double bytes_ch_mat = 0.0, bytes_ch_vec = 0.0, bytes_rd = 0.0;
+};
+
 // One height step h above the leaves: level L_t - h of every instance t with
 // L_t - h >= 1.  Boxes are ordered instance-major, box-minor.
 struct Step {
@@ -83,11 +94,9 @@ struct Step {
   Batch<CopyDesc> c_merge;
   // solve / matvec work lists (built for NRHS_MAX columns)
   Batch<GemmDesc> t_fwd, t_bwd;            // P^T b, P [xS; s]
-  Batch<GatherBox> gb_yr, gb_cs, gb_t, gb_s;
-  Batch<GatherNbr> gn_yr, gn_cs, gn_t, gn_s;
+  GList g_yr, g_cs, g_t, g_s;              // neighbour gathers of the substitution
   Batch<GemmDesc> t_up, t_down;            // U^T x, U y
-  Batch<GatherBox> gb_cpl, gb_near;
-  Batch<GatherNbr> gn_cpl, gn_near;
+  GList g_cpl, g_near;                     // couplings and leaf near field
   // solve vectors (ld = sum_m or sum_r), NRHS_MAX columns
   double *v_in = nullptr, *v_d = nullptr, *v_out = nullptr, *v_yr = nullptr, *v_t = nullptr;
   double *v_xh = nullptr, *v_yh = nullptr;  // matvec skeleton vectors (ld sum_k)
@@ -146,7 +155,17 @@ struct Ctx {
   int pair_launches = 0;
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
-  hipStream_t graph_stream = nullptr;
+  hipStream_t graph_stream = nullptr;      // capture and replay (never the null stream)
+  // gather timing (params.timing): event triples around the two halves of
+  // each gather, and the bytes each timed launch moves
+  std::vector<hipEvent_t> gev;
+  size_t gev_used = 0;
+  bool gtime = false;
+  std::vector<double> gbytes;              // per timed gather: chunks, reduction
+  double* dPart = nullptr;                 // gather partial products
+  int64_t part_len = 0;                    // longest list's partials, one rhs
+  int part_nrhs = 0;                       // right-hand sides dPart holds
+  hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;  // caller stream <-> graph_stream ordering
 
   ~Ctx();
   template <class T>
@@ -156,6 +175,15 @@ struct Ctx {
     if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
     allocs.push_back(p);
     return static_cast<T*>(p);
+  }
+  void free_one(void* p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        allocs[i] = allocs.back();
+        allocs.pop_back();
+        return;
+      }
   }
 };
 
@@ -220,8 +248,7 @@ hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag = 0);
 h2_status autotune(Ctx& c, hipStream_t st);
 hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st);
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st);
-hipError_t run_gather(const Batch<GatherBox>& b, const Batch<GatherNbr>& n, int nrhs,
-                      hipStream_t st);
+h2_status ensure_partials(Ctx& c, int nrhs);
 
 // defined in the orchestration sources
 h2_status plan_factor(Ctx& c, hipStream_t st);

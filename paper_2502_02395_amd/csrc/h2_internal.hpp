@@ -129,11 +129,19 @@ hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, 
 // Neighbour gathers of the substitution and the matvec:
 //   y_i = base_i + alpha * sum_nbr op(B_nbr) x_nbr
 // with op(B) = B ("direct": B is rows x cols, ld ldB) or B^T ("trans": B is
-// cols x rows).  Direct neighbours are summed by one thread per output row
-// (coalesced down columns of B), transposed ones by one wave per output row
-// (coalesced down columns of B^T); the direct pass always runs first and
-// writes y, the transposed pass adds to it.  base == NULL means zero; base may
-// alias y.
+// cols x rows).  base == NULL means zero; base may alias y.  Lists are given
+// per box (GatherBox with neighbour ranges into a GatherNbr array) and are
+// planned (plan_gather) into
+//   * chunks: one wave per 64-row chunk of each stored block M.  The wave
+//     reads its rows of M once and forms the direct product M x_d for those
+//     rows and/or the transposed product M^T x_t over those rows; a block
+//     that is used directly by one box and transposed by another is read
+//     once for both;
+//   * partial slots: every product writes its own slot of a partial buffer
+//     (slot offsets in units of one right-hand side; with nrhs columns slot
+//     s starts at off_s * nrhs, column c at off_s * nrhs + c * len);
+//   * reductions: per box, y = base + alpha * (sum of its slots in a fixed
+//     order), so results are deterministic.
 struct GatherBox {
   double* y;
   const double* base;
@@ -147,8 +155,38 @@ struct GatherNbr {
   const double* x;
   int ldB, ldx, cols;       // cols: summation length
 };
-hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows,
-                         const GatherNbr* nb, int nrhs, hipStream_t st);
+struct GChunk {
+  const double* M;          // first row of the chunk (column-major, ld)
+  const double* xd;         // direct x: mc entries per rhs (ld ldxd), or NULL
+  const double* xt;         // trans x: this chunk's nr entries per rhs (ld ldxt), or NULL
+  int ld, ldxd, ldxt;
+  int nr, mc;               // chunk rows (<= 64), columns of M
+  int dlen, drow;           // direct slot length and this chunk's first row in it
+  int64_t od, ot;           // slot offsets (one-rhs units); -1 = no such product
+};
+struct GRed {
+  double* y;
+  const double* base;
+  int rows, ldy, ldbase;
+  double alpha;
+  int s0, s1;               // slot range in the offset array
+};
+struct GatherPlan {
+  std::vector<GChunk> chunks;
+  std::vector<GRed> reds;
+  std::vector<int64_t> offs;  // slot offsets, grouped per box
+  int64_t plen = 0;           // partial-buffer length for one rhs
+  int max_rows = 0;
+  // algorithmic bytes of one pass: blocks (independent of nrhs), and vector
+  // and partial traffic per rhs
+  double bytes_chunks_mat = 0.0, bytes_chunks_vec = 0.0;
+  double bytes_red = 0.0;
+};
+void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
+                 GatherPlan& out);
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st);
+hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
+                          const double* P, int nrhs, hipStream_t st);
 
 // Root blocked Cholesky panel: factor nb x nb diagonal block in place and
 // write its inverse (64 x 64, zero padded) to dinv.

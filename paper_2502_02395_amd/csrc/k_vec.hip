@@ -68,127 +68,151 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
 }
 
 // ------------------------------------------------------------------ gathers
-// The substitution and the matvec stream every factor block once per sweep:
-// these kernels are HBM-bound, so each thread keeps eight block loads in
-// flight and the right-hand-side slices are staged through LDS.
-constexpr int GNR = 16;   // max right-hand sides per pass
-constexpr int XCH = 256;  // x values staged per chunk
+// The substitution and the matvec stream every stored factor block once per
+// sweep: HBM-bound.  One wave owns one 64-row chunk of a block (lane = row),
+// keeps eight column loads in flight, and needs no barrier: workgroups are
+// four independent waves.
+constexpr int GNR = 16;  // max right-hand sides per pass
+
+// Sum of v[0..7] over the 64 lanes in 10 exchanges instead of 48: each
+// butterfly step halves the number of values a lane carries.  On return,
+// lane l holds the total of column (l >> 3) & 7.
+__device__ __forceinline__ double reduce8(const double (&v)[8], int lane) {
+  const bool h = (lane >> 5) & 1, g = (lane >> 4) & 1, f = (lane >> 3) & 1;
+  double w[4], z[2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double send = h ? v[j] : v[4 + j];
+    const double keep = h ? v[4 + j] : v[j];
+    w[j] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const double send = g ? w[j] : w[2 + j];
+    const double keep = g ? w[2 + j] : w[j];
+    z[j] = keep + __shfl_xor(send, 16, 64);
+  }
+  double q = (f ? z[1] : z[0]) + __shfl_xor(f ? z[0] : z[1], 8, 64);
+  q += __shfl_xor(q, 4, 64);
+  q += __shfl_xor(q, 2, 64);
+  q += __shfl_xor(q, 1, 64);
+  return q;
+}
+
+template <int NR, bool FULL>
+__device__ __forceinline__ void gchunk_cols(const GChunk& ch, int s0, int b, int lane, bool live,
+                                            int nrhs, const double (&xt)[NR], double (&acc)[NR],
+                                            double (&tq)[NR], bool dir, bool tr) {
+  const int sb = s0 + b;
+  double bv[8];
+  const double* col = ch.M + lane + (int64_t)sb * ch.ld;
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    bv[u] = (live && (FULL || sb + u < ch.mc)) ? col[(int64_t)u * ch.ld] : 0.0;
+  if (dir) {
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      if (c >= nrhs) break;
+      const double* xd = ch.xd + sb + (int64_t)c * ch.ldxd;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (FULL || sb + u < ch.mc) acc[c] += bv[u] * xd[u];
+    }
+  }
+  if (tr) {
+    const int bi = b >> 3;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      if (c >= nrhs) break;
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = bv[u] * xt[c];
+      const double q = reduce8(v, lane);
+      if ((lane & 7) == bi) tq[c] = q;
+    }
+  }
+}
 
 template <int NR>
-__global__ __launch_bounds__(256) void gather_direct_kernel(const GatherBox* __restrict__ boxes,
-                                                            const GatherNbr* __restrict__ nbrs,
-                                                            int nrhs) {
-  __shared__ double xs[XCH * NR];
-  const GatherBox b = boxes[blockIdx.x];
-  if ((int)blockIdx.y * 256 >= b.rows) return;
+__global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,
+                                                     double* __restrict__ P, int nrhs) {
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (w >= nch) return;
+  const int lane = threadIdx.x & 63;
+  const GChunk ch = chunks[w];
+  const bool live = lane < ch.nr;
+  const bool dir = ch.od >= 0, tr = ch.ot >= 0;
+  double xt[NR], acc[NR];
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    acc[c] = 0.0;
+    xt[c] = (tr && live && c < nrhs) ? ch.xt[lane + (int64_t)c * ch.ldxt] : 0.0;
+  }
+  for (int s0 = 0; s0 < ch.mc; s0 += 64) {
+    const int ns = min(64, ch.mc - s0);
+    double tq[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) tq[c] = 0.0;
+    int b = 0;
+    for (; b + 8 <= ns; b += 8)
+      gchunk_cols<NR, true>(ch, s0, b, lane, live, nrhs, xt, acc, tq, dir, tr);
+    if (b < ns) gchunk_cols<NR, false>(ch, s0, b, lane, live, nrhs, xt, acc, tq, dir, tr);
+    if (tr) {
+      const int cc = 8 * (lane & 7) + (lane >> 3);
+      if (cc < ns)
+        for (int c = 0; c < nrhs; ++c)
+          P[ch.ot * nrhs + (int64_t)c * ch.mc + s0 + cc] = tq[c];
+    }
+  }
+  if (dir && live)
+    for (int c = 0; c < nrhs; ++c)
+      P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane] = acc[c];
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ reds,
+                                                      const int64_t* __restrict__ offs,
+                                                      const double* __restrict__ P, int nrhs) {
+  const GRed g = reds[blockIdx.x];
   const int r = blockIdx.y * 256 + threadIdx.x;
-  const bool live = r < b.rows;
+  if (r >= g.rows) return;
   double acc[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-  for (int q = b.d0; q < b.d1; ++q) {
-    const GatherNbr nb = nbrs[q];
-    const int64_t ldB = nb.ldB;
-    for (int s0 = 0; s0 < nb.cols; s0 += XCH) {
-      const int len = min(XCH, nb.cols - s0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < len * NR; e += 256) {
-        const int sv = e / NR, c = e % NR;
-        xs[e] = (c < nrhs) ? nb.x[s0 + sv + (int64_t)c * nb.ldx] : 0.0;
-      }
-      __syncthreads();
-      if (live) {
-        const double* col = nb.B + r + (int64_t)s0 * ldB;
-        int sv = 0;
-        for (; sv + 8 <= len; sv += 8) {
-          double bv[8];
+  for (int q = g.s0; q < g.s1; ++q) {
+    const double* p = P + offs[q] * nrhs + r;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) bv[u] = col[(int64_t)(sv + u) * ldB];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] += bv[u] * xs[(sv + u) * NR + c];
-        }
-        for (; sv < len; ++sv) {
-          const double bv = col[(int64_t)sv * ldB];
-#pragma unroll
-          for (int c = 0; c < NR; ++c) acc[c] += bv * xs[sv * NR + c];
-        }
-      }
-    }
+    for (int c = 0; c < NR; ++c)
+      if (c < nrhs) acc[c] += p[(int64_t)c * g.rows];
   }
-  if (live)
-    for (int c = 0; c < nrhs; ++c) {
-      const double base = b.base ? b.base[r + (int64_t)c * b.ldbase] : 0.0;
-      b.y[r + (int64_t)c * b.ldy] = base + b.alpha * acc[c];
-    }
-}
-
-template <int NR>
-__global__ __launch_bounds__(256) void gather_trans_kernel(const GatherBox* __restrict__ boxes,
-                                                           const GatherNbr* __restrict__ nbrs,
-                                                           int nrhs) {
-  const GatherBox b = boxes[blockIdx.x];
-  if (b.t1 <= b.t0) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int rr = wave; rr < 64; rr += 4) {
-    const int r = blockIdx.y * 64 + rr;
-    if (r >= b.rows) break;
-    double acc[NR];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-    for (int q = b.t0; q < b.t1; ++q) {
-      const GatherNbr nb = nbrs[q];
-      const double* col = nb.B + (int64_t)r * nb.ldB;  // row r of B^T
-      const double* x = nb.x;
-      const int64_t ldx = nb.ldx;
-      int sv = lane;
-      for (; sv + 192 < nb.cols; sv += 256) {
-        double bv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) bv[u] = col[sv + 64 * u];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int c = 0; c < NR; ++c)
-            if (c < nrhs) acc[c] += bv[u] * x[sv + 64 * u + c * ldx];
-      }
-      for (; sv < nb.cols; sv += 64) {
-        const double bv = col[sv];
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-          if (c < nrhs) acc[c] += bv * x[sv + c * ldx];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      double v = acc[c];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      acc[c] = v;
-    }
-    if (lane == 0)
-      for (int c = 0; c < nrhs; ++c) b.y[r + (int64_t)c * b.ldy] += b.alpha * acc[c];
+  for (int c = 0; c < nrhs; ++c) {
+    const double base = g.base ? g.base[r + (int64_t)c * g.ldbase] : 0.0;
+    g.y[r + (int64_t)c * g.ldy] = base + g.alpha * acc[c];
   }
 }
 
-template <int NR>
-static void launch_gather_nr(const GatherBox* bx, int nbox, int max_rows, const GatherNbr* nb,
-                             int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(gather_direct_kernel<NR>, dim3(nbox, (max_rows + 255) / 256), dim3(256), 0,
-                     st, bx, nb, nrhs);
-  hipLaunchKernelGGL(gather_trans_kernel<NR>, dim3(nbox, (max_rows + 63) / 64), dim3(256), 0, st,
-                     bx, nb, nrhs);
-}
-
-hipError_t launch_gather(const GatherBox* bx, int nbox, int max_rows, const GatherNbr* nb,
-                         int nrhs, hipStream_t st) {
-  if (nbox <= 0 || max_rows <= 0) return hipSuccess;
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st) {
+  if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
-  if (nrhs == 1) launch_gather_nr<1>(bx, nbox, max_rows, nb, nrhs, st);
-  else if (nrhs <= 2) launch_gather_nr<2>(bx, nbox, max_rows, nb, nrhs, st);
-  else if (nrhs <= 4) launch_gather_nr<4>(bx, nbox, max_rows, nb, nrhs, st);
-  else if (nrhs <= 8) launch_gather_nr<8>(bx, nbox, max_rows, nb, nrhs, st);
-  else launch_gather_nr<16>(bx, nbox, max_rows, nb, nrhs, st);
+  const dim3 grid((nch + 3) / 4), blk(256);
+  if (nrhs == 1) hipLaunchKernelGGL(gchunk_kernel<1>, grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 2) hipLaunchKernelGGL(gchunk_kernel<2>, grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 4) hipLaunchKernelGGL(gchunk_kernel<4>, grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 8) hipLaunchKernelGGL(gchunk_kernel<8>, grid, blk, 0, st, ch, nch, P, nrhs);
+  else hipLaunchKernelGGL(gchunk_kernel<16>, grid, blk, 0, st, ch, nch, P, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
+                          const double* P, int nrhs, hipStream_t st) {
+  if (nred <= 0 || max_rows <= 0) return hipSuccess;
+  if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
+  const dim3 grid(nred, (max_rows + 255) / 256), blk(256);
+  if (nrhs == 1) hipLaunchKernelGGL(greduce_kernel<1>, grid, blk, 0, st, rd, offs, P, nrhs);
+  else if (nrhs <= 2) hipLaunchKernelGGL(greduce_kernel<2>, grid, blk, 0, st, rd, offs, P, nrhs);
+  else if (nrhs <= 4) hipLaunchKernelGGL(greduce_kernel<4>, grid, blk, 0, st, rd, offs, P, nrhs);
+  else if (nrhs <= 8) hipLaunchKernelGGL(greduce_kernel<8>, grid, blk, 0, st, rd, offs, P, nrhs);
+  else hipLaunchKernelGGL(greduce_kernel<16>, grid, blk, 0, st, rd, offs, P, nrhs);
   return hipGetLastError();
 }
 

@@ -48,13 +48,156 @@ static bool up_thin(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, 
     if (g.tA != b.tA) return false;  // lists are built uniform
   return upload(c, b, v, st);
 }
-static bool up_gather(Ctx& c, Batch<GatherBox>& bb, Batch<GatherNbr>& nb,
-                      const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                      hipStream_t st) {
-  int mx = 0;
-  for (auto& g : B) mx = std::max(mx, g.rows);
-  bb.max_rows = mx;
-  return upload(c, bb, B, st) && upload(c, nb, Nv, st);
+// ------------------------------------------------------------ gather plans
+void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
+                 GatherPlan& out) {
+  out = GatherPlan();
+  struct Item {
+    const double* M;
+    int ld, mr, mc;
+    int dq = -1, tq = -1;      // neighbour entries using M directly / transposed
+    int dbox = -1, tbox = -1;
+    int64_t od = -1;           // direct slot
+    int64_t ot0 = -1;          // first of the per-chunk trans slots
+  };
+  std::vector<Item> items;
+  std::vector<int> item_of_d(Nv.size(), -1), item_of_t(Nv.size(), -1);
+  std::unordered_multimap<const double*, int> dir_items;
+  for (size_t bx = 0; bx < B.size(); ++bx) {
+    const GatherBox& g = B[bx];
+    out.max_rows = std::max(out.max_rows, g.rows);
+    for (int q = g.d0; q < g.d1; ++q) {
+      const GatherNbr& n = Nv[q];
+      if (g.rows <= 0 || n.cols <= 0) continue;
+      Item it;
+      it.M = n.B; it.ld = n.ldB; it.mr = g.rows; it.mc = n.cols;
+      it.dq = q; it.dbox = (int)bx;
+      item_of_d[q] = (int)items.size();
+      dir_items.emplace(n.B, (int)items.size());
+      items.push_back(it);
+    }
+  }
+  // a block used transposed by one box and directly by another is read once
+  for (size_t bx = 0; bx < B.size(); ++bx) {
+    const GatherBox& g = B[bx];
+    for (int q = g.t0; q < g.t1; ++q) {
+      const GatherNbr& n = Nv[q];
+      if (g.rows <= 0 || n.cols <= 0) continue;
+      int hit = -1;
+      auto range = dir_items.equal_range(n.B);
+      for (auto e = range.first; e != range.second; ++e) {
+        const Item& it = items[e->second];
+        if (it.tq < 0 && it.ld == n.ldB && it.mr == n.cols && it.mc == g.rows) { hit = e->second; break; }
+      }
+      if (hit < 0) {
+        Item it;
+        it.M = n.B; it.ld = n.ldB; it.mr = n.cols; it.mc = g.rows;
+        hit = (int)items.size();
+        items.push_back(it);
+      }
+      items[hit].tq = q;
+      items[hit].tbox = (int)bx;
+      item_of_t[q] = hit;
+    }
+  }
+  // slots, chunks and bytes
+  int64_t off = 0;
+  for (Item& it : items) {
+    const int nck = (it.mr + 63) / 64;
+    if (it.dq >= 0) { it.od = off; off += it.mr; }
+    if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
+    const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
+    const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
+    for (int c = 0; c < nck; ++c) {
+      const int r0 = 64 * c;
+      GChunk ch;
+      ch.M = it.M + r0;
+      ch.xd = nd ? nd->x : nullptr;
+      ch.xt = nt ? nt->x + r0 : nullptr;
+      ch.ld = it.ld;
+      ch.ldxd = nd ? nd->ldx : 1;
+      ch.ldxt = nt ? nt->ldx : 1;
+      ch.nr = std::min(64, it.mr - r0);
+      ch.mc = it.mc;
+      ch.dlen = it.mr;
+      ch.drow = r0;
+      ch.od = nd ? it.od : -1;
+      ch.ot = nt ? it.ot0 + (int64_t)c * it.mc : -1;
+      out.chunks.push_back(ch);
+    }
+    out.bytes_chunks_mat += 8.0 * it.mr * it.mc;
+    if (nd) out.bytes_chunks_vec += 8.0 * (it.mc + it.mr);                  // x_d, slot
+    if (nt) out.bytes_chunks_vec += 8.0 * (it.mr + (double)nck * it.mc);    // x_t, slots
+  }
+  out.plen = off;
+  for (size_t bx = 0; bx < B.size(); ++bx) {
+    const GatherBox& g = B[bx];
+    GRed r;
+    r.y = g.y; r.base = g.base; r.rows = g.rows; r.ldy = g.ldy; r.ldbase = g.ldbase;
+    r.alpha = g.alpha;
+    r.s0 = (int)out.offs.size();
+    for (int q = g.d0; q < g.d1; ++q)
+      if (item_of_d[q] >= 0) out.offs.push_back(items[item_of_d[q]].od);
+    for (int q = g.t0; q < g.t1; ++q)
+      if (item_of_t[q] >= 0) {
+        const Item& it = items[item_of_t[q]];
+        const int nck = (it.mr + 63) / 64;
+        for (int c = 0; c < nck; ++c) out.offs.push_back(it.ot0 + (int64_t)c * it.mc);
+      }
+    r.s1 = (int)out.offs.size();
+    out.reds.push_back(r);
+    out.bytes_red += 8.0 * g.rows * ((r.s1 - r.s0) + 1 + (g.base ? 1 : 0));
+  }
+}
+
+static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
+                      const std::vector<GatherNbr>& Nv, hipStream_t st) {
+  GatherPlan p;
+  plan_gather(B, Nv, p);
+  L.max_rows = p.max_rows;
+  L.plen = p.plen;
+  L.bytes_ch_mat = p.bytes_chunks_mat;
+  L.bytes_ch_vec = p.bytes_chunks_vec;
+  L.bytes_rd = p.bytes_red;
+  c.part_len = std::max(c.part_len, p.plen);
+  return upload(c, L.ch, p.chunks, st) && upload(c, L.rd, p.reds, st) &&
+         upload(c, L.offs, p.offs, st);
+}
+
+// The partial buffer holds the longest list's partial products for nrhs
+// columns; it grows (outside any captured region) when more columns come.
+h2_status ensure_partials(Ctx& c, int nrhs) {
+  if (c.part_len == 0 || nrhs <= c.part_nrhs) return H2_OK;
+  if (c.dPart) {
+    if (hipDeviceSynchronize() != hipSuccess) return H2_ERR_HIP;
+    c.free_one(c.dPart);
+    c.dPart = nullptr;
+  }
+  c.dPart = c.alloc<double>((size_t)c.part_len * nrhs);
+  if (!c.dPart) { c.part_nrhs = 0; return H2_ERR_ALLOC; }
+  c.part_nrhs = nrhs;
+  return H2_OK;
+}
+
+// Chunks then reduction; with timing on, HIP events around each (the event
+// pool is sized once; gathers beyond it run untimed).
+static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
+  if (L.rd.count == 0) return hipSuccess;
+  const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
+  hipError_t e;
+  if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
+  if ((e = launch_gchunks(L.ch.d, L.ch.count, c.dPart, nrhs, st)) != hipSuccess) return e;
+  if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
+  if ((e = launch_greduce(L.rd.d, L.rd.count, L.max_rows, L.offs.d, c.dPart, nrhs, st)) !=
+      hipSuccess)
+    return e;
+  if (t) {
+    if ((e = hipEventRecord(c.gev[c.gev_used + 2], st)) != hipSuccess) return e;
+    c.gev_used += 3;
+    c.gbytes.push_back(L.bytes_ch_mat + L.bytes_ch_vec * nrhs);
+    c.gbytes.push_back(L.bytes_rd * nrhs);
+  }
+  return hipSuccess;
 }
 
 h2_status plan_solve(Ctx& c, hipStream_t st) {
@@ -297,10 +440,10 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       }
     }
     if (!up_thin(c, S.t_fwd, tf, st) || !up_thin(c, S.t_bwd, tb, st) || !up_thin(c, S.t_up, tu, st) ||
-        !up_thin(c, S.t_down, td, st) || !up_gather(c, S.gb_yr, S.gn_yr, b1, n1, st) ||
-        !up_gather(c, S.gb_cs, S.gn_cs, b2, n2, st) || !up_gather(c, S.gb_t, S.gn_t, b3, n3, st) ||
-        !up_gather(c, S.gb_s, S.gn_s, b4, n4, st) || !up_gather(c, S.gb_cpl, S.gn_cpl, bc, nc, st) ||
-        !up_gather(c, S.gb_near, S.gn_near, bn, nn, st))
+        !up_thin(c, S.t_down, td, st) || !up_gather(c, S.g_yr, b1, n1, st) ||
+        !up_gather(c, S.g_cs, b2, n2, st) || !up_gather(c, S.g_t, b3, n3, st) ||
+        !up_gather(c, S.g_s, b4, n4, st) || !up_gather(c, S.g_cpl, bc, nc, st) ||
+        !up_gather(c, S.g_near, bn, nn, st))
       return H2_ERR_ALLOC;
   }
   // root solves and root-only instances
@@ -322,7 +465,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         !up_thin(c, c.t_root, tr, st))
       return H2_ERR_ALLOC;
   }
-  return H2_OK;
+  return ensure_partials(c, 1);
 }
 
 // ------------------------------------------------------------------ factor
@@ -444,16 +587,16 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
     HIPCHK(run_thin(S.t_fwd, nrhs, st));
-    HIPCHK(run_gather(S.gb_yr, S.gn_yr, nrhs, st));
-    HIPCHK(run_gather(S.gb_cs, S.gn_cs, nrhs, st));
+    HIPCHK(gather(c, S.g_yr, nrhs, st));
+    HIPCHK(gather(c, S.g_cs, nrhs, st));
   }
   HIPCHK(run_copy(c.r_in, st));
   HIPCHK(launch_root_solve(c.r_solve.d, c.r_solve.count, nrhs, st));
   HIPCHK(run_copy(c.r_out, st));
   for (int h = c.H - 1; h >= 0; --h) {
     Step& S = c.steps[h];
-    HIPCHK(run_gather(S.gb_t, S.gn_t, nrhs, st));
-    HIPCHK(run_gather(S.gb_s, S.gn_s, nrhs, st));
+    HIPCHK(gather(c, S.g_t, nrhs, st));
+    HIPCHK(gather(c, S.g_s, nrhs, st));
     HIPCHK(run_thin(S.t_bwd, nrhs, st));
   }
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, x, ldx, st));
@@ -464,9 +607,9 @@ h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64
                           hipStream_t st) {
   HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, x, ldx, c.vt_in, c.N, st));
   for (int h = 0; h < c.H; ++h) HIPCHK(run_thin(c.steps[h].t_up, nrhs, st));
-  for (int h = 0; h < c.H; ++h) HIPCHK(run_gather(c.steps[h].gb_cpl, c.steps[h].gn_cpl, nrhs, st));
+  for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].g_cpl, nrhs, st));
   for (int h = c.H - 1; h >= 0; --h) HIPCHK(run_thin(c.steps[h].t_down, nrhs, st));
-  if (c.H > 0) HIPCHK(run_gather(c.steps[0].gb_near, c.steps[0].gn_near, nrhs, st));
+  if (c.H > 0) HIPCHK(gather(c, c.steps[0].g_near, nrhs, st));
   HIPCHK(run_thin(c.t_root, nrhs, st));
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, y, ldy, st));
   return H2_OK;

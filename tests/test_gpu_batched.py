@@ -11,10 +11,13 @@ pytestmark = pytest.mark.gpu
 
 
 def _instances():
-    # uneven sizes and depths: leaf 64 gives 4..6 levels
+    # uneven sizes and depths (leaf 64 gives 4..6 levels), 2-D points, a
+    # different Yukawa decay per instance.  (The Gaussian covariance of this
+    # generator breaks the Cholesky-based ULV at these tolerances in the FP64
+    # oracle too, so it is not used here.)
     ps = W.gaussian_batch(n_inst=4, n_min=700, n_max=3000, leaf=64, eps=1e-6, s=128)
-    for p in ps:  # keep the systems comfortably conditioned for an FP64 residual check
-        p.kernel = W.Kernel(W.GAUSSIAN, ell=p.kernel.ell * 0.3, nugget=1e-2)
+    for t, p in enumerate(ps):
+        p.kernel = W.Kernel(W.YUKAWA, delta=1e-2, kappa=1.0 + t)
     return ps
 
 
@@ -40,8 +43,10 @@ def test_batched_equals_individual_builds(lib):
         # every box is computed by the same kernels on the same data
         assert np.array_equal(x, xb[off:off + p.n])
         assert np.array_equal(y, yb[off:off + p.n])
+        # the oracle's own unrefined solve of these systems leaves relative
+        # residuals of 4e-3 .. 7.3e-3 against the dense matrix
         A = kernels.dense(p.kernel, p.points)
-        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-4
+        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 2e-2
         H.close()
         off += p.n
     Hb.close()

@@ -94,7 +94,15 @@ def test_same_h2_solve_matches_oracle(lib, name):
         rg = H.root()
         ev_o = np.linalg.eigvalsh((ro + ro.T) / 2)
         ev_g = np.linalg.eigvalsh((rg + rg.T) / 2)
-        assert np.allclose(ev_g, ev_o, rtol=1e-9, atol=1e-11 * np.abs(ev_o).max() * np.sqrt(len(ev_o)))
+        # Weyl: |d lambda_i| <= ||root_gpu - root_oracle||_2.  Unlike x, the
+        # root is expressed in the skeleton bases, and the interpolation
+        # coefficients T = R_11^{-1} R_12 solve a system whose retained pivots
+        # go down to eps |R_00|: rounding differences in the sample matrix can
+        # move T (hence the root) by up to u / eps relative, even when the H^2
+        # operator itself agrees to 1e-12.
+        dev = np.abs(ev_g - ev_o).max() / np.abs(ev_o).max()
+        tol_root = max(tol, np.finfo(float).eps / p.eps)
+        assert dev < tol_root, (dev, kappa, tol_root)
     H.close()
 
 
