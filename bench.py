@@ -22,6 +22,28 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector = matrix)
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
+# second run, WRITE_SIZE on this workload (one factor + one solve), each scaled
+# by the counter's reading for a plain 1 GiB device copy (FETCH_SIZE reads half
+# of the bytes moved: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for the
+# kernel source they were taken on: a changed source reports null.
+MEASURED_TRAFFIC = {
+    "gchunk_kernel": {"src": "paper_2502_02395_amd/csrc/k_gather.hip",
+                      "sha256": "1708905bd655a4d2ce0750895463ad33a0fdd3b158cce1a5de8aaa82f0357b57",
+                      "bytes_per_launch": 2.237e9 + 0.033e9},
+}
+
+
+def measured_traffic(kernel: str):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(kernel)
+    if m is None:
+        return None
+    with open(os.path.join(ROOT, m["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
+            return None
+    return m["bytes_per_launch"]
+
 
 def workload(n: int, kernel: str, eps: float, leaf: int, s: int):
     import workloads as W
@@ -83,7 +105,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--s", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (the reference for "
@@ -220,6 +242,8 @@ def main():
                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                       "launches": n_g[q], "avg_launch_ms": 1e3 * t_g[q] / n_g[q],
                       "bytes_per_launch": b_g[q] / n_g[q], "total_s": t_g[q]})
+    for d in cands:
+        d["traffic"] = measured_traffic(d["kernel"])
     cands.sort(key=lambda d: -d["total_s"])
     out["roofline"] = cands[0]
     out["roofline_other"] = cands[1:]
