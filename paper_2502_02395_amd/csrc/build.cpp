@@ -36,9 +36,6 @@ Ctx::~Ctx() {
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
   return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
 }
-hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st) {
-  return launch_thin(b.d, b.count, b.max_rows, ncols, b.tA, st);
-}
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
   return launch_copy(b.d, b.count, st);
 }
@@ -91,9 +88,9 @@ static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st) {
   TmpBuf tb1, tb2;
   GemmDesc* d = nullptr;
   int* t = nullptr;
-  auto toff = gemm_tiles(g);
-  if (!upload_tmp(tb1, d, g, st) || !upload_tmp(tb2, t, toff, st)) return H2_ERR_ALLOC;
-  HIPCHK(launch_gemm(d, t, (int)g.size(), toff.back(), st, 0, 0, g[0].tA, g[0].tB));
+  auto tmap = gemm_tile_map(g, GEMM_BM[0], GEMM_BN[0]);
+  if (!upload_tmp(tb1, d, g, st) || !upload_tmp(tb2, t, tmap, st)) return H2_ERR_ALLOC;
+  HIPCHK(launch_gemm(d, t, (int)g.size(), (int)(tmap.size() / 2), st, 0, 0, g[0].tA, g[0].tB));
   HIPCHK(hipStreamSynchronize(st));
   return H2_OK;
 }
@@ -591,7 +588,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       const int r = S.m[b] - S.k[b];
       S.rkoff[b + 1] = S.rkoff[b] + (int64_t)S.k[b] * S.k[b];
       S.lioff[b + 1] = S.lioff[b] + (int64_t)r * r;
-      if (S.k[b] > QR_KMAX || S.m[b] > QR_MMAX) return H2_ERR_UNSUPPORTED;
+      if (S.m[b] > QR_MMAX) return H2_ERR_UNSUPPORTED;
     }
     const int64_t q = S.qoff[nb];
     S.dQ = c.alloc<double>(q); S.dP = c.alloc<double>(q); S.dTA = c.alloc<double>(q);
@@ -786,7 +783,29 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         return H2_ERR_ALLOC;
     }
     S.qr.max_rows = 0;
-    for (auto& q : qr) S.qr.max_rows = std::max(S.qr.max_rows, q.m);
+    S.max_k = 0;
+    for (auto& q : qr) {
+      S.qr.max_rows = std::max(S.qr.max_rows, q.m);
+      if (q.m > 0) S.max_k = std::max(S.max_k, q.k);
+    }
+    // T above its diagonal blocks: Y = T[0:q0,0:q0] G[0:q0,q] (into TB),
+    // T[0:q0,q] = -Y T_qq
+    const int nqb = (S.max_k + 63) / 64;
+    S.g_t1.assign(nqb, {});
+    S.g_t2.assign(nqb, {});
+    for (int qb = 1; qb < nqb; ++qb) {
+      const int q0 = 64 * qb;
+      std::vector<GemmDesc> t1, t2;
+      for (auto& q : qr) {
+        if (q.m == 0 || q.k <= q0) continue;
+        const int k = q.k, w = std::min(64, k - q0);
+        t1.push_back(gd(q.P, k, 0, q.P + (int64_t)q0 * k, k, 0, nullptr, 1, q.tmpB, q0, q0, w, q0,
+                        1.0, 0.0));
+        t2.push_back(gd(q.tmpB, q0, 0, q.P + q0 + (int64_t)q0 * k, k, 0, nullptr, 1,
+                        q.P + (int64_t)q0 * k, k, q0, w, w, -1.0, 0.0));
+      }
+      if (!up_g(S.g_t1[qb], t1) || !up_g(S.g_t2[qb], t2)) return H2_ERR_ALLOC;
+    }
   }
   // root plan: save, then blocked Cholesky panels
   {

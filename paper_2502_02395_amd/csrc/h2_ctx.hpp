@@ -14,11 +14,11 @@ namespace h2 {
 template <class T>
 struct Batch {
   T* d = nullptr;          // descriptors
-  int* toff = nullptr;     // tile prefix (GEMM / eval), count + 1 entries
+  int* toff = nullptr;     // eval: tile prefix (count + 1); GEMM: (item, tile) map of the shape in use
   int count = 0;
   int tiles = 0;
   int max_rows = 0;        // thin / gather: row extent for the grid
-  // GEMM batches: tile prefix of every tile shape, and the one in use
+  // GEMM batches: (item, tile) maps of every tile shape, and the one in use
   int* toffs[GEMM_NCFG] = {nullptr, nullptr, nullptr};
   int tiles_c[GEMM_NCFG] = {0, 0, 0};
   int cfg = 0;
@@ -77,6 +77,8 @@ struct Step {
   // factor work lists
   Batch<GemmDesc> g_w;                     // W = D_i U_i (upper steps)
   Batch<GemmDesc> g_qr1, g_qr2, g_qr3;     // compact-WY Q: V^T V, T V^T, -V (T V^T)
+  std::vector<Batch<GemmDesc>> g_t1, g_t2; // T blocks above the diagonal, per block column
+  int max_k = 0;
   Batch<CopyDesc> c_w;                     // W = U (leaf step)
   Batch<BoxDev> qr;
   Batch<GemmDesc> g_diag1, g_diag2;        // D_ii Q, Q^T (.)
@@ -93,9 +95,9 @@ struct Step {
   Batch<GemmDesc> g_far1, g_far2;          // R_i S_ij, (.) R_j^T into the parent
   Batch<CopyDesc> c_merge;
   // solve / matvec work lists (built for NRHS_MAX columns)
-  Batch<GemmDesc> t_fwd, t_bwd;            // P^T b, P [xS; s]
+  GList t_fwd, t_bwd;                      // P^T b, P [xS; s]
   GList g_yr, g_cs, g_t, g_s;              // neighbour gathers of the substitution
-  Batch<GemmDesc> t_up, t_down;            // U^T x, U y
+  GList t_up, t_down;                      // U^T x, U y
   GList g_cpl, g_near;                     // couplings and leaf near field
   // solve vectors (ld = sum_m or sum_r), NRHS_MAX columns
   double *v_in = nullptr, *v_d = nullptr, *v_out = nullptr, *v_yr = nullptr, *v_t = nullptr;
@@ -147,7 +149,7 @@ struct Ctx {
   // and root-only instances read and write them directly
   double *vt_in = nullptr, *vt_out = nullptr;
   Batch<CopyDesc> r_in, r_out;             // root-only instances <-> v_root
-  Batch<GemmDesc> t_root;                  // root-only instances: matvec
+  GList t_root;                            // root-only instances: matvec
   // refinement vectors (N x NRHS_MAX)
   double *w_x = nullptr, *w_r = nullptr, *w_z = nullptr, *w_p = nullptr, *w_q = nullptr, *w_t = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;  // pair-transform timing
@@ -209,15 +211,6 @@ bool upload(Ctx& c, Batch<T>& b, const std::vector<T>& v, hipStream_t st,
   return hipStreamSynchronize(st) == hipSuccess;
 }
 
-// Tile prefix for GEMM items (BM x BN tiles).
-inline std::vector<int> gemm_tiles(const std::vector<GemmDesc>& v, int BM = 64, int BN = 64) {
-  std::vector<int> off(v.size() + 1, 0);
-  for (size_t i = 0; i < v.size(); ++i) {
-    const int tm = (v[i].M + BM - 1) / BM, tn = (v[i].N + BN - 1) / BN;
-    off[i + 1] = off[i] + ((v[i].M > 0 && v[i].N > 0) ? tm * tn : 0);
-  }
-  return off;
-}
 
 // Upload a GEMM batch with the tile prefix of every tile shape (shape 0 in use).
 inline bool upload_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v,
@@ -246,7 +239,6 @@ inline GemmDesc gd(const double* A, int lda, int tA, const double* B, int ldb, i
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag = 0);
 // Time every tile shape on every factor GEMM batch and keep the fastest.
 h2_status autotune(Ctx& c, hipStream_t st);
-hipError_t run_thin(const Batch<GemmDesc>& b, int ncols, hipStream_t st);
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st);
 h2_status ensure_partials(Ctx& c, int nrhs);
 
@@ -271,17 +263,16 @@ inline bool upload_gemm(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>&
   b.tB = v[0].tB;
   for (auto& g : v)
     if (g.tA != b.tA || g.tB != b.tB) return false;  // lists are built uniform
-  auto t0 = gemm_tiles(v, GEMM_BM[0], GEMM_BN[0]);
-  if (!upload(c, b, v, st, &t0)) return false;
-  b.toffs[0] = b.toff;
-  b.tiles_c[0] = b.tiles;
-  for (int q = 1; q < GEMM_NCFG; ++q) {
-    auto tq = gemm_tiles(v, GEMM_BM[q], GEMM_BN[q]);
-    b.toffs[q] = c.alloc<int>(tq.size());
+  if (!upload(c, b, v, st)) return false;
+  for (int q = 0; q < GEMM_NCFG; ++q) {
+    const std::vector<int> map = gemm_tile_map(v, GEMM_BM[q], GEMM_BN[q]);
+    b.toffs[q] = c.alloc<int>(map.size());
     if (!b.toffs[q]) return false;
-    if (hipMemcpy(b.toffs[q], tq.data(), tq.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+    if (!map.empty() &&
+        hipMemcpy(b.toffs[q], map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice) !=
+            hipSuccess)
       return false;
-    b.tiles_c[q] = tq.back();
+    b.tiles_c[q] = (int)(map.size() / 2);
   }
   b.use(0);
   return true;

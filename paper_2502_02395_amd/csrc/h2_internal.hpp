@@ -64,7 +64,6 @@ struct BoxDev {
   double* tau;              // k Householder scalars
 };
 
-constexpr int QR_KMAX = 4096;  // rank limit of the QR kernels
 constexpr int QR_MMAX = 7680;  // row limit of the QR panel kernel
 
 // ------------------------------------------------------------- launch wrappers
@@ -76,13 +75,29 @@ constexpr int QR_MMAX = 7680;  // row limit of the QR panel kernel
 constexpr int GEMM_NCFG = 3;
 constexpr int GEMM_BM[GEMM_NCFG] = {64, 128, 128};
 constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128};
-// Every item of one launch must have the transposes tA, tB.
-hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
+// Every item of one launch must have the transposes tA, tB.  d_tile_map holds
+// two ints per output tile: the item and the tile's index within the item
+// (gemm_tile_map, for the launch's tile shape), so a workgroup finds its work
+// with one load.
+hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
                        int tiles, hipStream_t st, int tag, int cfg, int tA, int tB);
 // Same work lists in reduced precision (prec = H2_PREC_FP32 or H2_PREC_BF16,
-// FP32 accumulation, FP64 in and out); H2_PREC_FP64 forwards to launch_gemm.
-hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count,
+// FP32 accumulation, FP64 in and out), 64 x 64 tiles.
+hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int count,
                           int tiles, int prec, hipStream_t st, int tag, int tA, int tB);
+// Host: the (item, tile) map of a work list for BM x BN tiles.
+inline std::vector<int> gemm_tile_map(const std::vector<GemmDesc>& v, int BM, int BN) {
+  std::vector<int> map;
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (v[i].M <= 0 || v[i].N <= 0) continue;
+    const int nt = ((v[i].M + BM - 1) / BM) * ((v[i].N + BN - 1) / BN);
+    for (int t = 0; t < nt; ++t) {
+      map.push_back((int)i);
+      map.push_back(t);
+    }
+  }
+  return map;
+}
 hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
                        int tiles, const double* X, int dim, const KernelDev* kern,
                        hipStream_t st);
@@ -90,10 +105,11 @@ hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st);
 
 // QR of W (m x k) with R (k x k) and the full Q (m x m) in compact WY form:
 // qr_panel writes V (tmpA), tau and R; a GEMM writes G = V^T V into P;
-// qr_tbuild turns G into T in place; GEMMs write Q = -V (T V^T); qr_diag adds
-// the identity.  One workgroup per box.
+// qr_tdiag turns the diagonal 64-blocks of G into those of T in place and
+// GEMMs the blocks above them; GEMMs write Q = -V (T V^T); qr_diag adds the
+// identity.  One workgroup per box (per box and block for qr_tdiag).
 hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t st);
-hipError_t launch_qr_tbuild(const BoxDev* boxes, int nbox, hipStream_t st);
+hipError_t launch_qr_tdiag(const BoxDev* boxes, int nbox, int max_k, hipStream_t st);
 hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st);
 // Cholesky + explicit inverse of n x n SPD blocks: A (ld lda, destroyed),
 // Linv (n x n dense, zero upper triangle).  Breakdown: *fail = min(code).
@@ -121,10 +137,6 @@ hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps,
 // Write U for IDs whose rank exceeded the capacity given to cpqr_id.
 hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 
-// Thin products y = alpha op(A) x + beta y for ncols <= 16 columns (every
-// item's N is ignored); every item of one launch has the transpose tA.
-hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
-                       hipStream_t st);
 
 // Neighbour gathers of the substitution and the matvec:
 //   y_i = base_i + alpha * sum_nbr op(B_nbr) x_nbr

@@ -78,8 +78,9 @@ __device__ __forceinline__ double apply_reflector_wave(const double* vcol, doubl
 //   qr_panel   -- blocked right-looking factorization, one workgroup per box,
 //                 panels of up to QR_NB columns resident in LDS; writes V
 //                 explicitly (tmpA), tau, and R (Rf);
-//   qr_tbuild  -- T from G = V^T V (a batched GEMM writes G into P):
-//                 T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j];
+//   qr_tdiag   -- T from G = V^T V (a batched GEMM writes G into P):
+//                 T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j],
+//                 on the diagonal 64-blocks; GEMMs fill the blocks above;
 //   qr_diag    -- after the GEMMs Q = -V (T V^T): add the identity (k = 0
 //                 boxes get Q = I outright).
 constexpr int QR_PAN = 7680;  // LDS doubles holding one panel (60 KiB)
@@ -193,26 +194,48 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   }
 }
 
-__global__ __launch_bounds__(256) void qr_tbuild_kernel(const BoxDev* __restrict__ boxes) {
-  __shared__ double g[QR_KMAX];
+// Diagonal 64-blocks of T, one workgroup per (box, block q): with G_qq the
+// block of G = V^T V and tau the Householder scalars of its columns,
+// T_qq[0:j, j] = -tau_j T_qq[0:j, 0:j] G_qq[0:j, j] and T_qq[j, j] = tau_j.
+// T_qq overwrites G_qq; the rows below the block in its columns are zeroed.
+// The blocks above the diagonal follow by GEMMs,
+// T[0:q0, q] = -(T[0:q0, 0:q0] G[0:q0, q]) T_qq.
+__global__ __launch_bounds__(256) void qr_tdiag_kernel(const BoxDev* __restrict__ boxes) {
+  __shared__ double t[64 * 65];
+  __shared__ double gcol[64];
   const BoxDev b = boxes[blockIdx.x];
-  const int k = b.k;
-  if (k == 0 || b.m == 0) return;
-  double* T = b.P;  // k x k, ld k, holds G on entry
-  for (int j = 0; j < k; ++j) {
-    for (int i = threadIdx.x; i < j; i += 256) g[i] = T[i + (int64_t)j * k];
-    const double tj = b.tau[j];
+  const int k = b.k, q0 = 64 * blockIdx.y;
+  if (b.m == 0 || q0 >= k) return;
+  const int w = min(64, k - q0);
+  double* T = b.P + q0 + (int64_t)q0 * k;  // T_qq, ld k
+  for (int e = threadIdx.x; e < w * w; e += 256) {
+    const int i = e % w, j = e / w;
+    t[i + 65 * j] = T[i + (int64_t)j * k];
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    if ((int)threadIdx.x < j) gcol[threadIdx.x] = t[threadIdx.x + 65 * j];
     __syncthreads();
-    for (int i = threadIdx.x; i < k; i += 256) {
+    const double tj = b.tau[q0 + j];
+    for (int i = threadIdx.x; i < w; i += 256) {
       double v = (i == j) ? tj : 0.0;
       if (i < j) {
-        double s = 0.0;
-        for (int q = i; q < j; ++q) s += T[i + (int64_t)q * k] * g[q];
-        v = -tj * s;
+        double acc = 0.0;
+        for (int q = i; q < j; ++q) acc += t[i + 65 * q] * gcol[q];
+        v = -tj * acc;
       }
-      T[i + (int64_t)j * k] = v;
+      t[i + 65 * j] = v;
     }
     __syncthreads();
+  }
+  for (int e = threadIdx.x; e < w * w; e += 256) {
+    const int i = e % w, j = e / w;
+    T[i + (int64_t)j * k] = t[i + 65 * j];
+  }
+  const int below = k - q0 - w;
+  for (int e = threadIdx.x; e < below * w; e += 256) {
+    const int i = e % below, j = e / below;
+    T[w + i + (int64_t)j * k] = 0.0;
   }
 }
 
@@ -239,9 +262,9 @@ hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_qr_tbuild(const BoxDev* boxes, int nbox, hipStream_t st) {
-  if (nbox <= 0) return hipSuccess;
-  hipLaunchKernelGGL(qr_tbuild_kernel, dim3(nbox), dim3(256), 0, st, boxes);
+hipError_t launch_qr_tdiag(const BoxDev* boxes, int nbox, int max_k, hipStream_t st) {
+  if (nbox <= 0 || max_k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(qr_tdiag_kernel, dim3(nbox, (max_k + 63) / 64), dim3(256), 0, st, boxes);
   return hipGetLastError();
 }
 

@@ -8,8 +8,8 @@ namespace h2 {
 // ------------------------------------------------------------------ gathers
 // The substitution and the matvec stream every stored factor block once per
 // sweep: HBM-bound.  One wave owns one 64-row chunk of a block (lane = row),
-// keeps eight column loads in flight, and needs no barrier: workgroups are
-// four independent waves.
+// keeps sixteen column loads in flight (non-temporal: every block is read
+// once per pass), and needs no barrier: workgroups are four independent waves.
 constexpr int GNR = 16;  // max right-hand sides per pass
 
 // Sum of v[0..7] over the 64 lanes in 10 exchanges instead of 48: each
@@ -37,64 +37,87 @@ __device__ __forceinline__ double reduce8(const double (&v)[8], int lane) {
   return q;
 }
 
+// Global-address-space view of a pointer: plain global loads instead of
+// flat ones (the pointers arrive through descriptors).
+typedef const double __attribute__((address_space(1)))* gcptr;
+__device__ __forceinline__ gcptr as_global(const double* p) { return (gcptr)p; }
+
+// Value of v in lane l (l uniform), through the scalar unit.
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One batch of 16 columns starting at column sb (16 loads in flight per
+// lane); xv[c] holds x_d of the current 64 columns, one per lane, and bo is
+// the batch's first column within them.  Rows past the chunk read the chunk's last row (always in bounds);
+// their x_t is zero and their direct sums are never stored.
 template <int NR, bool FULL>
-__device__ __forceinline__ void gchunk_cols(const GChunk& ch, int s0, int b, int lane, bool live,
-                                            int nrhs, const double (&xt)[NR], double (&acc)[NR],
-                                            double (&tq)[NR], bool dir, bool tr) {
-  const int sb = s0 + b;
-  double bv[8];
-  const double* col = ch.M + lane + (int64_t)sb * ch.ld;
+__device__ __forceinline__ void gchunk_cols(gcptr col, int64_t ld, int sb, int mc, int lane,
+                                            int nrhs, const double (&xv)[NR], int bo,
+                                            const double (&xt)[NR], double (&acc)[NR],
+                                            double (&tq)[NR], bool dir, bool tr, int bi) {
+  double bv[16];
 #pragma unroll
-  for (int u = 0; u < 8; ++u)
-    bv[u] = (live && (FULL || sb + u < ch.mc)) ? col[(int64_t)u * ch.ld] : 0.0;
+  for (int u = 0; u < 16; ++u)
+    bv[u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col + (int64_t)u * ld) : 0.0;
   if (dir) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
-      const double* xd = ch.xd + sb + (int64_t)c * ch.ldxd;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (FULL || sb + u < ch.mc) acc[c] += bv[u] * xd[u];
+      for (int u = 0; u < 16; ++u)
+        if (FULL || sb + u < mc) acc[c] += bv[u] * bcast(xv[c], bo + u);
     }
   }
   if (tr) {
-    const int bi = b >> 3;
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
-      double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = bv[u] * xt[c];
-      const double q = reduce8(v, lane);
-      if ((lane & 7) == bi) tq[c] = q;
+      for (int h = 0; h < 2; ++h) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = bv[8 * h + u] * xt[c];
+        const double q = reduce8(v, lane);
+        if ((lane & 7) == bi + h) tq[c] = q;
+      }
     }
   }
 }
 
 template <int NR>
-__global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,
-                                                     double* __restrict__ P, int nrhs) {
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (w >= nch) return;
-  const int lane = threadIdx.x & 63;
-  const GChunk ch = chunks[w];
+__device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict__ P, int nrhs,
+                                           int lane) {
   const bool live = lane < ch.nr;
   const bool dir = ch.od >= 0, tr = ch.ot >= 0;
+  const int row = live ? lane : ch.nr - 1;
   double xt[NR], acc[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) {
     acc[c] = 0.0;
-    xt[c] = (tr && live && c < nrhs) ? ch.xt[lane + (int64_t)c * ch.ldxt] : 0.0;
+    xt[c] = (tr && live && c < nrhs) ? as_global(ch.xt)[lane + (int64_t)c * ch.ldxt] : 0.0;
   }
+  const int64_t ld = ch.ld;
+  const gcptr base = as_global(ch.M) + row;
   for (int s0 = 0; s0 < ch.mc; s0 += 64) {
     const int ns = min(64, ch.mc - s0);
-    double tq[NR];
+    double tq[NR], xv[NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c) tq[c] = 0.0;
+    for (int c = 0; c < NR; ++c) {
+      tq[c] = 0.0;
+      xv[c] = (dir && lane < ns && c < nrhs) ? as_global(ch.xd)[s0 + lane + (int64_t)c * ch.ldxd]
+                                             : 0.0;
+    }
     int b = 0;
-    for (; b + 8 <= ns; b += 8)
-      gchunk_cols<NR, true>(ch, s0, b, lane, live, nrhs, xt, acc, tq, dir, tr);
-    if (b < ns) gchunk_cols<NR, false>(ch, s0, b, lane, live, nrhs, xt, acc, tq, dir, tr);
+    for (; b + 16 <= ns; b += 16)
+      gchunk_cols<NR, true>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
+                            xt, acc, tq, dir, tr, b >> 3);
+    if (b < ns)
+      gchunk_cols<NR, false>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
+                             xt, acc, tq, dir, tr, b >> 3);
     if (tr) {
       const int cc = 8 * (lane & 7) + (lane >> 3);
       if (cc < ns)
@@ -105,6 +128,15 @@ __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ 
   if (dir && live)
     for (int c = 0; c < nrhs; ++c)
       P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane] = acc[c];
+}
+
+
+template <int NR>
+__global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,
+                                                     double* __restrict__ P, int nrhs) {
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (w >= nch) return;
+  gchunk_one<NR>(chunks[w], P, nrhs, threadIdx.x & 63);
 }
 
 template <int NR>

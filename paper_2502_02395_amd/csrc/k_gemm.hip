@@ -1,13 +1,14 @@
-// Batched variable-size FP64 GEMM on CDNA4 matrix cores, thin products for
-// the substitution, and batched block copies.
+// Batched variable-size FP64 GEMM on CDNA4 matrix cores and batched block
+// copies.
 //
 // The basis transforms of the ULV sweep (Algorithm 4: U_i^T A_ij V_j, the
 // diagonal transform and the Schur update of Eq. 21) are many independent
 // small dense products of uneven shape.  Instead of padding them to a common
 // size (the paper's choice for its vendor batched calls, Section 4.1), every
 // launch takes a work list of items of their own M, N, K, strides and
-// transposes; each workgroup computes one 64 x 64 tile of one item, found by a
-// binary search over the per-item tile prefix.
+// transposes; each workgroup computes one tile (64 x 64, 128 x 64 or
+// 128 x 128, chosen per list by the autotuner) of one item, found by a binary
+// search over the per-item tile prefix.
 #include "h2_internal.hpp"
 
 namespace h2 {
@@ -15,15 +16,6 @@ namespace h2 {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int TK = 16, LPAD = 1;
-
-__device__ __forceinline__ int find_item(const int* off, int count, int t) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {  // largest i with off[i] <= t
-    int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that
 // consecutive logical tiles (the tiles of one item, which share operands) run
@@ -40,14 +32,14 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 // operands) are compile-time so that every index is plain arithmetic.
 template <int BM, int BN, int TA, int TB>
 __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs,
-                                              const int* __restrict__ toff, int count, int tiles) {
+                                              const int* __restrict__ tmap, int tiles) {
   constexpr int MI = BM / 32, NJ = BN / 32;
   constexpr int QA = BM / 16, QB = BN / 16;  // operand elements per thread per K tile
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
-  const int item = find_item(toff, count, logical);
-  const GemmDesc d = descs[item];
-  const int t = logical - toff[item];
+  const int2 it = reinterpret_cast<const int2*>(tmap)[logical];
+  const GemmDesc d = descs[it.x];
+  const int t = it.y;
   const int tiles_m = (d.M + BM - 1) / BM;
   const int m0 = (t % tiles_m) * BM;
   const int n0 = (t / tiles_m) * BN;
@@ -147,169 +139,45 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
 // the near-pair basis transforms (the dominant cost) from every other product.
 template <int BM, int BN, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
-                                                       const int* __restrict__ toff, int count,
-                                                       int tiles) {
-  gemm_f64_body<BM, BN, TA, TB>(descs, toff, count, tiles);
+                                                       const int* __restrict__ tmap, int tiles) {
+  gemm_f64_body<BM, BN, TA, TB>(descs, tmap, tiles);
 }
 template <int BM, int BN, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_pair_kernel(const GemmDesc* __restrict__ descs,
-                                                            const int* __restrict__ toff,
-                                                            int count, int tiles) {
-  gemm_f64_body<BM, BN, TA, TB>(descs, toff, count, tiles);
+                                                            const int* __restrict__ tmap,
+                                                            int tiles) {
+  gemm_f64_body<BM, BN, TA, TB>(descs, tmap, tiles);
 }
 
 template <int BM, int BN, int TA, int TB>
-static void launch_cfg(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
-                       hipStream_t st, int tag) {
+static void launch_cfg(const GemmDesc* d_desc, const int* d_tile_map, int tiles, hipStream_t st,
+                       int tag) {
   const int grid = (tiles + 7) & ~7;
   if (tag == 1)
     hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st,
-                       d_desc, d_tile_off, count, tiles);
+                       d_desc, d_tile_map, tiles);
   else
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d_desc,
-                       d_tile_off, count, tiles);
+                       d_tile_map, tiles);
 }
 
 template <int BM, int BN>
-static void launch_t(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
-                     hipStream_t st, int tag, int tA, int tB) {
-  if (!tA && !tB) launch_cfg<BM, BN, 0, 0>(d_desc, d_tile_off, count, tiles, st, tag);
-  else if (!tA && tB) launch_cfg<BM, BN, 0, 1>(d_desc, d_tile_off, count, tiles, st, tag);
-  else if (tA && !tB) launch_cfg<BM, BN, 1, 0>(d_desc, d_tile_off, count, tiles, st, tag);
-  else launch_cfg<BM, BN, 1, 1>(d_desc, d_tile_off, count, tiles, st, tag);
+static void launch_t(const GemmDesc* d_desc, const int* d_tile_map, int tiles, hipStream_t st,
+                     int tag, int tA, int tB) {
+  if (!tA && !tB) launch_cfg<BM, BN, 0, 0>(d_desc, d_tile_map, tiles, st, tag);
+  else if (!tA && tB) launch_cfg<BM, BN, 0, 1>(d_desc, d_tile_map, tiles, st, tag);
+  else if (tA && !tB) launch_cfg<BM, BN, 1, 0>(d_desc, d_tile_map, tiles, st, tag);
+  else launch_cfg<BM, BN, 1, 1>(d_desc, d_tile_map, tiles, st, tag);
 }
 
-hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_off, int count,
+hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
                        int tiles, hipStream_t st, int tag, int cfg, int tA, int tB) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: launch_t<128, 64>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
-    case 2: launch_t<128, 128>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
-    default: launch_t<64, 64>(d_desc, d_tile_off, count, tiles, st, tag, tA, tB); break;
+    case 1: launch_t<128, 64>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    case 2: launch_t<128, 128>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    default: launch_t<64, 64>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
   }
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Thin products y = alpha op(A) x + beta y, x with at most 16 columns.  Each
-// item's A is read exactly once; eight loads per thread are kept in flight.
-//   op(A) = A   : one thread per output row, x staged through LDS;
-//   op(A) = A^T : one wave per output row (a column of A), lanes along it.
-constexpr int THIN_NMAX = 16, THIN_XCH = 256;
-
-template <int NR>
-__global__ __launch_bounds__(256) void thin_n_kernel(const GemmDesc* __restrict__ descs, int ncols) {
-  __shared__ double xs[THIN_XCH * NR];
-  const GemmDesc d = descs[blockIdx.y];
-  if ((int)blockIdx.x * 256 >= d.M) return;
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const bool live = r < d.M;
-  double acc[NR];
-#pragma unroll
-  for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-  const int64_t lda = d.lda;
-  for (int k0 = 0; k0 < d.K; k0 += THIN_XCH) {
-    const int len = min(THIN_XCH, d.K - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < len * NR; e += 256) {
-      const int kv = e / NR, c = e % NR;
-      xs[e] = (c < ncols) ? d.B[k0 + kv + (int64_t)c * d.ldb] : 0.0;
-    }
-    __syncthreads();
-    if (live) {
-      const double* col = d.A + r + (int64_t)k0 * lda;
-      int kv = 0;
-      for (; kv + 8 <= len; kv += 8) {
-        double av[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) av[u] = col[(int64_t)(kv + u) * lda];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int c = 0; c < NR; ++c) acc[c] += av[u] * xs[(kv + u) * NR + c];
-      }
-      for (; kv < len; ++kv) {
-        const double av = col[(int64_t)kv * lda];
-#pragma unroll
-        for (int c = 0; c < NR; ++c) acc[c] += av * xs[kv * NR + c];
-      }
-    }
-  }
-  if (live)
-    for (int c = 0; c < ncols; ++c) {
-      double v = d.alpha * acc[c];
-      if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
-      d.D[r + (int64_t)c * d.ldd] = v;
-    }
-}
-
-template <int NR>
-__global__ __launch_bounds__(256) void thin_t_kernel(const GemmDesc* __restrict__ descs, int ncols) {
-  const GemmDesc d = descs[blockIdx.y];
-  const int r0 = blockIdx.x * 64;
-  if (r0 >= d.M) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int rr = wave; rr < 64; rr += 4) {
-    const int r = r0 + rr;
-    if (r >= d.M) break;
-    double p[NR];
-#pragma unroll
-    for (int c = 0; c < NR; ++c) p[c] = 0.0;
-    const double* col = d.A + (int64_t)r * d.lda;
-    const int64_t ldb = d.ldb;
-    int k = lane;
-    for (; k + 192 < d.K; k += 256) {
-      double av[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = col[k + 64 * u];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int c = 0; c < NR; ++c)
-          if (c < ncols) p[c] += av[u] * d.B[k + 64 * u + c * ldb];
-    }
-    for (; k < d.K; k += 64) {
-      const double av = col[k];
-#pragma unroll
-      for (int c = 0; c < NR; ++c)
-        if (c < ncols) p[c] += av * d.B[k + c * ldb];
-    }
-#pragma unroll
-    for (int c = 0; c < NR; ++c) {
-      double v = p[c];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-      p[c] = v;
-    }
-    if (lane == 0) {
-      for (int c = 0; c < ncols; ++c) {
-        double v = d.alpha * p[c];
-        if (d.beta != 0.0) v += d.beta * d.C[r + (int64_t)c * d.ldc];
-        d.D[r + (int64_t)c * d.ldd] = v;
-      }
-    }
-  }
-}
-
-template <int NR>
-static void launch_thin_nr(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
-                           hipStream_t st) {
-  if (tA)
-    hipLaunchKernelGGL(thin_t_kernel<NR>, dim3((max_m + 63) / 64, count), dim3(256), 0, st, d_desc,
-                       ncols);
-  else
-    hipLaunchKernelGGL(thin_n_kernel<NR>, dim3((max_m + 255) / 256, count), dim3(256), 0, st,
-                       d_desc, ncols);
-}
-
-hipError_t launch_thin(const GemmDesc* d_desc, int count, int max_m, int ncols, int tA,
-                       hipStream_t st) {
-  if (count <= 0 || max_m <= 0) return hipSuccess;
-  if (ncols > THIN_NMAX || ncols < 1) return hipErrorInvalidValue;
-  if (ncols == 1) launch_thin_nr<1>(d_desc, count, max_m, ncols, tA, st);
-  else if (ncols <= 2) launch_thin_nr<2>(d_desc, count, max_m, ncols, tA, st);
-  else if (ncols <= 4) launch_thin_nr<4>(d_desc, count, max_m, ncols, tA, st);
-  else if (ncols <= 8) launch_thin_nr<8>(d_desc, count, max_m, ncols, tA, st);
-  else launch_thin_nr<16>(d_desc, count, max_m, ncols, tA, st);
   return hipGetLastError();
 }
 

@@ -11,15 +11,6 @@ namespace h2 {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ int find_item_lp(const int* off, int count, int t) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int xcd_remap_lp(int b, int nb) {
   const int per = (nb + 7) >> 3;
   return (b & 7) * per + (b >> 3);
@@ -39,14 +30,15 @@ __device__ __forceinline__ unsigned short to_bf16(double x) {
 // ---------------------------------------------------------------- FP32 MFMA
 template <int TAG, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restrict__ descs,
-                                                       const int* __restrict__ toff, int count,
+                                                       const int* __restrict__ tmap, int count,
                                                        int tiles) {
   constexpr int TK = 16;
   const int logical = xcd_remap_lp(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
-  const int item = find_item_lp(toff, count, logical);
+  const int2 it = reinterpret_cast<const int2*>(tmap)[logical];
+  const int item = it.x;
   const GemmDesc d = descs[item];
-  const int t = logical - toff[item];
+  const int t = it.y;
   const int tiles_m = (d.M + 63) / 64;
   const int m0 = (t % tiles_m) * 64, n0 = (t / tiles_m) * 64;
   __shared__ float As[TK][65];
@@ -120,14 +112,15 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restric
 // its four consecutive k values of one row with a single 8-byte read.
 template <int TAG, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmDesc* __restrict__ descs,
-                                                        const int* __restrict__ toff, int count,
+                                                        const int* __restrict__ tmap, int count,
                                                         int tiles) {
   constexpr int TK = 32, KP = TK + 4;
   const int logical = xcd_remap_lp(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
-  const int item = find_item_lp(toff, count, logical);
+  const int2 it = reinterpret_cast<const int2*>(tmap)[logical];
+  const int item = it.x;
   const GemmDesc d = descs[item];
-  const int t = logical - toff[item];
+  const int t = it.y;
   const int tiles_m = (d.M + 63) / 64;
   const int m0 = (t % tiles_m) * 64, n0 = (t / tiles_m) * 64;
   __shared__ __attribute__((aligned(16))) unsigned short As[64][KP];
@@ -215,17 +208,17 @@ static void launch_lp_t(const GemmDesc* d, const int* o, int count, int tiles, h
   else launch_lp<P, TAG, 1, 1>(d, o, count, tiles, st);
 }
 
-hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_off, int count, int tiles,
+hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int count, int tiles,
                           int prec, hipStream_t st, int tag, int tA, int tB) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
   if (prec == H2_PREC_FP32) {
-    if (tag == 1) launch_lp_t<H2_PREC_FP32, 1>(d_desc, d_tile_off, count, tiles, st, tA, tB);
-    else launch_lp_t<H2_PREC_FP32, 0>(d_desc, d_tile_off, count, tiles, st, tA, tB);
+    if (tag == 1) launch_lp_t<H2_PREC_FP32, 1>(d_desc, d_tile_map, count, tiles, st, tA, tB);
+    else launch_lp_t<H2_PREC_FP32, 0>(d_desc, d_tile_map, count, tiles, st, tA, tB);
   } else if (prec == H2_PREC_BF16) {
-    if (tag == 1) launch_lp_t<H2_PREC_BF16, 1>(d_desc, d_tile_off, count, tiles, st, tA, tB);
-    else launch_lp_t<H2_PREC_BF16, 0>(d_desc, d_tile_off, count, tiles, st, tA, tB);
+    if (tag == 1) launch_lp_t<H2_PREC_BF16, 1>(d_desc, d_tile_map, count, tiles, st, tA, tB);
+    else launch_lp_t<H2_PREC_BF16, 0>(d_desc, d_tile_map, count, tiles, st, tA, tB);
   } else {
-    return launch_gemm(d_desc, d_tile_off, count, tiles, st, tag, 0, tA, tB);
+    return launch_gemm(d_desc, d_tile_map, count, tiles, st, tag, 0, tA, tB);
   }
   return hipGetLastError();
 }

@@ -39,15 +39,6 @@ static int local_box(const Step& S, int t, int i) {
   return first + i;
 }
 
-static bool up_thin(Ctx& c, Batch<GemmDesc>& b, const std::vector<GemmDesc>& v, hipStream_t st) {
-  int mx = 0;
-  for (auto& g : v) mx = std::max(mx, g.M);
-  b.max_rows = mx;
-  b.tA = v.empty() ? 0 : v[0].tA;
-  for (auto& g : v)
-    if (g.tA != b.tA) return false;  // lists are built uniform
-  return upload(c, b, v, st);
-}
 // ------------------------------------------------------------ gather plans
 void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
                  GatherPlan& out) {
@@ -148,6 +139,25 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     out.reds.push_back(r);
     out.bytes_red += 8.0 * g.rows * ((r.s1 - r.s0) + 1 + (g.base ? 1 : 0));
   }
+}
+
+static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
+                      const std::vector<GatherNbr>& Nv, hipStream_t st);
+
+// Per-box products D = alpha op(A) B + beta C (beta 0, or 1 with C == D) as
+// gathers with one neighbour: A direct (tA = 0) or transposed (tA = 1).
+static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_t st) {
+  std::vector<GatherBox> B;
+  std::vector<GatherNbr> Nv;
+  for (const GemmDesc& g : v) {
+    if (g.beta != 0.0 && (g.beta != 1.0 || g.C != g.D)) return false;
+    const int q = (int)Nv.size();
+    Nv.push_back({g.A, g.B, g.lda, g.ldb, g.K});
+    GatherBox x{g.D, g.beta != 0.0 ? g.C : nullptr, g.M, g.ldd, g.ldc, g.alpha, q, q, q, q};
+    if (g.tA) x.t1 = q + 1; else x.d1 = q + 1;
+    B.push_back(x);
+  }
+  return up_gather(c, L, B, Nv, st);
 }
 
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
@@ -512,6 +522,11 @@ h2_status autotune(Ctx& c, hipStream_t st) {
       h2_status e = tune(*b, 0);
       if (e != H2_OK) return e;
     }
+    for (size_t p = 1; p < S.g_t1.size(); ++p)
+      for (Batch<GemmDesc>* b : {&S.g_t1[p], &S.g_t2[p]}) {
+        h2_status e = tune(*b, 0);
+        if (e != H2_OK) return e;
+      }
     for (size_t p = 0; p < S.ch_trsm.size(); ++p)
       for (Batch<GemmDesc>* b : {&S.ch_trsm[p], &S.ch_syrk[p], &S.ch_inv1[p], &S.ch_inv2[p]}) {
         h2_status e = tune(*b, 0);
@@ -535,7 +550,11 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     else HIPCHK(run_gemm(S.g_w, st));
     HIPCHK(launch_qr_panel(S.qr.d, S.qr.count, S.qr.max_rows, st));
     HIPCHK(run_gemm(S.g_qr1, st));
-    HIPCHK(launch_qr_tbuild(S.qr.d, S.qr.count, st));
+    HIPCHK(launch_qr_tdiag(S.qr.d, S.qr.count, S.max_k, st));
+    for (size_t q = 1; q < S.g_t1.size(); ++q) {
+      HIPCHK(run_gemm(S.g_t1[q], st));
+      HIPCHK(run_gemm(S.g_t2[q], st));
+    }
     HIPCHK(run_gemm(S.g_qr2, st));
     HIPCHK(run_gemm(S.g_qr3, st));
     HIPCHK(launch_qr_diag(S.qr.d, S.qr.count, st));
@@ -586,7 +605,7 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
   HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, b, ldb, c.vt_in, c.N, st));
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
-    HIPCHK(run_thin(S.t_fwd, nrhs, st));
+    HIPCHK(gather(c, S.t_fwd, nrhs, st));
     HIPCHK(gather(c, S.g_yr, nrhs, st));
     HIPCHK(gather(c, S.g_cs, nrhs, st));
   }
@@ -597,7 +616,7 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
     Step& S = c.steps[h];
     HIPCHK(gather(c, S.g_t, nrhs, st));
     HIPCHK(gather(c, S.g_s, nrhs, st));
-    HIPCHK(run_thin(S.t_bwd, nrhs, st));
+    HIPCHK(gather(c, S.t_bwd, nrhs, st));
   }
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, x, ldx, st));
   return H2_OK;
@@ -606,11 +625,11 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
 h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs,
                           hipStream_t st) {
   HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, x, ldx, c.vt_in, c.N, st));
-  for (int h = 0; h < c.H; ++h) HIPCHK(run_thin(c.steps[h].t_up, nrhs, st));
+  for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].t_up, nrhs, st));
   for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].g_cpl, nrhs, st));
-  for (int h = c.H - 1; h >= 0; --h) HIPCHK(run_thin(c.steps[h].t_down, nrhs, st));
+  for (int h = c.H - 1; h >= 0; --h) HIPCHK(gather(c, c.steps[h].t_down, nrhs, st));
   if (c.H > 0) HIPCHK(gather(c, c.steps[0].g_near, nrhs, st));
-  HIPCHK(run_thin(c.t_root, nrhs, st));
+  HIPCHK(gather(c, c.t_root, nrhs, st));
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, y, ldy, st));
   return H2_OK;
 }
