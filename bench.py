@@ -178,6 +178,7 @@ def main():
               flush=True)
     torch.cuda.synchronize()
     t_fac = t_sol = t_pair = 0.0
+    t_phase = [0.0] * 8
     t_g = [0.0, 0.0]
     b_g = [0.0, 0.0]
     n_g = [0, 0]
@@ -189,6 +190,7 @@ def main():
         st = H.stats()
         t_fac += st["t_factor"]
         t_pair += st["t_pair_gemm"]
+        t_phase = [a + b for a, b in zip(t_phase, st["t_factor_phase"])]
         s = H.solve_into(cols_b, cols_x)
         if s != h2.OK:
             raise h2.H2Error(s, "h2_solve")
@@ -222,7 +224,11 @@ def main():
                    "autotuned_lists": st_all["tuned_lists"], "tile_choice": st_all["tuned_cfg_hist"],
                    "ir_tol": a.tol, "levels": st["levels"], "root_n": st["root_n"],
                    "max_rank": st["max_rank_seen"], "near_pairs": st["near_pairs"]},
-        "factor_s": t_fac / K, "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
+        "factor_s": t_fac / K,
+        "factor_phase_s": dict(zip(["basis_qr", "diag_transform", "rr_cholesky_inverse",
+                                    "v_schur", "near_pair_transform", "far_coupling", "merge",
+                                    "root"], [round(x / K, 5) for x in t_phase])),
+        "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
         "build_s": t_build, "flops_factor": st["flops_factor"], "flops_solve": st["flops_solve"],
     }
     # Dominant kernel by time inside the timed steps: the neighbour gathers of

@@ -112,7 +112,8 @@ typedef struct {
   double bytes_basis;     /* bytes allocated for the bases U_i (predicted
                              capacities plus fallbacks, or m_i^2 per box)       */
   int32_t tuned_lists;    /* GEMM work lists timed by the autotuner             */
-  int32_t tuned_cfg_hist[3]; /* how many chose 64x64, 128x64, 128x128 tiles     */
+  int32_t tuned_cfg_hist[4]; /* how many chose 64x64x16, 128x64x16, 128x128x16,
+                                64x64x32 tiles (BM x BN x K-step)               */
   double t_gather[2];     /* seconds in the neighbour-gather launches of the last
                              solve: [0] block products, [1] per-box reductions
                              (HIP events around each launch; params.timing = 1) */
@@ -120,6 +121,11 @@ typedef struct {
                              stored block once plus x slices and partial
                              products, [1] partials, base and y once          */
   int32_t gather_launches[2]; /* number of timed launches of each kind           */
+  double t_factor_phase[8]; /* seconds of the last factor per phase (HIP events;
+                               params.timing = 1, no graph): basis QR, diagonal
+                               transform, RR Cholesky + inverse, V and Schur
+                               update, near-pair transforms, far couplings,
+                               merge, root                                      */
 } h2_stats_t;
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).

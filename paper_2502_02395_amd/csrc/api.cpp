@@ -174,6 +174,10 @@ h2_status h2_factor(h2_handle h, void* stream) {
   HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   c.st.t_factor = now_seconds() - t0;
+  if (c.prm.timing && !c.prm.use_graph) {
+    h2_status e = collect_factor_times(c);
+    if (e != H2_OK) return e;
+  }
   if (fail != INT_MAX) {
     const int hstep = fail >> 20, b = fail & ((1 << 20) - 1);
     if (hstep == 1023) {

@@ -27,6 +27,7 @@ Ctx::~Ctx() {
   if (graph) (void)hipGraphExecDestroy(graph);
   if (graph_def) (void)hipGraphDestroy(graph_def);
   for (hipEvent_t e : gev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : fev) (void)hipEventDestroy(e);
   if (ev_g0) (void)hipEventDestroy(ev_g0);
   if (ev_g1) (void)hipEventDestroy(ev_g1);
   if (graph_stream) (void)hipStreamDestroy(graph_stream);

@@ -19,8 +19,8 @@ struct Batch {
   int tiles = 0;
   int max_rows = 0;        // thin / gather: row extent for the grid
   // GEMM batches: (item, tile) maps of every tile shape, and the one in use
-  int* toffs[GEMM_NCFG] = {nullptr, nullptr, nullptr};
-  int tiles_c[GEMM_NCFG] = {0, 0, 0};
+  int* toffs[GEMM_NCFG] = {};
+  int tiles_c[GEMM_NCFG] = {};
   int cfg = 0;
   int tA = 0, tB = 0;      // transposes shared by every item of the list
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
@@ -160,6 +160,9 @@ struct Ctx {
   hipStream_t graph_stream = nullptr;      // capture and replay (never the null stream)
   // gather timing (params.timing): event triples around the two halves of
   // each gather, and the bytes each timed launch moves
+  std::vector<hipEvent_t> fev;             // factor phases: (before, after) pairs
+  std::vector<int> fev_phase;
+  size_t fev_used = 0;
   std::vector<hipEvent_t> gev;
   size_t gev_used = 0;
   bool gtime = false;
@@ -241,6 +244,7 @@ hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag = 0);
 h2_status autotune(Ctx& c, hipStream_t st);
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st);
 h2_status ensure_partials(Ctx& c, int nrhs);
+h2_status collect_factor_times(Ctx& c);
 
 // defined in the orchestration sources
 h2_status plan_factor(Ctx& c, hipStream_t st);

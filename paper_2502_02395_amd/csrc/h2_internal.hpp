@@ -72,9 +72,11 @@ constexpr int QR_MMAX = 7680;  // row limit of the QR panel kernel
 // tag 1 launches the same kernel under the symbol gemm_f64_pair_kernel;
 // cfg selects the tile shape: 0 = 64x64, 1 = 128x64, 2 = 128x128 (the tile
 // prefix d_tile_off must have been computed for that shape).
-constexpr int GEMM_NCFG = 3;
-constexpr int GEMM_BM[GEMM_NCFG] = {64, 128, 128};
-constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128};
+// Tile shapes (BM x BN, K staged TK at a time): 64x64x16, 128x64x16,
+// 128x128x16, 64x64x32.
+constexpr int GEMM_NCFG = 4;
+constexpr int GEMM_BM[GEMM_NCFG] = {64, 128, 128, 64};
+constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128, 64};
 // Every item of one launch must have the transposes tA, tB.  d_tile_map holds
 // two ints per output tile: the item and the tile's index within the item
 // (gemm_tile_map, for the launch's tile shape), so a workgroup finds its work

@@ -15,7 +15,7 @@ namespace h2 {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int TK = 16, LPAD = 1;
+constexpr int LPAD = 1;
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that
 // consecutive logical tiles (the tiles of one item, which share operands) run
@@ -27,14 +27,16 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 
 // One BM x BN output tile per 256-thread workgroup; the four waves form a 2x2
 // grid, each wave accumulating (BM/32) x (BN/32) 16x16 MFMA tiles.  Operand
-// tiles of TK = 16 are staged through LDS; the next one is prefetched into
-// registers while the current one is multiplied.  TA / TB (transposed
-// operands) are compile-time so that every index is plain arithmetic.
-template <int BM, int BN, int TA, int TB>
+// tiles of TK (16 or 32) are staged through LDS; the next one is prefetched
+// into registers while the current one is multiplied (TK = 32 gives the
+// loads the time of twice as many MFMAs, at one wave per SIMD less).  Tiles inside M x N and full K tiles load
+// without bounds tests.  TA / TB (transposed operands) are compile-time so
+// that every index is plain arithmetic.
+template <int BM, int BN, int TK, int TA, int TB>
 __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs,
                                               const int* __restrict__ tmap, int tiles) {
   constexpr int MI = BM / 32, NJ = BN / 32;
-  constexpr int QA = BM / 16, QB = BN / 16;  // operand elements per thread per K tile
+  constexpr int QA = BM * TK / 256, QB = BN * TK / 256;  // elements per thread per K tile
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   if (logical >= tiles) return;
   const int2 it = reinterpret_cast<const int2*>(tmap)[logical];
@@ -52,14 +54,14 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
   const int wave = tid >> 6;
   const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
 
-  // this thread's operand elements: A(m, k) and B(k, n) of the tile
-  //   A not transposed: m fixed, k steps by 256/BM;  transposed: k fixed, m steps by 16
-  const int am = TA ? (tid >> 4) : (tid % BM);
-  const int ak = TA ? (tid & 15) : (tid / BM);
-  const int bn = TB ? (tid % BN) : (tid >> 4);
-  const int bk = TB ? (tid / BN) : (tid & 15);
-  constexpr int ASTEP = TA ? 16 : 256 / BM;   // along m (TA) or k (!TA)
-  constexpr int BSTEP = TB ? 256 / BN : 16;   // along k (TB) or n (!TB)
+  // this thread's operand elements: A(m, k) and B(k, n) of the tile, the
+  // contiguous index fastest
+  const int am = TA ? (tid / TK) : (tid % BM);
+  const int ak = TA ? (tid % TK) : (tid / BM);
+  const int bn = TB ? (tid % BN) : (tid / TK);
+  const int bk = TB ? (tid / BN) : (tid % TK);
+  constexpr int ASTEP = TA ? 256 / TK : 256 / BM;   // along m (TA) or k (!TA)
+  constexpr int BSTEP = TB ? 256 / BN : 256 / TK;   // along k (TB) or n (!TB)
 
   d4 acc[MI][NJ];
 #pragma unroll
@@ -72,23 +74,30 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
   const double* __restrict__ Ap = d.A;
   const double* __restrict__ Bp = d.B;
   const int64_t lda = d.lda, ldb = d.ldb;
+  const bool inside = (m0 + BM <= M) && (n0 + BN <= N);
 
-#define H2_LOAD(k0)                                                              \
+#define H2_LOAD(k0, GUARD)                                                       \
   {                                                                              \
     _Pragma("unroll") for (int q = 0; q < QA; ++q) {                             \
       const int gm = m0 + am + (TA ? ASTEP * q : 0);                             \
       const int gk = (k0) + ak + (TA ? 0 : ASTEP * q);                           \
-      ra[q] = (gm < M && gk < K) ? (TA ? Ap[gk + gm * lda] : Ap[gm + gk * lda]) : 0.0; \
+      ra[q] = (!(GUARD) || (gm < M && gk < K))                                   \
+                  ? (TA ? Ap[gk + gm * lda] : Ap[gm + gk * lda]) : 0.0;          \
     }                                                                            \
     _Pragma("unroll") for (int q = 0; q < QB; ++q) {                             \
       const int gn = n0 + bn + (TB ? 0 : BSTEP * q);                             \
       const int gk = (k0) + bk + (TB ? BSTEP * q : 0);                           \
-      rb[q] = (gn < N && gk < K) ? (TB ? Bp[gn + gk * ldb] : Bp[gk + gn * ldb]) : 0.0; \
+      rb[q] = (!(GUARD) || (gn < N && gk < K))                                   \
+                  ? (TB ? Bp[gn + gk * ldb] : Bp[gk + gn * ldb]) : 0.0;          \
     }                                                                            \
+  }
+#define H2_LOAD_TILE(k0)                                                         \
+  {                                                                              \
+    if (inside && (k0) + TK <= K) H2_LOAD(k0, false) else H2_LOAD(k0, true)      \
   }
 
   const int nk = (K + TK - 1) / TK;
-  if (nk > 0) H2_LOAD(0);
+  if (nk > 0) H2_LOAD_TILE(0);
   for (int kt = 0; kt < nk; ++kt) {
     __syncthreads();
 #pragma unroll
@@ -96,7 +105,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
 #pragma unroll
     for (int q = 0; q < QB; ++q) Bs[bk + (TB ? BSTEP * q : 0)][bn + (TB ? 0 : BSTEP * q)] = rb[q];
     __syncthreads();
-    if (kt + 1 < nk) H2_LOAD((kt + 1) * TK);
+    if (kt + 1 < nk) H2_LOAD_TILE((kt + 1) * TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
@@ -113,6 +122,7 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
+#undef H2_LOAD_TILE
 #undef H2_LOAD
 
   // Accumulator layout of the 16x16x4 f64 MFMA (measured on gfx950): element e
@@ -137,46 +147,47 @@ __device__ __forceinline__ void gemm_f64_body(const GemmDesc* __restrict__ descs
 
 // Two symbols per instantiation with the same body so that profiles separate
 // the near-pair basis transforms (the dominant cost) from every other product.
-template <int BM, int BN, int TA, int TB>
+template <int BM, int BN, int TK, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
                                                        const int* __restrict__ tmap, int tiles) {
-  gemm_f64_body<BM, BN, TA, TB>(descs, tmap, tiles);
+  gemm_f64_body<BM, BN, TK, TA, TB>(descs, tmap, tiles);
 }
-template <int BM, int BN, int TA, int TB>
+template <int BM, int BN, int TK, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f64_pair_kernel(const GemmDesc* __restrict__ descs,
                                                             const int* __restrict__ tmap,
                                                             int tiles) {
-  gemm_f64_body<BM, BN, TA, TB>(descs, tmap, tiles);
+  gemm_f64_body<BM, BN, TK, TA, TB>(descs, tmap, tiles);
 }
 
-template <int BM, int BN, int TA, int TB>
+template <int BM, int BN, int TK, int TA, int TB>
 static void launch_cfg(const GemmDesc* d_desc, const int* d_tile_map, int tiles, hipStream_t st,
                        int tag) {
   const int grid = (tiles + 7) & ~7;
   if (tag == 1)
-    hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st,
+    hipLaunchKernelGGL((gemm_f64_pair_kernel<BM, BN, TK, TA, TB>), dim3(grid), dim3(256), 0, st,
                        d_desc, d_tile_map, tiles);
   else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d_desc,
-                       d_tile_map, tiles);
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, TK, TA, TB>), dim3(grid), dim3(256), 0, st,
+                       d_desc, d_tile_map, tiles);
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int TK>
 static void launch_t(const GemmDesc* d_desc, const int* d_tile_map, int tiles, hipStream_t st,
                      int tag, int tA, int tB) {
-  if (!tA && !tB) launch_cfg<BM, BN, 0, 0>(d_desc, d_tile_map, tiles, st, tag);
-  else if (!tA && tB) launch_cfg<BM, BN, 0, 1>(d_desc, d_tile_map, tiles, st, tag);
-  else if (tA && !tB) launch_cfg<BM, BN, 1, 0>(d_desc, d_tile_map, tiles, st, tag);
-  else launch_cfg<BM, BN, 1, 1>(d_desc, d_tile_map, tiles, st, tag);
+  if (!tA && !tB) launch_cfg<BM, BN, TK, 0, 0>(d_desc, d_tile_map, tiles, st, tag);
+  else if (!tA && tB) launch_cfg<BM, BN, TK, 0, 1>(d_desc, d_tile_map, tiles, st, tag);
+  else if (tA && !tB) launch_cfg<BM, BN, TK, 1, 0>(d_desc, d_tile_map, tiles, st, tag);
+  else launch_cfg<BM, BN, TK, 1, 1>(d_desc, d_tile_map, tiles, st, tag);
 }
 
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
                        int tiles, hipStream_t st, int tag, int cfg, int tA, int tB) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: launch_t<128, 64>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
-    case 2: launch_t<128, 128>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
-    default: launch_t<64, 64>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    case 1: launch_t<128, 64, 16>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    case 2: launch_t<128, 128, 16>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    case 3: launch_t<64, 64, 32>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
+    default: launch_t<64, 64, 16>(d_desc, d_tile_map, tiles, st, tag, tA, tB); break;
   }
   return hipGetLastError();
 }

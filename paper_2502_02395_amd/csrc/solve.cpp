@@ -540,12 +540,33 @@ h2_status autotune(Ctx& c, hipStream_t st) {
   return H2_OK;
 }
 
+// Phases of the factorization timed with params.timing (events from a pool
+// in the handle, read after the factorization without stalling it).
+enum FactorPhase { FP_QR, FP_DIAG, FP_CHOL, FP_VS, FP_PAIR, FP_FAR, FP_MERGE, FP_ROOT, FP_N };
+
 h2_status do_factor(Ctx& c, hipStream_t st) {
   HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
   const bool timing = c.prm.timing != 0 && !c.prm.use_graph;
-  double t_pair = 0.0;
+  if (timing && c.fev.empty()) {
+    c.fev.resize(2 * FP_N * (c.H + 1), nullptr);
+    for (auto& e : c.fev) HIPCHK(hipEventCreate(&e));
+  }
+  c.fev_phase.clear();
+  size_t ne = 0;
+  auto mark = [&](int phase) -> hipError_t {  // event before the phase, event after
+    if (!timing || ne + 2 > c.fev.size()) return hipSuccess;
+    c.fev_phase.push_back(phase);
+    return hipEventRecord(c.fev[ne], st);
+  };
+  auto done = [&]() -> hipError_t {
+    if (!timing || c.fev_phase.size() * 2 != ne + 2) return hipSuccess;
+    const hipError_t e = hipEventRecord(c.fev[ne + 1], st);
+    ne += 2;
+    return e;
+  };
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
+    HIPCHK(mark(FP_QR));
     if (h == 0) HIPCHK(run_copy(S.c_w, st));
     else HIPCHK(run_gemm(S.g_w, st));
     HIPCHK(launch_qr_panel(S.qr.d, S.qr.count, S.qr.max_rows, st));
@@ -558,8 +579,12 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(S.g_qr2, st));
     HIPCHK(run_gemm(S.g_qr3, st));
     HIPCHK(launch_qr_diag(S.qr.d, S.qr.count, st));
+    HIPCHK(done());
+    HIPCHK(mark(FP_DIAG));
     HIPCHK(run_gemm_p(c, S.g_diag1, st));
     HIPCHK(run_gemm_p(c, S.g_diag2, st));
+    HIPCHK(done());
+    HIPCHK(mark(FP_CHOL));
     HIPCHK(launch_fill(S.dLi, S.lioff.back(), 0.0, st));
     for (size_t p = 0; p < S.ch_panel.size(); ++p) {
       HIPCHK(launch_panel(S.ch_panel[p].d, S.ch_panel[p].count, c.dFail, st));
@@ -571,23 +596,25 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
       HIPCHK(run_gemm(S.ch_inv1[p], st));
       HIPCHK(run_gemm(S.ch_inv2[p], st));
     }
+    HIPCHK(done());
+    HIPCHK(mark(FP_VS));
     HIPCHK(run_copy(S.c_ps, st));
     HIPCHK(run_gemm(S.g_v, st));
     HIPCHK(run_gemm_p(c, S.g_schur, st));
-    if (timing && S.g_pair1.count > 0) HIPCHK(hipEventRecord(c.ev_a, st));
+    HIPCHK(done());
+    HIPCHK(mark(FP_PAIR));
     HIPCHK(run_gemm_p(c, S.g_pair1, st, 1));
     HIPCHK(run_gemm_p(c, S.g_pair2, st, 1));
-    if (timing && S.g_pair1.count > 0) {
-      HIPCHK(hipEventRecord(c.ev_b, st));
-      HIPCHK(hipEventSynchronize(c.ev_b));
-      float ms = 0.f;
-      HIPCHK(hipEventElapsedTime(&ms, c.ev_a, c.ev_b));
-      t_pair += 1e-3 * ms;
-    }
+    HIPCHK(done());
+    HIPCHK(mark(FP_FAR));
     HIPCHK(run_gemm_p(c, S.g_far1, st));
     HIPCHK(run_gemm_p(c, S.g_far2, st));
+    HIPCHK(done());
+    HIPCHK(mark(FP_MERGE));
     HIPCHK(run_copy(S.c_merge, st));
+    HIPCHK(done());
   }
+  HIPCHK(mark(FP_ROOT));
   HIPCHK(run_copy(c.r_save, st));
   for (size_t p = 0; p < c.r_panel.size(); ++p) {
     HIPCHK(launch_panel(c.r_panel[p].d, c.r_panel[p].count, c.dFail, st));
@@ -595,7 +622,20 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(c.r_syrk[p], st));
     HIPCHK(run_copy(c.r_back[p], st));
   }
-  if (timing) c.st.t_pair_gemm = t_pair;
+  HIPCHK(done());
+  c.fev_used = ne;
+  return H2_OK;
+}
+
+// After the factorization has completed: per-phase seconds into the stats.
+h2_status collect_factor_times(Ctx& c) {
+  for (int q = 0; q < 8; ++q) c.st.t_factor_phase[q] = 0.0;
+  for (size_t i = 0; 2 * i + 1 < c.fev_used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c.fev[2 * i], c.fev[2 * i + 1]));
+    c.st.t_factor_phase[c.fev_phase[i]] += 1e-3 * ms;
+  }
+  c.st.t_pair_gemm = c.st.t_factor_phase[FP_PAIR];
   return H2_OK;
 }
 

@@ -57,14 +57,15 @@ class Stats(ctypes.Structure):
                 ("rank_fallbacks", ctypes.c_int32), ("t_pair_gemm", ctypes.c_double),
                 ("flops_pair_gemm", ctypes.c_double), ("pair_launches", ctypes.c_int32),
                 ("bytes_basis", ctypes.c_double), ("tuned_lists", ctypes.c_int32),
-                ("tuned_cfg_hist", ctypes.c_int32 * 3),
+                ("tuned_cfg_hist", ctypes.c_int32 * 4),
                 ("t_gather", ctypes.c_double * 2), ("bytes_gather", ctypes.c_double * 2),
-                ("gather_launches", ctypes.c_int32 * 2)]
+                ("gather_launches", ctypes.c_int32 * 2),
+                ("t_factor_phase", ctypes.c_double * 8)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["tuned_cfg_hist"] = list(self.tuned_cfg_hist)
-        for f in ("t_gather", "bytes_gather", "gather_launches"):
+        for f in ("t_gather", "bytes_gather", "gather_launches", "t_factor_phase"):
             d[f] = list(getattr(self, f))
         return d
 
