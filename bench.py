@@ -146,13 +146,13 @@ def main():
         import numpy as np
         H = h2.build_batched([q.points for q in p], [q.kernel for q in p], a.leaf, 1.0, a.eps,
                              perms=[q.perm() for q in p], s_far=a.s, s_near=a.s, gemm_prec=prec,
-                             ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=not a.graph,
+                             ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=True,
                              use_graph=a.graph)
         bnp = np.concatenate([q.b() for q in p], axis=0)
         n_total = sum(q.n for q in p)
     else:
         H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
-                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=not a.graph,
+                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
                      gemm_prec=prec, rank_model=model, use_graph=a.graph,
                      use_pcg=not a.stationary)
         bnp = p.b()
@@ -239,7 +239,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": pair_tflops / FP64_PEAK_TFLOPS,
             "traffic": None, "launches": st["pair_launches"] * K,
             "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1), "total_s": t_pair}
-    cands = [pair]
+    # (a captured factorization is not timed per launch: no pair figure then)
+    cands = [pair] if t_pair > 0 else []
     for q, kname in ((0, "gchunk_kernel"), (1, "greduce_kernel")):
         if n_g[q] == 0:
             continue
@@ -251,7 +252,7 @@ def main():
     for d in cands:
         d["traffic"] = measured_traffic(d["kernel"])
     cands.sort(key=lambda d: -d["total_s"])
-    out["roofline"] = cands[0]
+    out["roofline"] = cands[0] if cands else None
     out["roofline_other"] = cands[1:]
     H.close()
     if not a.no_cpu_baseline and a.kernel != "gaussian_batch":

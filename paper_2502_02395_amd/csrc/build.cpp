@@ -704,14 +704,24 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       gp2.push_back(gd(S.dP + S.qoff[i], mi, 1, S.dT2 + S.poff[p], mi, 0, nullptr, 1,
                        S.dF + S.poff[p], mi, mi, mj, mi, 1.0, 0.0));
     }
+    // R_i S_ij for all far partners j of box i at once: the far list is sorted
+    // by i, so S_ij1 | S_ij2 | ... (each k_i x k_j, ld k_i) is one k_i x sum k_j
+    // matrix, and so is its product
+    for (size_t f = 0; f < S.fp_i.size();) {
+      const int i = S.fp_i[f], ki = S.k[i];
+      size_t g = f;
+      int ncol = 0;
+      while (g < S.fp_i.size() && S.fp_i[g] == i) ncol += S.k[S.fp_j[g++]];
+      gf1.push_back(gd(S.dR + S.rkoff[i], ki, 0, S.dS + S.soff[f], ki, 0, nullptr, 1,
+                       S.dT3 + S.soff[f], ki, ki, ncol, ki, 1.0, 0.0));
+      f = g;
+    }
     for (size_t f = 0; f < S.fp_i.size(); ++f) {
       const int i = S.fp_i[f], j = S.fp_j[f];
       const int ki = S.k[i], kj = S.k[j];
       double* dst;
       int ldp;
       parent_block(h, i, j, dst, ldp);
-      gf1.push_back(gd(S.dR + S.rkoff[i], ki, 0, S.dS + S.soff[f], ki, 0, nullptr, 1,
-                       S.dT3 + S.soff[f], ki, ki, kj, ki, 1.0, 0.0));
       gf2.push_back(gd(S.dT3 + S.soff[f], ki, 0, S.dR + S.rkoff[j], kj, 1, nullptr, 1, dst, ldp, ki,
                        kj, kj, 1.0, 0.0));
       const bool sib = (S.idx[i] >> 1) == (S.idx[j] >> 1);
@@ -788,6 +798,28 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     for (auto& q : qr) {
       S.qr.max_rows = std::max(S.qr.max_rows, q.m);
       if (q.m > 0) S.max_k = std::max(S.max_k, q.k);
+    }
+    // blocked QR: per panel J..J+w-1, Z = U_p^T W_t (into P, ld w) and
+    // W_t -= V_p Z, W_t = rows J.. of the trailing columns
+    S.qr_w = qr_panel_width(S.qr.max_rows);
+    {
+      const int w = S.qr_w, npan = (S.max_k + w - 1) / w;
+      S.g_pz.assign(npan, {});
+      S.g_pu.assign(npan, {});
+      for (int pp = 0; pp < npan; ++pp) {
+        const int J = pp * w;
+        std::vector<GemmDesc> z, u;
+        for (auto& q : qr) {
+          if (q.m == 0 || q.k <= J) continue;
+          const int m = q.m, wj = std::min(w, q.k - J), L = m - J, N = q.k - J - wj;
+          if (N <= 0) continue;
+          double* Wt = q.W + J + (int64_t)(J + wj) * m;
+          z.push_back(gd(q.tmpB + J, m, 1, Wt, m, 0, nullptr, 1, q.P, wj, wj, N, L, 1.0, 0.0));
+          u.push_back(gd(q.tmpA + J + (int64_t)J * m, m, 0, q.P, wj, 0, Wt, m, Wt, m, L, N, wj,
+                         -1.0, 1.0));
+        }
+        if (!up_g(S.g_pz[pp], z) || !up_g(S.g_pu[pp], u)) return H2_ERR_ALLOC;
+      }
     }
     // T above its diagonal blocks: Y = T[0:q0,0:q0] G[0:q0,q] (into TB),
     // T[0:q0,q] = -Y T_qq

@@ -78,6 +78,8 @@ struct Step {
   Batch<GemmDesc> g_w;                     // W = D_i U_i (upper steps)
   Batch<GemmDesc> g_qr1, g_qr2, g_qr3;     // compact-WY Q: V^T V, T V^T, -V (T V^T)
   std::vector<Batch<GemmDesc>> g_t1, g_t2; // T blocks above the diagonal, per block column
+  int qr_w = 1;                            // QR panel width of this level
+  std::vector<Batch<GemmDesc>> g_pz, g_pu; // per panel: Z = U_p^T W_t, W_t -= V_p Z
   int max_k = 0;
   Batch<CopyDesc> c_w;                     // W = U (leaf step)
   Batch<BoxDev> qr;

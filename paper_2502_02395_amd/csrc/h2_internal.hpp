@@ -64,7 +64,7 @@ struct BoxDev {
   double* tau;              // k Householder scalars
 };
 
-constexpr int QR_MMAX = 7680;  // row limit of the QR panel kernel
+constexpr int QR_MMAX = 6912;  // row limit of the QR panel kernel
 
 // ------------------------------------------------------------- launch wrappers
 // All wrappers enqueue on `st`; they return hipSuccess or the launch error.
@@ -106,11 +106,17 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
 hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st);
 
 // QR of W (m x k) with R (k x k) and the full Q (m x m) in compact WY form:
-// qr_panel writes V (tmpA), tau and R; a GEMM writes G = V^T V into P;
+// qr_panel factors one panel (V into tmpA, tau, R, U_p = V_p T_p into tmpB)
+// and GEMMs update the trailing columns, panel after panel; a GEMM writes
+// G = V^T V into P;
 // qr_tdiag turns the diagonal 64-blocks of G into those of T in place and
 // GEMMs the blocks above them; GEMMs write Q = -V (T V^T); qr_diag adds the
 // identity.  One workgroup per box (per box and block for qr_tdiag).
-hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t st);
+// Panel width for a level whose largest box has max_m rows (the panel of
+// max_m x w doubles must fit in LDS), and one panel J .. J+w-1 of every box.
+int qr_panel_width(int max_m);
+hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, int J, int w,
+                           hipStream_t st);
 hipError_t launch_qr_tdiag(const BoxDev* boxes, int nbox, int max_k, hipStream_t st);
 hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st);
 // Cholesky + explicit inverse of n x n SPD blocks: A (ld lda, destroyed),

@@ -75,122 +75,177 @@ __device__ __forceinline__ double apply_reflector_wave(const double* vcol, doubl
 // Householder QR of W = D_i U_i (m x k) and the full square Q_i in compact
 // WY form, Q = H_0 H_1 ... H_{k-1} = I - V T V^T (V unit lower trapezoidal,
 // T upper triangular):
-//   qr_panel   -- blocked right-looking factorization, one workgroup per box,
-//                 panels of up to QR_NB columns resident in LDS; writes V
-//                 explicitly (tmpA), tau, and R (Rf);
+//   qr_panel   -- one panel of a blocked right-looking factorization, one
+//                 workgroup per box, the panel resident in LDS; writes V
+//                 explicitly (tmpA), tau, R (Rf) and U_p = V_p T_p (tmpB);
+//                 batched GEMMs apply the panel to the trailing columns;
 //   qr_tdiag   -- T from G = V^T V (a batched GEMM writes G into P):
 //                 T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j],
 //                 on the diagonal 64-blocks; GEMMs fill the blocks above;
 //   qr_diag    -- after the GEMMs Q = -V (T V^T): add the identity (k = 0
 //                 boxes get Q = I outright).
-constexpr int QR_PAN = 7680;  // LDS doubles holding one panel (60 KiB)
+constexpr int QR_PAN = 6912;  // LDS doubles of one panel (54 KiB: two workgroups per CU)
+constexpr int QR_PW = 32;     // widest panel
 
-// Panel width NB is fixed per launch (NB * max m <= QR_PAN); only the last
-// panel of a box is narrower, and it has no trailing columns.
-template <int NB>
-__global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict__ boxes) {
+// One panel of the blocked factorization, one workgroup per box with k > J:
+// columns J .. J+w-1 of W (rows J .. m-1, already updated by the previous
+// panels) are factored in LDS by unblocked Householder steps.  The kernel
+// writes the panel's columns of V (explicitly, all m rows) into tmpA, its
+// columns of R into Rf, its tau, and, when trailing columns remain,
+// U_p = V_p T_p (rows J .. m-1, ld m) into tmpB, T_p being the panel's WY
+// factor.  The trailing update W_t -= V_p (U_p^T W_t) is two batched GEMMs.
+__global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict__ boxes, int J,
+                                                       int w) {
   __shared__ double pan[QR_PAN];
-  __shared__ double Tp[NB * NB];
-  __shared__ double taup[NB];
+  __shared__ double Tp[QR_PW * QR_PW], Gp[QR_PW * QR_PW], Xp[QR_PW * QR_PW];
+  __shared__ double taup[QR_PW], scalp[QR_PW], betap[QR_PW], wv[QR_PW];
   __shared__ double sh[4];
   const BoxDev b = boxes[blockIdx.x];
   const int m = b.m, k = b.k;
-  if (k == 0 || m == 0) return;
-  constexpr int nb = NB;
+  if (m == 0 || k <= J) return;
+  const int wj = min(w, k - J), L = m - J;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* W = b.W;
-  for (int J = 0; J < k; J += nb) {
-    const int w = min(nb, k - J), L = m - J;
-    for (int e = threadIdx.x; e < L * w; e += 256) {
-      const int r = e % L, c = e / L;
-      pan[e] = W[J + r + (int64_t)(J + c) * m];
-    }
+  for (int e = threadIdx.x; e < L * wj; e += 256) {
+    const int r = e % L, c = e / L;
+    pan[e] = W[J + r + (int64_t)(J + c) * m];
+  }
+  __syncthreads();
+  // Householder steps, thread-parallel, two barriers per column.  Column jj
+  // stays unscaled while later columns are updated (v_r = pan[r, jj] * scal
+  // for r > jj, v_jj = 1); its scaling and beta are applied at the end.  The
+  // update of column jj+1 also accumulates the squared norm of its rows below
+  // the diagonal, the sigma of the next step.
+  {
+    double part = 0.0;
+    for (int r = 1 + threadIdx.x; r < L; r += 256) part += pan[r] * pan[r];
+    part = wave_sum(part);
+    if (lane == 0) sh[wave] = part;
     __syncthreads();
-    // unblocked factorization of the panel
-    for (int jj = 0; jj < w; ++jj) {
-      double beta;
-      const double tau = householder(pan + jj * L, jj, L, sh, &beta);
-      if (threadIdx.x == 0) taup[jj] = tau;
-      if (tau != 0.0)
-        for (int c = jj + 1 + wave; c < w; c += 4)
-          apply_reflector_wave(pan + jj * L, pan + c * L, jj, L, tau, false);
-      __syncthreads();
+  }
+  for (int jj = 0; jj < wj; ++jj) {
+    const double sigma = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    const double alpha = pan[jj * L + jj];
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (sigma != 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
     }
-    // R columns J..J+w-1 (rows above the panel are final in W), tau
-    for (int e = threadIdx.x; e < k * w; e += 256) {
-      const int r = e % k, c = e / k;
-      double v = 0.0;
-      if (r < J) v = W[r + (int64_t)(J + c) * m];
-      else if (r <= J + c) v = pan[c * L + (r - J)];
-      b.Rf[r + (int64_t)(J + c) * k] = v;
-    }
-    if (threadIdx.x < w) b.tau[J + threadIdx.x] = taup[threadIdx.x];
-    __syncthreads();
-    // make V explicit in the panel: zeros above the diagonal, ones on it
-    for (int e = threadIdx.x; e < w * w; e += 256) {
-      const int r = e % w, c = e / w;
-      if (r <= c) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    // V into tmpA (all m rows)
-    for (int e = threadIdx.x; e < m * w; e += 256) {
-      const int r = e % m, c = e / m;
-      b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
-    }
-    if (J + w < k) {
-      // here w == NB.  Panel T: dots of V columns, then the triangular
-      // recurrence.
-      for (int pq = wave; pq < NB * NB; pq += 4) {
-        const int i = pq % NB, jj = pq / NB;
-        if (i >= jj) continue;
-        double d = 0.0;
-        for (int r = jj + lane; r < L; r += 64) d += pan[i * L + r] * pan[jj * L + r];
-        d = wave_sum(d);
-        if (lane == 0) Tp[i + jj * NB] = d;
+    const int nc = wj - jj - 1;
+    if (nc > 0 && tau != 0.0) {
+      // w_c = tau (pan[jj, c] + scal sum_{r > jj} pan[r, jj] pan[r, c]),
+      // G threads per column (G a power of two dividing 64)
+      int G = 64;
+      while (G > 8 && G * nc > 256) G >>= 1;
+      const int grp = threadIdx.x / G, sub = threadIdx.x % G;
+      double acc = 0.0;
+      if (grp < nc) {
+        const double* vc = pan + jj * L;
+        const double* xc = pan + (jj + 1 + grp) * L;
+        for (int r = jj + 1 + sub; r < L; r += G) acc += vc[r] * xc[r];
       }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int jj = 0; jj < NB; ++jj) {
-          const double tj = taup[jj];
-          for (int i = 0; i < jj; ++i) {
-            double t = 0.0;
-            for (int q = i; q < jj; ++q) t += Tp[i + q * NB] * Tp[q + jj * NB];
-            Tp[i + jj * NB] = -tj * t;
-          }
-          Tp[jj + jj * NB] = tj;
+      for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (grp < nc && sub == 0) wv[grp] = tau * (pan[(jj + 1 + grp) * L + jj] + scal * acc);
+    }
+    if (threadIdx.x == 0) {
+      taup[jj] = tau;
+      scalp[jj] = scal;
+      betap[jj] = beta;
+    }
+    __syncthreads();
+    double nxt = 0.0;
+    if (nc > 0) {
+      const int rows = L - jj;
+      if (tau != 0.0) {
+        for (int e = threadIdx.x; e < rows * nc; e += 256) {
+          const int r = jj + e % rows, ci = e / rows;
+          const double v = (r == jj) ? 1.0 : pan[jj * L + r] * scal;
+          const double x = pan[(jj + 1 + ci) * L + r] - v * wv[ci];
+          pan[(jj + 1 + ci) * L + r] = x;
+          if (ci == 0 && r > jj + 1) nxt += x * x;
         }
-      }
-      __syncthreads();
-      // trailing columns: c <- (I - V T^T V^T) c, one wave per column
-      for (int c = J + NB + wave; c < k; c += 4) {
-        double* col = W + J + (int64_t)c * m;
-        double y[NB];
-#pragma unroll
-        for (int i = 0; i < NB; ++i) y[i] = 0.0;
-        for (int r = lane; r < L; r += 64) {
-          const double x = col[r];
-#pragma unroll
-          for (int i = 0; i < NB; ++i) y[i] += pan[i * L + r] * x;
-        }
-#pragma unroll
-        for (int i = 0; i < NB; ++i) y[i] = wave_sum(y[i]);
-        // z = T^T y, computed in place from the last entry down
-#pragma unroll
-        for (int i = NB - 1; i >= 0; --i) {
-          double t = 0.0;
-#pragma unroll
-          for (int q = 0; q <= i; ++q) t += Tp[q + i * NB] * y[q];
-          y[i] = t;
-        }
-        for (int r = lane; r < L; r += 64) {
-          double x = col[r];
-#pragma unroll
-          for (int i = 0; i < NB; ++i) x -= pan[i * L + r] * y[i];
-          col[r] = x;
-        }
+      } else {
+        for (int r = jj + 2 + threadIdx.x; r < L; r += 256)
+          nxt += pan[(jj + 1) * L + r] * pan[(jj + 1) * L + r];
       }
     }
+    nxt = wave_sum(nxt);
+    if (lane == 0) sh[wave] = nxt;
     __syncthreads();
+  }
+  for (int e = threadIdx.x; e < L * wj; e += 256) {
+    const int r = e % L, c = e / L;
+    if (r > c) pan[e] *= scalp[c];
+    else if (r == c) pan[e] = betap[c];
+  }
+  __syncthreads();
+  // R columns J..J+wj-1 (rows above the panel are final in W), tau
+  for (int e = threadIdx.x; e < k * wj; e += 256) {
+    const int r = e % k, c = e / k;
+    double v = 0.0;
+    if (r < J) v = W[r + (int64_t)(J + c) * m];
+    else if (r <= J + c) v = pan[c * L + (r - J)];
+    b.Rf[r + (int64_t)(J + c) * k] = v;
+  }
+  if ((int)threadIdx.x < wj) b.tau[J + threadIdx.x] = taup[threadIdx.x];
+  __syncthreads();
+  // V explicit in the panel: zeros above the diagonal, ones on it
+  for (int e = threadIdx.x; e < wj * wj; e += 256) {
+    const int r = e % wj, c = e / wj;
+    if (r <= c) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * wj; e += 256) {
+    const int r = e % m, c = e / m;
+    b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
+  }
+  if (J + wj >= k) return;
+  // T_p from G_p = V_p^T V_p by recursive doubling: for two adjacent blocks
+  // of reflectors, T = [T1, -T1 (V1^T V2) T2; 0, T2].  G_p's strict upper
+  // triangle (one thread per entry, rows from the later column's diagonal
+  // down) goes to Gp; T_p starts as diag(tau).
+  for (int pq = threadIdx.x; pq < wj * wj; pq += 256) {
+    const int i = pq % wj, jj = pq / wj;
+    double d = 0.0;
+    if (i < jj)
+      for (int r = jj; r < L; ++r) d += pan[i * L + r] * pan[jj * L + r];
+    Gp[i + jj * QR_PW] = d;
+    Tp[i + jj * QR_PW] = (i == jj) ? taup[i] : 0.0;
+  }
+  __syncthreads();
+  for (int sz = 1; sz < wj; sz <<= 1) {
+    // X = G12 T2 into Xp, then T12 = -T1 X, for every pair of blocks of size sz
+    const int nblk = (wj + 2 * sz - 1) / (2 * sz);
+    for (int e = threadIdx.x; e < nblk * sz * sz; e += 256) {
+      const int o = (e / (sz * sz)) * 2 * sz, r = e % sz, c = (e / sz) % sz;
+      const int c2 = o + sz + c;
+      if (c2 < wj) {
+        double acc = 0.0;
+        for (int q = 0; q <= c; ++q) acc += Gp[o + r + (o + sz + q) * QR_PW] * Tp[o + sz + q + c2 * QR_PW];
+        Xp[o + r + c2 * QR_PW] = acc;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nblk * sz * sz; e += 256) {
+      const int o = (e / (sz * sz)) * 2 * sz, r = e % sz, c = (e / sz) % sz;
+      const int c2 = o + sz + c;
+      if (c2 < wj) {
+        double acc = 0.0;
+        for (int q = r; q < sz; ++q) acc += Tp[o + r + (o + q) * QR_PW] * Xp[o + q + c2 * QR_PW];
+        Tp[o + r + c2 * QR_PW] = -acc;
+      }
+    }
+    __syncthreads();
+  }
+  // U_p = V_p T_p, rows J..m-1 of tmpB (ld m)
+  double* U = b.tmpB + J;
+  for (int r = threadIdx.x; r < L; r += 256) {
+    for (int c = 0; c < wj; ++c) {
+      double acc = 0.0;
+      for (int i = 0; i <= c; ++i) acc += pan[i * L + r] * Tp[i + c * QR_PW];
+      U[r + (int64_t)c * m] = acc;
+    }
   }
 }
 
@@ -250,15 +305,16 @@ __global__ __launch_bounds__(256) void qr_diag_kernel(const BoxDev* __restrict__
   }
 }
 
-hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, hipStream_t st) {
-  if (nbox <= 0 || max_m <= 0) return hipSuccess;
-  if (max_m > QR_PAN) return hipErrorInvalidValue;
-  const int nb = QR_PAN / max_m;
-  if (nb >= 16) hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(nbox), dim3(256), 0, st, boxes);
-  else if (nb >= 8) hipLaunchKernelGGL(qr_panel_kernel<8>, dim3(nbox), dim3(256), 0, st, boxes);
-  else if (nb >= 4) hipLaunchKernelGGL(qr_panel_kernel<4>, dim3(nbox), dim3(256), 0, st, boxes);
-  else if (nb >= 2) hipLaunchKernelGGL(qr_panel_kernel<2>, dim3(nbox), dim3(256), 0, st, boxes);
-  else hipLaunchKernelGGL(qr_panel_kernel<1>, dim3(nbox), dim3(256), 0, st, boxes);
+int qr_panel_width(int max_m) {
+  if (max_m <= 0) return QR_PW;
+  return std::max(1, std::min(QR_PW, QR_PAN / max_m));
+}
+
+hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, int J, int w,
+                           hipStream_t st) {
+  if (nbox <= 0) return hipSuccess;
+  if (w < 1 || w > QR_PW || (int64_t)max_m * w > QR_PAN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(qr_panel_kernel, dim3(nbox), dim3(256), 0, st, boxes, J, w);
   return hipGetLastError();
 }
 

@@ -91,16 +91,28 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       item_of_t[q] = hit;
     }
   }
+  // Chunks of 64 rows (boundaries independent of addresses, so that results
+  // are reproducible across handles and runs).
+  auto chunk_starts = [](const Item& it) {
+    std::vector<int> r;
+    for (int r0 = 0; r0 < it.mr; r0 += 64) r.push_back(r0);
+    r.push_back(it.mr);
+    return r;
+  };
   // slots, chunks and bytes
   int64_t off = 0;
-  for (Item& it : items) {
-    const int nck = (it.mr + 63) / 64;
+  std::vector<int> nck_of(items.size());
+  for (size_t ii = 0; ii < items.size(); ++ii) {
+    Item& it = items[ii];
+    const std::vector<int> rs = chunk_starts(it);
+    const int nck = (int)rs.size() - 1;
+    nck_of[ii] = nck;
     if (it.dq >= 0) { it.od = off; off += it.mr; }
     if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
     const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
     const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
     for (int c = 0; c < nck; ++c) {
-      const int r0 = 64 * c;
+      const int r0 = rs[c];
       GChunk ch;
       ch.M = it.M + r0;
       ch.xd = nd ? nd->x : nullptr;
@@ -108,7 +120,7 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       ch.ld = it.ld;
       ch.ldxd = nd ? nd->ldx : 1;
       ch.ldxt = nt ? nt->ldx : 1;
-      ch.nr = std::min(64, it.mr - r0);
+      ch.nr = rs[c + 1] - r0;
       ch.mc = it.mc;
       ch.dlen = it.mr;
       ch.drow = r0;
@@ -132,8 +144,8 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     for (int q = g.t0; q < g.t1; ++q)
       if (item_of_t[q] >= 0) {
         const Item& it = items[item_of_t[q]];
-        const int nck = (it.mr + 63) / 64;
-        for (int c = 0; c < nck; ++c) out.offs.push_back(it.ot0 + (int64_t)c * it.mc);
+        for (int c = 0; c < nck_of[item_of_t[q]]; ++c)
+          out.offs.push_back(it.ot0 + (int64_t)c * it.mc);
       }
     r.s1 = (int)out.offs.size();
     out.reds.push_back(r);
@@ -522,6 +534,11 @@ h2_status autotune(Ctx& c, hipStream_t st) {
       h2_status e = tune(*b, 0);
       if (e != H2_OK) return e;
     }
+    for (size_t p = 0; p < S.g_pz.size(); ++p)
+      for (Batch<GemmDesc>* b : {&S.g_pz[p], &S.g_pu[p]}) {
+        h2_status e = tune(*b, 0);
+        if (e != H2_OK) return e;
+      }
     for (size_t p = 1; p < S.g_t1.size(); ++p)
       for (Batch<GemmDesc>* b : {&S.g_t1[p], &S.g_t2[p]}) {
         h2_status e = tune(*b, 0);
@@ -569,7 +586,11 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(mark(FP_QR));
     if (h == 0) HIPCHK(run_copy(S.c_w, st));
     else HIPCHK(run_gemm(S.g_w, st));
-    HIPCHK(launch_qr_panel(S.qr.d, S.qr.count, S.qr.max_rows, st));
+    for (size_t pp = 0; pp < S.g_pz.size(); ++pp) {  // one entry per panel
+      HIPCHK(launch_qr_panel(S.qr.d, S.qr.count, S.qr.max_rows, (int)pp * S.qr_w, S.qr_w, st));
+      HIPCHK(run_gemm(S.g_pz[pp], st));
+      HIPCHK(run_gemm(S.g_pu[pp], st));
+    }
     HIPCHK(run_gemm(S.g_qr1, st));
     HIPCHK(launch_qr_tdiag(S.qr.d, S.qr.count, S.max_k, st));
     for (size_t q = 1; q < S.g_t1.size(); ++q) {
