@@ -95,6 +95,9 @@ def main():
                     help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="precision of the basis-transform and Schur-update GEMMs")
+    ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the factor copies the substitution reads (the H^2 matvec, "
+                         "the refinement and all arithmetic stay FP64)")
     ap.add_argument("--rank-model", action="store_true",
                     help="train the rank predictor on smaller seeded builds first (untimed) "
                          "and size the basis buffers with it")
@@ -126,6 +129,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     prec = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16}[a.prec]
+    sprec = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32}[a.solve_prec]
     model = None
     if a.rank_model:
         import numpy as np
@@ -147,14 +151,14 @@ def main():
         H = h2.build_batched([q.points for q in p], [q.kernel for q in p], a.leaf, 1.0, a.eps,
                              perms=[q.perm() for q in p], s_far=a.s, s_near=a.s, gemm_prec=prec,
                              ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=True,
-                             use_graph=a.graph)
+                             use_graph=a.graph, solve_prec=sprec)
         bnp = np.concatenate([q.b() for q in p], axis=0)
         n_total = sum(q.n for q in p)
     else:
         H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
                      s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
                      gemm_prec=prec, rank_model=model, use_graph=a.graph,
-                     use_pcg=not a.stationary)
+                     use_pcg=not a.stationary, solve_prec=sprec)
         bnp = p.b()
         n_total = p.n
     t_build = time.perf_counter() - t0
@@ -178,7 +182,7 @@ def main():
               flush=True)
     torch.cuda.synchronize()
     t_fac = t_sol = t_pair = 0.0
-    t_phase = [0.0] * 8
+    t_phase = [0.0] * 9
     t_g = [0.0, 0.0]
     b_g = [0.0, 0.0]
     n_g = [0, 0]
@@ -214,12 +218,14 @@ def main():
         "metric": "H2-ULV factor+solve TFLOP/s at N=2^20 (rel. residual <= 1e-8 vs FP64 H2 operator)",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f64"}[a.prec],
+        "vs_baseline": None,
+        "dtype": "f64" if a.prec == "fp64" and a.solve_prec == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": a.kernel if a.kernel == "gaussian_batch" else f"{a.kernel}_cube",
                    "n": n_total, "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
                    "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s, "nrhs": 1,
-                   "gemm_prec": a.prec, "rank_model": a.rank_model, "graph": a.graph,
+                   "gemm_prec": a.prec, "solve_prec": a.solve_prec, "rank_model": a.rank_model,
+                   "graph": a.graph,
                    "rank_fallbacks": st_all["rank_fallbacks"], "basis_bytes": st_all["bytes_basis"],
                    "autotuned_lists": st_all["tuned_lists"], "tile_choice": st_all["tuned_cfg_hist"],
                    "ir_tol": a.tol, "levels": st["levels"], "root_n": st["root_n"],
@@ -227,7 +233,8 @@ def main():
         "factor_s": t_fac / K,
         "factor_phase_s": dict(zip(["basis_qr", "diag_transform", "rr_cholesky_inverse",
                                     "v_schur", "near_pair_transform", "far_coupling", "merge",
-                                    "root"], [round(x / K, 5) for x in t_phase])),
+                                    "root", "solve_copies_fp32"],
+                                   [round(x / K, 5) for x in t_phase])),
         "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
         "build_s": t_build, "flops_factor": st["flops_factor"], "flops_solve": st["flops_solve"],
     }

@@ -81,8 +81,13 @@ typedef struct {
   int32_t use_graph;      /* 1 = capture factor launches in a hipGraph           */
   const float* rank_model;/* host, 4801 MLP weights; NULL = plain pivoted QR    */
   double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
-  int32_t timing;         /* 1 = time the near-pair transform launches of factor */
+  int32_t timing;         /* 1 = time factor phases and solve gathers (events)   */
   int32_t no_autotune;    /* 1 = skip the tile-shape autotuner (64x64 tiles)     */
+  int32_t solve_prec;     /* h2_prec (FP64 or FP32) in which the substitution
+                             reads the factors: FP32 copies of the transformed
+                             near blocks and bases are made at the end of
+                             h2_factor; arithmetic, the root, the H^2 matvec
+                             and the refinement stay FP64                       */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -121,11 +126,11 @@ typedef struct {
                              stored block once plus x slices and partial
                              products, [1] partials, base and y once          */
   int32_t gather_launches[2]; /* number of timed launches of each kind           */
-  double t_factor_phase[8]; /* seconds of the last factor per phase (HIP events;
+  double t_factor_phase[9]; /* seconds of the last factor per phase (HIP events;
                                params.timing = 1, no graph): basis QR, diagonal
                                transform, RR Cholesky + inverse, V and Schur
                                update, near-pair transforms, far couplings,
-                               merge, root                                      */
+                               merge, root, FP32 copies for the substitution  */
 } h2_stats_t;
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).

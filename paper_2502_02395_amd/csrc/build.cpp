@@ -105,6 +105,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   if (prm->dim != 2 && prm->dim != 3) return H2_ERR_ARG;
   if (prm->leaf < 2 || !(prm->eps >= 0.0) || !(prm->eta >= 0.0)) return H2_ERR_ARG;
   if (prm->s_far < -1 || prm->s_near < -1 || prm->max_rank < 0) return H2_ERR_ARG;
+  if (prm->solve_prec != H2_PREC_FP64 && prm->solve_prec != H2_PREC_FP32) return H2_ERR_ARG;
   if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
       prm->gemm_prec != H2_PREC_BF16)
     return H2_ERR_ARG;

@@ -35,6 +35,7 @@ struct GList {
   int max_rows = 0;
   int64_t plen = 0;
   double bytes_ch_mat = 0.0, bytes_ch_vec = 0.0, bytes_rd = 0.0;
+  bool f32 = false;                        // blocks read from FP32 copies
 };
 
 // One height step h above the leaves: level L_t - h of every instance t with
@@ -72,6 +73,7 @@ struct Step {
   double *dQ = nullptr, *dP = nullptr, *dTA = nullptr, *dTB = nullptr;  // at qoff
   double* dW = nullptr;                    // QR workspace at qoff
   double* dTau = nullptr;                  // Householder scalars at koff
+  float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
   double* dR = nullptr;                    // at rkoff
   double* dLi = nullptr;                   // at lioff
   // factor work lists

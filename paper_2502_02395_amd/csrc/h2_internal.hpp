@@ -176,7 +176,7 @@ struct GatherNbr {
   int ldB, ldx, cols;       // cols: summation length
 };
 struct GChunk {
-  const double* M;          // first row of the chunk (column-major, ld)
+  const void* M;            // first row of the chunk (column-major, ld; FP64 or FP32)
   const double* xd;         // direct x: mc entries per rhs (ld ldxd), or NULL
   const double* xt;         // trans x: this chunk's nr entries per rhs (ld ldxt), or NULL
   int ld, ldxd, ldxt;
@@ -191,7 +191,14 @@ struct GRed {
   double alpha;
   int s0, s1;               // slot range in the offset array
 };
+// A range of FP64 blocks with an FP32 copy at base32 (same offsets).
+struct Rebase {
+  const double* base;
+  int64_t n;
+  const float* base32;
+};
 struct GatherPlan {
+  bool f32 = false;           // blocks read from FP32 copies
   std::vector<GChunk> chunks;
   std::vector<GRed> reds;
   std::vector<int64_t> offs;  // slot offsets, grouped per box
@@ -202,9 +209,14 @@ struct GatherPlan {
   double bytes_chunks_mat = 0.0, bytes_chunks_vec = 0.0;
   double bytes_red = 0.0;
 };
-void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                 GatherPlan& out);
-hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st);
+// rb non-empty: every block must lie in one of its ranges and is read from
+// the FP32 copy (returns false otherwise).
+bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
+                 GatherPlan& out, const std::vector<Rebase>& rb = {});
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
+                          hipStream_t st);
+// FP32 copy of n doubles.
+hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 

@@ -39,8 +39,10 @@ __device__ __forceinline__ double reduce8(const double (&v)[8], int lane) {
 
 // Global-address-space view of a pointer: plain global loads instead of
 // flat ones (the pointers arrive through descriptors).
-typedef const double __attribute__((address_space(1)))* gcptr;
-__device__ __forceinline__ gcptr as_global(const double* p) { return (gcptr)p; }
+template <typename T>
+using gptr_t = const T __attribute__((address_space(1)))*;
+template <typename T>
+__device__ __forceinline__ gptr_t<T> as_global(const T* p) { return (gptr_t<T>)p; }
 
 // Value of v in lane l (l uniform), through the scalar unit.
 __device__ __forceinline__ double bcast(double v, int l) {
@@ -50,26 +52,32 @@ __device__ __forceinline__ double bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One batch of 16 columns starting at column sb (16 loads in flight per
-// lane); xv[c] holds x_d of the current 64 columns, one per lane, and bo is
-// the batch's first column within them.  Rows past the chunk read the chunk's last row (always in bounds);
-// their x_t is zero and their direct sums are never stored.
-template <int NR, bool FULL>
-__device__ __forceinline__ void gchunk_cols(gcptr col, int64_t ld, int sb, int mc, int lane,
+// One batch of BW = 16 columns starting at column sb (16 loads in flight per
+// lane; 32 for FP32 blocks measured slower: the registers cost occupancy);
+// xv[c] holds x_d of the current 64
+// columns, one per lane, and bo is the batch's first column within them.
+// Rows past the chunk read the chunk's last row (always in bounds); their
+// x_t is zero and their direct sums are never stored.
+template <typename T>
+constexpr int batch_width() { return 16; }
+
+template <int NR, bool FULL, typename T>
+__device__ __forceinline__ void gchunk_cols(gptr_t<T> col, int64_t ld, int sb, int mc, int lane,
                                             int nrhs, const double (&xv)[NR], int bo,
                                             const double (&xt)[NR], double (&acc)[NR],
                                             double (&tq)[NR], bool dir, bool tr, int bi) {
-  double bv[16];
+  constexpr int BW = batch_width<T>();
+  T bv[BW];
 #pragma unroll
-  for (int u = 0; u < 16; ++u)
-    bv[u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col + (int64_t)u * ld) : 0.0;
+  for (int u = 0; u < BW; ++u)
+    bv[u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col + (int64_t)u * ld) : T(0);
   if (dir) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (FULL || sb + u < mc) acc[c] += bv[u] * bcast(xv[c], bo + u);
+      for (int u = 0; u < BW; ++u)
+        if (FULL || sb + u < mc) acc[c] += (double)bv[u] * bcast(xv[c], bo + u);
     }
   }
   if (tr) {
@@ -77,10 +85,10 @@ __device__ __forceinline__ void gchunk_cols(gcptr col, int64_t ld, int sb, int m
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < BW / 8; ++h) {
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = bv[8 * h + u] * xt[c];
+        for (int u = 0; u < 8; ++u) v[u] = (double)bv[8 * h + u] * xt[c];
         const double q = reduce8(v, lane);
         if ((lane & 7) == bi + h) tq[c] = q;
       }
@@ -88,7 +96,7 @@ __device__ __forceinline__ void gchunk_cols(gcptr col, int64_t ld, int sb, int m
   }
 }
 
-template <int NR>
+template <int NR, typename T>
 __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict__ P, int nrhs,
                                            int lane) {
   const bool live = lane < ch.nr;
@@ -101,7 +109,7 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
     xt[c] = (tr && live && c < nrhs) ? as_global(ch.xt)[lane + (int64_t)c * ch.ldxt] : 0.0;
   }
   const int64_t ld = ch.ld;
-  const gcptr base = as_global(ch.M) + row;
+  const gptr_t<T> base = as_global(static_cast<const T*>(ch.M)) + row;
   for (int s0 = 0; s0 < ch.mc; s0 += 64) {
     const int ns = min(64, ch.mc - s0);
     double tq[NR], xv[NR];
@@ -111,12 +119,13 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
       xv[c] = (dir && lane < ns && c < nrhs) ? as_global(ch.xd)[s0 + lane + (int64_t)c * ch.ldxd]
                                              : 0.0;
     }
+    constexpr int BW = batch_width<T>();
     int b = 0;
-    for (; b + 16 <= ns; b += 16)
-      gchunk_cols<NR, true>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
+    for (; b + BW <= ns; b += BW)
+      gchunk_cols<NR, true, T>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
                             xt, acc, tq, dir, tr, b >> 3);
-    if (b < ns)
-      gchunk_cols<NR, false>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
+    for (; b < ns; b += BW)
+      gchunk_cols<NR, false, T>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
                              xt, acc, tq, dir, tr, b >> 3);
     if (tr) {
       const int cc = 8 * (lane & 7) + (lane >> 3);
@@ -131,12 +140,12 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
 }
 
 
-template <int NR>
+template <int NR, typename T>
 __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,
                                                      double* __restrict__ P, int nrhs) {
   const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (w >= nch) return;
-  gchunk_one<NR>(chunks[w], P, nrhs, threadIdx.x & 63);
+  gchunk_one<NR, T>(chunks[w], P, nrhs, threadIdx.x & 63);
 }
 
 template <int NR>
@@ -161,15 +170,22 @@ __global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ r
   }
 }
 
-hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st) {
+template <typename T>
+static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st) {
+  const dim3 grid((nch + 3) / 4), blk(256);
+  if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 2) hipLaunchKernelGGL((gchunk_kernel<2, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 4) hipLaunchKernelGGL((gchunk_kernel<4, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 8) hipLaunchKernelGGL((gchunk_kernel<8, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else hipLaunchKernelGGL((gchunk_kernel<16, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+}
+
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
+                          hipStream_t st) {
   if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
-  const dim3 grid((nch + 3) / 4), blk(256);
-  if (nrhs == 1) hipLaunchKernelGGL(gchunk_kernel<1>, grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 2) hipLaunchKernelGGL(gchunk_kernel<2>, grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 4) hipLaunchKernelGGL(gchunk_kernel<4>, grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 8) hipLaunchKernelGGL(gchunk_kernel<8>, grid, blk, 0, st, ch, nch, P, nrhs);
-  else hipLaunchKernelGGL(gchunk_kernel<16>, grid, blk, 0, st, ch, nch, P, nrhs);
+  if (f32) launch_gchunks_t<float>(ch, nch, P, nrhs, st);
+  else launch_gchunks_t<double>(ch, nch, P, nrhs, st);
   return hipGetLastError();
 }
 

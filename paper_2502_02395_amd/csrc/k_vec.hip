@@ -67,6 +67,19 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
 }
 
 // ------------------------------------------------------------ vector utilities
+__global__ __launch_bounds__(256) void cvt_f32_kernel(const double* __restrict__ src,
+                                                      float* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = (float)src[i];
+}
+
+hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(cvt_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
 __global__ void gather_rows_kernel(const int64_t* idx, int64_t n, int nrhs, const double* src,
                                    int64_t lds, double* dst, int64_t ldd) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;

@@ -40,9 +40,17 @@ static int local_box(const Step& S, int t, int i) {
 }
 
 // ------------------------------------------------------------ gather plans
-void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                 GatherPlan& out) {
+bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
+                 GatherPlan& out, const std::vector<Rebase>& rb) {
   out = GatherPlan();
+  out.f32 = !rb.empty();
+  const double esz = out.f32 ? 4.0 : 8.0;
+  // the FP32 copy of a block pointer, or nullptr
+  auto to32 = [&](const double* p) -> const float* {
+    for (const Rebase& r : rb)
+      if (p >= r.base && p < r.base + r.n) return r.base32 + (p - r.base);
+    return nullptr;
+  };
   struct Item {
     const double* M;
     int ld, mr, mc;
@@ -111,10 +119,12 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
     const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
     const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
+    const float* M32 = out.f32 ? to32(it.M) : nullptr;
+    if (out.f32 && !M32) return false;
     for (int c = 0; c < nck; ++c) {
       const int r0 = rs[c];
       GChunk ch;
-      ch.M = it.M + r0;
+      ch.M = out.f32 ? static_cast<const void*>(M32 + r0) : static_cast<const void*>(it.M + r0);
       ch.xd = nd ? nd->x : nullptr;
       ch.xt = nt ? nt->x + r0 : nullptr;
       ch.ld = it.ld;
@@ -128,7 +138,7 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       ch.ot = nt ? it.ot0 + (int64_t)c * it.mc : -1;
       out.chunks.push_back(ch);
     }
-    out.bytes_chunks_mat += 8.0 * it.mr * it.mc;
+    out.bytes_chunks_mat += esz * it.mr * it.mc;
     if (nd) out.bytes_chunks_vec += 8.0 * (it.mc + it.mr);                  // x_d, slot
     if (nt) out.bytes_chunks_vec += 8.0 * (it.mr + (double)nck * it.mc);    // x_t, slots
   }
@@ -151,14 +161,17 @@ void plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     out.reds.push_back(r);
     out.bytes_red += 8.0 * g.rows * ((r.s1 - r.s0) + 1 + (g.base ? 1 : 0));
   }
+  return true;
 }
 
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
-                      const std::vector<GatherNbr>& Nv, hipStream_t st);
+                      const std::vector<GatherNbr>& Nv, hipStream_t st,
+                      const std::vector<Rebase>& rb = {});
 
 // Per-box products D = alpha op(A) B + beta C (beta 0, or 1 with C == D) as
 // gathers with one neighbour: A direct (tA = 0) or transposed (tA = 1).
-static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_t st) {
+static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_t st,
+                    const std::vector<Rebase>& rb = {}) {
   std::vector<GatherBox> B;
   std::vector<GatherNbr> Nv;
   for (const GemmDesc& g : v) {
@@ -169,13 +182,15 @@ static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_
     if (g.tA) x.t1 = q + 1; else x.d1 = q + 1;
     B.push_back(x);
   }
-  return up_gather(c, L, B, Nv, st);
+  return up_gather(c, L, B, Nv, st, rb);
 }
 
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
-                      const std::vector<GatherNbr>& Nv, hipStream_t st) {
+                      const std::vector<GatherNbr>& Nv, hipStream_t st,
+                      const std::vector<Rebase>& rb) {
   GatherPlan p;
-  plan_gather(B, Nv, p);
+  if (!plan_gather(B, Nv, p, rb)) return false;
+  L.f32 = p.f32;
   L.max_rows = p.max_rows;
   L.plen = p.plen;
   L.bytes_ch_mat = p.bytes_chunks_mat;
@@ -208,7 +223,7 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(L.ch.d, L.ch.count, c.dPart, nrhs, st)) != hipSuccess) return e;
+  if ((e = launch_gchunks(L.ch.d, L.ch.count, c.dPart, nrhs, L.f32, st)) != hipSuccess) return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
   if ((e = launch_greduce(L.rd.d, L.rd.count, L.max_rows, L.offs.d, c.dPart, nrhs, st)) !=
       hipSuccess)
@@ -461,11 +476,20 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, dst, cld, dst, cld, m, NR, k, 1.0, 1.0));
       }
     }
-    if (!up_thin(c, S.t_fwd, tf, st) || !up_thin(c, S.t_bwd, tb, st) || !up_thin(c, S.t_up, tu, st) ||
-        !up_thin(c, S.t_down, td, st) || !up_gather(c, S.g_yr, b1, n1, st) ||
-        !up_gather(c, S.g_cs, b2, n2, st) || !up_gather(c, S.g_t, b3, n3, st) ||
-        !up_gather(c, S.g_s, b4, n4, st) || !up_gather(c, S.g_cpl, bc, nc, st) ||
-        !up_gather(c, S.g_near, bn, nn, st))
+    // the substitution may read FP32 copies of F and P; the matvec reads FP64
+    std::vector<Rebase> rb;
+    if (c.prm.solve_prec == H2_PREC_FP32) {
+      S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff.back(), 1));
+      S.dP32 = c.alloc<float>(std::max<int64_t>(S.qoff[S.nbox], 1));
+      ALLOCHK(S.dF32); ALLOCHK(S.dP32);
+      rb.push_back({S.dF, S.poff.back(), S.dF32});
+      rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
+    }
+    if (!up_thin(c, S.t_fwd, tf, st, rb) || !up_thin(c, S.t_bwd, tb, st, rb) ||
+        !up_thin(c, S.t_up, tu, st) || !up_thin(c, S.t_down, td, st) ||
+        !up_gather(c, S.g_yr, b1, n1, st, rb) || !up_gather(c, S.g_cs, b2, n2, st, rb) ||
+        !up_gather(c, S.g_t, b3, n3, st, rb) || !up_gather(c, S.g_s, b4, n4, st, rb) ||
+        !up_gather(c, S.g_cpl, bc, nc, st) || !up_gather(c, S.g_near, bn, nn, st))
       return H2_ERR_ALLOC;
   }
   // root solves and root-only instances
@@ -559,13 +583,15 @@ h2_status autotune(Ctx& c, hipStream_t st) {
 
 // Phases of the factorization timed with params.timing (events from a pool
 // in the handle, read after the factorization without stalling it).
-enum FactorPhase { FP_QR, FP_DIAG, FP_CHOL, FP_VS, FP_PAIR, FP_FAR, FP_MERGE, FP_ROOT, FP_N };
+enum FactorPhase {
+  FP_QR, FP_DIAG, FP_CHOL, FP_VS, FP_PAIR, FP_FAR, FP_MERGE, FP_ROOT, FP_F32, FP_N
+};
 
 h2_status do_factor(Ctx& c, hipStream_t st) {
   HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
   const bool timing = c.prm.timing != 0 && !c.prm.use_graph;
   if (timing && c.fev.empty()) {
-    c.fev.resize(2 * FP_N * (c.H + 1), nullptr);
+    c.fev.resize(2 * FP_N * (c.H + 2), nullptr);
     for (auto& e : c.fev) HIPCHK(hipEventCreate(&e));
   }
   c.fev_phase.clear();
@@ -644,13 +670,21 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_copy(c.r_back[p], st));
   }
   HIPCHK(done());
+  if (c.prm.solve_prec == H2_PREC_FP32) {
+    HIPCHK(mark(FP_F32));
+    for (auto& S : c.steps) {
+      HIPCHK(launch_cvt_f32(S.dF, S.dF32, S.poff.back(), st));
+      HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
+    }
+    HIPCHK(done());
+  }
   c.fev_used = ne;
   return H2_OK;
 }
 
 // After the factorization has completed: per-phase seconds into the stats.
 h2_status collect_factor_times(Ctx& c) {
-  for (int q = 0; q < 8; ++q) c.st.t_factor_phase[q] = 0.0;
+  for (int q = 0; q < FP_N; ++q) c.st.t_factor_phase[q] = 0.0;
   for (size_t i = 0; 2 * i + 1 < c.fev_used; ++i) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c.fev[2 * i], c.fev[2 * i + 1]));

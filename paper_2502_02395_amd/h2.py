@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
                 ("ir_max_iter", ctypes.c_int32), ("ir_tol", ctypes.c_double),
                 ("use_pcg", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
-                ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32),
+                ("solve_prec", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +61,7 @@ class Stats(ctypes.Structure):
                 ("tuned_cfg_hist", ctypes.c_int32 * 4),
                 ("t_gather", ctypes.c_double * 2), ("bytes_gather", ctypes.c_double * 2),
                 ("gather_launches", ctypes.c_int32 * 2),
-                ("t_factor_phase", ctypes.c_double * 8)]
+                ("t_factor_phase", ctypes.c_double * 9)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -136,7 +137,7 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
                 max_rank: int = 0, gemm_prec: int = PREC_FP64, ir_max_iter: int = 0,
                 ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
                 timing: bool = False, rank_model=None, rank_margin: float = 0.25,
-                autotune: bool = True) -> Params:
+                autotune: bool = True, solve_prec: int = PREC_FP64) -> Params:
     """rank_model: numpy float32 array of the 4801 predictor weights (kept alive
     by the caller for the duration of the build call)."""
     ptr = None
@@ -145,7 +146,8 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
         assert rank_model.flags["C_CONTIGUOUS"]
         ptr = rank_model.ctypes.data
     return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
-                  int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune))
+                  int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune),
+                  int(solve_prec))
 
 
 def _as_cols(t, n):
