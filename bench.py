@@ -1,11 +1,14 @@
 """Benchmark: H^2-ULV factor + solve at N = 2^20 on one MI355X.
 
-One step = h2_factor + h2_solve (parallel substitution with iterative
-refinement against the FP64 H^2 operator down to a relative residual of
-1e-8) on a resident H^2 matrix of 2^20 points; the H^2 construction runs once
-before the timed region.  Prints one JSON line.
+One step = h2_factor + h2_solve (the parallel substitution as the
+preconditioner of CG against the FP64 H^2 operator, down to a relative
+residual of 1e-8) on a resident H^2 matrix of 2^20 points; the H^2
+construction runs once before the timed region.  The default run times the
+target path (rank-predicted basis buffers, FP32 copies of the factors for the
+substitution, FP64 arithmetic) next to the plain FP64 path and prints one JSON
+line with both.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--path target|plain|custom]
 """
 from __future__ import annotations
 
@@ -23,15 +26,12 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector = matrix)
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
-# second run, WRITE_SIZE on this workload (one factor + one solve), each scaled
-# by the counter's reading for a plain 1 GiB device copy (FETCH_SIZE reads half
-# of the bytes moved: factor 2.0; WRITE_SIZE factor 1.0).  Valid only for the
-# kernel source they were taken on: a changed source reports null.
-MEASURED_TRAFFIC = {
-    "gchunk_kernel": {"src": "paper_2502_02395_amd/csrc/k_gather.hip",
-                      "sha256": "1708905bd655a4d2ce0750895463ad33a0fdd3b158cce1a5de8aaa82f0357b57",
-                      "bytes_per_launch": 2.237e9 + 0.033e9},
-}
+# second run, WRITE_SIZE on this workload (the default target path, one factor
+# + one solve), each scaled by the counter's reading for a plain 1 GiB device
+# copy (FETCH_SIZE reads half of the bytes moved: factor 2.0; WRITE_SIZE
+# factor 1.0).  Valid only for the sources they were taken on (the kernel and
+# the planner that shapes its launches): a changed source reports null.
+MEASURED_TRAFFIC = {}
 
 
 def measured_traffic(kernel: str):
@@ -39,10 +39,11 @@ def measured_traffic(kernel: str):
     m = MEASURED_TRAFFIC.get(kernel)
     if m is None:
         return None
-    with open(os.path.join(ROOT, m["src"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
-            return None
-    return m["bytes_per_launch"]
+    h = hashlib.sha256()
+    for src in m["src"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return m["bytes_per_launch"] if h.hexdigest() == m["sha256"] else None
 
 
 def workload(n: int, kernel: str, eps: float, leaf: int, s: int):
@@ -85,6 +86,125 @@ def cpu_baseline(kernel: str, eps: float, leaf: int, s: int, n_sample: int) -> d
                       f"steps, residual {hist[-1]:.1e}); canonical flops {total:.3e}"}
 
 
+def train_rank_model(a, h2):
+    """Train the rank predictor on three smaller seeded builds of the same
+    workload (2^16 points each); untimed."""
+    import workloads as W
+    from paper_2502_02395_amd import rank_model
+    train_ps = []
+    for sd in (100, 101, 102):
+        q = workload(1 << 16, a.kernel, a.eps, a.leaf, a.s)
+        q.points = W.cube_points(1 << 16, 3, sd)
+        train_ps.append(q)
+    X, y = rank_model.collect(train_ps)
+    model, hist = rank_model.train(X, y, steps=2000, lr=3e-3)
+    print(f"[bench] rank model trained on {len(y)} boxes, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
+          file=sys.stderr, flush=True)
+    return model
+
+
+def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
+    """Build once (untimed), W warm-up steps, then time K steps of factor +
+    solve with the inputs resident in HBM."""
+    import torch
+    p = workload(a.n, a.kernel, a.eps, a.leaf, a.s)
+    t0 = time.perf_counter()
+    if a.kernel == "gaussian_batch":
+        import numpy as np
+        H = h2.build_batched([q.points for q in p], [q.kernel for q in p], a.leaf, 1.0, a.eps,
+                             perms=[q.perm() for q in p], s_far=a.s, s_near=a.s, gemm_prec=prec,
+                             ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=True,
+                             use_graph=a.graph, solve_prec=sprec)
+        bnp = np.concatenate([q.b() for q in p], axis=0)
+        n_total = sum(q.n for q in p)
+    else:
+        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
+                     gemm_prec=prec, rank_model=model, use_graph=a.graph,
+                     use_pcg=not a.stationary, solve_prec=sprec)
+        bnp = p.b()
+        n_total = p.n
+    t_build = time.perf_counter() - t0
+    b = torch.from_numpy(bnp).cuda()
+    cols_b = b.t().contiguous()
+    cols_x = torch.empty_like(cols_b)
+    print(f"[bench] {label}: built N={n_total} in {t_build:.1f}s: {H.stats()['levels']} levels",
+          file=sys.stderr, flush=True)
+    for w in range(a.warmup):
+        H.factor()
+        s = H.solve_into(cols_b, cols_x)
+        if s != h2.OK:
+            raise h2.H2Error(s, "h2_solve")
+        st = H.stats()
+        print(f"[bench] {label} warmup {w}: factor {st['t_factor']:.3f}s solve "
+              f"{st['t_solve']:.3f}s ({st['ir_iters']} iterations, residual "
+              f"{st['ir_residual']:.1e})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    K = a.steps
+    t_fac = t_sol = t_pair = 0.0
+    t_phase = [0.0] * 9
+    t_g, b_g, n_g = [0.0] * 3, [0.0] * 3, [0] * 3
+    iters = 0
+    res = 0.0
+    t0 = time.perf_counter()
+    for k in range(K):
+        H.factor()
+        st = H.stats()
+        t_fac += st["t_factor"]
+        t_pair += st["t_pair_gemm"]
+        t_phase = [x + y for x, y in zip(t_phase, st["t_factor_phase"])]
+        s = H.solve_into(cols_b, cols_x)
+        if s != h2.OK:
+            raise h2.H2Error(s, "h2_solve")
+        st = H.stats()
+        t_sol += st["t_solve"]
+        for q in range(3):
+            t_g[q] += st["t_gather"][q]
+            b_g[q] += st["bytes_gather"][q]
+            n_g[q] += st["gather_launches"][q]
+        iters += st["ir_iters"]
+        res = max(res, st["ir_residual"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = H.stats()
+    H.close()
+    flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
+    # Kernels of the timed steps with their work per launch over their average
+    # launch time (HIP events on the launch stream), largest total time first:
+    # the neighbour gathers of the substitution and the matvec (HBM-bound; FP64
+    # blocks and FP32 copies are separate instances) and the near-pair
+    # transform GEMMs of the factorization (MFMA-bound).  A captured
+    # factorization is not timed per launch.
+    cands = []
+    if t_pair > 0:
+        tf = st["flops_pair_gemm"] * K / t_pair / 1e12
+        cands.append({"bound": "mfma", "kernel": "gemm_f64_pair_kernel", "achieved": tf,
+                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+                      "traffic": None, "launches": st["pair_launches"] * K,
+                      "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1),
+                      "total_s": t_pair})
+    for q, kname in ((0, "gchunk_kernel<f64>"), (1, "gchunk_kernel<f32>"),
+                     (2, "greduce_kernel")):
+        if n_g[q] == 0:
+            continue
+        gbs = b_g[q] / max(t_g[q], 1e-30) / 1e9
+        cands.append({"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                      "traffic": measured_traffic(kname), "launches": n_g[q],
+                      "avg_launch_ms": 1e3 * t_g[q] / n_g[q], "bytes_per_launch": b_g[q] / n_g[q],
+                      "total_s": t_g[q]})
+    cands.sort(key=lambda d: -d["total_s"])
+    return {
+        "value": flops_step * K / dt / 1e12, "ms_per_step": 1e3 * dt / K, "n_total": n_total,
+        "factor_s": t_fac / K, "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
+        "build_s": t_build, "stats": st, "cands": cands,
+        "factor_phase_s": dict(zip(["basis_qr", "diag_transform", "rr_cholesky_inverse",
+                                    "v_schur", "near_pair_transform", "far_coupling", "merge",
+                                    "root", "solve_copies_fp32"],
+                                   [round(x / K, 5) for x in t_phase])),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,14 +213,18 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--kernel", default="yukawa",
                     help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
+    ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
+                    help="target: rank-predicted buffers and FP32 copies for the substitution, "
+                         "timed next to the plain FP64 path (default); plain: the FP64 path "
+                         "only; custom: --prec / --solve-prec / --rank-model as given")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
-                    help="precision of the basis-transform and Schur-update GEMMs")
+                    help="custom path: precision of the basis-transform and Schur-update GEMMs")
     ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32"],
-                    help="precision of the factor copies the substitution reads (the H^2 matvec, "
-                         "the refinement and all arithmetic stay FP64)")
+                    help="custom path: precision of the factor copies the substitution reads "
+                         "(the H^2 matvec, the refinement and all arithmetic stay FP64)")
     ap.add_argument("--rank-model", action="store_true",
-                    help="train the rank predictor on smaller seeded builds first (untimed) "
-                         "and size the basis buffers with it")
+                    help="custom path: train the rank predictor on smaller seeded builds first "
+                         "(untimed) and size the basis buffers with it")
     ap.add_argument("--graph", action="store_true", help="capture the factorization in a hipGraph")
     ap.add_argument("--stationary", action="store_true",
                     help="stationary iterative refinement instead of PCG")
@@ -128,140 +252,53 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    prec = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16}[a.prec]
-    sprec = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32}[a.solve_prec]
-    model = None
-    if a.rank_model:
-        import numpy as np
-        import workloads as W
-        from paper_2502_02395_amd import rank_model
-        train_ps = []
-        for sd in (100, 101, 102):
-            q = workload(1 << 16, a.kernel, a.eps, a.leaf, a.s)
-            q.points = W.cube_points(1 << 16, 3, sd)
-            train_ps.append(q)
-        X, y = rank_model.collect(train_ps)
-        model, hist = rank_model.train(X, y, steps=2000, lr=3e-3)
-        print(f"[bench] rank model trained on {len(y)} boxes, loss {hist[0]:.3f} -> {hist[-1]:.4f}",
-              file=sys.stderr, flush=True)
-    p = workload(a.n, a.kernel, a.eps, a.leaf, a.s)
-    t0 = time.perf_counter()
-    if a.kernel == "gaussian_batch":
-        import numpy as np
-        H = h2.build_batched([q.points for q in p], [q.kernel for q in p], a.leaf, 1.0, a.eps,
-                             perms=[q.perm() for q in p], s_far=a.s, s_near=a.s, gemm_prec=prec,
-                             ir_max_iter=50, ir_tol=a.tol, use_pcg=True, timing=True,
-                             use_graph=a.graph, solve_prec=sprec)
-        bnp = np.concatenate([q.b() for q in p], axis=0)
-        n_total = sum(q.n for q in p)
+    P = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16}
+    plain = None
+    if a.path == "custom":
+        model = train_rank_model(a, h2) if a.rank_model else None
+        setting = (a.prec, a.solve_prec, a.rank_model)
+        r = run_path(a, h2, P[a.prec], P[a.solve_prec], model, "custom")
+    elif a.path == "plain":
+        setting = ("fp64", "fp64", False)
+        r = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain")
     else:
-        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
-                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
-                     gemm_prec=prec, rank_model=model, use_graph=a.graph,
-                     use_pcg=not a.stationary, solve_prec=sprec)
-        bnp = p.b()
-        n_total = p.n
-    t_build = time.perf_counter() - t0
-    b = torch.from_numpy(bnp).cuda()
-    cols_b = b.t().contiguous()
-    cols_x = torch.empty_like(cols_b)
-    print(f"[bench] built N={n_total} in {t_build:.1f}s: {H.stats()['levels']} levels",
-          file=sys.stderr, flush=True)
-
-    def step():
-        H.factor()
-        s = H.solve_into(cols_b, cols_x)
-        if s not in (h2.OK,):
-            raise h2.H2Error(s, "h2_solve")
-
-    for w in range(a.warmup):
-        step()
-        st = H.stats()
-        print(f"[bench] warmup {w}: factor {st['t_factor']:.3f}s solve {st['t_solve']:.3f}s "
-              f"({st['ir_iters']} iterations, residual {st['ir_residual']:.1e})", file=sys.stderr,
-              flush=True)
-    torch.cuda.synchronize()
-    t_fac = t_sol = t_pair = 0.0
-    t_phase = [0.0] * 9
-    t_g = [0.0, 0.0]
-    b_g = [0.0, 0.0]
-    n_g = [0, 0]
-    iters = 0
-    res = 0.0
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        H.factor()
-        st = H.stats()
-        t_fac += st["t_factor"]
-        t_pair += st["t_pair_gemm"]
-        t_phase = [a + b for a, b in zip(t_phase, st["t_factor_phase"])]
-        s = H.solve_into(cols_b, cols_x)
-        if s != h2.OK:
-            raise h2.H2Error(s, "h2_solve")
-        st = H.stats()
-        t_sol += st["t_solve"]
-        for q in range(2):
-            t_g[q] += st["t_gather"][q]
-            b_g[q] += st["bytes_gather"][q]
-            n_g[q] += st["gather_launches"][q]
-        iters += st["ir_iters"]
-        res = max(res, st["ir_residual"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = H.stats()
+        plain = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain fp64")
+        model = train_rank_model(a, h2) if a.kernel != "gaussian_batch" else None
+        setting = ("fp64", "fp32", model is not None)
+        r = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP32, model, "target")
+    st = r["stats"]
     K = a.steps
-    flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
-    value = flops_step * K / dt / 1e12
-    pair_tflops = st["flops_pair_gemm"] * K / max(t_pair, 1e-30) / 1e12
-    st_all = H.stats()
+    mixed = setting[0] != "fp64" or setting[1] != "fp64"
     out = {
         "metric": "H2-ULV factor+solve TFLOP/s at N=2^20 (rel. residual <= 1e-8 vs FP64 H2 operator)",
-        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
-        "ms_per_step": 1e3 * dt / K, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if a.prec == "fp64" and a.solve_prec == "fp64" else "f64+f32",
+        "value": r["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": a.kernel if a.kernel == "gaussian_batch" else f"{a.kernel}_cube",
-                   "n": n_total, "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
+                   "path": a.path, "n": r["n_total"],
+                   "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
                    "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s, "nrhs": 1,
-                   "gemm_prec": a.prec, "solve_prec": a.solve_prec, "rank_model": a.rank_model,
-                   "graph": a.graph,
-                   "rank_fallbacks": st_all["rank_fallbacks"], "basis_bytes": st_all["bytes_basis"],
-                   "autotuned_lists": st_all["tuned_lists"], "tile_choice": st_all["tuned_cfg_hist"],
-                   "ir_tol": a.tol, "levels": st["levels"], "root_n": st["root_n"],
-                   "max_rank": st["max_rank_seen"], "near_pairs": st["near_pairs"]},
-        "factor_s": t_fac / K,
-        "factor_phase_s": dict(zip(["basis_qr", "diag_transform", "rr_cholesky_inverse",
-                                    "v_schur", "near_pair_transform", "far_coupling", "merge",
-                                    "root", "solve_copies_fp32"],
-                                   [round(x / K, 5) for x in t_phase])),
-        "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
-        "build_s": t_build, "flops_factor": st["flops_factor"], "flops_solve": st["flops_solve"],
+                   "gemm_prec": setting[0], "solve_prec": setting[1], "rank_model": setting[2],
+                   "graph": a.graph, "rank_fallbacks": st["rank_fallbacks"],
+                   "basis_bytes": st["bytes_basis"], "autotuned_lists": st["tuned_lists"],
+                   "tile_choice": st["tuned_cfg_hist"], "ir_tol": a.tol, "levels": st["levels"],
+                   "root_n": st["root_n"], "max_rank": st["max_rank_seen"],
+                   "near_pairs": st["near_pairs"]},
+        "factor_s": r["factor_s"], "factor_phase_s": r["factor_phase_s"],
+        "solve_s": r["solve_s"], "ir_iters": r["ir_iters"], "residual": r["residual"],
+        "build_s": r["build_s"], "flops_factor": st["flops_factor"],
+        "flops_solve": st["flops_solve"],
+        "roofline": r["cands"][0] if r["cands"] else None,
+        "roofline_other": r["cands"][1:],
     }
-    # Dominant kernel by time inside the timed steps: the neighbour gathers of
-    # the substitution and the matvec (HBM-bound) or the near-pair transform
-    # GEMMs of the factorization (MFMA-bound).  Each figure is the kernel's
-    # algorithmic work per launch over its average launch time (HIP events).
-    pair = {"bound": "mfma", "kernel": "gemm_f64_pair_kernel", "achieved": pair_tflops,
-            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": pair_tflops / FP64_PEAK_TFLOPS,
-            "traffic": None, "launches": st["pair_launches"] * K,
-            "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1), "total_s": t_pair}
-    # (a captured factorization is not timed per launch: no pair figure then)
-    cands = [pair] if t_pair > 0 else []
-    for q, kname in ((0, "gchunk_kernel"), (1, "greduce_kernel")):
-        if n_g[q] == 0:
-            continue
-        gbs = b_g[q] / max(t_g[q], 1e-30) / 1e9
-        cands.append({"bound": "hbm", "kernel": kname, "achieved": gbs, "peak": HBM_PEAK_GBS,
-                      "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                      "launches": n_g[q], "avg_launch_ms": 1e3 * t_g[q] / n_g[q],
-                      "bytes_per_launch": b_g[q] / n_g[q], "total_s": t_g[q]})
-    for d in cands:
-        d["traffic"] = measured_traffic(d["kernel"])
-    cands.sort(key=lambda d: -d["total_s"])
-    out["roofline"] = cands[0] if cands else None
-    out["roofline_other"] = cands[1:]
-    H.close()
+    if plain is not None:
+        out["plain_fp64"] = {"value": plain["value"], "ms_per_step": plain["ms_per_step"],
+                             "factor_s": plain["factor_s"], "solve_s": plain["solve_s"],
+                             "ir_iters": plain["ir_iters"], "residual": plain["residual"],
+                             "basis_bytes": plain["stats"]["bytes_basis"],
+                             "roofline": plain["cands"][0] if plain["cands"] else None}
+        out["speedup_vs_plain_fp64"] = plain["ms_per_step"] / r["ms_per_step"]
     if not a.no_cpu_baseline and a.kernel != "gaussian_batch":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.kernel, a.eps, a.leaf, a.s, a.cpu_sample)

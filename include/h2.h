@@ -119,13 +119,14 @@ typedef struct {
   int32_t tuned_lists;    /* GEMM work lists timed by the autotuner             */
   int32_t tuned_cfg_hist[4]; /* how many chose 64x64x16, 128x64x16, 128x128x16,
                                 64x64x32 tiles (BM x BN x K-step)               */
-  double t_gather[2];     /* seconds in the neighbour-gather launches of the last
-                             solve: [0] block products, [1] per-box reductions
-                             (HIP events around each launch; params.timing = 1) */
-  double bytes_gather[2]; /* algorithmic bytes of those launches: [0] every
-                             stored block once plus x slices and partial
-                             products, [1] partials, base and y once          */
-  int32_t gather_launches[2]; /* number of timed launches of each kind           */
+  double t_gather[3];     /* seconds in the neighbour-gather launches of the last
+                             solve: [0] block products on FP64 blocks, [1] on
+                             FP32 copies, [2] per-box reductions (HIP events
+                             around each launch; params.timing = 1)           */
+  double bytes_gather[3]; /* algorithmic bytes of those launches: every stored
+                             block once plus x slices and partial products;
+                             for [2] partials, base and y once                */
+  int32_t gather_launches[3]; /* number of timed launches of each kind           */
   double t_factor_phase[9]; /* seconds of the last factor per phase (HIP events;
                                params.timing = 1, no graph): basis QR, diagonal
                                transform, RR Cholesky + inverse, V and Schur

@@ -227,6 +227,7 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
     c.gtime = true;
     c.gev_used = 0;
     c.gbytes.clear();
+    c.gkind.clear();
   }
   int iters_total = 0;
   double worst = 0.0;
@@ -295,16 +296,17 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
   c.st.t_solve = now_seconds() - t0;
   if (c.gtime) {
     c.gtime = false;
-    double tt[2] = {0.0, 0.0}, bb[2] = {0.0, 0.0};
-    int nl[2] = {0, 0};
+    double tt[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
+    int nl[3] = {0, 0, 0};
     for (size_t q = 0; q + 3 <= c.gev_used; q += 3) {
       float ms0 = 0.f, ms1 = 0.f;
       HIPCHK(hipEventElapsedTime(&ms0, c.gev[q], c.gev[q + 1]));
       HIPCHK(hipEventElapsedTime(&ms1, c.gev[q + 1], c.gev[q + 2]));
-      tt[0] += 1e-3 * ms0; bb[0] += c.gbytes[2 * (q / 3)]; ++nl[0];
-      tt[1] += 1e-3 * ms1; bb[1] += c.gbytes[2 * (q / 3) + 1]; ++nl[1];
+      const int g = q / 3, kind = c.gkind[g];
+      tt[kind] += 1e-3 * ms0; bb[kind] += c.gbytes[2 * g]; ++nl[kind];
+      tt[2] += 1e-3 * ms1; bb[2] += c.gbytes[2 * g + 1]; ++nl[2];
     }
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 3; ++q) {
       c.st.t_gather[q] = tt[q];
       c.st.bytes_gather[q] = bb[q];
       c.st.gather_launches[q] = nl[q];

@@ -171,6 +171,7 @@ struct Ctx {
   size_t gev_used = 0;
   bool gtime = false;
   std::vector<double> gbytes;              // per timed gather: chunks, reduction
+  std::vector<int> gkind;                  // per timed gather: 0 FP64 blocks, 1 FP32
   double* dPart = nullptr;                 // gather partial products
   int64_t part_len = 0;                    // longest list's partials, one rhs
   int part_nrhs = 0;                       // right-hand sides dPart holds

@@ -152,7 +152,8 @@ hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 // cols x rows).  base == NULL means zero; base may alias y.  Lists are given
 // per box (GatherBox with neighbour ranges into a GatherNbr array) and are
 // planned (plan_gather) into
-//   * chunks: one wave per 64-row chunk of each stored block M.  The wave
+//   * chunks: one wave per 64-row chunk (128 rows for FP32 copies, two rows
+//     per lane) of each stored block M.  The wave
 //     reads its rows of M once and forms the direct product M x_d for those
 //     rows and/or the transposed product M^T x_t over those rows; a block
 //     that is used directly by one box and transposed by another is read
@@ -180,7 +181,7 @@ struct GChunk {
   const double* xd;         // direct x: mc entries per rhs (ld ldxd), or NULL
   const double* xt;         // trans x: this chunk's nr entries per rhs (ld ldxt), or NULL
   int ld, ldxd, ldxt;
-  int nr, mc;               // chunk rows (<= 64), columns of M
+  int nr, mc;               // chunk rows (<= 64, <= 128 for FP32), columns of M
   int dlen, drow;           // direct slot length and this chunk's first row in it
   int64_t od, ot;           // slot offsets (one-rhs units); -1 = no such product
 };

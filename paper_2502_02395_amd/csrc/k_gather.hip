@@ -52,32 +52,41 @@ __device__ __forceinline__ double bcast(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One batch of BW = 16 columns starting at column sb (16 loads in flight per
-// lane; 32 for FP32 blocks measured slower: the registers cost occupancy);
-// xv[c] holds x_d of the current 64
-// columns, one per lane, and bo is the batch's first column within them.
-// Rows past the chunk read the chunk's last row (always in bounds); their
-// x_t is zero and their direct sums are never stored.
+// Rows per lane: a chunk is 64 * RPL rows, lane l owns rows l + 64 t.  FP32
+// blocks take two rows per lane (the same bytes per load as one FP64 row, and
+// the transposed sums add both rows before the cross-lane reduction).
 template <typename T>
-constexpr int batch_width() { return 16; }
+constexpr int rows_per_lane() { return sizeof(T) == 4 ? 2 : 1; }
 
-template <int NR, bool FULL, typename T>
-__device__ __forceinline__ void gchunk_cols(gptr_t<T> col, int64_t ld, int sb, int mc, int lane,
-                                            int nrhs, const double (&xv)[NR], int bo,
-                                            const double (&xt)[NR], double (&acc)[NR],
-                                            double (&tq)[NR], bool dir, bool tr, int bi) {
-  constexpr int BW = batch_width<T>();
-  T bv[BW];
+// One batch of 16 columns starting at column sb (16 loads per row in
+// flight); xv[c] holds x_d of the current 64 columns, one per lane, and bo is
+// the batch's first column within them.  Rows past the chunk read the
+// chunk's last row (always in bounds); their x_t is zero and their direct
+// sums are never stored.
+template <int NR, int RPL, bool FULL, typename T>
+__device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t ld, int sb,
+                                            int mc, int lane, int nrhs, const double (&xv)[NR],
+                                            int bo, const double (&xt)[RPL][NR],
+                                            double (&acc)[RPL][NR], double (&tq)[NR], bool dir,
+                                            bool tr, int bi) {
+  T bv[RPL][16];
 #pragma unroll
-  for (int u = 0; u < BW; ++u)
-    bv[u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col + (int64_t)u * ld) : T(0);
+  for (int u = 0; u < 16; ++u)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      bv[t][u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col[t] + (int64_t)u * ld)
+                                       : T(0);
   if (dir) {
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int u = 0; u < BW; ++u)
-        if (FULL || sb + u < mc) acc[c] += (double)bv[u] * bcast(xv[c], bo + u);
+      for (int u = 0; u < 16; ++u)
+        if (FULL || sb + u < mc) {
+          const double xu = bcast(xv[c], bo + u);
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) acc[t][c] += (double)bv[t][u] * xu;
+        }
     }
   }
   if (tr) {
@@ -85,10 +94,15 @@ __device__ __forceinline__ void gchunk_cols(gptr_t<T> col, int64_t ld, int sb, i
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int h = 0; h < BW / 8; ++h) {
+      for (int h = 0; h < 2; ++h) {
         double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = (double)bv[8 * h + u] * xt[c];
+        for (int u = 0; u < 8; ++u) {
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) s += (double)bv[t][8 * h + u] * xt[t][c];
+          v[u] = s;
+        }
         const double q = reduce8(v, lane);
         if ((lane & 7) == bi + h) tq[c] = q;
       }
@@ -99,17 +113,23 @@ __device__ __forceinline__ void gchunk_cols(gptr_t<T> col, int64_t ld, int sb, i
 template <int NR, typename T>
 __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict__ P, int nrhs,
                                            int lane) {
-  const bool live = lane < ch.nr;
+  constexpr int RPL = rows_per_lane<T>();
   const bool dir = ch.od >= 0, tr = ch.ot >= 0;
-  const int row = live ? lane : ch.nr - 1;
-  double xt[NR], acc[NR];
+  bool live[RPL];
+  gptr_t<T> col0[RPL];
+  double xt[RPL][NR], acc[RPL][NR];
 #pragma unroll
-  for (int c = 0; c < NR; ++c) {
-    acc[c] = 0.0;
-    xt[c] = (tr && live && c < nrhs) ? as_global(ch.xt)[lane + (int64_t)c * ch.ldxt] : 0.0;
+  for (int t = 0; t < RPL; ++t) {
+    const int r = lane + 64 * t;
+    live[t] = r < ch.nr;
+    col0[t] = as_global(static_cast<const T*>(ch.M)) + (live[t] ? r : ch.nr - 1);
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      acc[t][c] = 0.0;
+      xt[t][c] = (tr && live[t] && c < nrhs) ? as_global(ch.xt)[r + (int64_t)c * ch.ldxt] : 0.0;
+    }
   }
   const int64_t ld = ch.ld;
-  const gptr_t<T> base = as_global(static_cast<const T*>(ch.M)) + row;
   for (int s0 = 0; s0 < ch.mc; s0 += 64) {
     const int ns = min(64, ch.mc - s0);
     double tq[NR], xv[NR];
@@ -119,14 +139,21 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
       xv[c] = (dir && lane < ns && c < nrhs) ? as_global(ch.xd)[s0 + lane + (int64_t)c * ch.ldxd]
                                              : 0.0;
     }
-    constexpr int BW = batch_width<T>();
     int b = 0;
-    for (; b + BW <= ns; b += BW)
-      gchunk_cols<NR, true, T>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
-                            xt, acc, tq, dir, tr, b >> 3);
-    for (; b < ns; b += BW)
-      gchunk_cols<NR, false, T>(base + (int64_t)(s0 + b) * ld, ld, s0 + b, ch.mc, lane, nrhs, xv, b,
-                             xt, acc, tq, dir, tr, b >> 3);
+    for (; b <= ns - 16; b += 16) {
+      gptr_t<T> col[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) col[t] = col0[t] + (int64_t)(s0 + b) * ld;
+      gchunk_cols<NR, RPL, true, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
+                                    tr, b >> 3);
+    }
+    if (b < ns) {
+      gptr_t<T> col[RPL];
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) col[t] = col0[t] + (int64_t)(s0 + b) * ld;
+      gchunk_cols<NR, RPL, false, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
+                                     tr, b >> 3);
+    }
     if (tr) {
       const int cc = 8 * (lane & 7) + (lane >> 3);
       if (cc < ns)
@@ -134,11 +161,13 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
           P[ch.ot * nrhs + (int64_t)c * ch.mc + s0 + cc] = tq[c];
     }
   }
-  if (dir && live)
-    for (int c = 0; c < nrhs; ++c)
-      P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane] = acc[c];
+  if (dir)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t)
+      if (live[t])
+        for (int c = 0; c < nrhs; ++c)
+          P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane + 64 * t] = acc[t][c];
 }
-
 
 template <int NR, typename T>
 __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,

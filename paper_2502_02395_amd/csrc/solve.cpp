@@ -99,11 +99,13 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       item_of_t[q] = hit;
     }
   }
-  // Chunks of 64 rows (boundaries independent of addresses, so that results
-  // are reproducible across handles and runs).
-  auto chunk_starts = [](const Item& it) {
+  // Chunks of 64 rows, 128 for FP32 blocks (one or two rows per lane;
+  // boundaries independent of addresses, so that results are reproducible
+  // across handles and runs).
+  const int crows = out.f32 ? 128 : 64;
+  auto chunk_starts = [crows](const Item& it) {
     std::vector<int> r;
-    for (int r0 = 0; r0 < it.mr; r0 += 64) r.push_back(r0);
+    for (int r0 = 0; r0 < it.mr; r0 += crows) r.push_back(r0);
     r.push_back(it.mr);
     return r;
   };
@@ -233,6 +235,7 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
     c.gev_used += 3;
     c.gbytes.push_back(L.bytes_ch_mat + L.bytes_ch_vec * nrhs);
     c.gbytes.push_back(L.bytes_rd * nrhs);
+    c.gkind.push_back(L.f32 ? 1 : 0);
   }
   return hipSuccess;
 }

@@ -59,8 +59,8 @@ class Stats(ctypes.Structure):
                 ("flops_pair_gemm", ctypes.c_double), ("pair_launches", ctypes.c_int32),
                 ("bytes_basis", ctypes.c_double), ("tuned_lists", ctypes.c_int32),
                 ("tuned_cfg_hist", ctypes.c_int32 * 4),
-                ("t_gather", ctypes.c_double * 2), ("bytes_gather", ctypes.c_double * 2),
-                ("gather_launches", ctypes.c_int32 * 2),
+                ("t_gather", ctypes.c_double * 3), ("bytes_gather", ctypes.c_double * 3),
+                ("gather_launches", ctypes.c_int32 * 3),
                 ("t_factor_phase", ctypes.c_double * 9)]
 
     def as_dict(self) -> dict:
