@@ -4,9 +4,11 @@ One step = h2_factor + h2_solve (the parallel substitution as the
 preconditioner of CG against the FP64 H^2 operator, down to a relative
 residual of 1e-8) on a resident H^2 matrix of 2^20 points; the H^2
 construction runs once before the timed region.  The default run times the
-target path (rank-predicted basis buffers, FP32 copies of the factors for the
-substitution, FP64 arithmetic) next to the plain FP64 path and prints one JSON
-line with both.
+target path (rank-predicted basis buffers; basis-transform and Schur-update
+GEMMs on FP32 MFMA with FP32 accumulation, the near-pair transforms on FP32
+copies of the bases and near blocks, the substitution reading FP32 copies of
+the factors; Cholesky factors, root, H^2 matvec and refinement in FP64) next
+to the plain FP64 path and prints one JSON line with both.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--path target|plain|custom]
 """
@@ -23,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector = matrix)
+# dense matrix peaks of the pair-transform GEMM by its precision
+PAIR_KERNEL = {0: ("gemm_f64_pair_kernel", FP64_PEAK_TFLOPS),
+               1: ("gemm_f32io_pair_kernel", 157.3),
+               2: ("gemm_bf16_kernel", 2500.0)}
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
@@ -188,8 +194,9 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     cands = []
     if t_pair > 0:
         tf = st["flops_pair_gemm"] * K / t_pair / 1e12
-        cands.append({"bound": "mfma", "kernel": "gemm_f64_pair_kernel", "achieved": tf,
-                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+        kname, peak = PAIR_KERNEL[prec]
+        cands.append({"bound": "mfma", "kernel": kname, "achieved": tf,
+                      "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                       "traffic": None, "launches": st["pair_launches"] * K,
                       "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1),
                       "total_s": t_pair})
@@ -224,8 +231,9 @@ def main():
     ap.add_argument("--kernel", default="yukawa",
                     help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
-                    help="target: rank-predicted buffers and FP32 copies for the substitution, "
-                         "timed next to the plain FP64 path (default); plain: the FP64 path "
+                    help="target: rank-predicted buffers, FP32 transform GEMMs and FP32 "
+                         "copies for the substitution, timed next to the plain FP64 path "
+                         "(default); plain: the FP64 path "
                          "only; custom: --prec / --solve-prec / --rank-model as given")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="custom path: precision of the basis-transform and Schur-update GEMMs")
@@ -274,8 +282,8 @@ def main():
     else:
         plain = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain fp64")
         model = train_rank_model(a, h2) if a.kernel != "gaussian_batch" else None
-        setting = ("fp64", "fp32", model is not None)
-        r = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP32, model, "target")
+        setting = ("fp32", "fp32", model is not None)
+        r = run_path(a, h2, h2.PREC_FP32, h2.PREC_FP32, model, "target")
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20:
         for d in r["cands"]:  # traffic was measured on this workload and path
             d["traffic"] = measured_traffic(d["kernel"])

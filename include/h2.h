@@ -74,7 +74,11 @@ typedef struct {
   double eps;             /* ID truncation: keep |R_jj| > eps |R_00|             */
   int32_t max_rank;       /* 0 = no cap                                          */
   int32_t s_far, s_near;  /* sample sizes per box; -1 = every candidate point    */
-  int32_t gemm_prec;      /* h2_prec of the basis-transform / Schur GEMMs        */
+  int32_t gemm_prec;      /* h2_prec of the basis-transform / Schur GEMMs.  FP32
+                             also keeps the near-pair transforms' operands and
+                             results in FP32 (FP32 copies of the bases and near
+                             blocks), so the substitution then reads the FP32
+                             copies whatever solve_prec says                   */
   int32_t ir_max_iter;    /* 0 = plain direct solve                              */
   double ir_tol;          /* relative residual target of refinement              */
   int32_t use_pcg;        /* 1 = PCG instead of stationary refinement            */

@@ -35,6 +35,7 @@ Ctx::~Ctx() {
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
+  if (b.f32io) return launch_gemm_f32io(b.d, b.toff, b.count, b.tiles, st, b.cfg, b.tA, b.tB);
   return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
 }
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
@@ -605,9 +606,26 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     for (size_t p = 0; p < np; ++p) S.poff[p + 1] = S.poff[p] + (int64_t)S.m[S.np_i[p]] * S.m[S.np_j[p]];
     if (h > 0) { S.dD = c.alloc<double>(S.poff[np]); ALLOCHK(S.dD); }
     S.dF = c.alloc<double>(S.poff[np]);
-    S.dT2 = c.alloc<double>(S.poff[np]);
     S.dT3 = c.alloc<double>(S.soff.back());
-    ALLOCHK(S.dF); ALLOCHK(S.dT2); ALLOCHK(S.dT3);
+    ALLOCHK(S.dF); ALLOCHK(S.dT3);
+    // FP32 pair transforms: FP32 near blocks, pair scratch and results; else
+    // the FP64 pair scratch.  FP32 copies of F and P whenever the
+    // substitution reads FP32.
+    const bool f32pair = c.prm.gemm_prec == H2_PREC_FP32;
+    if (f32pair) {
+      S.dD32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
+      S.dT232 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
+      ALLOCHK(S.dD32); ALLOCHK(S.dT232);
+      if (h == 0) HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff[np], st));  // the fixed near field
+    } else {
+      S.dT2 = c.alloc<double>(S.poff[np]);
+      ALLOCHK(S.dT2);
+    }
+    if (f32pair || c.prm.solve_prec == H2_PREC_FP32) {
+      S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
+      S.dP32 = c.alloc<float>(std::max<int64_t>(q, 1));
+      ALLOCHK(S.dF32); ALLOCHK(S.dP32);
+    }
   }
   // index of (instance, level-local box) in each step
   auto local = [&](int h, int t, int i) -> int {
@@ -696,14 +714,30 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gs.push_back(gd(Fii + (int64_t)k * m, m, 0, Fii + (int64_t)k * m, m, 1, TB, m, Fii, m, k, k, r,
                         -1.0, 1.0));
     }
+    const bool f32pair = S.dD32 != nullptr;
+    // FP32 arrays travel in the double-typed descriptors (the FP32 kernels
+    // read them back as float)
+    auto asd = [](float* p) { return reinterpret_cast<double*>(p); };
+    std::vector<ConvDesc> cvf;
     for (size_t p = 0; p < S.np_i.size(); ++p) {
       const int i = S.np_i[p], j = S.np_j[p];
-      if (i == j) continue;
+      if (i == j) {
+        if (f32pair)  // F_ii is formed in FP64; the substitution reads its copy
+          cvf.push_back({S.dF + S.poff[p], S.dF32 + S.poff[p], (int64_t)S.m[i] * S.m[i], 1});
+        continue;
+      }
       const int mi = S.m[i], mj = S.m[j];
-      gp1.push_back(gd(S.dD + S.poff[p], mi, 0, S.dP + S.qoff[j], mj, 0, nullptr, 1,
-                       S.dT2 + S.poff[p], mi, mi, mj, mj, 1.0, 0.0));
-      gp2.push_back(gd(S.dP + S.qoff[i], mi, 1, S.dT2 + S.poff[p], mi, 0, nullptr, 1,
-                       S.dF + S.poff[p], mi, mi, mj, mi, 1.0, 0.0));
+      if (f32pair) {
+        gp1.push_back(gd(asd(S.dD32 + S.poff[p]), mi, 0, asd(S.dP32 + S.qoff[j]), mj, 0, nullptr,
+                         1, asd(S.dT232 + S.poff[p]), mi, mi, mj, mj, 1.0, 0.0));
+        gp2.push_back(gd(asd(S.dP32 + S.qoff[i]), mi, 1, asd(S.dT232 + S.poff[p]), mi, 0, nullptr,
+                         1, asd(S.dF32 + S.poff[p]), mi, mi, mj, mi, 1.0, 0.0));
+      } else {
+        gp1.push_back(gd(S.dD + S.poff[p], mi, 0, S.dP + S.qoff[j], mj, 0, nullptr, 1,
+                         S.dT2 + S.poff[p], mi, mi, mj, mj, 1.0, 0.0));
+        gp2.push_back(gd(S.dP + S.qoff[i], mi, 1, S.dT2 + S.poff[p], mi, 0, nullptr, 1,
+                         S.dF + S.poff[p], mi, mi, mj, mi, 1.0, 0.0));
+      }
     }
     // R_i S_ij for all far partners j of box i at once: the far list is sorted
     // by i, so S_ij1 | S_ij2 | ... (each k_i x k_j, ld k_i) is one k_i x sum k_j
@@ -731,6 +765,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         cm.push_back({dst, dst - S.k[j] + (int64_t)S.k[j] * ldp, kj, ki, ldp, ldp, 1});
       }
     }
+    std::vector<CopyDesc> cm32;  // from FP32 transformed blocks
     for (size_t p = 0; p < S.np_i.size(); ++p) {
       const int a = S.np_i[p], b = S.np_j[p];
       const int ka = S.k[a], kb = S.k[b];
@@ -738,11 +773,14 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       double* dst;
       int ldp;
       parent_block(h, a, b, dst, ldp);
-      cm.push_back({S.dF + S.poff[p], dst, ka, kb, S.m[a], ldp, 0});
+      const bool from32 = f32pair && a != b;
+      const double* src = from32 ? asd(S.dF32 + S.poff[p]) : S.dF + S.poff[p];
+      std::vector<CopyDesc>& out = from32 ? cm32 : cm;
+      out.push_back({src, dst, ka, kb, S.m[a], ldp, 0});
       if (a != b && (S.idx[a] >> 1) == (S.idx[b] >> 1)) {
         // sibling block (2I+1, 2I): also write (2I, 2I+1) = transpose
         double* base = dst - kb;  // row offset of a is k_b; back to the parent origin row
-        cm.push_back({S.dF + S.poff[p], base + (int64_t)kb * ldp, kb, ka, S.m[a], ldp, 1});
+        out.push_back({src, base + (int64_t)kb * ldp, kb, ka, S.m[a], ldp, 1});
       }
     }
     auto up_g = [&](Batch<GemmDesc>& B, const std::vector<GemmDesc>& v) {
@@ -754,8 +792,10 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2))
       return H2_ERR_ALLOC;
     if (!upload(c, S.c_w, cw, st) || !upload(c, S.c_ps, cps, st) || !upload(c, S.c_merge, cm, st) ||
+        !upload(c, S.c_merge32, cm32, st) || !upload(c, S.cv_fii, cvf, st) ||
         !upload(c, S.qr, qr, st))
       return H2_ERR_ALLOC;
+    S.g_pair1.f32io = S.g_pair2.f32io = f32pair;
     // blocked Cholesky + inverse of the RR blocks (A at TB + k + k m, ld m;
     // L^{-1} at Li, ld r; panel scratch in TA)
     int rmax = 0;

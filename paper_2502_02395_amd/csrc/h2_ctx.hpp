@@ -23,6 +23,7 @@ struct Batch {
   int tiles_c[GEMM_NCFG] = {};
   int cfg = 0;
   int tA = 0, tB = 0;      // transposes shared by every item of the list
+  bool f32io = false;      // GEMM list on FP32 operands and results
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 
@@ -74,6 +75,9 @@ struct Step {
   double* dW = nullptr;                    // QR workspace at qoff
   double* dTau = nullptr;                  // Householder scalars at koff
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
+  float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)
+  Batch<ConvDesc> cv_fii;                  // F_ii -> FP32 (diagonal blocks)
+  Batch<CopyDesc> c_merge32;               // merge from FP32 transformed blocks
   double* dR = nullptr;                    // at rkoff
   double* dLi = nullptr;                   // at lioff
   // factor work lists

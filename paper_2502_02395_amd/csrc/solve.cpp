@@ -479,12 +479,11 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, dst, cld, dst, cld, m, NR, k, 1.0, 1.0));
       }
     }
-    // the substitution may read FP32 copies of F and P; the matvec reads FP64
+    // the substitution may read FP32 copies of F and P (a gather list is
+    // all FP64 or all FP32); the matvec reads FP64.  FP32 pair transforms
+    // leave the off-diagonal F in FP32 only, so they imply the FP32 reads.
     std::vector<Rebase> rb;
-    if (c.prm.solve_prec == H2_PREC_FP32) {
-      S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff.back(), 1));
-      S.dP32 = c.alloc<float>(std::max<int64_t>(S.qoff[S.nbox], 1));
-      ALLOCHK(S.dF32); ALLOCHK(S.dP32);
+    if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec == H2_PREC_FP32) {
       rb.push_back({S.dF, S.poff.back(), S.dF32});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
     }
@@ -520,7 +519,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
 // ------------------------------------------------------------------ factor
 // Basis transforms and Schur update in the handle's GEMM precision.
 static hipError_t run_gemm_p(const Ctx& c, const Batch<GemmDesc>& b, hipStream_t st, int tag = 0) {
-  if (c.prm.gemm_prec == H2_PREC_FP64) return run_gemm(b, st, tag);
+  if (c.prm.gemm_prec == H2_PREC_FP64 || b.f32io) return run_gemm(b, st, tag);
   return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], c.prm.gemm_prec, st, tag, b.tA, b.tB);
 }
 
@@ -530,9 +529,10 @@ static hipError_t run_gemm_p(const Ctx& c, const Batch<GemmDesc>& b, hipStream_t
 // that the first factorization has not yet filled is safe: the kernels have no
 // data-dependent control flow and write only the list's own outputs.
 h2_status autotune(Ctx& c, hipStream_t st) {
-  if (c.prm.gemm_prec != H2_PREC_FP64) return H2_OK;
+  // reduced precision: only the FP32-operand pair lists have tile shapes
+  const bool fp64 = c.prm.gemm_prec == H2_PREC_FP64;
   auto tune = [&](Batch<GemmDesc>& b, int tag) -> h2_status {
-    if (b.count == 0) return H2_OK;
+    if (b.count == 0 || (!fp64 && !b.f32io)) return H2_OK;
     int best = 0;
     float best_ms = 1e30f;
     for (int q = 0; q < GEMM_NCFG; ++q) {
@@ -652,6 +652,13 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(S.g_v, st));
     HIPCHK(run_gemm_p(c, S.g_schur, st));
     HIPCHK(done());
+    if (S.dD32) {  // FP32 pair transforms: operands and finished F_ii to FP32
+      HIPCHK(mark(FP_F32));
+      HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
+      if (h > 0) HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff.back(), st));
+      HIPCHK(launch_cvt_list(S.cv_fii.d, S.cv_fii.count, st));
+      HIPCHK(done());
+    }
     HIPCHK(mark(FP_PAIR));
     HIPCHK(run_gemm_p(c, S.g_pair1, st, 1));
     HIPCHK(run_gemm_p(c, S.g_pair2, st, 1));
@@ -662,6 +669,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(done());
     HIPCHK(mark(FP_MERGE));
     HIPCHK(run_copy(S.c_merge, st));
+    HIPCHK(launch_copy_f32(S.c_merge32.d, S.c_merge32.count, st));
     HIPCHK(done());
   }
   HIPCHK(mark(FP_ROOT));
@@ -673,7 +681,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_copy(c.r_back[p], st));
   }
   HIPCHK(done());
-  if (c.prm.solve_prec == H2_PREC_FP32) {
+  if (c.prm.solve_prec == H2_PREC_FP32 && c.prm.gemm_prec != H2_PREC_FP32) {
     HIPCHK(mark(FP_F32));
     for (auto& S : c.steps) {
       HIPCHK(launch_cvt_f32(S.dF, S.dF32, S.poff.back(), st));
