@@ -550,11 +550,13 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     const int n0 = std::max(in.n0, 1);
     in.dRoot = c.alloc<double>((size_t)n0 * n0);
     in.dRootA = c.alloc<double>((size_t)n0 * n0);
-    in.dDinv = c.alloc<double>((size_t)((n0 + 63) / 64) * 4096);
+    in.dRootX = c.alloc<double>((size_t)n0 * n0);
+    in.dRinv = c.alloc<double>((size_t)n0 * n0);
     in.dPan = c.alloc<double>((size_t)n0 * 64);
-    ALLOCHK(in.dRoot); ALLOCHK(in.dRootA); ALLOCHK(in.dDinv); ALLOCHK(in.dPan);
-    // the panels write only their nb x nb corner: keep the padding zero
-    HIPCHK(hipMemsetAsync(in.dDinv, 0, (size_t)((n0 + 63) / 64) * 4096 * sizeof(double), st));
+    ALLOCHK(in.dRoot); ALLOCHK(in.dRootA); ALLOCHK(in.dRootX); ALLOCHK(in.dRinv); ALLOCHK(in.dPan);
+    // L^{-1}: the panels write the diagonal blocks, the inverse block rows
+    // the blocks below them; the blocks above stay zero
+    HIPCHK(hipMemsetAsync(in.dRootX, 0, (size_t)n0 * n0 * sizeof(double), st));
     max_n0 = std::max(max_n0, in.n0);
   }
   // L == 0 instances: the dense kernel block is the whole matrix
@@ -900,6 +902,8 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     c.r_trsm.resize(np);
     c.r_syrk.resize(np);
     c.r_back.resize(np);
+    c.r_inv1.resize(np);
+    c.r_inv2.resize(np);
     for (int pi = 0; pi < np; ++pi) {
       const int p = pi * 64;
       std::vector<PanelDesc> pd;
@@ -911,12 +915,13 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         if (n <= p) continue;
         const int nbk = std::min(64, n - p);
         double* A = in.dRoot;
-        pd.push_back({A + p + (int64_t)p * n, n, nbk, in.dDinv + (int64_t)pi * 4096, 64, (1023 << 20) + t});
+        double* Xpp = in.dRootX + p + (int64_t)p * n;  // L_pp^{-1}, ld n
+        pd.push_back({A + p + (int64_t)p * n, n, nbk, Xpp, n, (1023 << 20) + t});
         const int rows = n - p - nbk;
         if (rows > 0) {
           double* A21 = A + (p + nbk) + (int64_t)p * n;
           double* A22 = A + (p + nbk) + (int64_t)(p + nbk) * n;
-          tr.push_back(gd(A21, n, 0, in.dDinv + (int64_t)pi * 4096, 64, 1, nullptr, 1, in.dPan, n,
+          tr.push_back(gd(A21, n, 0, Xpp, n, 1, nullptr, 1, in.dPan, n,
                           rows, nbk, nbk, 1.0, 0.0));
           sy.push_back(gd(in.dPan, n, 0, in.dPan, n, 1, A22, n, A22, n, rows, rows, nbk, -1.0, 1.0));
           bk.push_back({in.dPan, A21, rows, nbk, n, n, 0});
@@ -925,7 +930,29 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       if (!upload(c, c.r_panel[pi], pd, st) || !upload_gemm(c, c.r_trsm[pi], tr, st) ||
           !upload_gemm(c, c.r_syrk[pi], sy, st) || !upload(c, c.r_back[pi], bk, st))
         return H2_ERR_ALLOC;
+      // block row p of X = L^{-1}: X_{p,<p} = -X_pp (L_{p,<p} X_{<p,<p})
+      // (T in the panel scratch, ld 64), after the whole factorization
+      std::vector<GemmDesc> i1, i2;
+      for (int t = 0; pi > 0 && t < c.n_inst; ++t) {
+        Instance& in = c.ins[t];
+        const int n = in.n0;
+        if (n <= p) continue;
+        const int nbk = std::min(64, n - p);
+        i1.push_back(gd(in.dRoot + p, n, 0, in.dRootX, n, 0, nullptr, 1, in.dPan, 64, nbk, p, p,
+                        1.0, 0.0));
+        i2.push_back(gd(in.dRootX + p + (int64_t)p * n, n, 0, in.dPan, 64, 0, nullptr, 1,
+                        in.dRootX + p, n, nbk, p, nbk, -1.0, 0.0));
+      }
+      if (!upload_gemm(c, c.r_inv1[pi], i1, st) || !upload_gemm(c, c.r_inv2[pi], i2, st))
+        return H2_ERR_ALLOC;
     }
+    // root^{-1} = X^T X: the root solve of the substitution is one product
+    std::vector<GemmDesc> fl;
+    for (auto& in : c.ins)
+      if (in.n0 > 0)
+        fl.push_back(gd(in.dRootX, in.n0, 1, in.dRootX, in.n0, 0, nullptr, 1, in.dRinv, in.n0,
+                        in.n0, in.n0, in.n0, 1.0, 0.0));
+    if (!upload_gemm(c, c.r_full, fl, st)) return H2_ERR_ALLOC;
   }
   return H2_OK;
 }

@@ -122,7 +122,8 @@ struct Instance {
   double* dRoot = nullptr;                 // n0 x n0 (factored in place)
   double* dRootA = nullptr;                // copy of the assembled root block
   double* dRootOrig = nullptr;             // L == 0: the dense kernel block
-  double* dDinv = nullptr;                 // ceil(n0/64) x 64 x 64
+  double* dRootX = nullptr;                // n0 x n0: L^{-1} of the root Cholesky factor
+  double* dRinv = nullptr;                 // n0 x n0: root^{-1} = L^{-T} L^{-1}
   double* dPan = nullptr;                  // n0 x 64 panel scratch
   double* v_root = nullptr;                // n0 x NRHS_MAX
 };
@@ -148,7 +149,9 @@ struct Ctx {
   std::vector<Batch<GemmDesc>> r_trsm, r_syrk;
   std::vector<Batch<CopyDesc>> r_back;
   Batch<CopyDesc> r_save;
-  Batch<RootDesc> r_solve;
+  std::vector<Batch<GemmDesc>> r_inv1, r_inv2;  // block rows of L^{-1}
+  Batch<GemmDesc> r_full;                  // root^{-1} = X^T X
+  GList g_root;                            // substitution: v_root <- root^{-1} v_root
   bool factored = false;
   bool failed = false;
   h2_stats_t st{};

@@ -246,15 +246,6 @@ struct PanelDesc {
   int code;
 };
 hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st);
-// Root triangular solves with blocked diagonal inverses, one workgroup per
-// instance: b (n x nrhs, ld n) overwritten by L^{-T} L^{-1} b.
-struct RootDesc {
-  const double* L;          // n x n lower Cholesky factor (ld n)
-  const double* dinv;       // ceil(n/64) blocks of 64 x 64
-  double* b;
-  int n;
-};
-hipError_t launch_root_solve(const RootDesc* d, int count, int nrhs, hipStream_t st);
 
 // Vector permutations: dst[r + c*ldd] = src[idx[r] + c*lds]  (gather)
 hipError_t launch_gather_rows(const int64_t* idx, int64_t n, int nrhs,

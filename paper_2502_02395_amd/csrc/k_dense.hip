@@ -8,8 +8,9 @@
 //                     leading |R_jj| > eps |R_00|, then T = R_11^{-1} R_12;
 //   * chol_inv     -- Cholesky of an SPD block and the explicit inverse of its
 //                     factor (redundant diagonal blocks, near-sample matrices);
-//   * panel        -- the same on the 64-wide diagonal panels of the root;
-//   * root_solve   -- forward and backward triangular solves at the root.
+//   * panel        -- the same on the 64-wide diagonal panels of the blocked
+//                     Cholesky factorizations (redundant blocks and the root;
+//                     the root's inverse is then formed with batched GEMMs).
 // Householder vectors follow LAPACK's convention (beta = -sign(alpha)||x||,
 // v_0 = 1, tau = (beta - alpha)/beta).
 #include "h2_internal.hpp"
@@ -593,73 +594,6 @@ __global__ __launch_bounds__(256) void panel_kernel(const PanelDesc* __restrict_
 hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(panel_kernel, dim3(count), dim3(256), 0, st, d, fail);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------- root solves
-// b <- L^{-T} L^{-1} b with L blocked in 64-wide panels whose diagonal
-// inverses are in dinv.  One workgroup per instance, columns one at a time.
-__global__ __launch_bounds__(256) void root_solve_kernel(const RootDesc* __restrict__ descs, int nrhs) {
-  __shared__ double xb[64];
-  __shared__ double part[4][64];
-  const RootDesc d = descs[blockIdx.x];
-  const int n = d.n;
-  const int nblk = (n + 63) / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int c = 0; c < nrhs; ++c) {
-    double* b = d.b + (int64_t)c * n;
-    // forward: x_p = Dinv_p b_p ; b_rest -= L_{rest,p} x_p
-    for (int p = 0; p < nblk; ++p) {
-      const int p0 = p * 64, nb = min(64, n - p0);
-      const double* Di = d.dinv + (int64_t)p * 4096;
-      // xb[r] = sum_q Di[r, q] b[p0+q]
-      {
-        double v = 0.0;
-        const int r = lane;
-        for (int q = wave; q < nb; q += 4) v += Di[r + q * 64] * b[p0 + q];
-        part[wave][lane] = v;
-      }
-      __syncthreads();
-      if (threadIdx.x < 64) {
-        xb[lane] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-      }
-      __syncthreads();
-      if (threadIdx.x < nb) b[p0 + threadIdx.x] = xb[threadIdx.x];
-      for (int i = p0 + nb + threadIdx.x; i < n; i += 256) {
-        double v = 0.0;
-        for (int q = 0; q < nb; ++q) v += d.L[i + (int64_t)(p0 + q) * n] * xb[q];
-        b[i] -= v;
-      }
-      __syncthreads();
-    }
-    // backward: x_p = Dinv_p^T (b_p - sum_{i > p block} L_{i,p}^T x_i)
-    for (int p = nblk - 1; p >= 0; --p) {
-      const int p0 = p * 64, nb = min(64, n - p0);
-      // w_q = b[p0+q] - sum_{i >= p0+nb} L[i, p0+q] x_i   (wave per q)
-      for (int q = wave; q < nb; q += 4) {
-        double v = 0.0;
-        const double* col = d.L + (int64_t)(p0 + q) * n;
-        for (int i = p0 + nb + lane; i < n; i += 64) v += col[i] * b[i];
-        v = wave_sum(v);
-        if (lane == 0) xb[q] = b[p0 + q] - v;
-      }
-      __syncthreads();
-      const double* Di = d.dinv + (int64_t)p * 4096;
-      double out = 0.0;
-      if (threadIdx.x < nb) {
-        const int r = threadIdx.x;
-        for (int q = 0; q < nb; ++q) out += Di[q + r * 64] * xb[q];  // (Dinv^T)[r, q]
-      }
-      __syncthreads();
-      if (threadIdx.x < nb) b[p0 + threadIdx.x] = out;
-      __syncthreads();
-    }
-  }
-}
-
-hipError_t launch_root_solve(const RootDesc* d, int count, int nrhs, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(root_solve_kernel, dim3(count), dim3(256), 0, st, d, nrhs);
   return hipGetLastError();
 }
 

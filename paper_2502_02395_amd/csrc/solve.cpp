@@ -496,12 +496,21 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
   }
   // root solves and root-only instances
   {
-    std::vector<RootDesc> rd;
     std::vector<CopyDesc> ri, ro;
     std::vector<GemmDesc> tr;
+    // v_root <- root^{-1} v_root in place (the chunks read x before the
+    // reduction writes y), one neighbour per 64 columns so that the product
+    // spreads over many waves
+    std::vector<GatherBox> rb;
+    std::vector<GatherNbr> rn;
     for (auto& in : c.ins) {
       if (in.n0 == 0) continue;
-      rd.push_back({in.dRoot, in.dDinv, in.v_root, in.n0});
+      GatherBox g{in.v_root, nullptr, in.n0, in.n0, in.n0, 1.0, (int)rn.size(), 0, 0, 0};
+      for (int c0 = 0; c0 < in.n0; c0 += 64)
+        rn.push_back({in.dRinv + (int64_t)c0 * in.n0, in.v_root + c0, in.n0, in.n0,
+                      std::min(64, in.n0 - c0)});
+      g.d1 = g.t0 = g.t1 = (int)rn.size();
+      rb.push_back(g);
       if (in.tree.L == 0) {
         ri.push_back({c.vt_in + in.pbase, in.v_root, in.n0, NR, (int)c.N, in.n0, 0});
         ro.push_back({in.v_root, c.vt_out + in.pbase, in.n0, NR, in.n0, (int)c.N, 0});
@@ -509,8 +518,8 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
                         c.vt_out + in.pbase, (int)c.N, in.n0, NR, in.n0, 1.0, 0.0));
       }
     }
-    if (!upload(c, c.r_solve, rd, st) || !upload(c, c.r_in, ri, st) || !upload(c, c.r_out, ro, st) ||
-        !up_thin(c, c.t_root, tr, st))
+    if (!up_gather(c, c.g_root, rb, rn, st) || !upload(c, c.r_in, ri, st) ||
+        !upload(c, c.r_out, ro, st) || !up_thin(c, c.t_root, tr, st))
       return H2_ERR_ALLOC;
   }
   return ensure_partials(c, 1);
@@ -680,6 +689,11 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(c.r_syrk[p], st));
     HIPCHK(run_copy(c.r_back[p], st));
   }
+  for (size_t p = 1; p < c.r_inv1.size(); ++p) {
+    HIPCHK(run_gemm(c.r_inv1[p], st));
+    HIPCHK(run_gemm(c.r_inv2[p], st));
+  }
+  HIPCHK(run_gemm(c.r_full, st));
   HIPCHK(done());
   if (c.prm.solve_prec == H2_PREC_FP32 && c.prm.gemm_prec != H2_PREC_FP32) {
     HIPCHK(mark(FP_F32));
@@ -716,7 +730,7 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
     HIPCHK(gather(c, S.g_cs, nrhs, st));
   }
   HIPCHK(run_copy(c.r_in, st));
-  HIPCHK(launch_root_solve(c.r_solve.d, c.r_solve.count, nrhs, st));
+  HIPCHK(gather(c, c.g_root, nrhs, st));
   HIPCHK(run_copy(c.r_out, st));
   for (int h = c.H - 1; h >= 0; --h) {
     Step& S = c.steps[h];
