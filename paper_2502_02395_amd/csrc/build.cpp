@@ -35,7 +35,8 @@ Ctx::~Ctx() {
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
-  if (b.f32io) return launch_gemm_f32io(b.d, b.toff, b.count, b.tiles, st, b.cfg, b.tA, b.tB);
+  if (b.f32io)
+    return launch_gemm_f32io(b.d, b.toff, b.count, b.tiles, st, b.cfg, b.tA, b.tB, b.f32io == 2);
   return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
 }
 hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
@@ -608,20 +609,27 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     for (size_t p = 0; p < np; ++p) S.poff[p + 1] = S.poff[p] + (int64_t)S.m[S.np_i[p]] * S.m[S.np_j[p]];
     if (h > 0) { S.dD = c.alloc<double>(S.poff[np]); ALLOCHK(S.dD); }
     S.dF = c.alloc<double>(S.poff[np]);
-    S.dT3 = c.alloc<double>(S.soff.back());
-    ALLOCHK(S.dF); ALLOCHK(S.dT3);
-    // FP32 pair transforms: FP32 near blocks, pair scratch and results; else
-    // the FP64 pair scratch.  FP32 copies of F and P whenever the
-    // substitution reads FP32.
+    ALLOCHK(S.dF);
+    // FP32 transforms: FP32 near blocks (the off-diagonal parent blocks exist
+    // only in FP32), far couplings, R factors, pair and far scratch; else the
+    // FP64 scratch.  FP32 copies of F and P whenever the substitution reads
+    // FP32.
     const bool f32pair = c.prm.gemm_prec == H2_PREC_FP32;
     if (f32pair) {
+      const int64_t ns = std::max<int64_t>(S.soff.back(), 1);
       S.dD32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
       S.dT232 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
-      ALLOCHK(S.dD32); ALLOCHK(S.dT232);
-      if (h == 0) HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff[np], st));  // the fixed near field
+      S.dR32 = c.alloc<float>(std::max<int64_t>(S.rkoff[nb], 1));
+      S.dS32 = c.alloc<float>(ns);
+      S.dT332 = c.alloc<float>(ns);
+      ALLOCHK(S.dD32); ALLOCHK(S.dT232); ALLOCHK(S.dR32); ALLOCHK(S.dS32); ALLOCHK(S.dT332);
+      // the fixed leaf near field and far couplings
+      if (h == 0) HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff[np], st));
+      HIPCHK(launch_cvt_f32(S.dS, S.dS32, S.soff.back(), st));
     } else {
       S.dT2 = c.alloc<double>(S.poff[np]);
-      ALLOCHK(S.dT2);
+      S.dT3 = c.alloc<double>(S.soff.back());
+      ALLOCHK(S.dT2); ALLOCHK(S.dT3);
     }
     if (f32pair || c.prm.solve_prec == H2_PREC_FP32) {
       S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
@@ -647,8 +655,11 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     for (size_t p = 0; p < S.np_i.size(); ++p)
       pmap[h][(int64_t)S.np_i[p] * S.nbox + S.np_j[p]] = (int)p;
   }
-  // parent block of child pair (a, b), a >= b, at step h: pointer, ld
-  auto parent_block = [&](int h, int a, int b, double*& ptr, int& ld) {
+  // parent block of child pair (a, b), a >= b, at step h: pointer, ld; with
+  // FP32 transforms an off-diagonal parent block below the root exists only
+  // in FP32: then ptr32 is set (else nullptr)
+  auto parent_block = [&](int h, int a, int b, double*& ptr, int& ld, float*& ptr32) {
+    ptr32 = nullptr;
     const Step& S = c.steps[h];
     const int t = S.inst[a];
     const int l = S.lvl[a];
@@ -665,6 +676,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     const int pp = pmap[h + 1].at((int64_t)pI * P.nbox + pJ);
     ld = P.m[pI];
     ptr = P.dD + P.poff[pp] + ro + (int64_t)co * ld;
+    if (P.dD32 && pI != pJ) ptr32 = P.dD32 + P.poff[pp] + ro + (int64_t)co * ld;
   };
 
   for (int h = 0; h < c.H; ++h) {
@@ -744,39 +756,60 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     // R_i S_ij for all far partners j of box i at once: the far list is sorted
     // by i, so S_ij1 | S_ij2 | ... (each k_i x k_j, ld k_i) is one k_i x sum k_j
     // matrix, and so is its product
+    // (FP32 transforms: R32 S32 -> T3_32; T3_32 R32^T into FP32 off-diagonal
+    // parent blocks, or into FP64 ones for siblings and the root)
+    std::vector<GemmDesc> gf3;
     for (size_t f = 0; f < S.fp_i.size();) {
       const int i = S.fp_i[f], ki = S.k[i];
       size_t g = f;
       int ncol = 0;
       while (g < S.fp_i.size() && S.fp_i[g] == i) ncol += S.k[S.fp_j[g++]];
-      gf1.push_back(gd(S.dR + S.rkoff[i], ki, 0, S.dS + S.soff[f], ki, 0, nullptr, 1,
-                       S.dT3 + S.soff[f], ki, ki, ncol, ki, 1.0, 0.0));
+      if (f32pair)
+        gf1.push_back(gd(asd(S.dR32 + S.rkoff[i]), ki, 0, asd(S.dS32 + S.soff[f]), ki, 0, nullptr,
+                         1, asd(S.dT332 + S.soff[f]), ki, ki, ncol, ki, 1.0, 0.0));
+      else
+        gf1.push_back(gd(S.dR + S.rkoff[i], ki, 0, S.dS + S.soff[f], ki, 0, nullptr, 1,
+                         S.dT3 + S.soff[f], ki, ki, ncol, ki, 1.0, 0.0));
       f = g;
     }
     for (size_t f = 0; f < S.fp_i.size(); ++f) {
       const int i = S.fp_i[f], j = S.fp_j[f];
       const int ki = S.k[i], kj = S.k[j];
       double* dst;
+      float* dst32;
       int ldp;
-      parent_block(h, i, j, dst, ldp);
-      gf2.push_back(gd(S.dT3 + S.soff[f], ki, 0, S.dR + S.rkoff[j], kj, 1, nullptr, 1, dst, ldp, ki,
-                       kj, kj, 1.0, 0.0));
+      parent_block(h, i, j, dst, ldp, dst32);
+      if (!f32pair)
+        gf2.push_back(gd(S.dT3 + S.soff[f], ki, 0, S.dR + S.rkoff[j], kj, 1, nullptr, 1, dst, ldp,
+                         ki, kj, kj, 1.0, 0.0));
+      else if (dst32)
+        gf2.push_back(gd(asd(S.dT332 + S.soff[f]), ki, 0, asd(S.dR32 + S.rkoff[j]), kj, 1, nullptr,
+                         1, asd(dst32), ldp, ki, kj, kj, 1.0, 0.0));
+      else
+        gf3.push_back(gd(asd(S.dT332 + S.soff[f]), ki, 0, asd(S.dR32 + S.rkoff[j]), kj, 1, nullptr,
+                         1, dst, ldp, ki, kj, kj, 1.0, 0.0));
       const bool sib = (S.idx[i] >> 1) == (S.idx[j] >> 1);
       if (sib && ki * kj > 0) {
         // transposed copy inside the parent's diagonal block
         cm.push_back({dst, dst - S.k[j] + (int64_t)S.k[j] * ldp, kj, ki, ldp, ldp, 1});
       }
     }
-    std::vector<CopyDesc> cm32;  // from FP32 transformed blocks
+    // from FP32 transformed blocks into FP64 / FP32 parent blocks
+    std::vector<CopyDesc> cm32, cm3232;
     for (size_t p = 0; p < S.np_i.size(); ++p) {
       const int a = S.np_i[p], b = S.np_j[p];
       const int ka = S.k[a], kb = S.k[b];
       if (ka * kb == 0) continue;
       double* dst;
+      float* dst32;
       int ldp;
-      parent_block(h, a, b, dst, ldp);
+      parent_block(h, a, b, dst, ldp, dst32);
       const bool from32 = f32pair && a != b;
       const double* src = from32 ? asd(S.dF32 + S.poff[p]) : S.dF + S.poff[p];
+      if (dst32) {  // off-diagonal parent block (not siblings): no transposed copy
+        cm3232.push_back({src, asd(dst32), ka, kb, S.m[a], ldp, 0});
+        continue;
+      }
       std::vector<CopyDesc>& out = from32 ? cm32 : cm;
       out.push_back({src, dst, ka, kb, S.m[a], ldp, 0});
       if (a != b && (S.idx[a] >> 1) == (S.idx[b] >> 1)) {
@@ -791,13 +824,16 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     if (!up_g(S.g_w, gw) || !up_g(S.g_qr1, gq1) || !up_g(S.g_qr2, gq2) || !up_g(S.g_qr3, gq3) ||
         !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
         !up_g(S.g_schur, gs) || !up_g(S.g_pair1, gp1) || !up_g(S.g_pair2, gp2) ||
-        !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2))
+        !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2) || !up_g(S.g_far3, gf3))
       return H2_ERR_ALLOC;
     if (!upload(c, S.c_w, cw, st) || !upload(c, S.c_ps, cps, st) || !upload(c, S.c_merge, cm, st) ||
-        !upload(c, S.c_merge32, cm32, st) || !upload(c, S.cv_fii, cvf, st) ||
-        !upload(c, S.qr, qr, st))
+        !upload(c, S.c_merge32, cm32, st) || !upload(c, S.c_merge3232, cm3232, st) ||
+        !upload(c, S.cv_fii, cvf, st) || !upload(c, S.qr, qr, st))
       return H2_ERR_ALLOC;
-    S.g_pair1.f32io = S.g_pair2.f32io = f32pair;
+    if (f32pair) {
+      S.g_pair1.f32io = S.g_pair2.f32io = S.g_far1.f32io = S.g_far2.f32io = 1;
+      S.g_far3.f32io = 2;
+    }
     // blocked Cholesky + inverse of the RR blocks (A at TB + k + k m, ld m;
     // L^{-1} at Li, ld r; panel scratch in TA)
     int rmax = 0;

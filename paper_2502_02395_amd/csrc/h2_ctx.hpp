@@ -23,7 +23,7 @@ struct Batch {
   int tiles_c[GEMM_NCFG] = {};
   int cfg = 0;
   int tA = 0, tB = 0;      // transposes shared by every item of the list
-  bool f32io = false;      // GEMM list on FP32 operands and results
+  int f32io = 0;           // GEMM list on FP32 operands: 1 FP32 results, 2 FP64 results
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 
@@ -76,8 +76,10 @@ struct Step {
   double* dTau = nullptr;                  // Householder scalars at koff
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
   float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)
+  float *dR32 = nullptr, *dS32 = nullptr, *dT332 = nullptr;  // FP32 R, far couplings, scratch
   Batch<ConvDesc> cv_fii;                  // F_ii -> FP32 (diagonal blocks)
   Batch<CopyDesc> c_merge32;               // merge from FP32 transformed blocks
+  Batch<CopyDesc> c_merge3232;             // FP32 blocks into FP32 parent near blocks
   double* dR = nullptr;                    // at rkoff
   double* dLi = nullptr;                   // at lioff
   // factor work lists
@@ -101,6 +103,7 @@ struct Step {
   Batch<GemmDesc> g_schur;                 // SS_ii -= L(s) L(s)^T
   Batch<GemmDesc> g_pair1, g_pair2;        // D_ij P_j, P_i^T (.)
   Batch<GemmDesc> g_far1, g_far2;          // R_i S_ij, (.) R_j^T into the parent
+  Batch<GemmDesc> g_far3;                  // FP32 pairs: (.) R_j^T into FP64 parent blocks
   Batch<CopyDesc> c_merge;
   // solve / matvec work lists (built for NRHS_MAX columns)
   GList t_fwd, t_bwd;                      // P^T b, P [xS; s]

@@ -87,11 +87,12 @@ hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
 // FP32 accumulation, FP64 in and out), 64 x 64 tiles.
 hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int count,
                           int tiles, int prec, hipStream_t st, int tag, int tA, int tB);
-// FP32 operands and results (pointers in the descriptors hold float arrays),
-// FP32 MFMA with FP32 accumulation, beta = 0; the same tile maps and shapes
-// (cfg 3 runs as cfg 0).
+// FP32 operands (pointers in the descriptors hold float arrays), FP32 MFMA
+// with FP32 accumulation, beta = 0, results in FP32 (out64 = false) or FP64;
+// the same tile maps and shapes (cfg 3 runs as cfg 0).
 hipError_t launch_gemm_f32io(const GemmDesc* d_desc, const int* d_tile_map, int count,
-                             int tiles, hipStream_t st, int cfg, int tA, int tB);
+                             int tiles, hipStream_t st, int cfg, int tA, int tB,
+                             bool out64 = false);
 // Host: the (item, tile) map of a work list for BM x BN tiles.
 inline std::vector<int> gemm_tile_map(const std::vector<GemmDesc>& v, int BM, int BN) {
   std::vector<int> map;
@@ -109,8 +110,10 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
                        int tiles, const double* X, int dim, const KernelDev* kern,
                        hipStream_t st);
 hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st);
-// The same copies with an FP32 source (src holds a float pointer).
-hipError_t launch_copy_f32(const CopyDesc* d_desc, int count, hipStream_t st);
+// The same copies with an FP32 source (src holds a float pointer), into FP64
+// or (dst32) FP32 destinations.
+hipError_t launch_copy_f32(const CopyDesc* d_desc, int count, hipStream_t st,
+                           bool dst32 = false);
 // Contiguous conversions FP64 -> FP32 (to32) or FP32 -> FP64.
 struct ConvDesc {
   const void* src;

@@ -18,7 +18,7 @@ __device__ __forceinline__ int xcd_remap_f32(int b, int nb) {
 
 // Accumulator layout of the 16x16 FP32-output MFMAs (measured on gfx950):
 // element e of lane l holds row 4 * (l / 16) + e, column l % 16.
-template <int BM, int BN, int TA, int TB>
+template <int BM, int BN, int TA, int TB, typename TO>
 __device__ __forceinline__ void gemm_f32io_body(const GemmDesc* __restrict__ descs,
                                                 const int* __restrict__ tmap, int tiles) {
   constexpr int TK = 32;
@@ -109,7 +109,7 @@ __device__ __forceinline__ void gemm_f32io_body(const GemmDesc* __restrict__ des
 #undef H2F_LOAD_TILE
 #undef H2F_LOAD
 
-  float* __restrict__ Dp = reinterpret_cast<float*>(d.D);
+  TO* __restrict__ Dp = reinterpret_cast<TO*>(d.D);
   const float alpha = (float)d.alpha;
   const int col = lane & 15;
   const int rg = 4 * (lane >> 4);
@@ -121,7 +121,7 @@ __device__ __forceinline__ void gemm_f32io_body(const GemmDesc* __restrict__ des
       for (int e = 0; e < 4; ++e) {
         const int gm = m0 + wm + 16 * i + rg + e;
         const int gn = n0 + wn + 16 * j + col;
-        if (gm < M && gn < N) Dp[gm + (int64_t)gn * d.ldd] = alpha * acc[i][j][e];
+        if (gm < M && gn < N) Dp[gm + (int64_t)gn * d.ldd] = (TO)(alpha * acc[i][j][e]);
       }
 }
 
@@ -129,32 +129,43 @@ template <int BM, int BN, int TA, int TB>
 __global__ __launch_bounds__(256) void gemm_f32io_pair_kernel(const GemmDesc* __restrict__ descs,
                                                               const int* __restrict__ tmap,
                                                               int tiles) {
-  gemm_f32io_body<BM, BN, TA, TB>(descs, tmap, tiles);
+  gemm_f32io_body<BM, BN, TA, TB, float>(descs, tmap, tiles);
+}
+template <int BM, int BN, int TA, int TB>
+__global__ __launch_bounds__(256) void gemm_f32i64o_kernel(const GemmDesc* __restrict__ descs,
+                                                           const int* __restrict__ tmap,
+                                                           int tiles) {
+  gemm_f32io_body<BM, BN, TA, TB, double>(descs, tmap, tiles);
 }
 
 template <int BM, int BN, int TA, int TB>
-static void launch_f32io_cfg(const GemmDesc* d, const int* tmap, int tiles, hipStream_t st) {
+static void launch_f32io_cfg(const GemmDesc* d, const int* tmap, int tiles, hipStream_t st,
+                             bool out64) {
   const int grid = (tiles + 7) & ~7;
-  hipLaunchKernelGGL((gemm_f32io_pair_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d,
-                     tmap, tiles);
+  if (out64)
+    hipLaunchKernelGGL((gemm_f32i64o_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d,
+                       tmap, tiles);
+  else
+    hipLaunchKernelGGL((gemm_f32io_pair_kernel<BM, BN, TA, TB>), dim3(grid), dim3(256), 0, st, d,
+                       tmap, tiles);
 }
 
 template <int BM, int BN>
 static void launch_f32io_t(const GemmDesc* d, const int* tmap, int tiles, hipStream_t st, int tA,
-                           int tB) {
-  if (!tA && !tB) launch_f32io_cfg<BM, BN, 0, 0>(d, tmap, tiles, st);
-  else if (!tA && tB) launch_f32io_cfg<BM, BN, 0, 1>(d, tmap, tiles, st);
-  else if (tA && !tB) launch_f32io_cfg<BM, BN, 1, 0>(d, tmap, tiles, st);
-  else launch_f32io_cfg<BM, BN, 1, 1>(d, tmap, tiles, st);
+                           int tB, bool out64) {
+  if (!tA && !tB) launch_f32io_cfg<BM, BN, 0, 0>(d, tmap, tiles, st, out64);
+  else if (!tA && tB) launch_f32io_cfg<BM, BN, 0, 1>(d, tmap, tiles, st, out64);
+  else if (tA && !tB) launch_f32io_cfg<BM, BN, 1, 0>(d, tmap, tiles, st, out64);
+  else launch_f32io_cfg<BM, BN, 1, 1>(d, tmap, tiles, st, out64);
 }
 
 hipError_t launch_gemm_f32io(const GemmDesc* d_desc, const int* d_tile_map, int count, int tiles,
-                             hipStream_t st, int cfg, int tA, int tB) {
+                             hipStream_t st, int cfg, int tA, int tB, bool out64) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
   switch (cfg) {
-    case 1: launch_f32io_t<128, 64>(d_desc, d_tile_map, tiles, st, tA, tB); break;
-    case 2: launch_f32io_t<128, 128>(d_desc, d_tile_map, tiles, st, tA, tB); break;
-    default: launch_f32io_t<64, 64>(d_desc, d_tile_map, tiles, st, tA, tB); break;
+    case 1: launch_f32io_t<128, 64>(d_desc, d_tile_map, tiles, st, tA, tB, out64); break;
+    case 2: launch_f32io_t<128, 128>(d_desc, d_tile_map, tiles, st, tA, tB, out64); break;
+    default: launch_f32io_t<64, 64>(d_desc, d_tile_map, tiles, st, tA, tB, out64); break;
   }
   return hipGetLastError();
 }
@@ -180,23 +191,29 @@ hipError_t launch_cvt_list(const ConvDesc* d, int count, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Block copies from an FP32 source into FP64 destinations (the merge of the
-// FP32 transformed blocks' SS parts into the parent's near blocks); the
-// CopyDesc's src holds a float pointer.
+// Block copies from an FP32 source (the merge of the FP32 transformed blocks'
+// SS parts into the parent's near blocks): FP64 destinations (diagonal parent
+// blocks, the root) or FP32 ones (off-diagonal parent blocks, read only by the
+// FP32 pair transforms).  The CopyDesc pointers hold float arrays where FP32.
+template <typename TD>
 __global__ __launch_bounds__(256) void copy_f32_kernel(const CopyDesc* __restrict__ descs) {
   const CopyDesc c = descs[blockIdx.y];
   const float* src = reinterpret_cast<const float*>(c.src);
+  TD* dst = reinterpret_cast<TD*>(c.dst);
   const int64_t n = (int64_t)c.rows * c.cols;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
     const int r = (int)(e % c.rows), q = (int)(e / c.rows);
-    const double v = c.trans ? (double)src[q + (int64_t)r * c.lds] : (double)src[r + (int64_t)q * c.lds];
-    c.dst[r + (int64_t)q * c.ldd] = v;
+    const float v = c.trans ? src[q + (int64_t)r * c.lds] : src[r + (int64_t)q * c.lds];
+    dst[r + (int64_t)q * c.ldd] = (TD)v;
   }
 }
 
-hipError_t launch_copy_f32(const CopyDesc* d_desc, int count, hipStream_t st) {
+hipError_t launch_copy_f32(const CopyDesc* d_desc, int count, hipStream_t st, bool dst32) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_f32_kernel, dim3(16, count), dim3(256), 0, st, d_desc);
+  if (dst32)
+    hipLaunchKernelGGL(copy_f32_kernel<float>, dim3(4, count), dim3(256), 0, st, d_desc);
+  else
+    hipLaunchKernelGGL(copy_f32_kernel<double>, dim3(4, count), dim3(256), 0, st, d_desc);
   return hipGetLastError();
 }
 

@@ -566,7 +566,7 @@ h2_status autotune(Ctx& c, hipStream_t st) {
   };
   for (auto& S : c.steps) {
     for (Batch<GemmDesc>* b : {&S.g_w, &S.g_qr1, &S.g_qr2, &S.g_qr3, &S.g_diag1, &S.g_diag2,
-                               &S.g_v, &S.g_schur, &S.g_far1, &S.g_far2}) {
+                               &S.g_v, &S.g_schur, &S.g_far1, &S.g_far2, &S.g_far3}) {
       h2_status e = tune(*b, 0);
       if (e != H2_OK) return e;
     }
@@ -664,7 +664,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     if (S.dD32) {  // FP32 pair transforms: operands and finished F_ii to FP32
       HIPCHK(mark(FP_F32));
       HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
-      if (h > 0) HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff.back(), st));
+      HIPCHK(launch_cvt_f32(S.dR, S.dR32, S.rkoff[S.nbox], st));
       HIPCHK(launch_cvt_list(S.cv_fii.d, S.cv_fii.count, st));
       HIPCHK(done());
     }
@@ -675,10 +675,12 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(mark(FP_FAR));
     HIPCHK(run_gemm_p(c, S.g_far1, st));
     HIPCHK(run_gemm_p(c, S.g_far2, st));
+    HIPCHK(run_gemm(S.g_far3, st));
     HIPCHK(done());
     HIPCHK(mark(FP_MERGE));
     HIPCHK(run_copy(S.c_merge, st));
     HIPCHK(launch_copy_f32(S.c_merge32.d, S.c_merge32.count, st));
+    HIPCHK(launch_copy_f32(S.c_merge3232.d, S.c_merge3232.count, st, true));
     HIPCHK(done());
   }
   HIPCHK(mark(FP_ROOT));
