@@ -29,14 +29,21 @@ struct Batch {
 
 // A planned neighbour gather (see GatherPlan): chunk and reduction
 // descriptors, and the algorithmic bytes of one pass with one rhs.
-struct GList {
+struct GSet {
   Batch<GChunk> ch;
   Batch<GRed> rd;
   Batch<int64_t> offs;
   int max_rows = 0;
   int64_t plen = 0;
   double bytes_ch_mat = 0.0, bytes_ch_vec = 0.0, bytes_rd = 0.0;
+};
+struct GList {
+  GSet n;                                  // chunks of 64 rows (128 for FP32 copies)
+  GSet w;                                  // wide chunks (up to 4 rows per lane) for
+                                           // nrhs <= GATHER_WIDE_NR
   bool f32 = false;                        // blocks read from FP32 copies
+  bool has_w = false;
+  const GSet& pick(int nrhs) const { return has_w && nrhs <= GATHER_WIDE_NR ? w : n; }
 };
 
 // One height step h above the leaves: level L_t - h of every instance t with

@@ -171,11 +171,15 @@ hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 // per box (GatherBox with neighbour ranges into a GatherNbr array) and are
 // planned (plan_gather) into
 //   * chunks: one wave per 64-row chunk (128 rows for FP32 copies, two rows
-//     per lane) of each stored block M.  The wave
-//     reads its rows of M once and forms the direct product M x_d for those
-//     rows and/or the transposed product M^T x_t over those rows; a block
-//     that is used directly by one box and transposed by another is read
-//     once for both;
+//     per lane) and, where the plan asks for segments, per seg-column
+//     segment of each stored block M.  The wave reads its part of M once and
+//     forms the direct product M x_d for those rows and/or the transposed
+//     product M^T x_t over those rows; a block that is used directly by one
+//     box and transposed by another is read once for both.  Segments bound
+//     the serial column walk of one wave: the few, large blocks of the upper
+//     levels otherwise leave a launch with a handful of long waves.  The
+//     caller picks them per tree height, so a box gets the same arithmetic
+//     in every list and handle (batched or not) it appears in;
 //   * partial slots: every product writes its own slot of a partial buffer
 //     (slot offsets in units of one right-hand side; with nrhs columns slot
 //     s starts at off_s * nrhs, column c at off_s * nrhs + c * len);
@@ -201,6 +205,8 @@ struct GChunk {
   int ld, ldxd, ldxt;
   int nr, mc;               // chunk rows (<= 64, <= 128 for FP32), columns of M
   int dlen, drow;           // direct slot length and this chunk's first row in it
+  int tlen, tcol;           // trans slot length and this chunk's first column in it
+  int rpl;                  // rows per lane: nr <= 64 rpl
   int64_t od, ot;           // slot offsets (one-rhs units); -1 = no such product
 };
 struct GRed {
@@ -211,6 +217,25 @@ struct GRed {
   int s0, s1;               // slot range in the offset array
 };
 // A range of FP64 blocks with an FP32 copy at base32 (same offsets).
+// Column segments of the gathers at heights >= GATHER_SEG_FROM above the
+// leaves (measured: below that the lists have enough waves and the extra
+// direct slots cost more than the shorter waves gain).
+constexpr int GATHER_SEG = 128;
+constexpr int GATHER_SEG_FROM = 5;
+// Wide chunks: a block's rows split evenly into chunks of at most 64 x RPL
+// rows (one wave each, up to RPL rows per lane: 4 for FP32 copies, 2 for
+// FP64 blocks), so that e.g. an FP32 block of 150 rows takes one wave with
+// most lanes busy instead of two with most lanes of the second idle; used
+// for up to GATHER_WIDE_NR right-hand sides (the per-lane accumulators grow
+// with rows x rhs).
+// Measured: wide chunks win at heights GATHER_WIDE_FROM..GATHER_WIDE_TO; at
+// the leaves (many small blocks) and at the top (few waves) the narrow ones
+// with 16 columns per batch do.
+constexpr int GATHER_WIDE_RPL32 = 4;
+constexpr int GATHER_WIDE_RPL64 = 2;
+constexpr int GATHER_WIDE_NR = 2;
+constexpr int GATHER_WIDE_FROM = 1;
+constexpr int GATHER_WIDE_TO = 6;
 struct Rebase {
   const double* base;
   int64_t n;
@@ -229,11 +254,14 @@ struct GatherPlan {
   double bytes_red = 0.0;
 };
 // rb non-empty: every block must lie in one of its ranges and is read from
-// the FP32 copy (returns false otherwise).
+// the FP32 copy (returns false otherwise).  seg > 0: column segments of at
+// most seg columns (a multiple of 16).  wide: wide chunks (see above).
 bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                 GatherPlan& out, const std::vector<Rebase>& rb = {});
+                 GatherPlan& out, const std::vector<Rebase>& rb = {}, int seg = 0,
+                 bool wide = false);
+// wide: the chunks come from a wide plan (nrhs <= GATHER_WIDE_NR required).
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
-                          hipStream_t st);
+                          hipStream_t st, bool wide = false);
 // FP32 copy of n doubles.
 hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,

@@ -58,20 +58,20 @@ __device__ __forceinline__ double bcast(double v, int l) {
 template <typename T>
 constexpr int rows_per_lane() { return sizeof(T) == 4 ? 2 : 1; }
 
-// One batch of 16 columns starting at column sb (16 loads per row in
+// One batch of BW columns (8 or 16) starting at column sb (BW loads per row in
 // flight); xv[c] holds x_d of the current 64 columns, one per lane, and bo is
 // the batch's first column within them.  Rows past the chunk read the
 // chunk's last row (always in bounds); their x_t is zero and their direct
 // sums are never stored.
-template <int NR, int RPL, bool FULL, typename T>
+template <int NR, int RPL, int BW, bool FULL, typename T>
 __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t ld, int sb,
                                             int mc, int lane, int nrhs, const double (&xv)[NR],
                                             int bo, const double (&xt)[RPL][NR],
                                             double (&acc)[RPL][NR], double (&tq)[NR], bool dir,
                                             bool tr, int bi) {
-  T bv[RPL][16];
+  T bv[RPL][BW];
 #pragma unroll
-  for (int u = 0; u < 16; ++u)
+  for (int u = 0; u < BW; ++u)
 #pragma unroll
     for (int t = 0; t < RPL; ++t)
       bv[t][u] = (FULL || sb + u < mc) ? __builtin_nontemporal_load(col[t] + (int64_t)u * ld)
@@ -81,7 +81,7 @@ __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
+      for (int u = 0; u < BW; ++u)
         if (FULL || sb + u < mc) {
           const double xu = bcast(xv[c], bo + u);
 #pragma unroll
@@ -94,7 +94,7 @@ __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t
     for (int c = 0; c < NR; ++c) {
       if (c >= nrhs) break;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < BW / 8; ++h) {
         double v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -110,10 +110,9 @@ __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t
   }
 }
 
-template <int NR, typename T>
+template <int NR, typename T, int RPL, int BW>
 __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict__ P, int nrhs,
                                            int lane) {
-  constexpr int RPL = rows_per_lane<T>();
   const bool dir = ch.od >= 0, tr = ch.ot >= 0;
   bool live[RPL];
   gptr_t<T> col0[RPL];
@@ -140,25 +139,25 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
                                              : 0.0;
     }
     int b = 0;
-    for (; b <= ns - 16; b += 16) {
+    for (; b <= ns - BW; b += BW) {
       gptr_t<T> col[RPL];
 #pragma unroll
       for (int t = 0; t < RPL; ++t) col[t] = col0[t] + (int64_t)(s0 + b) * ld;
-      gchunk_cols<NR, RPL, true, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
+      gchunk_cols<NR, RPL, BW, true, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
                                     tr, b >> 3);
     }
     if (b < ns) {
       gptr_t<T> col[RPL];
 #pragma unroll
       for (int t = 0; t < RPL; ++t) col[t] = col0[t] + (int64_t)(s0 + b) * ld;
-      gchunk_cols<NR, RPL, false, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
+      gchunk_cols<NR, RPL, BW, false, T>(col, ld, s0 + b, ch.mc, lane, nrhs, xv, b, xt, acc, tq, dir,
                                      tr, b >> 3);
     }
     if (tr) {
       const int cc = 8 * (lane & 7) + (lane >> 3);
       if (cc < ns)
         for (int c = 0; c < nrhs; ++c)
-          P[ch.ot * nrhs + (int64_t)c * ch.mc + s0 + cc] = tq[c];
+          P[ch.ot * nrhs + (int64_t)c * ch.tlen + ch.tcol + s0 + cc] = tq[c];
     }
   }
   if (dir)
@@ -169,12 +168,25 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
           P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane + 64 * t] = acc[t][c];
 }
 
-template <int NR, typename T>
+// RMAX: the largest rows-per-lane of the plan the chunks come from; each
+// chunk runs the variant of its own row count (wave-uniform).  BW: columns
+// per batch; 8 keeps the wide variants at four or more waves per SIMD.
+template <int NR, typename T, int RMAX, int BW>
 __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ chunks, int nch,
                                                      double* __restrict__ P, int nrhs) {
   const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (w >= nch) return;
-  gchunk_one<NR, T>(chunks[w], P, nrhs, threadIdx.x & 63);
+  const GChunk& ch = chunks[w];
+  const int rpl = __builtin_amdgcn_readfirstlane(ch.rpl);
+  const int lane = threadIdx.x & 63;
+  if constexpr (RMAX >= 4) {
+    if (rpl >= 4) { gchunk_one<NR, T, 4, BW>(ch, P, nrhs, lane); return; }
+    if (rpl == 3) { gchunk_one<NR, T, 3, BW>(ch, P, nrhs, lane); return; }
+  }
+  if constexpr (RMAX >= 2) {
+    if (rpl == 2) { gchunk_one<NR, T, 2, BW>(ch, P, nrhs, lane); return; }
+  }
+  gchunk_one<NR, T, 1, BW>(ch, P, nrhs, lane);
 }
 
 template <int NR>
@@ -200,21 +212,31 @@ __global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ r
 }
 
 template <typename T>
-static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st) {
+static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st,
+                             bool wide) {
   const dim3 grid((nch + 3) / 4), blk(256);
-  if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 2) hipLaunchKernelGGL((gchunk_kernel<2, T>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 4) hipLaunchKernelGGL((gchunk_kernel<4, T>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 8) hipLaunchKernelGGL((gchunk_kernel<8, T>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else hipLaunchKernelGGL((gchunk_kernel<16, T>), grid, blk, 0, st, ch, nch, P, nrhs);
+  constexpr int RN = rows_per_lane<T>();
+  constexpr int RW = sizeof(T) == 4 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64;
+  static_assert(GATHER_WIDE_NR == 2, "wide instantiations below");
+  if (wide) {
+    if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T, RW, 8>), grid, blk, 0, st, ch, nch, P, nrhs);
+    else hipLaunchKernelGGL((gchunk_kernel<2, T, RW, 8>), grid, blk, 0, st, ch, nch, P, nrhs);
+    return;
+  }
+  if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 2) hipLaunchKernelGGL((gchunk_kernel<2, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 4) hipLaunchKernelGGL((gchunk_kernel<4, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else if (nrhs <= 8) hipLaunchKernelGGL((gchunk_kernel<8, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+  else hipLaunchKernelGGL((gchunk_kernel<16, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
 }
 
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
-                          hipStream_t st) {
+                          hipStream_t st, bool wide) {
   if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
-  if (f32) launch_gchunks_t<float>(ch, nch, P, nrhs, st);
-  else launch_gchunks_t<double>(ch, nch, P, nrhs, st);
+  if (wide && nrhs > GATHER_WIDE_NR) return hipErrorInvalidValue;
+  if (f32) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide);
+  else launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 // Every step is a batched product or neighbour gather; only the root keeps
 // triangular solves.
 #include <algorithm>
+#include <climits>
 #include <unordered_map>
 
 #include "h2_ctx.hpp"
@@ -41,7 +42,9 @@ static int local_box(const Step& S, int t, int i) {
 
 // ------------------------------------------------------------ gather plans
 bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                 GatherPlan& out, const std::vector<Rebase>& rb) {
+                 GatherPlan& out, const std::vector<Rebase>& rb, int seg, bool wide) {
+  if (seg < 0 || seg % 16 != 0) return false;
+  const int W = seg > 0 ? seg : INT_MAX;
   out = GatherPlan();
   out.f32 = !rb.empty();
   const double esz = out.f32 ? 4.0 : 8.0;
@@ -56,9 +59,10 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     int ld, mr, mc;
     int dq = -1, tq = -1;      // neighbour entries using M directly / transposed
     int dbox = -1, tbox = -1;
-    int64_t od = -1;           // direct slot
-    int64_t ot0 = -1;          // first of the per-chunk trans slots
+    int64_t od = -1;           // first of the per-segment direct slots (mr each)
+    int64_t ot0 = -1;          // first of the per-row-chunk trans slots (mc each)
   };
+  auto nseg_of = [W](int mc) { return mc <= W ? 1 : (mc + W - 1) / W; };
   std::vector<Item> items;
   std::vector<int> item_of_d(Nv.size(), -1), item_of_t(Nv.size(), -1);
   std::unordered_multimap<const double*, int> dir_items;
@@ -99,13 +103,20 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       item_of_t[q] = hit;
     }
   }
-  // Chunks of 64 rows, 128 for FP32 blocks (one or two rows per lane;
-  // boundaries independent of addresses, so that results are reproducible
-  // across handles and runs).
-  const int crows = out.f32 ? 128 : 64;
-  auto chunk_starts = [crows](const Item& it) {
+  // Chunks of 64 rows, 128 for FP32 blocks (one or two rows per lane), or
+  // wide: the rows split evenly into the fewest chunks of at most 64 x
+  // GATHER_WIDE_RPL32 / GATHER_WIDE_RPL64 rows.  Boundaries depend only on the block's size, so
+  // results are reproducible across handles and runs.
+  const int crows = wide ? 64 * (out.f32 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64)
+                         : out.f32 ? 128 : 64;
+  auto chunk_starts = [crows, wide](const Item& it) {
     std::vector<int> r;
-    for (int r0 = 0; r0 < it.mr; r0 += crows) r.push_back(r0);
+    if (wide) {
+      const int nck = (it.mr + crows - 1) / crows;
+      for (int c = 0; c < nck; ++c) r.push_back((int)((int64_t)it.mr * c / nck));
+    } else {
+      for (int r0 = 0; r0 < it.mr; r0 += crows) r.push_back(r0);
+    }
     r.push_back(it.mr);
     return r;
   };
@@ -116,8 +127,9 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     Item& it = items[ii];
     const std::vector<int> rs = chunk_starts(it);
     const int nck = (int)rs.size() - 1;
+    const int nseg = nseg_of(it.mc);
     nck_of[ii] = nck;
-    if (it.dq >= 0) { it.od = off; off += it.mr; }
+    if (it.dq >= 0) { it.od = off; off += (int64_t)nseg * it.mr; }
     if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
     const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
     const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
@@ -125,23 +137,30 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (out.f32 && !M32) return false;
     for (int c = 0; c < nck; ++c) {
       const int r0 = rs[c];
-      GChunk ch;
-      ch.M = out.f32 ? static_cast<const void*>(M32 + r0) : static_cast<const void*>(it.M + r0);
-      ch.xd = nd ? nd->x : nullptr;
-      ch.xt = nt ? nt->x + r0 : nullptr;
-      ch.ld = it.ld;
-      ch.ldxd = nd ? nd->ldx : 1;
-      ch.ldxt = nt ? nt->ldx : 1;
-      ch.nr = rs[c + 1] - r0;
-      ch.mc = it.mc;
-      ch.dlen = it.mr;
-      ch.drow = r0;
-      ch.od = nd ? it.od : -1;
-      ch.ot = nt ? it.ot0 + (int64_t)c * it.mc : -1;
-      out.chunks.push_back(ch);
+      for (int sg = 0; sg < nseg; ++sg) {
+        const int c0 = sg * std::min(W, it.mc), c1 = std::min(it.mc, c0 + W);
+        const int64_t e0 = r0 + (int64_t)c0 * it.ld;
+        GChunk ch;
+        ch.M = out.f32 ? static_cast<const void*>(M32 + e0) : static_cast<const void*>(it.M + e0);
+        ch.xd = nd ? nd->x + c0 : nullptr;
+        ch.xt = nt ? nt->x + r0 : nullptr;
+        ch.ld = it.ld;
+        ch.ldxd = nd ? nd->ldx : 1;
+        ch.ldxt = nt ? nt->ldx : 1;
+        ch.nr = rs[c + 1] - r0;
+        ch.mc = c1 - c0;
+        ch.dlen = it.mr;
+        ch.drow = r0;
+        ch.tlen = it.mc;
+        ch.tcol = c0;
+        ch.rpl = (ch.nr + 63) / 64;
+        ch.od = nd ? it.od + (int64_t)sg * it.mr : -1;
+        ch.ot = nt ? it.ot0 + (int64_t)c * it.mc : -1;
+        out.chunks.push_back(ch);
+      }
     }
     out.bytes_chunks_mat += esz * it.mr * it.mc;
-    if (nd) out.bytes_chunks_vec += 8.0 * (it.mc + it.mr);                  // x_d, slot
+    if (nd) out.bytes_chunks_vec += 8.0 * (it.mc + (double)nseg * it.mr);   // x_d, slots
     if (nt) out.bytes_chunks_vec += 8.0 * (it.mr + (double)nck * it.mc);    // x_t, slots
   }
   out.plen = off;
@@ -152,7 +171,10 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     r.alpha = g.alpha;
     r.s0 = (int)out.offs.size();
     for (int q = g.d0; q < g.d1; ++q)
-      if (item_of_d[q] >= 0) out.offs.push_back(items[item_of_d[q]].od);
+      if (item_of_d[q] >= 0) {
+        const Item& it = items[item_of_d[q]];
+        for (int sg = 0; sg < nseg_of(it.mc); ++sg) out.offs.push_back(it.od + (int64_t)sg * it.mr);
+      }
     for (int q = g.t0; q < g.t1; ++q)
       if (item_of_t[q] >= 0) {
         const Item& it = items[item_of_t[q]];
@@ -168,12 +190,12 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
 
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
                       const std::vector<GatherNbr>& Nv, hipStream_t st,
-                      const std::vector<Rebase>& rb = {});
+                      const std::vector<Rebase>& rb = {}, int seg = 0, bool wide = false);
 
 // Per-box products D = alpha op(A) B + beta C (beta 0, or 1 with C == D) as
 // gathers with one neighbour: A direct (tA = 0) or transposed (tA = 1).
 static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_t st,
-                    const std::vector<Rebase>& rb = {}) {
+                    const std::vector<Rebase>& rb = {}, int seg = 0, bool wide = false) {
   std::vector<GatherBox> B;
   std::vector<GatherNbr> Nv;
   for (const GemmDesc& g : v) {
@@ -184,23 +206,27 @@ static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_
     if (g.tA) x.t1 = q + 1; else x.d1 = q + 1;
     B.push_back(x);
   }
-  return up_gather(c, L, B, Nv, st, rb);
+  return up_gather(c, L, B, Nv, st, rb, seg, wide);
 }
 
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
                       const std::vector<GatherNbr>& Nv, hipStream_t st,
-                      const std::vector<Rebase>& rb) {
-  GatherPlan p;
-  if (!plan_gather(B, Nv, p, rb)) return false;
-  L.f32 = p.f32;
-  L.max_rows = p.max_rows;
-  L.plen = p.plen;
-  L.bytes_ch_mat = p.bytes_chunks_mat;
-  L.bytes_ch_vec = p.bytes_chunks_vec;
-  L.bytes_rd = p.bytes_red;
-  c.part_len = std::max(c.part_len, p.plen);
-  return upload(c, L.ch, p.chunks, st) && upload(c, L.rd, p.reds, st) &&
-         upload(c, L.offs, p.offs, st);
+                      const std::vector<Rebase>& rb, int seg, bool wide) {
+  auto up_set = [&](GSet& S, bool wide) {
+    GatherPlan p;
+    if (!plan_gather(B, Nv, p, rb, seg, wide)) return false;
+    L.f32 = p.f32;
+    S.max_rows = p.max_rows;
+    S.plen = p.plen;
+    S.bytes_ch_mat = p.bytes_chunks_mat;
+    S.bytes_ch_vec = p.bytes_chunks_vec;
+    S.bytes_rd = p.bytes_red;
+    c.part_len = std::max(c.part_len, p.plen);
+    return upload(c, S.ch, p.chunks, st) && upload(c, S.rd, p.reds, st) &&
+           upload(c, S.offs, p.offs, st);
+  };
+  L.has_w = wide;
+  return up_set(L.n, false) && (!wide || up_set(L.w, true));
 }
 
 // The partial buffer holds the longest list's partial products for nrhs
@@ -221,20 +247,23 @@ h2_status ensure_partials(Ctx& c, int nrhs) {
 // Chunks then reduction; with timing on, HIP events around each (the event
 // pool is sized once; gathers beyond it run untimed).
 static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
-  if (L.rd.count == 0) return hipSuccess;
+  const bool wide = L.has_w && nrhs <= GATHER_WIDE_NR;
+  const GSet& S = L.pick(nrhs);
+  if (S.rd.count == 0) return hipSuccess;
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(L.ch.d, L.ch.count, c.dPart, nrhs, L.f32, st)) != hipSuccess) return e;
+  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.dPart, nrhs, L.f32, st, wide)) != hipSuccess)
+    return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
-  if ((e = launch_greduce(L.rd.d, L.rd.count, L.max_rows, L.offs.d, c.dPart, nrhs, st)) !=
+  if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.dPart, nrhs, st)) !=
       hipSuccess)
     return e;
   if (t) {
     if ((e = hipEventRecord(c.gev[c.gev_used + 2], st)) != hipSuccess) return e;
     c.gev_used += 3;
-    c.gbytes.push_back(L.bytes_ch_mat + L.bytes_ch_vec * nrhs);
-    c.gbytes.push_back(L.bytes_rd * nrhs);
+    c.gbytes.push_back(S.bytes_ch_mat + S.bytes_ch_vec * nrhs);
+    c.gbytes.push_back(S.bytes_rd * nrhs);
     c.gkind.push_back(L.f32 ? 1 : 0);
   }
   return hipSuccess;
@@ -487,11 +516,17 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       rb.push_back({S.dF, S.poff.back(), S.dF32});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
     }
-    if (!up_thin(c, S.t_fwd, tf, st, rb) || !up_thin(c, S.t_bwd, tb, st, rb) ||
-        !up_thin(c, S.t_up, tu, st) || !up_thin(c, S.t_down, td, st) ||
-        !up_gather(c, S.g_yr, b1, n1, st, rb) || !up_gather(c, S.g_cs, b2, n2, st, rb) ||
-        !up_gather(c, S.g_t, b3, n3, st, rb) || !up_gather(c, S.g_s, b4, n4, st, rb) ||
-        !up_gather(c, S.g_cpl, bc, nc, st) || !up_gather(c, S.g_near, bn, nn, st))
+    const int sg = h >= GATHER_SEG_FROM ? GATHER_SEG : 0;
+    const bool wd = h >= GATHER_WIDE_FROM && h <= GATHER_WIDE_TO;
+    const std::vector<Rebase> none;
+    if (!up_thin(c, S.t_fwd, tf, st, rb, sg, wd) || !up_thin(c, S.t_bwd, tb, st, rb, sg, wd) ||
+        !up_thin(c, S.t_up, tu, st, none, sg, wd) || !up_thin(c, S.t_down, td, st, none, sg, wd) ||
+        !up_gather(c, S.g_yr, b1, n1, st, rb, sg, wd) ||
+        !up_gather(c, S.g_cs, b2, n2, st, rb, sg, wd) ||
+        !up_gather(c, S.g_t, b3, n3, st, rb, sg, wd) ||
+        !up_gather(c, S.g_s, b4, n4, st, rb, sg, wd) ||
+        !up_gather(c, S.g_cpl, bc, nc, st, none, sg, wd) ||
+        !up_gather(c, S.g_near, bn, nn, st, none, sg, wd))
       return H2_ERR_ALLOC;
   }
   // root solves and root-only instances
