@@ -22,7 +22,7 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_gemm_f32.hip", "k_dense.hip", "k_vec.hip", "k_gather.hip", "mlp.hip"]
-HOST_HIP_SOURCES = ["build.cpp", "solve.cpp", "api.cpp"]
+HOST_HIP_SOURCES = ["build.cpp", "solve.cpp", "gather_plan.cpp", "api.cpp"]
 PLAIN_SOURCES = ["tree.cpp"]
 
 # packed FP32 instructions are disabled: hand-checked FP32 paths only
