@@ -37,16 +37,15 @@ HBM_PEAK_GBS = 8000.0
 # copy (FETCH_SIZE reads half of the bytes moved: factor 2.0; WRITE_SIZE
 # factor 1.0).  Valid only for the sources they were taken on (the kernel and
 # the planner that shapes its launches): a changed source reports null.
+GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
+              'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f32>": {"src": ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/solve.cpp'],
-                           "sha256": "34d79d8f9ae1663dfb845e830c014a21e7c1bcc97c1c34a747be0eca7180ab9b",
-                           "bytes_per_launch": 0.7530e9 + 0.0112e9},
-    "gchunk_kernel<f64>": {"src": ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/solve.cpp'],
-                           "sha256": "34d79d8f9ae1663dfb845e830c014a21e7c1bcc97c1c34a747be0eca7180ab9b",
-                           "bytes_per_launch": 1.4662e9 + 0.0278e9},
-    "gemm_f64_pair_kernel": {"src": ['paper_2502_02395_amd/csrc/k_gemm.hip', 'paper_2502_02395_amd/csrc/build.cpp', 'paper_2502_02395_amd/csrc/solve.cpp'],
-                             "sha256": "76ddefbdbccfc4544eb1ee91882dfb13436d0a554c5c53042184b4042a9a7b2f",
-                             "bytes_per_launch": 7.3320e9 + 4.6859e9},
+    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
+                           "bytes_per_launch": 0.7236e9 + 0.0095e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
+                           "bytes_per_launch": 1.3964e9 + 0.0249e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
+                       "bytes_per_launch": 0.0153e9 + 0.0012e9},
 }
 
 
