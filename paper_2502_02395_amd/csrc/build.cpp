@@ -684,6 +684,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     const int nb = S.nbox;
     std::vector<GemmDesc> gw, gq1, gq2, gq3, gd1, gd2, gv, gs, gp1, gp2, gf1, gf2;
     std::vector<CopyDesc> cw, cps, cm;
+    std::vector<ConvDesc> cvd;  // FP32 transforms: D_ii -> FP32 above the leaves
     std::vector<BoxDev> qr(nb);
     for (int b = 0; b < nb; ++b) {
       const int m = S.m[b], k = S.k[b], r = m - k;
@@ -714,8 +715,21 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gq2.push_back(gd(P, k, 0, TA, m, 1, nullptr, 1, TB, k, k, m, k, 1.0, 0.0));
         gq3.push_back(gd(TA, m, 0, TB, k, 0, nullptr, 1, Q, m, m, m, k, -1.0, 0.0));
       }
-      gd1.push_back(gd(Dii, m, 0, Q, m, 0, nullptr, 1, TA, m, m, m, m, 1.0, 0.0));
-      gd2.push_back(gd(Q, m, 1, TA, m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
+      if (S.dD32) {
+        // FP32 transforms: D_ii and Q_i from their FP32 copies (Q32 in the
+        // P32 buffer, free until P exists), the product in TA's memory as
+        // FP32, F_ii = Q^T (.) in FP64 for the Cholesky of its RR part
+        float* D32 = S.dD32 + S.poff[S.diag_pair[b]];
+        float* Q32 = S.dP32 + S.qoff[b];
+        float* T32 = reinterpret_cast<float*>(TA);
+        auto asd = [](float* p) { return reinterpret_cast<double*>(p); };
+        gd1.push_back(gd(asd(D32), m, 0, asd(Q32), m, 0, nullptr, 1, asd(T32), m, m, m, m, 1.0, 0.0));
+        gd2.push_back(gd(asd(Q32), m, 1, asd(T32), m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
+        if (h > 0) cvd.push_back({Dii, D32, (int64_t)m * m, 1});
+      } else {
+        gd1.push_back(gd(Dii, m, 0, Q, m, 0, nullptr, 1, TA, m, m, m, m, 1.0, 0.0));
+        gd2.push_back(gd(Q, m, 1, TA, m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
+      }
       if (m * k > 0) cps.push_back({Q, P, m, k, m, m, 0});
       if (r > 0) {
         gv.push_back(gd(Q + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, P + (int64_t)k * m, m, m, r,
@@ -828,11 +842,12 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       return H2_ERR_ALLOC;
     if (!upload(c, S.c_w, cw, st) || !upload(c, S.c_ps, cps, st) || !upload(c, S.c_merge, cm, st) ||
         !upload(c, S.c_merge32, cm32, st) || !upload(c, S.c_merge3232, cm3232, st) ||
-        !upload(c, S.cv_fii, cvf, st) || !upload(c, S.qr, qr, st))
+        !upload(c, S.cv_fii, cvf, st) || !upload(c, S.cv_dii, cvd, st) ||
+        !upload(c, S.qr, qr, st))
       return H2_ERR_ALLOC;
     if (f32pair) {
-      S.g_pair1.f32io = S.g_pair2.f32io = S.g_far1.f32io = S.g_far2.f32io = 1;
-      S.g_far3.f32io = 2;
+      S.g_pair1.f32io = S.g_pair2.f32io = S.g_far1.f32io = S.g_far2.f32io = S.g_diag1.f32io = 1;
+      S.g_far3.f32io = S.g_diag2.f32io = 2;
     }
     // blocked Cholesky + inverse of the RR blocks (A at TB + k + k m, ld m;
     // L^{-1} at Li, ld r; panel scratch in TA)

@@ -85,6 +85,7 @@ struct Step {
   float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)
   float *dR32 = nullptr, *dS32 = nullptr, *dT332 = nullptr;  // FP32 R, far couplings, scratch
   Batch<ConvDesc> cv_fii;                  // F_ii -> FP32 (diagonal blocks)
+  Batch<ConvDesc> cv_dii;                  // D_ii -> FP32 above the leaves
   Batch<CopyDesc> c_merge32;               // merge from FP32 transformed blocks
   Batch<CopyDesc> c_merge3232;             // FP32 blocks into FP32 parent near blocks
   double* dR = nullptr;                    // at rkoff

@@ -193,14 +193,15 @@ hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
 }
 
 // ---------------------------------------------------------------------------
+// Columns spread over the blockIdx.y workgroups of a descriptor, rows over
+// the threads.
 __global__ __launch_bounds__(256) void copy_kernel(const CopyDesc* __restrict__ descs) {
   const CopyDesc d = descs[blockIdx.x];
-  const int64_t total = (int64_t)d.rows * d.cols;
-  for (int64_t e = threadIdx.x + (int64_t)blockIdx.y * 256; e < total; e += 256 * (int64_t)gridDim.y) {
-    const int r = (int)(e % d.rows), c = (int)(e / d.rows);
-    const double v = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
-    d.dst[r + (int64_t)c * d.ldd] = v;
-  }
+  for (int c = blockIdx.y; c < d.cols; c += gridDim.y)
+    for (int r = threadIdx.x; r < d.rows; r += 256) {
+      const double v = d.trans ? d.src[c + (int64_t)r * d.lds] : d.src[r + (int64_t)c * d.lds];
+      d.dst[r + (int64_t)c * d.ldd] = v;
+    }
 }
 
 hipError_t launch_copy(const CopyDesc* d_desc, int count, hipStream_t st) {

@@ -171,23 +171,31 @@ hipError_t launch_gemm_f32io(const GemmDesc* d_desc, const int* d_tile_map, int 
 }
 
 // Conversions between the FP64 factors and their FP32 copies, over lists of
-// contiguous ranges (one workgroup per range).
+// contiguous ranges (blockIdx.x = range, CVT_WG workgroups per range, four
+// independent elements per thread and pass).
+constexpr int CVT_WG = 8;
+template <typename TS, typename TD>
+__device__ __forceinline__ void cvt_range(const TS* __restrict__ s, TD* __restrict__ t, int64_t n) {
+  for (int64_t i0 = (int64_t)blockIdx.y * 1024 + threadIdx.x; i0 < n; i0 += CVT_WG * 1024) {
+    TS v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i0 + 256 * u < n ? s[i0 + 256 * u] : TS(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 256 * u < n) t[i0 + 256 * u] = (TD)v[u];
+  }
+}
 __global__ __launch_bounds__(256) void cvt_list_kernel(const ConvDesc* __restrict__ descs) {
   const ConvDesc c = descs[blockIdx.x];
-  if (c.to32) {
-    const double* s = static_cast<const double*>(c.src);
-    float* t = static_cast<float*>(c.dst);
-    for (int64_t i = threadIdx.x; i < c.n; i += 256) t[i] = (float)s[i];
-  } else {
-    const float* s = static_cast<const float*>(c.src);
-    double* t = static_cast<double*>(c.dst);
-    for (int64_t i = threadIdx.x; i < c.n; i += 256) t[i] = (double)s[i];
-  }
+  if (c.to32)
+    cvt_range(static_cast<const double*>(c.src), static_cast<float*>(c.dst), c.n);
+  else
+    cvt_range(static_cast<const float*>(c.src), static_cast<double*>(c.dst), c.n);
 }
 
 hipError_t launch_cvt_list(const ConvDesc* d, int count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cvt_list_kernel, dim3(count), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(cvt_list_kernel, dim3(count, CVT_WG), dim3(256), 0, st, d);
   return hipGetLastError();
 }
 
@@ -197,23 +205,22 @@ hipError_t launch_cvt_list(const ConvDesc* d, int count, hipStream_t st) {
 // FP32 pair transforms).  The CopyDesc pointers hold float arrays where FP32.
 template <typename TD>
 __global__ __launch_bounds__(256) void copy_f32_kernel(const CopyDesc* __restrict__ descs) {
-  const CopyDesc c = descs[blockIdx.y];
+  const CopyDesc c = descs[blockIdx.x];
   const float* src = reinterpret_cast<const float*>(c.src);
   TD* dst = reinterpret_cast<TD*>(c.dst);
-  const int64_t n = (int64_t)c.rows * c.cols;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const int r = (int)(e % c.rows), q = (int)(e / c.rows);
-    const float v = c.trans ? src[q + (int64_t)r * c.lds] : src[r + (int64_t)q * c.lds];
-    dst[r + (int64_t)q * c.ldd] = (TD)v;
-  }
+  for (int q = blockIdx.y; q < c.cols; q += gridDim.y)
+    for (int r = threadIdx.x; r < c.rows; r += 256) {
+      const float v = c.trans ? src[q + (int64_t)r * c.lds] : src[r + (int64_t)q * c.lds];
+      dst[r + (int64_t)q * c.ldd] = (TD)v;
+    }
 }
 
 hipError_t launch_copy_f32(const CopyDesc* d_desc, int count, hipStream_t st, bool dst32) {
   if (count <= 0) return hipSuccess;
   if (dst32)
-    hipLaunchKernelGGL(copy_f32_kernel<float>, dim3(4, count), dim3(256), 0, st, d_desc);
+    hipLaunchKernelGGL(copy_f32_kernel<float>, dim3(count, 8), dim3(256), 0, st, d_desc);
   else
-    hipLaunchKernelGGL(copy_f32_kernel<double>, dim3(4, count), dim3(256), 0, st, d_desc);
+    hipLaunchKernelGGL(copy_f32_kernel<double>, dim3(count, 8), dim3(256), 0, st, d_desc);
   return hipGetLastError();
 }
 

@@ -67,15 +67,24 @@ hipError_t launch_eval(const EvalDesc* d_desc, const int* d_tile_off, int count,
 }
 
 // ------------------------------------------------------------ vector utilities
+// Four independent elements per thread and pass (coalesced: element
+// i0 + 256 u of the block's 1024).
 __global__ __launch_bounds__(256) void cvt_f32_kernel(const double* __restrict__ src,
                                                       float* __restrict__ dst, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-    dst[i] = (float)src[i];
+  for (int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x; i0 < n;
+       i0 += (int64_t)gridDim.x * 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i0 + 256 * u < n ? src[i0 + 256 * u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 256 * u < n) dst[i0 + 256 * u] = (float)v[u];
+  }
 }
 
 hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  const int64_t blocks = std::min<int64_t>((n + 1023) / 1024, 65536);
   hipLaunchKernelGGL(cvt_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
 }

@@ -526,6 +526,12 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(S.g_qr3, st));
     HIPCHK(launch_qr_diag(S.qr.d, S.qr.count, st));
     HIPCHK(done());
+    if (S.dD32) {  // FP32 transforms: Q_i and (above the leaves) D_ii to FP32
+      HIPCHK(mark(FP_F32));
+      HIPCHK(launch_cvt_f32(S.dQ, S.dP32, S.qoff[S.nbox], st));
+      HIPCHK(launch_cvt_list(S.cv_dii.d, S.cv_dii.count, st));
+      HIPCHK(done());
+    }
     HIPCHK(mark(FP_DIAG));
     HIPCHK(run_gemm_p(c, S.g_diag1, st));
     HIPCHK(run_gemm_p(c, S.g_diag2, st));
