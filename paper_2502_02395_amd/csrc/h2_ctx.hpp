@@ -117,7 +117,6 @@ struct Step {
   GList t_fwd, t_bwd;                      // P^T b, P [xS; s]
   GList g_yr, g_cs, g_t, g_s;              // neighbour gathers of the substitution
   GList t_up, t_down;                      // U^T x, U y
-  GList g_cpl, g_near;                     // couplings and leaf near field
   // solve vectors (ld = sum_m or sum_r), NRHS_MAX columns
   double *v_in = nullptr, *v_d = nullptr, *v_out = nullptr, *v_yr = nullptr, *v_t = nullptr;
   double *v_xh = nullptr, *v_yh = nullptr;  // matvec skeleton vectors (ld sum_k)
@@ -172,6 +171,8 @@ struct Ctx {
   double *vt_in = nullptr, *vt_out = nullptr;
   Batch<CopyDesc> r_in, r_out;             // root-only instances <-> v_root
   GList t_root;                            // root-only instances: matvec
+  GList g_mv;                              // matvec: couplings y^ = S x^ of every level
+                                           // and the leaf near field y = D x
   // refinement vectors (N x NRHS_MAX)
   double *w_x = nullptr, *w_r = nullptr, *w_z = nullptr, *w_p = nullptr, *w_q = nullptr, *w_t = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;  // pair-transform timing

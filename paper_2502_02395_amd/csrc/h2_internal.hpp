@@ -222,6 +222,8 @@ struct GRed {
 // direct slots cost more than the shorter waves gain).
 constexpr int GATHER_SEG = 128;
 constexpr int GATHER_SEG_FROM = 5;
+constexpr int GATHER_SEG_TOP = 32;       // the top levels: a few blocks each
+constexpr int GATHER_SEG_TOP_FROM = 8;
 // Wide chunks: a block's rows split evenly into chunks of at most 64 x RPL
 // rows (one wave each, up to RPL rows per lane: 4 for FP32 copies, 2 for
 // FP64 blocks), so that e.g. an FP32 block of 150 rows takes one wave with

@@ -182,6 +182,10 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
     ld = (int)P.vld;
   };
 
+  // the matvec's couplings of every level and the leaf near field are
+  // independent of each other: one list, planned after the loop
+  std::vector<std::vector<GatherBox>> mv_b(c.H + 1);
+  std::vector<std::vector<GatherNbr>> mv_n(c.H + 1);
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
     const int nb = S.nbox;
@@ -334,11 +338,12 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       }
       // downward U y^
       if (h == 0) {
-        td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, nullptr, 1, c.vt_out + S.voff[b], vld, m,
-                        NR, k, 1.0, 0.0));
-        // near field y_i += sum_j D_ij x_j
-        GatherBox g{c.vt_out + S.voff[b], c.vt_out + S.voff[b], m, vld, vld, 1.0, (int)nn.size(), 0, 0,
-                    0};
+        // y_i = (near field, written first) + U y^
+        if (k > 0)
+          td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, c.vt_out + S.voff[b], vld,
+                          c.vt_out + S.voff[b], vld, m, NR, k, 1.0, 1.0));
+        // near field y_i = sum_j D_ij x_j
+        GatherBox g{c.vt_out + S.voff[b], nullptr, m, vld, vld, 1.0, (int)nn.size(), 0, 0, 0};
         nn.push_back({S.dD + S.poff[S.diag_pair[b]], c.vt_in + S.voff[b], m, vld, m});
         for (auto& jp : lower[b]) {
           const int j = jp.first;
@@ -368,7 +373,9 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       rb.push_back({S.dF, S.poff.back(), S.dF32});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
     }
-    const int sg = h >= GATHER_SEG_FROM ? GATHER_SEG : 0;
+    const int sg = h >= GATHER_SEG_TOP_FROM ? GATHER_SEG_TOP
+                 : h >= GATHER_SEG_FROM     ? GATHER_SEG
+                                            : 0;
     const bool wd = h >= GATHER_WIDE_FROM && h <= GATHER_WIDE_TO;
     const std::vector<Rebase> none;
     if (!up_thin(c, S.t_fwd, tf, st, rb, sg, wd) || !up_thin(c, S.t_bwd, tb, st, rb, sg, wd) ||
@@ -376,10 +383,29 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         !up_gather(c, S.g_yr, b1, n1, st, rb, sg, wd) ||
         !up_gather(c, S.g_cs, b2, n2, st, rb, sg, wd) ||
         !up_gather(c, S.g_t, b3, n3, st, rb, sg, wd) ||
-        !up_gather(c, S.g_s, b4, n4, st, rb, sg, wd) ||
-        !up_gather(c, S.g_cpl, bc, nc, st, none, sg, wd) ||
-        !up_gather(c, S.g_near, bn, nn, st, none, sg, wd))
+        !up_gather(c, S.g_s, b4, n4, st, rb, sg, wd))
       return H2_ERR_ALLOC;
+    mv_b[h + 1] = std::move(bc);
+    mv_n[h + 1] = std::move(nc);
+    if (h == 0) {
+      mv_b[0] = std::move(bn);
+      mv_n[0] = std::move(nn);
+    }
+  }
+  {
+    // top level first, so that the few long waves of the top levels start
+    // at once and run under the leaf lists instead of trailing them
+    std::vector<GatherBox> B;
+    std::vector<GatherNbr> Nv;
+    for (int q = c.H; q >= 0; --q) {
+      const int off = (int)Nv.size();
+      for (GatherBox g : mv_b[q]) {
+        g.d0 += off; g.d1 += off; g.t0 += off; g.t1 += off;
+        B.push_back(g);
+      }
+      Nv.insert(Nv.end(), mv_n[q].begin(), mv_n[q].end());
+    }
+    if (!up_gather(c, c.g_mv, B, Nv, st)) return H2_ERR_ALLOC;
   }
   // root solves and root-only instances
   {
@@ -641,9 +667,8 @@ h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64
                           hipStream_t st) {
   HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, x, ldx, c.vt_in, c.N, st));
   for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].t_up, nrhs, st));
-  for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].g_cpl, nrhs, st));
+  HIPCHK(gather(c, c.g_mv, nrhs, st));  // couplings of every level, leaf near field
   for (int h = c.H - 1; h >= 0; --h) HIPCHK(gather(c, c.steps[h].t_down, nrhs, st));
-  if (c.H > 0) HIPCHK(gather(c, c.steps[0].g_near, nrhs, st));
   HIPCHK(gather(c, c.t_root, nrhs, st));
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, y, ldy, st));
   return H2_OK;
