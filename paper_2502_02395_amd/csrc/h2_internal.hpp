@@ -269,8 +269,9 @@ hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t 
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 
-// Root blocked Cholesky panel: factor nb x nb diagonal block in place and
-// write its inverse (64 x 64, zero padded) to dinv.
+// Blocked Cholesky panel (nb <= 64; the root and the redundant blocks):
+// factor the nb x nb diagonal block in place (L below, zeros above) and write
+// the inverse of L (nb x nb, zeros above the diagonal) to dinv.
 struct PanelDesc {
   double* A;                // diagonal block pointer
   int lda, nb;

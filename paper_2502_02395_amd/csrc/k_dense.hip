@@ -573,21 +573,91 @@ hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail, hipStre
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------- root panels
+// ------------------------------------------------------------- 64-wide panels
+// Cholesky of an nb x nb diagonal block (nb <= 64) and the inverse of its
+// factor, all in LDS.  The block is padded to 64 x 64 with the identity (the
+// factor and its inverse are then the identity there too).  Cholesky:
+// right-looking, one barrier per column (every thread reads the pivot; column
+// j is scaled after the barrier, when step j+1 no longer reads it).  Inverse:
+// block recursion X = [X11, 0; -X22 L21 X11, X22] from the 16 x 16 diagonal
+// blocks (forward substitution, one thread per column) to 32 and 64.
+constexpr int PLD = 65;  // LDS leading dimension (odd: column walks are conflict-free)
+
+// X21 = -X22 (L21 X11) for the two diagonal blocks of size 2h starting at
+// rows/columns o = 0 and 2h (h = 16), or the one of size 64 (h = 32).
+template <int H>
+__device__ __forceinline__ void panel_inv_merge(const double* __restrict__ a, double* __restrict__ x,
+                                                double* __restrict__ t) {
+  constexpr int NBLK = 64 / (2 * H);
+  // T = L21 X11  (H x H per block; X11 lower triangular)
+  for (int e = threadIdx.x; e < NBLK * H * H; e += 256) {
+    const int blk = e / (H * H), r = e % H, c = (e / H) % H;
+    const int o = blk * 2 * H;
+    double s = 0.0;
+    for (int q = c; q < H; ++q) s += a[(o + H + r) + (o + q) * PLD] * x[(o + q) + (o + c) * PLD];
+    t[r + c * H + blk * H * H] = s;
+  }
+  __syncthreads();
+  // X21 = -X22 T  (X22 lower triangular)
+  for (int e = threadIdx.x; e < NBLK * H * H; e += 256) {
+    const int blk = e / (H * H), r = e % H, c = (e / H) % H;
+    const int o = blk * 2 * H;
+    double s = 0.0;
+    for (int q = 0; q <= r; ++q) s += x[(o + H + r) + (o + H + q) * PLD] * t[q + c * H + blk * H * H];
+    x[(o + H + r) + (o + c) * PLD] = -s;
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void panel_kernel(const PanelDesc* __restrict__ descs, int* fail) {
-  __shared__ double buf[64 * 64];
+  __shared__ double a[64 * PLD];
+  __shared__ double x[64 * PLD];
+  __shared__ double t[32 * 32];
   const PanelDesc d = descs[blockIdx.x];
   const int n = d.nb;
   if (n <= 0) return;
-  for (int e = threadIdx.x; e < n * n; e += 256) {
-    const int r = e % n, c = e / n;
-    buf[e] = d.A[r + (int64_t)c * d.lda];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    a[r + c * PLD] = (r < n && c < n) ? d.A[r + (int64_t)c * d.lda] : (r == c ? 1.0 : 0.0);
+    x[r + c * PLD] = 0.0;
   }
   __syncthreads();
-  chol_inv_impl(buf, n, d.dinv, d.ldd, n, fail, d.code);
-  for (int e = threadIdx.x; e < n * n; e += 256) {
+  for (int j = 0; j < 64; ++j) {
+    double djj = a[j + j * PLD];
+    if (!(djj > 0.0)) {
+      if (tid == 0) atomicMin(fail, d.code);
+      djj = 1.0;
+    }
+    const double rd = 1.0 / djj;
+    // a[i, c] -= a[i, j] a[c, j] / a[j, j] for j < c <= i (unscaled column j)
+    for (int c = j + 1 + wave; c < 64; c += 4) {
+      const double acj = a[c + j * PLD] * rd;
+      for (int i = c + lane; i < 64; i += 64) a[i + c * PLD] -= a[i + j * PLD] * acj;
+    }
+    __syncthreads();
+    if (tid >= j && tid < 64) {
+      const double sj = sqrt(djj);
+      a[tid + j * PLD] = tid == j ? sj : a[tid + j * PLD] / sj;
+    }
+  }
+  __syncthreads();
+  // diagonal 16 x 16 blocks of the inverse: thread = column, forward substitution
+  if (tid < 64) {
+    const int o = tid & ~15, j = tid;
+    for (int i = o; i < o + 16; ++i) {
+      double s = i == j ? 1.0 : 0.0;
+      for (int q = o; q < i; ++q) s -= a[i + q * PLD] * x[q + j * PLD];
+      x[i + j * PLD] = s / a[i + i * PLD];
+    }
+  }
+  __syncthreads();
+  panel_inv_merge<16>(a, x, t);
+  panel_inv_merge<32>(a, x, t);
+  for (int e = tid; e < n * n; e += 256) {
     const int r = e % n, c = e / n;
-    d.A[r + (int64_t)c * d.lda] = (r >= c) ? buf[e] : 0.0;
+    d.A[r + (int64_t)c * d.lda] = r >= c ? a[r + c * PLD] : 0.0;
+    d.dinv[r + (int64_t)c * d.ldd] = x[r + c * PLD];
   }
 }
 
