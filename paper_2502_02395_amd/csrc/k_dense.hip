@@ -107,10 +107,9 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   const int wj = min(w, k - J), L = m - J;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* W = b.W;
-  for (int e = threadIdx.x; e < L * wj; e += 256) {
-    const int r = e % L, c = e / L;
-    pan[e] = W[J + r + (int64_t)(J + c) * m];
-  }
+  // (column loops over waves, row loops over lanes: no index divisions)
+  for (int c = wave; c < wj; c += 4)
+    for (int r = lane; r < L; r += 64) pan[c * L + r] = W[J + r + (int64_t)(J + c) * m];
   __syncthreads();
   // Householder steps, thread-parallel, two barriers per column.  Column jj
   // stays unscaled while later columns are updated (v_r = pan[r, jj] * scal
@@ -157,14 +156,16 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
     __syncthreads();
     double nxt = 0.0;
     if (nc > 0) {
-      const int rows = L - jj;
       if (tau != 0.0) {
-        for (int e = threadIdx.x; e < rows * nc; e += 256) {
-          const int r = jj + e % rows, ci = e / rows;
-          const double v = (r == jj) ? 1.0 : pan[jj * L + r] * scal;
-          const double x = pan[(jj + 1 + ci) * L + r] - v * wv[ci];
-          pan[(jj + 1 + ci) * L + r] = x;
-          if (ci == 0 && r > jj + 1) nxt += x * x;
+        for (int ci = wave; ci < nc; ci += 4) {
+          const double wc = wv[ci];
+          double* xc = pan + (jj + 1 + ci) * L;
+          for (int r = jj + lane; r < L; r += 64) {
+            const double v = (r == jj) ? 1.0 : pan[jj * L + r] * scal;
+            const double x = xc[r] - v * wc;
+            xc[r] = x;
+            if (ci == 0 && r > jj + 1) nxt += x * x;
+          }
         }
       } else {
         for (int r = jj + 2 + threadIdx.x; r < L; r += 256)
@@ -175,32 +176,31 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
     if (lane == 0) sh[wave] = nxt;
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < L * wj; e += 256) {
-    const int r = e % L, c = e / L;
-    if (r > c) pan[e] *= scalp[c];
-    else if (r == c) pan[e] = betap[c];
+  for (int c = wave; c < wj; c += 4) {
+    const double sc = scalp[c];
+    for (int r = c + lane; r < L; r += 64) {
+      if (r > c) pan[c * L + r] *= sc;
+      else pan[c * L + r] = betap[c];
+    }
   }
   __syncthreads();
   // R columns J..J+wj-1 (rows above the panel are final in W), tau
-  for (int e = threadIdx.x; e < k * wj; e += 256) {
-    const int r = e % k, c = e / k;
-    double v = 0.0;
-    if (r < J) v = W[r + (int64_t)(J + c) * m];
-    else if (r <= J + c) v = pan[c * L + (r - J)];
-    b.Rf[r + (int64_t)(J + c) * k] = v;
-  }
+  for (int c = wave; c < wj; c += 4)
+    for (int r = lane; r < k; r += 64) {
+      double v = 0.0;
+      if (r < J) v = W[r + (int64_t)(J + c) * m];
+      else if (r <= J + c) v = pan[c * L + (r - J)];
+      b.Rf[r + (int64_t)(J + c) * k] = v;
+    }
   if ((int)threadIdx.x < wj) b.tau[J + threadIdx.x] = taup[threadIdx.x];
   __syncthreads();
   // V explicit in the panel: zeros above the diagonal, ones on it
-  for (int e = threadIdx.x; e < wj * wj; e += 256) {
-    const int r = e % wj, c = e / wj;
-    if (r <= c) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
-  }
+  for (int c = wave; c < wj; c += 4)
+    for (int r = lane; r <= c; r += 64) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
   __syncthreads();
-  for (int e = threadIdx.x; e < m * wj; e += 256) {
-    const int r = e % m, c = e / m;
-    b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
-  }
+  for (int c = wave; c < wj; c += 4)
+    for (int r = lane; r < m; r += 64)
+      b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
   if (J + wj >= k) return;
   // T_p from G_p = V_p^T V_p by recursive doubling: for two adjacent blocks
   // of reflectors, T = [T1, -T1 (V1^T V2) T2; 0, T2].  G_p's strict upper
