@@ -1,0 +1,126 @@
+"""Single-node studies on synthetic geometry, after the paper's Section 6
+scaling and parameter studies (the sphere-surface family of Section 6.2;
+the paper's plotted values are not available as numbers, so these are
+measurements of this build only):
+
+  scaling  -- build, factor and solve time, factor TFLOP/s and the number of
+              near (dense, non-zero) and far blocks vs N (O(N) behaviour);
+  eta      -- factor flops, near / far blocks, ranks and times vs the
+              admissibility eta at a fixed N;
+  hss      -- HSS (eta = 0, weak admissibility) vs H^2 (eta = 1): ranks,
+              factor flops and the accuracy of the H^2 operator and of the
+              unrefined solve against the dense kernel matrix.
+
+    python -m paper_2502_02395_amd.studies [scaling|eta|hss|all] [--max-n N]
+
+Every line printed is one JSON record.  The dense reference of the hss
+study is the kernel matrix formed with plain torch operations on the GPU
+(N = 8192), not the library.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+
+def _run(h2, p, gemm_prec, solve_prec, nrhs=1, refine=True):
+    import numpy as np
+    import torch
+    t0 = time.perf_counter()
+    kw = dict(s_far=p.s_far, s_near=p.s_near, gemm_prec=gemm_prec, solve_prec=solve_prec)
+    if refine:
+        kw.update(ir_max_iter=100, ir_tol=1e-8, use_pcg=True)
+    H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), **kw)
+    t_build = time.perf_counter() - t0
+    b = torch.from_numpy(p.b()[:, :nrhs].copy()).cuda()
+    H.factor()          # warm-up (first-use costs)
+    H.solve(b)
+    torch.cuda.synchronize()
+    H.factor()
+    x = H.solve(b)
+    torch.cuda.synchronize()
+    st = H.stats()
+    _, ranks, ms, _ = H.structure()
+    rec = {"n": p.n, "leaf": p.leaf, "eta": p.eta, "eps": p.eps, "levels": st["levels"],
+           "near_pairs": st["near_pairs"], "far_pairs": st["far_pairs"],
+           "leaf_near_blocks": st["leaf_near_blocks"], "max_rank": int(ranks.max()),
+           "mean_rank": float(ranks.mean()), "root_n": st["root_n"],
+           "build_s": t_build, "factor_s": st["t_factor"], "solve_s": st["t_solve"],
+           "flops_factor": st["flops_factor"],
+           "factor_tflops": st["flops_factor"] / max(st["t_factor"], 1e-12) / 1e12,
+           "ir_iters": st["ir_iters"], "residual": st["ir_residual"]}
+    return H, b, x, rec
+
+
+def scaling(h2, max_n: int, prec):
+    import workloads as W
+    n = 1 << 14
+    while n <= max_n:
+        p = W.laplace_sphere(n=n, leaf=256, eps=1e-8, nrhs=1)
+        H, _, _, rec = _run(h2, p, prec, prec)
+        H.close()
+        rec["study"] = "scaling"
+        print(json.dumps(rec), flush=True)
+        n *= 2
+
+
+def eta_sweep(h2, n: int, prec):
+    import workloads as W
+    for eta in (0.0, 0.5, 1.0, 1.5, 2.0, 3.0):
+        p = W.laplace_sphere(n=n, leaf=256, eps=1e-8, eta=eta, nrhs=1)
+        try:
+            H, _, _, rec = _run(h2, p, prec, prec)
+            H.close()
+        except h2.H2Error as e:  # e.g. a Cholesky breakdown: recorded, not fatal
+            rec = {"n": p.n, "leaf": p.leaf, "eta": eta, "eps": p.eps, "error": str(e)}
+        rec["study"] = "eta"
+        print(json.dumps(rec), flush=True)
+
+
+def hss_vs_h2(h2):
+    import torch
+    import workloads as W
+    for eta in (0.0, 1.0):
+        p = W.laplace_sphere(n=8192, leaf=512, eps=1e-8, eta=eta, nrhs=1, s=1024)
+        try:
+            H, b, x, rec = _run(h2, p, h2.PREC_FP64, h2.PREC_FP64, refine=False)
+        except h2.H2Error as e:
+            print(json.dumps({"study": "hss" if eta == 0.0 else "h2", "n": p.n, "eta": eta,
+                              "error": str(e)}), flush=True)
+            continue
+        X = torch.from_numpy(p.points).cuda()
+        A = 1.0 / (torch.cdist(X, X) + p.kernel.delta)
+        v = torch.randn(p.n, 1, dtype=torch.float64, device="cuda")
+        y = H.matvec(v)
+        rec["matvec_rel_err"] = float(torch.linalg.norm(y - A @ v) / torch.linalg.norm(A @ v))
+        rec["solve_rel_residual_dense"] = float(torch.linalg.norm(b - A @ x) /
+                                                torch.linalg.norm(b))
+        H.close()
+        rec["study"] = "hss" if eta == 0.0 else "h2"
+        print(json.dumps(rec), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("study", nargs="?", default="all", choices=["scaling", "eta", "hss", "all"])
+    ap.add_argument("--max-n", type=int, default=1 << 19)
+    ap.add_argument("--eta-n", type=int, default=1 << 18)
+    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"],
+                    help="transform and substitution precision of the scaling and eta runs")
+    a = ap.parse_args()
+    import torch
+    from paper_2502_02395_amd import h2
+    torch.cuda.set_device(0)
+    prec = h2.PREC_FP32 if a.prec == "fp32" else h2.PREC_FP64
+    if a.study in ("scaling", "all"):
+        scaling(h2, a.max_n, prec)
+    if a.study in ("eta", "all"):
+        eta_sweep(h2, a.eta_n, prec)
+    if a.study in ("hss", "all"):
+        hss_vs_h2(h2)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
