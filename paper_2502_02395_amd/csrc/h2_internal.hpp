@@ -64,7 +64,7 @@ struct BoxDev {
   double* tau;              // k Householder scalars
 };
 
-constexpr int QR_MMAX = 6912;  // row limit of the QR panel kernel
+constexpr int QR_MMAX = 6911;  // row limit of the QR panel kernel (m + 1 doubles per panel column)
 
 // ------------------------------------------------------------- launch wrappers
 // All wrappers enqueue on `st`; they return hipSuccess or the launch error.

@@ -105,11 +105,14 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   const int m = b.m, k = b.k;
   if (m == 0 || k <= J) return;
   const int wj = min(w, k - J), L = m - J;
+  // column stride of the panel in LDS: odd, so that threads reading the
+  // same row of different columns hit different banks
+  const int LP = L | 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* W = b.W;
   // (column loops over waves, row loops over lanes: no index divisions)
   for (int c = wave; c < wj; c += 4)
-    for (int r = lane; r < L; r += 64) pan[c * L + r] = W[J + r + (int64_t)(J + c) * m];
+    for (int r = lane; r < L; r += 64) pan[c * LP + r] = W[J + r + (int64_t)(J + c) * m];
   __syncthreads();
   // Householder steps, thread-parallel, two barriers per column.  Column jj
   // stays unscaled while later columns are updated (v_r = pan[r, jj] * scal
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   }
   for (int jj = 0; jj < wj; ++jj) {
     const double sigma = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-    const double alpha = pan[jj * L + jj];
+    const double alpha = pan[jj * LP + jj];
     double tau = 0.0, beta = alpha, scal = 0.0;
     if (sigma != 0.0) {
       beta = -copysign(sqrt(alpha * alpha + sigma), alpha);
@@ -141,12 +144,12 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
       const int grp = threadIdx.x / G, sub = threadIdx.x % G;
       double acc = 0.0;
       if (grp < nc) {
-        const double* vc = pan + jj * L;
-        const double* xc = pan + (jj + 1 + grp) * L;
+        const double* vc = pan + jj * LP;
+        const double* xc = pan + (jj + 1 + grp) * LP;
         for (int r = jj + 1 + sub; r < L; r += G) acc += vc[r] * xc[r];
       }
       for (int o = G >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-      if (grp < nc && sub == 0) wv[grp] = tau * (pan[(jj + 1 + grp) * L + jj] + scal * acc);
+      if (grp < nc && sub == 0) wv[grp] = tau * (pan[(jj + 1 + grp) * LP + jj] + scal * acc);
     }
     if (threadIdx.x == 0) {
       taup[jj] = tau;
@@ -159,9 +162,9 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
       if (tau != 0.0) {
         for (int ci = wave; ci < nc; ci += 4) {
           const double wc = wv[ci];
-          double* xc = pan + (jj + 1 + ci) * L;
+          double* xc = pan + (jj + 1 + ci) * LP;
           for (int r = jj + lane; r < L; r += 64) {
-            const double v = (r == jj) ? 1.0 : pan[jj * L + r] * scal;
+            const double v = (r == jj) ? 1.0 : pan[jj * LP + r] * scal;
             const double x = xc[r] - v * wc;
             xc[r] = x;
             if (ci == 0 && r > jj + 1) nxt += x * x;
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
         }
       } else {
         for (int r = jj + 2 + threadIdx.x; r < L; r += 256)
-          nxt += pan[(jj + 1) * L + r] * pan[(jj + 1) * L + r];
+          nxt += pan[(jj + 1) * LP + r] * pan[(jj + 1) * LP + r];
       }
     }
     nxt = wave_sum(nxt);
@@ -179,8 +182,8 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   for (int c = wave; c < wj; c += 4) {
     const double sc = scalp[c];
     for (int r = c + lane; r < L; r += 64) {
-      if (r > c) pan[c * L + r] *= sc;
-      else pan[c * L + r] = betap[c];
+      if (r > c) pan[c * LP + r] *= sc;
+      else pan[c * LP + r] = betap[c];
     }
   }
   __syncthreads();
@@ -189,18 +192,18 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
     for (int r = lane; r < k; r += 64) {
       double v = 0.0;
       if (r < J) v = W[r + (int64_t)(J + c) * m];
-      else if (r <= J + c) v = pan[c * L + (r - J)];
+      else if (r <= J + c) v = pan[c * LP + (r - J)];
       b.Rf[r + (int64_t)(J + c) * k] = v;
     }
   if ((int)threadIdx.x < wj) b.tau[J + threadIdx.x] = taup[threadIdx.x];
   __syncthreads();
   // V explicit in the panel: zeros above the diagonal, ones on it
   for (int c = wave; c < wj; c += 4)
-    for (int r = lane; r <= c; r += 64) pan[c * L + r] = (r == c) ? 1.0 : 0.0;
+    for (int r = lane; r <= c; r += 64) pan[c * LP + r] = (r == c) ? 1.0 : 0.0;
   __syncthreads();
   for (int c = wave; c < wj; c += 4)
     for (int r = lane; r < m; r += 64)
-      b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * L + (r - J)];
+      b.tmpA[r + (int64_t)(J + c) * m] = (r < J) ? 0.0 : pan[c * LP + (r - J)];
   if (J + wj >= k) return;
   // T_p from G_p = V_p^T V_p by recursive doubling: for two adjacent blocks
   // of reflectors, T = [T1, -T1 (V1^T V2) T2; 0, T2].  G_p's strict upper
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
     const int i = pq % wj, jj = pq / wj;
     double d = 0.0;
     if (i < jj)
-      for (int r = jj; r < L; ++r) d += pan[i * L + r] * pan[jj * L + r];
+      for (int r = jj; r < L; ++r) d += pan[i * LP + r] * pan[jj * LP + r];
     Gp[i + jj * QR_PW] = d;
     Tp[i + jj * QR_PW] = (i == jj) ? taup[i] : 0.0;
   }
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(const BoxDev* __restrict_
   for (int r = threadIdx.x; r < L; r += 256) {
     for (int c = 0; c < wj; ++c) {
       double acc = 0.0;
-      for (int i = 0; i <= c; ++i) acc += pan[i * L + r] * Tp[i + c * QR_PW];
+      for (int i = 0; i <= c; ++i) acc += pan[i * LP + r] * Tp[i + c * QR_PW];
       U[r + (int64_t)c * m] = acc;
     }
   }
@@ -308,13 +311,13 @@ __global__ __launch_bounds__(256) void qr_diag_kernel(const BoxDev* __restrict__
 
 int qr_panel_width(int max_m) {
   if (max_m <= 0) return QR_PW;
-  return std::max(1, std::min(QR_PW, QR_PAN / max_m));
+  return std::max(1, std::min(QR_PW, QR_PAN / (max_m + 1)));  // + 1: odd column stride
 }
 
 hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, int J, int w,
                            hipStream_t st) {
   if (nbox <= 0) return hipSuccess;
-  if (w < 1 || w > QR_PW || (int64_t)max_m * w > QR_PAN) return hipErrorInvalidValue;
+  if (w < 1 || w > QR_PW || (int64_t)(max_m + 1) * w > QR_PAN) return hipErrorInvalidValue;
   hipLaunchKernelGGL(qr_panel_kernel, dim3(nbox), dim3(256), 0, st, boxes, J, w);
   return hipGetLastError();
 }
