@@ -40,12 +40,12 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
-                           "bytes_per_launch": 0.7236e9 + 0.0095e9},
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
-                           "bytes_per_launch": 1.3964e9 + 0.0249e9},
-    "greduce_kernel": {"src": GATHER_SRC, "sha256": "df79bfa753440554e46614f44cb524cb9f2a103f670b2f0d5bbe8231b8469bfd",
-                       "bytes_per_launch": 0.0153e9 + 0.0012e9},
+    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "f4f729d0e4b66b3a2b99c04514b133bd943cadc1c9b3ac4a35da9cb081808ac2",
+                           "bytes_per_launch": 0.7235e9 + 0.0095e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "f4f729d0e4b66b3a2b99c04514b133bd943cadc1c9b3ac4a35da9cb081808ac2",
+                           "bytes_per_launch": 1.9673e9 + 0.0374e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "f4f729d0e4b66b3a2b99c04514b133bd943cadc1c9b3ac4a35da9cb081808ac2",
+                       "bytes_per_launch": 0.0178e9 + 0.0013e9},
 }
 
 
