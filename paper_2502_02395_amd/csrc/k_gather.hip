@@ -199,11 +199,22 @@ __global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ r
   double acc[NR];
 #pragma unroll
   for (int c = 0; c < NR; ++c) acc[c] = 0.0;
-  for (int q = g.s0; q < g.s1; ++q) {
-    const double* p = P + offs[q] * nrhs + r;
+  // UN slots in flight per pass; the sum still runs over the slots in order
+  constexpr int UN = NR <= 2 ? 8 : NR <= 4 ? 4 : 2;
+  for (int q = g.s0; q < g.s1; q += UN) {
+    double v[UN][NR];
 #pragma unroll
-    for (int c = 0; c < NR; ++c)
-      if (c < nrhs) acc[c] += p[(int64_t)c * g.rows];
+    for (int u = 0; u < UN; ++u) {
+      const bool in = q + u < g.s1;
+      const double* p = P + (in ? offs[q + u] : 0) * nrhs + r;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) v[u][c] = (in && c < nrhs) ? p[(int64_t)c * g.rows] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; ++u)
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (q + u < g.s1) acc[c] += v[u][c];
   }
   for (int c = 0; c < nrhs; ++c) {
     const double base = g.base ? g.base[r + (int64_t)c * g.ldbase] : 0.0;
