@@ -6,7 +6,8 @@ For each level l from the leaves up to 1 and each box i of that level:
   * S_C: sample of the near field, the active points of every near box j != i
     (box i itself excluded, otherwise A_Close would hold identity rows);
   * A_cc = G(S_C, S_C), A_Far = G(B_i, S_F), A_Close = G(B_i, S_C) A_cc^{-1}
-    (the pre-factorization of Section 3.5, here an exact Cholesky solve);
+    (the pre-factorization of Section 3.5: an exact Cholesky solve, or the
+    paper's Gauss-Seidel approximation with a given number of sweeps);
   * (U_i, SK_i) = ID([A_Far, A_Close]) -- a row interpolative decomposition
     by column-pivoted QR of the transpose (rank k_i: the leading pivots with
     |R_jj| > eps |R_11|, optionally capped), U_i having identity rows at the
@@ -92,6 +93,19 @@ def build_basis(piv: np.ndarray, k: int, T: np.ndarray, m: int) -> np.ndarray:
     return U
 
 
+def gauss_seidel(A: np.ndarray, B: np.ndarray, sweeps: int) -> np.ndarray:
+    """Approximate A^{-1} B by forward Gauss-Seidel sweeps from X = 0 (the
+    Section 3.5 replacement of the factorization of A_cc): in each sweep the
+    rows i = 0, 1, ... of X become (B_i - sum_{j != i} A_ij X_j) / A_ii,
+    using the rows already replaced in the same sweep."""
+    X = np.zeros_like(B, dtype=np.float64)
+    for _ in range(sweeps):
+        for i in range(A.shape[0]):
+            s = B[i] - A[i] @ X + A[i, i] * X[i]
+            X[i] = s / A[i, i]
+    return X
+
+
 def _sample(cands: np.ndarray, pirank: np.ndarray, count: int) -> np.ndarray:
     o = np.argsort(pirank[cands], kind="stable")
     c = cands[o]
@@ -100,11 +114,14 @@ def _sample(cands: np.ndarray, pirank: np.ndarray, count: int) -> np.ndarray:
 
 def construct(X: np.ndarray, kernel, leaf: int, eta: float, eps: float,
               pi: np.ndarray, s_far: int = -1, s_near: int = -1,
-              max_rank: int = 0, skeletons: dict | None = None) -> H2Matrix:
+              max_rank: int = 0, skeletons: dict | None = None,
+              gs_sweeps: int = 0) -> H2Matrix:
     """Algorithm 1.  ``skeletons`` optionally fixes, per (l, i), the skeleton
     (positions into B_i, in pivot order; its length is the rank) instead of
     running the pivoted QR; the remaining rows follow in increasing position.
-    Used to build an H^2 matrix with a prescribed skeleton selection."""
+    Used to build an H^2 matrix with a prescribed skeleton selection.
+    ``gs_sweeps`` > 0 replaces the exact solve with A_cc by that many
+    Gauss-Seidel sweeps (Section 3.5)."""
     tree = ClusterTree(X, leaf, eta)
     L = tree.L
     n = X.shape[0]
@@ -133,8 +150,11 @@ def construct(X: np.ndarray, kernel, leaf: int, eta: float, eps: float,
             if SC.size:
                 A_cc = kernels.evaluate(kernel, X[SC], X[SC], SC, SC)
                 G_bc = kernels.evaluate(kernel, X[Bi], X[SC], Bi, SC)
-                cf = sla.cho_factor(A_cc, lower=True)
-                A_close = sla.cho_solve(cf, G_bc.T).T       # G(B_i,S_C) A_cc^{-1}
+                if gs_sweeps > 0:
+                    A_close = gauss_seidel(A_cc, G_bc.T, gs_sweeps).T
+                else:
+                    cf = sla.cho_factor(A_cc, lower=True)
+                    A_close = sla.cho_solve(cf, G_bc.T).T   # G(B_i,S_C) A_cc^{-1}
             else:
                 A_close = np.zeros((Bi.size, 0))
             M = np.hstack([A_far, A_close])
