@@ -92,6 +92,10 @@ typedef struct {
                              near blocks and bases are made at the end of
                              h2_factor; arithmetic, the root, the H^2 matvec
                              and the refinement stay FP64                       */
+  int32_t gs_sweeps;      /* pre-factorization of h2_build (Section 3.5): 0 =
+                             exact Cholesky solve with the near-sample block
+                             A_cc; n > 0 = n Gauss-Seidel sweeps (from zero)
+                             approximating A_Close = G(B_i, S_C) A_cc^{-1}     */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;

@@ -108,6 +108,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   if (prm->leaf < 2 || !(prm->eps >= 0.0) || !(prm->eta >= 0.0)) return H2_ERR_ARG;
   if (prm->s_far < -1 || prm->s_near < -1 || prm->max_rank < 0) return H2_ERR_ARG;
   if (prm->solve_prec != H2_PREC_FP64 && prm->solve_prec != H2_PREC_FP32) return H2_ERR_ARG;
+  if (prm->gs_sweeps < 0 || prm->gs_sweeps > 64) return H2_ERR_ARG;
   if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
       prm->gemm_prec != H2_PREC_BF16)
     return H2_ERR_ARG;
@@ -389,8 +390,30 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     }
     h2_status e = run_eval(c, ev, st);
     if (e != H2_OK) return e;
-    // ---- A_Close^T = A_cc^{-1} G(S_C, B_i) = Lc^{-T} (Lc^{-1} G(S_C, B_i))
-    {
+    // ---- A_Close^T = A_cc^{-1} G(S_C, B_i) by Gauss-Seidel sweeps ...
+    if (prm->gs_sweeps > 0) {
+      std::vector<GsDesc> gsd;
+      // the row-major iterates reuse the (unused) second product buffer
+      for (int b = 0; b < nb; ++b)
+        if (sc[b] > 0)
+          gsd.push_back({dAcc + acco[b], dT1 + t1o[b], dXid + xo[b] + sf[b], dT2 + t1o[b], sc[b],
+                         S.m[b], sc[b], sc[b], s[b], b});
+      TmpBuf tgs;
+      GsDesc* dgs = nullptr;
+      if (!upload_tmp(tgs, dgs, gsd, st)) return H2_ERR_ALLOC;
+      HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
+      HIPCHK(launch_gauss_seidel(dgs, (int)gsd.size(), prm->gs_sweeps, c.dFail, st));
+      int fail = INT_MAX;
+      HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (fail != INT_MAX) {
+        c.st.fail_level = c.ins[S.inst[fail]].tree.L - h;
+        c.st.fail_box = S.idx[fail];
+        c.st.fail_inst = S.inst[fail];
+        return H2_ERR_NOT_SPD;
+      }
+    } else {
+    // ... or exactly: Lc^{-T} (Lc^{-1} G(S_C, B_i))
       std::vector<CholDesc> cd;
       for (int b = 0; b < nb; ++b)
         if (sc[b] > 0) cd.push_back({dAcc + acco[b], dLc + acco[b], sc[b], sc[b], b});

@@ -147,6 +147,21 @@ struct CholDesc {
 };
 hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail,
                            hipStream_t st);
+// Gauss-Seidel approximation of X = A^{-1} B (Section 3.5): A n x n SPD
+// (lda), B n x m (ldb), X n x m (ldx), sweeps forward sweeps from X = 0; one
+// workgroup per block, one thread per column of X, the iterate held row-major
+// in the scratch W (n x m) so that a row's reads are coalesced.  A
+// non-positive diagonal reports code through *fail.
+struct GsDesc {
+  const double* A;
+  const double* B;
+  double* X;
+  double* W;
+  int n, m, lda, ldb, ldx;
+  int code;
+};
+hipError_t launch_gauss_seidel(const GsDesc* d_desc, int count, int sweeps, int* fail,
+                               hipStream_t st);
 // Column-pivoted QR interpolative decomposition of X (s x m, ld s), one box
 // per workgroup.  Free mode: rank by eps; forced mode: skel[] given.
 struct IdDesc {

@@ -570,6 +570,52 @@ __global__ __launch_bounds__(256) void chol_inv_kernel(const CholDesc* __restric
   }
 }
 
+// Gauss-Seidel sweeps: the columns of X are independent, so each thread owns
+// its columns and walks the rows in order (no barriers).  Row i of A is read
+// as column i (A symmetric), the same address for every thread.
+__global__ __launch_bounds__(256) void gauss_seidel_kernel(const GsDesc* __restrict__ descs,
+                                                           int sweeps, int* fail) {
+  const GsDesc d = descs[blockIdx.x];
+  const int64_t m = d.m;
+  for (int c = threadIdx.x; c < d.m; c += 256) {
+    double* w = d.W + c;  // w[j * m]: row j of the iterate
+    const double* b = d.B + (int64_t)c * d.ldb;
+    for (int i = 0; i < d.n; ++i) w[i * m] = 0.0;
+    for (int s = 0; s < sweeps; ++s)
+      for (int i = 0; i < d.n; ++i) {
+        const double* ai = d.A + (int64_t)i * d.lda;
+        // four partial sums (independent loads in flight); the diagonal term
+        // is added back instead of skipped
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        int j = 0;
+        for (; j + 4 <= d.n; j += 4) {
+          p0 += ai[j] * w[j * m];
+          p1 += ai[j + 1] * w[(j + 1) * m];
+          p2 += ai[j + 2] * w[(j + 2) * m];
+          p3 += ai[j + 3] * w[(j + 3) * m];
+        }
+        for (; j < d.n; ++j) p0 += ai[j] * w[j * m];
+        const double aii = ai[i];
+        const double acc = b[i] - ((p0 + p1) + (p2 + p3) - aii * w[i * m]);
+        if (!(aii > 0.0)) {
+          atomicMin(fail, d.code);
+          w[i * m] = 0.0;
+        } else {
+          w[i * m] = acc / aii;
+        }
+      }
+    double* x = d.X + (int64_t)c * d.ldx;
+    for (int i = 0; i < d.n; ++i) x[i] = w[i * m];
+  }
+}
+
+hipError_t launch_gauss_seidel(const GsDesc* d_desc, int count, int sweeps, int* fail,
+                               hipStream_t st) {
+  if (count <= 0 || sweeps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gauss_seidel_kernel, dim3(count), dim3(256), 0, st, d_desc, sweeps, fail);
+  return hipGetLastError();
+}
+
 hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(chol_inv_kernel, dim3(count), dim3(256), 0, st, d_desc, fail);

@@ -41,7 +41,7 @@ class Params(ctypes.Structure):
                 ("use_pcg", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
                 ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32),
-                ("solve_prec", ctypes.c_int32)]
+                ("solve_prec", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -137,7 +137,7 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
                 max_rank: int = 0, gemm_prec: int = PREC_FP64, ir_max_iter: int = 0,
                 ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
                 timing: bool = False, rank_model=None, rank_margin: float = 0.25,
-                autotune: bool = True, solve_prec: int = PREC_FP64) -> Params:
+                autotune: bool = True, solve_prec: int = PREC_FP64, gs_sweeps: int = 0) -> Params:
     """rank_model: numpy float32 array of the 4801 predictor weights (kept alive
     by the caller for the duration of the build call)."""
     ptr = None
@@ -147,7 +147,7 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
         ptr = rank_model.ctypes.data
     return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
                   int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune),
-                  int(solve_prec))
+                  int(solve_prec), int(gs_sweeps))
 
 
 def _as_cols(t, n):

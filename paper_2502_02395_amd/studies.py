@@ -9,9 +9,13 @@ measurements of this build only):
               admissibility eta at a fixed N;
   hss      -- HSS (eta = 0, weak admissibility) vs H^2 (eta = 1): ranks,
               factor flops and the accuracy of the H^2 operator and of the
-              unrefined solve against the dense kernel matrix.
+              unrefined solve against the dense kernel matrix;
+  prefactor -- the pre-factorization of the construction (Section 3.5):
+              exact near-sample solve vs Gauss-Seidel sweeps, on the Yukawa
+              cube of the headline configuration (build time, ranks, PCG
+              iterations and residual).
 
-    python -m paper_2502_02395_amd.studies [scaling|eta|hss|all] [--max-n N]
+    python -m paper_2502_02395_amd.studies [scaling|eta|hss|prefactor|all] [--max-n N]
 
 Every line printed is one JSON record.  The dense reference of the hss
 study is the kernel matrix formed with plain torch operations on the GPU
@@ -25,11 +29,12 @@ import sys
 import time
 
 
-def _run(h2, p, gemm_prec, solve_prec, nrhs=1, refine=True):
+def _run(h2, p, gemm_prec, solve_prec, nrhs=1, refine=True, gs_sweeps=0):
     import numpy as np
     import torch
     t0 = time.perf_counter()
-    kw = dict(s_far=p.s_far, s_near=p.s_near, gemm_prec=gemm_prec, solve_prec=solve_prec)
+    kw = dict(s_far=p.s_far, s_near=p.s_near, gemm_prec=gemm_prec, solve_prec=solve_prec,
+              gs_sweeps=gs_sweeps)
     if refine:
         kw.update(ir_max_iter=100, ir_tol=1e-8, use_pcg=True)
     H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), **kw)
@@ -102,9 +107,24 @@ def hss_vs_h2(h2):
         print(json.dumps(rec), flush=True)
 
 
+def prefactor(h2, n: int):
+    import workloads as W
+    for sweeps in (0, 1, 2, 4):
+        p = W.yukawa_cube(n=n, leaf=256, eps=1e-6, nrhs=1, s=512)
+        try:
+            H, _, _, rec = _run(h2, p, h2.PREC_FP32, h2.PREC_FP32, gs_sweeps=sweeps)
+            H.close()
+        except h2.H2Error as e:
+            rec = {"n": p.n, "error": str(e)}
+        rec["study"] = "prefactor"
+        rec["gs_sweeps"] = sweeps
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", nargs="?", default="all", choices=["scaling", "eta", "hss", "all"])
+    ap.add_argument("study", nargs="?", default="all",
+                    choices=["scaling", "eta", "hss", "prefactor", "all"])
     ap.add_argument("--max-n", type=int, default=1 << 19)
     ap.add_argument("--eta-n", type=int, default=1 << 18)
     ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32"],
@@ -120,6 +140,8 @@ def main():
         eta_sweep(h2, a.eta_n, prec)
     if a.study in ("hss", "all"):
         hss_vs_h2(h2)
+    if a.study in ("prefactor", "all"):
+        prefactor(h2, 1 << 20)
 
 
 if __name__ == "__main__":

@@ -168,3 +168,31 @@ def test_refinement_reaches_tolerance(lib):
     assert Hp.stats()["ir_residual"] <= 1e-12
     assert float(torch.linalg.norm(xp - x) / torch.linalg.norm(x)) < 1e-9
     Hp.close()
+
+
+def test_gauss_seidel_prefactorization_matches_oracle(lib):
+    """Section 3.5's Gauss-Seidel replacement of the near-sample solve: the
+    library's build with two sweeps against the oracle's with two sweeps
+    (ranks agree almost everywhere; the solve keeps the oracle's accuracy),
+    and the exact build for comparison."""
+    import torch
+    p = W.yukawa_cube(n=4096, leaf=64, eps=1e-7, s=128)
+    h2o = construct.construct(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), p.s_far,
+                              p.s_near, gs_sweeps=2)
+    H = lib.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                  s_near=p.s_near, gs_sweeps=2)
+    print(f"[case gauss_seidel] n={p.n} sweeps=2", flush=True)
+    _, ranks, _, _ = H.structure()
+    o_ranks = np.array([bb.k for l in range(h2o.tree.L, 0, -1) for bb in h2o.basis[l]])
+    assert np.mean(ranks == o_ranks) > 0.7
+    assert np.max(np.abs(ranks - o_ranks)) <= 3
+    H.factor()
+    b = p.b()
+    x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    A = kernels.dense(p.kernel, p.points)
+    res_g = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    xo = ulv.solve(ulv.factor(h2o), b)
+    res_o = np.linalg.norm(b - A @ xo) / np.linalg.norm(b)
+    print(f"[gauss_seidel] residual gpu {res_g:.2e} oracle {res_o:.2e}", flush=True)
+    assert res_g <= max(10 * res_o, 1e-12), (res_g, res_o)
+    H.close()
