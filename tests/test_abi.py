@@ -50,6 +50,11 @@ def test_status_strings_and_argument_errors_without_gpu():
     prm = h2.make_params(4, 8, 1.0, 1e-6)  # dim 4
     assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
                       ctypes.byref(out)) == h2.ERR_ARG
+    # Gauss-Seidel sweeps outside 0..64, unknown precisions
+    for kw in ({"gs_sweeps": -1}, {"gs_sweeps": 65}, {"gemm_prec": 7}, {"solve_prec": 2}):
+        prm = h2.make_params(3, 8, 1.0, 1e-6, **kw)
+        assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
+                          ctypes.byref(out)) == h2.ERR_ARG, kw
     assert L.h2_factor(None, None) == h2.ERR_ARG
     assert L.h2_solve(None, None, None, 1, 1, None) == h2.ERR_ARG
 
