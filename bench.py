@@ -40,12 +40,12 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "8055388dfc8ed052dd69c5f8baa8eb3e738702a86220c6ceb81b6776e0108525",
-                           "bytes_per_launch": 0.7235e9 + 0.0096e9},
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "8055388dfc8ed052dd69c5f8baa8eb3e738702a86220c6ceb81b6776e0108525",
-                           "bytes_per_launch": 1.9697e9 + 0.0374e9},
-    "greduce_kernel": {"src": GATHER_SRC, "sha256": "8055388dfc8ed052dd69c5f8baa8eb3e738702a86220c6ceb81b6776e0108525",
-                       "bytes_per_launch": 0.0178e9 + 0.0013e9},
+    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
+                           "bytes_per_launch": 0.7250e9 + 0.0096e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
+                           "bytes_per_launch": 1.9697e9 + 0.0375e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
+                       "bytes_per_launch": 0.0179e9 + 0.0013e9},
 }
 
 

@@ -237,6 +237,11 @@ struct GRed {
 // direct slots cost more than the shorter waves gain).
 constexpr int GATHER_SEG = 128;
 constexpr int GATHER_SEG_FROM = 5;
+// The per-box lists (P^T b, P d, U^T x, U y: one dense block per box) have
+// fewer blocks per wave of work, so they take the segments from height 3
+// (measured at h = 3, 4: 30-50 % shorter launches; from height 1 or 2 no
+// further gain).
+constexpr int GATHER_SEG_THIN_FROM = 3;
 constexpr int GATHER_SEG_TOP = 32;       // the top levels: a few blocks each
 constexpr int GATHER_SEG_TOP_FROM = 8;
 // Wide chunks: a block's rows split evenly into chunks of at most 64 x RPL

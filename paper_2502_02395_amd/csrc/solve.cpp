@@ -378,8 +378,9 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
                                             : 0;
     const bool wd = h >= GATHER_WIDE_FROM && h <= GATHER_WIDE_TO;
     const std::vector<Rebase> none;
-    if (!up_thin(c, S.t_fwd, tf, st, rb, sg, wd) || !up_thin(c, S.t_bwd, tb, st, rb, sg, wd) ||
-        !up_thin(c, S.t_up, tu, st, none, sg, wd) || !up_thin(c, S.t_down, td, st, none, sg, wd) ||
+    const int sgt = sg > 0 ? sg : h >= GATHER_SEG_THIN_FROM ? GATHER_SEG : 0;
+    if (!up_thin(c, S.t_fwd, tf, st, rb, sgt, wd) || !up_thin(c, S.t_bwd, tb, st, rb, sgt, wd) ||
+        !up_thin(c, S.t_up, tu, st, none, sgt, wd) || !up_thin(c, S.t_down, td, st, none, sgt, wd) ||
         !up_gather(c, S.g_yr, b1, n1, st, rb, sg, wd) ||
         !up_gather(c, S.g_cs, b2, n2, st, rb, sg, wd) ||
         !up_gather(c, S.g_t, b3, n3, st, rb, sg, wd) ||
