@@ -46,6 +46,7 @@ CASES = {
     "yukawa_ragged": (lambda: W.yukawa_cube(n=3001, leaf=100, eps=1e-7, s=150), 2),
     "sphere_hss": (lambda: W.laplace_sphere(n=2048, leaf=64, eps=1e-6, eta=0.0, s=-1, nrhs=1), 1),
     "gauss2d": (lambda: _gauss2d(), 1),
+    "matern_full": (lambda: W.matern_cube(n=1500, leaf=64, eps=1e-8, s=-1), 2),
     "root_only": (lambda: W.laplace_cube(n=100, leaf=128, eps=1e-8), 2),
 }
 
@@ -195,4 +196,34 @@ def test_gauss_seidel_prefactorization_matches_oracle(lib):
     res_o = np.linalg.norm(b - A @ xo) / np.linalg.norm(b)
     print(f"[gauss_seidel] residual gpu {res_g:.2e} oracle {res_o:.2e}", flush=True)
     assert res_g <= max(10 * res_o, 1e-12), (res_g, res_o)
+    H.close()
+
+
+def test_gauss_seidel_same_h2_matches_oracle(lib):
+    """The Gauss-Seidel construction with the oracle's skeleton selection: both
+    sides build the same H^2 matrix (interpolation from the sampled blocks with
+    one sweep in place of the near-sample solve), so the solve, the matvec and
+    the residual follow the same bounds as the exact same-H^2 cases."""
+    import torch
+    p = W.yukawa_cube(n=3001, leaf=100, eps=1e-7, nrhs=2, s=150)
+    print(f"[case gauss_seidel_same_h2] n={p.n} sweeps=1", flush=True)
+    h2o = construct.construct(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), p.s_far,
+                              p.s_near, gs_sweeps=1)
+    sk, ranks, pos = _skeletons(h2o)
+    h2f = construct.construct(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), p.s_far,
+                              p.s_near, skeletons=sk, gs_sweeps=1)
+    b = W.rhs(p.n, 2, 1)
+    xo = ulv.solve(ulv.factor(h2f), b)
+    H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                        s_far=p.s_far, s_near=p.s_near, gs_sweeps=1)
+    H.factor()
+    bt = torch.from_numpy(b).cuda()
+    x = H.solve(bt).cpu().numpy()
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    tol = max(1e-10, 100 * kappa * np.finfo(float).eps)
+    print(f"[gauss_seidel_same_h2] x rel {_rel(x, xo):.2e} kappa {kappa:.1e}", flush=True)
+    assert _rel(x, xo) < tol, (_rel(x, xo), kappa)
+    y = H.matvec(bt).cpu().numpy()
+    assert _rel(y, h2matrix.matvec(h2f, b)) < 1e-12
     H.close()
