@@ -53,7 +53,7 @@ hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
   } while (0)
 
 static constexpr int ID_MMAX = 4096;    // cpqr_id_kernel LDS capacity
-static constexpr int CHOL_NMAX = 2048;  // chol_inv rows per workgroup
+static constexpr int CHOL_NMAX = 2048;  // near-sample points per box (sc^2 doubles each)
 
 // Temporary device buffer freed at scope exit.
 struct TmpBuf {
@@ -83,6 +83,85 @@ static h2_status run_eval(Ctx& c, const std::vector<EvalDesc>& ev, hipStream_t s
   if (!upload_tmp(tb1, d, ev, st) || !upload_tmp(tb2, t, toff, st)) return H2_ERR_ALLOC;
   HIPCHK(launch_eval(d, t, (int)ev.size(), toff.back(), c.dX, c.dim, c.dKern, st));
   HIPCHK(hipStreamSynchronize(st));
+  return H2_OK;
+}
+
+static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st);
+
+// Blocked Cholesky of SPD blocks A (n x n, ld n) and the explicit inverse of
+// the factor, the near-sample solve of the construction (Section 3.5): per
+// 64-wide panel, the diagonal block's Cholesky and inverse in LDS
+// (panel_kernel), the rows below it times the inverse's transpose, the
+// trailing update; then the block rows of X = L^{-1} from the top,
+// X_{p,<p} = -X_pp (L_{p,<p} X_{<p,<p}).  A is overwritten by L (zeros above
+// the diagonal of the diagonal blocks); Linv (ld n) must hold zeros on entry
+// and receives L^{-1}.  A non-positive pivot writes the job's code to fail.
+struct CholJob {
+  double* A;
+  double* Linv;
+  int n, code;
+};
+static h2_status blocked_chol_inv(const std::vector<CholJob>& jobs, int* fail, hipStream_t st) {
+  if (jobs.empty()) return H2_OK;
+  int nmax = 0;
+  std::vector<int64_t> so(jobs.size() + 1, 0);  // panel scratch: 64 n per job
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    nmax = std::max(nmax, jobs[q].n);
+    so[q + 1] = so[q] + 64 * (int64_t)std::max(jobs[q].n, 0);
+  }
+  TmpBuf tsc;
+  double* dS = tsc.get<double>(so.back());
+  ALLOCHK(dS);
+  const int np = (nmax + 63) / 64;
+  for (int pi = 0; pi < np; ++pi) {
+    const int p0 = 64 * pi;
+    std::vector<PanelDesc> pd;
+    std::vector<GemmDesc> tr, sy;
+    std::vector<CopyDesc> bk;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      const CholJob& j = jobs[q];
+      const int n = j.n;
+      if (n <= p0) continue;
+      const int w = std::min(64, n - p0), rows = n - p0 - w;
+      double* Dp = j.Linv + p0 + (int64_t)p0 * n;
+      pd.push_back({j.A + p0 + (int64_t)p0 * n, n, w, Dp, n, j.code});
+      if (rows > 0) {
+        double* A21 = j.A + p0 + w + (int64_t)p0 * n;
+        double* A22 = A21 + (int64_t)w * n;
+        double* TA = dS + so[q];  // rows x w, ld n
+        tr.push_back(gd(A21, n, 0, Dp, n, 1, nullptr, 1, TA, n, rows, w, w, 1.0, 0.0));
+        sy.push_back(gd(TA, n, 0, TA, n, 1, A22, n, A22, n, rows, rows, w, -1.0, 1.0));
+        bk.push_back({TA, A21, rows, w, n, n, 0});
+      }
+    }
+    TmpBuf tp, tb;
+    PanelDesc* dpd = nullptr;
+    CopyDesc* dbk = nullptr;
+    if (!upload_tmp(tp, dpd, pd, st) || !upload_tmp(tb, dbk, bk, st)) return H2_ERR_ALLOC;
+    HIPCHK(launch_panel(dpd, (int)pd.size(), fail, st));
+    h2_status e = run_gemm_tmp(tr, st);
+    if (e == H2_OK) e = run_gemm_tmp(sy, st);
+    if (e != H2_OK) return e;
+    HIPCHK(launch_copy(dbk, (int)bk.size(), st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int pi = 1; pi < np; ++pi) {
+    const int p0 = 64 * pi;
+    std::vector<GemmDesc> i1, i2;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      const CholJob& j = jobs[q];
+      const int n = j.n;
+      if (n <= p0) continue;
+      const int w = std::min(64, n - p0);
+      double* TA = dS + so[q];  // w x p0, ld 64
+      i1.push_back(gd(j.A + p0, n, 0, j.Linv, n, 0, nullptr, 1, TA, 64, w, p0, p0, 1.0, 0.0));
+      i2.push_back(gd(j.Linv + p0 + (int64_t)p0 * n, n, 0, TA, 64, 0, nullptr, 1, j.Linv + p0, n,
+                      w, p0, w, -1.0, 0.0));
+    }
+    h2_status e = run_gemm_tmp(i1, st);
+    if (e == H2_OK) e = run_gemm_tmp(i2, st);
+    if (e != H2_OK) return e;
+  }
   return H2_OK;
 }
 
@@ -414,14 +493,12 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       }
     } else {
     // ... or exactly: Lc^{-T} (Lc^{-1} G(S_C, B_i))
-      std::vector<CholDesc> cd;
+      std::vector<CholJob> cj;
       for (int b = 0; b < nb; ++b)
-        if (sc[b] > 0) cd.push_back({dAcc + acco[b], dLc + acco[b], sc[b], sc[b], b});
-      TmpBuf tcd;
-      CholDesc* dcd = nullptr;
-      if (!upload_tmp(tcd, dcd, cd, st)) return H2_ERR_ALLOC;
+        if (sc[b] > 0) cj.push_back({dAcc + acco[b], dLc + acco[b], sc[b], b});
+      HIPCHK(hipMemsetAsync(dLc, 0, (size_t)std::max<int64_t>(acco[nb], 1) * sizeof(double), st));
       HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
-      HIPCHK(launch_chol_inv(dcd, (int)cd.size(), c.dFail, st));
+      if ((e = blocked_chol_inv(cj, c.dFail, st)) != H2_OK) return e;
       int fail = INT_MAX;
       HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));

@@ -137,16 +137,6 @@ hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, int J, int 
                            hipStream_t st);
 hipError_t launch_qr_tdiag(const BoxDev* boxes, int nbox, int max_k, hipStream_t st);
 hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st);
-// Cholesky + explicit inverse of n x n SPD blocks: A (ld lda, destroyed),
-// Linv (n x n dense, zero upper triangle).  Breakdown: *fail = min(code).
-struct CholDesc {
-  double* A;
-  double* Linv;
-  int n, lda;
-  int code;                 // reported through *fail when this block breaks down
-};
-hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail,
-                           hipStream_t st);
 // Gauss-Seidel approximation of X = A^{-1} B (Section 3.5): A n x n SPD
 // (lda), B n x m (ldb), X n x m (ldx), sweeps forward sweeps from X = 0; one
 // workgroup per block, one thread per column of X, the iterate held row-major

@@ -6,11 +6,13 @@
 //   * cpqr_id      -- column-pivoted Householder QR of M^T for the row
 //                     interpolative decomposition of Algorithm 1, rank by the
 //                     leading |R_jj| > eps |R_00|, then T = R_11^{-1} R_12;
-//   * chol_inv     -- Cholesky of an SPD block and the explicit inverse of its
-//                     factor (redundant diagonal blocks, near-sample matrices);
-//   * panel        -- the same on the 64-wide diagonal panels of the blocked
-//                     Cholesky factorizations (redundant blocks and the root;
-//                     the root's inverse is then formed with batched GEMMs).
+//   * gauss_seidel -- sweeps that approximate the near-sample solve of the
+//                     construction (one thread per right-hand-side column);
+//   * panel        -- Cholesky and the inverse of its factor on the 64-wide
+//                     diagonal panels of the blocked Cholesky factorizations
+//                     (near-sample matrices, redundant blocks and the root;
+//                     the rest of each, and the full inverse, are batched
+//                     GEMMs).
 // Householder vectors follow LAPACK's convention (beta = -sign(alpha)||x||,
 // v_0 = 1, tau = (beta - alpha)/beta).
 #include "h2_internal.hpp"
@@ -490,86 +492,7 @@ hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps, int max_r
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------ Cholesky + inv
-// n <= 256 * CHOL_ROWS_PER_THREAD (the host rejects larger blocks).
-constexpr int CHOL_ROWS_PER_THREAD = 8;
-// Right-looking Cholesky of the n x n lower part of a (ld lda), then the
-// explicit inverse of the factor into li (ld ldl), zero upper triangle.
-// a and li may live in LDS or global memory (flat addressing).
-__device__ void chol_inv_impl(double* a, int lda, double* li, int ldl, int n, int* fail,
-                              int code) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ double piv_s;
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double dj = a[j + (int64_t)j * lda];
-      if (!(dj > 0.0)) {
-        atomicMin(fail, code);
-        dj = 1.0;
-      }
-      dj = sqrt(dj);
-      a[j + (int64_t)j * lda] = dj;
-      piv_s = 1.0 / dj;
-    }
-    __syncthreads();
-    const double inv = piv_s;
-    for (int i = j + 1 + (int)threadIdx.x; i < n; i += 256) a[i + (int64_t)j * lda] *= inv;
-    __syncthreads();
-    for (int c = j + 1 + wave; c < n; c += 4) {
-      const double acj = a[c + (int64_t)j * lda];
-      for (int i = c + lane; i < n; i += 64) a[i + (int64_t)c * lda] -= a[i + (int64_t)j * lda] * acj;
-    }
-    __syncthreads();
-  }
-  for (int64_t e = threadIdx.x; e < (int64_t)n * n; e += 256) {
-    const int r = (int)(e % n), c = (int)(e / n);
-    li[r + (int64_t)c * ldl] = (r >= c) ? a[r + (int64_t)c * lda] : 0.0;
-  }
-  __syncthreads();
-  // in-place inversion of the lower-triangular li, last column first
-  for (int j = n - 1; j >= 0; --j) {
-    const double djj = 1.0 / li[j + (int64_t)j * ldl];
-    double y = 0.0;
-    const int i = j + 1 + (int)threadIdx.x;
-    // y_i = sum_{q=j+1..i} Linv[i, q] x_q, x_q = L[q, j] (column j, not yet overwritten)
-    double yv[CHOL_ROWS_PER_THREAD];
-    int cnt = 0;
-    for (int ii = i; ii < n; ii += 256) {
-      y = 0.0;
-      for (int q = j + 1; q <= ii; ++q) y += li[ii + (int64_t)q * ldl] * li[q + (int64_t)j * ldl];
-      if (cnt < CHOL_ROWS_PER_THREAD) yv[cnt] = y;
-      ++cnt;
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int ii = i; ii < n; ii += 256) {
-      if (cnt < CHOL_ROWS_PER_THREAD) li[ii + (int64_t)j * ldl] = -djj * yv[cnt];
-      ++cnt;
-    }
-    if (threadIdx.x == 0) li[j + (int64_t)j * ldl] = djj;
-    __syncthreads();
-  }
-}
-
-constexpr int CHOL_LDS_N = 88;  // n*n doubles fit in 62 KB of LDS
-
-__global__ __launch_bounds__(256) void chol_inv_kernel(const CholDesc* __restrict__ descs, int* fail) {
-  __shared__ double buf[CHOL_LDS_N * CHOL_LDS_N];
-  const CholDesc d = descs[blockIdx.x];
-  const int n = d.n;
-  if (n <= 0) return;
-  if (n <= CHOL_LDS_N) {
-    for (int e = threadIdx.x; e < n * n; e += 256) {
-      const int r = e % n, c = e / n;
-      buf[e] = d.A[r + (int64_t)c * d.lda];
-    }
-    __syncthreads();
-    chol_inv_impl(buf, n, d.Linv, n, n, fail, d.code);
-  } else {
-    chol_inv_impl(d.A, d.lda, d.Linv, n, n, fail, d.code);
-  }
-}
-
+// ------------------------------------------------------------ Gauss-Seidel
 // Gauss-Seidel sweeps: the columns of X are independent, so each thread owns
 // its columns and walks the rows in order (no barriers).  Row i of A is read
 // as column i (A symmetric), the same address for every thread.
@@ -613,12 +536,6 @@ hipError_t launch_gauss_seidel(const GsDesc* d_desc, int count, int sweeps, int*
                                hipStream_t st) {
   if (count <= 0 || sweeps <= 0) return hipSuccess;
   hipLaunchKernelGGL(gauss_seidel_kernel, dim3(count), dim3(256), 0, st, d_desc, sweeps, fail);
-  return hipGetLastError();
-}
-
-hipError_t launch_chol_inv(const CholDesc* d_desc, int count, int* fail, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(count), dim3(256), 0, st, d_desc, fail);
   return hipGetLastError();
 }
 
