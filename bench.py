@@ -40,11 +40,11 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
-                           "bytes_per_launch": 0.7250e9 + 0.0096e9},
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
-                           "bytes_per_launch": 1.9697e9 + 0.0375e9},
-    "greduce_kernel": {"src": GATHER_SRC, "sha256": "724e9a621489bed9876a6363689fc907a89fa7fe221963f1fe07f7b57521d703",
+    "gchunk_kernel<f32>": {"src": GATHER_SRC, "sha256": "0aeee513a90db78fcdf1069eddfec4212663e337b453c513c50606b4994e65b7",
+                           "bytes_per_launch": 0.7252e9 + 0.0096e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "0aeee513a90db78fcdf1069eddfec4212663e337b453c513c50606b4994e65b7",
+                           "bytes_per_launch": 1.9715e9 + 0.0375e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "0aeee513a90db78fcdf1069eddfec4212663e337b453c513c50606b4994e65b7",
                        "bytes_per_launch": 0.0179e9 + 0.0013e9},
 }
 
