@@ -9,6 +9,8 @@ let the library pick its own skeletons by its pivoted QR: the structure must
 agree exactly, most ranks must agree, and the residual against the exact
 kernel matrix must stay within the oracle's own accuracy.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -47,6 +49,12 @@ CASES = {
     "sphere_hss": (lambda: W.laplace_sphere(n=2048, leaf=64, eps=1e-6, eta=0.0, s=-1, nrhs=1), 1),
     "gauss2d": (lambda: _gauss2d(), 1),
     "matern_full": (lambda: W.matern_cube(n=1500, leaf=64, eps=1e-8, s=-1), 2),
+    # near-field sampling variants (Section 3.5): a near sample smaller than
+    # the far one, and every near candidate with a sampled far field
+    "yukawa_near_sampled": (lambda: dataclasses.replace(
+        W.yukawa_cube(n=4096, leaf=64, eps=1e-7, nrhs=1, s=256), s_near=48), 1),
+    "laplace_near_all": (lambda: dataclasses.replace(
+        W.laplace_cube(n=2048, leaf=128, eps=1e-7, s=128), s_near=-1), 1),
     "root_only": (lambda: W.laplace_cube(n=100, leaf=128, eps=1e-8), 2),
 }
 
