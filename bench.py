@@ -256,8 +256,8 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU H^2-ULV path "
-              "(the multi-GPU distribution is described in DESIGN.md, not built).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library implements the single-GPU H^2-ULV "
+              "path; a distribution over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -49,7 +49,7 @@ typedef enum {
   H2_ERR_NOT_SPD = 4,     /* Cholesky breakdown; h2_stats gives (level, box)    */
   H2_ERR_STATE = 5,       /* call out of order (e.g. solve before factor)       */
   H2_ERR_NOCONV = 6,      /* refinement did not reach the tolerance             */
-  H2_ERR_UNSUPPORTED = 7  /* option not available in this build                 */
+  H2_ERR_UNSUPPORTED = 7  /* option not available in this library               */
 } h2_status;
 
 /* Kernel functions (Eq. 35, Eq. 36 regularised; covariance kernels). */

@@ -1,7 +1,7 @@
 """Single-node studies on synthetic geometry, after the paper's Section 6
 scaling and parameter studies (the sphere-surface family of Section 6.2;
 the paper's plotted values are not available as numbers, so these are
-measurements of this build only):
+measurements of this library only):
 
   scaling  -- build, factor and solve time, factor TFLOP/s and the number of
               near (dense, non-zero) and far blocks vs N (O(N) behaviour);
