@@ -95,7 +95,10 @@ typedef struct {
   int32_t gs_sweeps;      /* pre-factorization of h2_build (Section 3.5): 0 =
                              exact Cholesky solve with the near-sample block
                              A_cc; n > 0 = n Gauss-Seidel sweeps (from zero)
-                             approximating A_Close = G(B_i, S_C) A_cc^{-1}     */
+                             approximating A_Close = G(B_i, S_C) A_cc^{-1}.
+                             Range 0..64 (else H2_ERR_ARG); a non-positive
+                             diagonal entry of A_cc returns H2_ERR_NOT_SPD
+                             with the box in h2_stats                          */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
