@@ -97,7 +97,8 @@ def hss_vs_h2(h2):
             continue
         X = torch.from_numpy(p.points).cuda()
         A = 1.0 / (torch.cdist(X, X) + p.kernel.delta)
-        v = torch.randn(p.n, 1, dtype=torch.float64, device="cuda")
+        gen = torch.Generator(device="cuda").manual_seed(3)
+        v = torch.randn(p.n, 1, dtype=torch.float64, device="cuda", generator=gen)
         y = H.matvec(v)
         rec["matvec_rel_err"] = float(torch.linalg.norm(y - A @ v) / torch.linalg.norm(A @ v))
         rec["solve_rel_residual_dense"] = float(torch.linalg.norm(b - A @ x) /
