@@ -87,13 +87,15 @@ def eta_sweep(h2, n: int, prec):
 def hss_vs_h2(h2):
     import torch
     import workloads as W
-    for eta in (0.0, 1.0):
-        p = W.laplace_sphere(n=8192, leaf=512, eps=1e-8, eta=eta, nrhs=1, s=1024)
+    # HSS with every candidate point sampled, then HSS and H^2 with 1024-point
+    # samples
+    for eta, s in ((0.0, -1), (0.0, 1024), (1.0, 1024)):
+        p = W.laplace_sphere(n=8192, leaf=512, eps=1e-8, eta=eta, nrhs=1, s=s)
         try:
             H, b, x, rec = _run(h2, p, h2.PREC_FP64, h2.PREC_FP64, refine=False)
         except h2.H2Error as e:
             print(json.dumps({"study": "hss" if eta == 0.0 else "h2", "n": p.n, "eta": eta,
-                              "error": str(e)}), flush=True)
+                              "s": s, "error": str(e)}), flush=True)
             continue
         X = torch.from_numpy(p.points).cuda()
         A = 1.0 / (torch.cdist(X, X) + p.kernel.delta)
@@ -105,6 +107,7 @@ def hss_vs_h2(h2):
                                                 torch.linalg.norm(b))
         H.close()
         rec["study"] = "hss" if eta == 0.0 else "h2"
+        rec["s"] = s
         print(json.dumps(rec), flush=True)
 
 
