@@ -25,8 +25,8 @@
  *     device work is enqueued on it; the call returns after the work that the
  *     call needs to inspect on the host (ranks during build, the breakdown flag
  *     after factor, residual norms during refinement) has completed.
- *   - The handle owns every device buffer it allocates (hipMalloc) and frees
- *     them in h2_destroy.  A handle must not be used from two threads or two
+ *   - The handle owns every device buffer it allocates (through
+ *     h2_params.allocator, else hipMalloc) and frees them in h2_destroy.  A handle must not be used from two threads or two
  *     streams at once.
  *   - After an error other than H2_ERR_ARG the handle may only be inspected
  *     (h2_stats, getters) or destroyed.
@@ -67,6 +67,19 @@ typedef struct {
 
 typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_BF16 = 2 } h2_prec;
 
+/* Device memory of a handle.  Every device buffer the handle owns and every
+ * temporary of the build comes from alloc(bytes, user), which returns NULL
+ * on failure (the call then returns H2_ERR_ALLOC), and goes back through
+ * free(ptr, user), which the library calls only after the device work that
+ * used the buffer has completed (h2_destroy and failed builds synchronize
+ * the device first).  The callbacks and `user` must stay valid until
+ * h2_destroy.  A Python caller passes PyTorch's caching allocator here. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} h2_allocator;
+
 typedef struct {
   int32_t dim;            /* 2 or 3                                              */
   int32_t leaf;           /* max points per leaf box (>= 2)                      */
@@ -99,6 +112,8 @@ typedef struct {
                              Range 0..64 (else H2_ERR_ARG); a non-positive
                              diagonal entry of A_cc returns H2_ERR_NOT_SPD
                              with the box in h2_stats                          */
+  const h2_allocator* allocator; /* host; copied at build; NULL = hipMalloc and
+                             hipFree                                          */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -150,8 +165,14 @@ typedef struct {
  *  perm:  host, n int64, the sampling permutation pi of 0..n-1; S_F / S_C take
  *         the candidates that come first in pi.  NULL = identity.
  *  out:   receives the new handle.
- * Errors: H2_ERR_ARG for n < 1, leaf < 2, dim not 2/3, bad kernel id, eps < 0;
- *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD. */
+ * Errors: H2_ERR_ARG for n < 1, leaf < 2, dim not 2/3, bad kernel id, eps < 0,
+ *         an allocator without both callbacks;
+ *         H2_ERR_ALLOC when a device allocation fails (everything allocated
+ *         so far is freed);
+ *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD: then
+ *         *out receives a handle in the failed state whose h2_stats give the
+ *         (level, box, instance); it accepts only h2_stats and h2_destroy.
+ *         On every other error *out is NULL. */
 h2_status h2_build(const double* pts, int64_t n, const h2_kernel* kernel,
                    const h2_params* params, const int64_t* perm, void* stream,
                    h2_handle* out);
@@ -209,6 +230,14 @@ h2_status h2_get_structure(h2_handle h, int64_t* perm, int32_t* ranks,
  * pairs is 2*count int32; pass NULL to query count only. */
 h2_status h2_get_pairs(h2_handle h, int32_t level, int32_t far, int32_t* pairs,
                        int64_t* count);
+/* The two-sided basis P_i = [Q_i^S | Q_i^R L(r)_ii^{-1}^T] of box `box` at
+ * tree level `level` (1..L) of instance `inst`, after h2_factor: m x m
+ * column-major into host `p` (pass NULL to query m and k only).  Q_i is the
+ * orthogonal completion of D_i U_i (Section 4.4, Eq. 32), so the last m - k
+ * columns are V_i = Q_i^R L(r)_ii^{-T} of Algorithm 4.  H2_ERR_STATE before
+ * a successful h2_factor. */
+h2_status h2_get_basis(h2_handle h, int32_t inst, int32_t level, int32_t box, double* p,
+                       int32_t* m, int32_t* k);
 /* The root matrix after factor: A_00 (before Cholesky) of instance t, n0 x n0
  * column-major into host `a` (n0 from h2_stats.root_n for t == 0). */
 h2_status h2_get_root(h2_handle h, int32_t inst, double* a, int64_t* n0);

@@ -12,9 +12,14 @@ m, k, r = m - k per box:
   far pairs:  k_i k_j (k_i + k_j) per unordered pair (R_i S_ij R_j^T)
   root:       n_0^3 / 3
 with GEQRF(m,k) = 2 m k^2 - 2/3 k^3 and ORGQR_full(m,k) = 4 m^2 k - 4 m k^2
-+ 4/3 k^3.  The solve, per right-hand side: 4 m^2 + 4 r^2 per box, 4 r_i r_j
-per near pair i > j, 4 k_i r_j per ordered near pair (i == j included),
-2 n_0^2 at the root.
++ 4/3 k^3, the leading terms of the operation counts LAPACK Working Note 41
+tabulates for xGEQRF (m x k, m >= k) and xORGQR (an m x n Q from k
+reflectors: 4 m n k - 2 (m + n) k^2 + 4/3 k^3, here with n = m).  The solve,
+per right-hand side: 4 m^2 + 4 r^2 per box, 4 r_i r_j per near pair i > j,
+4 k_i r_j per ordered near pair (i == j included), 2 n_0^2 at the root.
+
+Pinned by tests/test_oracle_flops.py against the operations that running
+Householder QR, Q accumulation, Cholesky and triangular-solve loops perform.
 """
 from __future__ import annotations
 

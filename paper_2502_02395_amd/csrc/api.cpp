@@ -266,9 +266,10 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
         res = 0.0;
         for (int q = 0; q < nc; ++q) {
           const double rel = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
-          res = std::max(res, rel);
+          if (!(rel <= res)) res = rel;  // a NaN column makes res NaN
         }
-        if (res <= c.prm.ir_tol || !(res == res)) break;
+        if (!std::isfinite(res)) { noconv = true; break; }
+        if (res <= c.prm.ir_tol) break;
         if (it >= maxit) { noconv = true; break; }
         ++it;
         if (!pcg) {
@@ -288,7 +289,7 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
         }
       }
       iters_total = std::max(iters_total, it);
-      worst = std::max(worst, res);
+      if (!(res <= worst)) worst = res;  // keeps a NaN
     }
     HIPCHK(launch_axpby(xx, ld, c.w_x, c.N, c.w_x, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
   }
@@ -386,6 +387,27 @@ h2_status h2_get_pairs(h2_handle h, int32_t level, int32_t far, int32_t* pairs, 
       pairs[2 * q] = v[q].first;
       pairs[2 * q + 1] = v[q].second;
     }
+  return H2_OK;
+}
+
+h2_status h2_get_basis(h2_handle h, int32_t inst, int32_t level, int32_t box, double* p,
+                       int32_t* m, int32_t* k) {
+  if (!h || !h->c || inst < 0 || inst >= h->c->n_inst) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  const Tree& t = c.ins[inst].tree;
+  if (level < 1 || level > t.L || box < 0 || box >= (1 << level)) return H2_ERR_ARG;
+  const Step& Sx = c.steps[t.L - level];
+  int b = -1;
+  for (int q = 0; q < Sx.nbox; ++q)
+    if (Sx.inst[q] == inst && Sx.idx[q] == box) { b = q; break; }
+  if (b < 0) return H2_ERR_ARG;
+  if (m) *m = Sx.m[b];
+  if (k) *k = Sx.k[b];
+  if (p && Sx.m[b] > 0) {
+    if (!c.factored) return H2_ERR_STATE;
+    HIPCHK(hipMemcpy(p, Sx.dP + Sx.qoff[b], sizeof(double) * Sx.m[b] * Sx.m[b],
+                     hipMemcpyDeviceToHost));
+  }
   return H2_OK;
 }
 

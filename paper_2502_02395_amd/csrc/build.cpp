@@ -31,7 +31,8 @@ Ctx::~Ctx() {
   if (ev_g0) (void)hipEventDestroy(ev_g0);
   if (ev_g1) (void)hipEventDestroy(ev_g1);
   if (graph_stream) (void)hipStreamDestroy(graph_stream);
-  for (void* p : allocs) (void)hipFree(p);
+  if (ua.alloc) (void)hipDeviceSynchronize();
+  for (void* p : allocs) dev_free(p);
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
@@ -55,13 +56,22 @@ hipError_t run_copy(const Batch<CopyDesc>& b, hipStream_t st) {
 static constexpr int ID_MMAX = 4096;    // cpqr_id_kernel LDS capacity
 static constexpr int CHOL_NMAX = 2048;  // near-sample points per box (sc^2 doubles each)
 
-// Temporary device buffer freed at scope exit.
+// Temporary device buffer of the build, from the handle's allocator, freed at
+// scope exit (after the device has finished with it when the caller's
+// allocator may hand the memory out again at once).
 struct TmpBuf {
+  Ctx& c;
   void* p = nullptr;
-  ~TmpBuf() { if (p) (void)hipFree(p); }
+  explicit TmpBuf(Ctx& ctx) : c(ctx) {}
+  TmpBuf(const TmpBuf&) = delete;
+  ~TmpBuf() {
+    if (!p) return;
+    if (c.ua.alloc) (void)hipDeviceSynchronize();
+    c.dev_free(p);
+  }
   template <class T> T* get(size_t n) {
     if (n == 0) n = 1;
-    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) p = nullptr;
+    p = c.dev_alloc(n * sizeof(T));
     return static_cast<T*>(p);
   }
 };
@@ -76,7 +86,7 @@ static bool upload_tmp(TmpBuf& tb, T*& dst, const std::vector<T>& v, hipStream_t
 
 static h2_status run_eval(Ctx& c, const std::vector<EvalDesc>& ev, hipStream_t st) {
   if (ev.empty()) return H2_OK;
-  TmpBuf tb1, tb2;
+  TmpBuf tb1(c), tb2(c);
   EvalDesc* d = nullptr;
   int* t = nullptr;
   auto toff = eval_tiles(ev);
@@ -86,7 +96,7 @@ static h2_status run_eval(Ctx& c, const std::vector<EvalDesc>& ev, hipStream_t s
   return H2_OK;
 }
 
-static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st);
+static h2_status run_gemm_tmp(Ctx& c, const std::vector<GemmDesc>& g, hipStream_t st);
 
 // Blocked Cholesky of SPD blocks A (n x n, ld n) and the explicit inverse of
 // the factor, the near-sample solve of the construction (Section 3.5): per
@@ -101,7 +111,8 @@ struct CholJob {
   double* Linv;
   int n, code;
 };
-static h2_status blocked_chol_inv(const std::vector<CholJob>& jobs, int* fail, hipStream_t st) {
+static h2_status blocked_chol_inv(Ctx& c, const std::vector<CholJob>& jobs, int* fail,
+                                  hipStream_t st) {
   if (jobs.empty()) return H2_OK;
   int nmax = 0;
   std::vector<int64_t> so(jobs.size() + 1, 0);  // panel scratch: 64 n per job
@@ -109,7 +120,7 @@ static h2_status blocked_chol_inv(const std::vector<CholJob>& jobs, int* fail, h
     nmax = std::max(nmax, jobs[q].n);
     so[q + 1] = so[q] + 64 * (int64_t)std::max(jobs[q].n, 0);
   }
-  TmpBuf tsc;
+  TmpBuf tsc(c);
   double* dS = tsc.get<double>(so.back());
   ALLOCHK(dS);
   const int np = (nmax + 63) / 64;
@@ -134,13 +145,13 @@ static h2_status blocked_chol_inv(const std::vector<CholJob>& jobs, int* fail, h
         bk.push_back({TA, A21, rows, w, n, n, 0});
       }
     }
-    TmpBuf tp, tb;
+    TmpBuf tp(c), tb(c);
     PanelDesc* dpd = nullptr;
     CopyDesc* dbk = nullptr;
     if (!upload_tmp(tp, dpd, pd, st) || !upload_tmp(tb, dbk, bk, st)) return H2_ERR_ALLOC;
     HIPCHK(launch_panel(dpd, (int)pd.size(), fail, st));
-    h2_status e = run_gemm_tmp(tr, st);
-    if (e == H2_OK) e = run_gemm_tmp(sy, st);
+    h2_status e = run_gemm_tmp(c, tr, st);
+    if (e == H2_OK) e = run_gemm_tmp(c, sy, st);
     if (e != H2_OK) return e;
     HIPCHK(launch_copy(dbk, (int)bk.size(), st));
     HIPCHK(hipStreamSynchronize(st));
@@ -158,16 +169,16 @@ static h2_status blocked_chol_inv(const std::vector<CholJob>& jobs, int* fail, h
       i2.push_back(gd(j.Linv + p0 + (int64_t)p0 * n, n, 0, TA, 64, 0, nullptr, 1, j.Linv + p0, n,
                       w, p0, w, -1.0, 0.0));
     }
-    h2_status e = run_gemm_tmp(i1, st);
-    if (e == H2_OK) e = run_gemm_tmp(i2, st);
+    h2_status e = run_gemm_tmp(c, i1, st);
+    if (e == H2_OK) e = run_gemm_tmp(c, i2, st);
     if (e != H2_OK) return e;
   }
   return H2_OK;
 }
 
-static h2_status run_gemm_tmp(const std::vector<GemmDesc>& g, hipStream_t st) {
+static h2_status run_gemm_tmp(Ctx& c, const std::vector<GemmDesc>& g, hipStream_t st) {
   if (g.empty()) return H2_OK;
-  TmpBuf tb1, tb2;
+  TmpBuf tb1(c), tb2(c);
   GemmDesc* d = nullptr;
   int* t = nullptr;
   auto tmap = gemm_tile_map(g, GEMM_BM[0], GEMM_BN[0]);
@@ -199,11 +210,23 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     if (k.nugget < 0.0) return H2_ERR_ARG;
   }
   if (fixed_ranks && n_inst != 1) return H2_ERR_ARG;
+  if (prm->allocator && (!prm->allocator->alloc || !prm->allocator->free)) return H2_ERR_ARG;
 
   const double t_begin = now_seconds();
   auto ctx = std::make_unique<Ctx>();
   Ctx& c = *ctx;
+  // a breakdown keeps the handle (failed state) so that h2_stats can report
+  // where it happened
+  auto not_spd = [&]() {
+    c.failed = true;
+    auto* hnd = new h2_ctx;
+    hnd->c = std::move(ctx);
+    *out = hnd;
+    return H2_ERR_NOT_SPD;
+  };
   c.prm = *prm;
+  if (prm->allocator) c.ua = *prm->allocator;
+  c.prm.allocator = nullptr;
   c.n_inst = n_inst;
   c.dim = prm->dim;
   c.ins.resize(n_inst);
@@ -302,7 +325,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         }
       }
     const int64_t nb_all = (int64_t)feats.size() / 8;
-    TmpBuf tw, tfe, ty;
+    TmpBuf tw(c), tfe(c), ty(c);
     float* dw = tw.get<float>(4801);
     float* df = tfe.get<float>(feats.size());
     float* dy = ty.get<float>(nb_all);
@@ -424,7 +447,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       }
       fixed_box += nb;
     }
-    TmpBuf tf, tc, tacc, tlc, tt1, tt2, tx, tpiv, tk, tfs;
+    TmpBuf tf(c), tc(c), tacc(c), tlc(c), tt1(c), tt2(c), tx(c), tpiv(c), tk(c), tfs(c);
     int64_t *dF = nullptr, *dC = nullptr;
     if (!upload_tmp(tf, dF, ids_f, st) || !upload_tmp(tc, dC, ids_c, st)) return H2_ERR_ALLOC;
     double* dAcc = tacc.get<double>(acco[nb]);
@@ -477,7 +500,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         if (sc[b] > 0)
           gsd.push_back({dAcc + acco[b], dT1 + t1o[b], dXid + xo[b] + sf[b], dT2 + t1o[b], sc[b],
                          S.m[b], sc[b], sc[b], s[b], b});
-      TmpBuf tgs;
+      TmpBuf tgs(c);
       GsDesc* dgs = nullptr;
       if (!upload_tmp(tgs, dgs, gsd, st)) return H2_ERR_ALLOC;
       HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
@@ -489,7 +512,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         c.st.fail_level = c.ins[S.inst[fail]].tree.L - h;
         c.st.fail_box = S.idx[fail];
         c.st.fail_inst = S.inst[fail];
-        return H2_ERR_NOT_SPD;
+        return not_spd();
       }
     } else {
     // ... or exactly: Lc^{-T} (Lc^{-1} G(S_C, B_i))
@@ -498,7 +521,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         if (sc[b] > 0) cj.push_back({dAcc + acco[b], dLc + acco[b], sc[b], b});
       HIPCHK(hipMemsetAsync(dLc, 0, (size_t)std::max<int64_t>(acco[nb], 1) * sizeof(double), st));
       HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
-      if ((e = blocked_chol_inv(cj, c.dFail, st)) != H2_OK) return e;
+      if ((e = blocked_chol_inv(c, cj, c.dFail, st)) != H2_OK) return e;
       int fail = INT_MAX;
       HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -506,7 +529,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         c.st.fail_level = c.ins[S.inst[fail]].tree.L - h;
         c.st.fail_box = S.idx[fail];
         c.st.fail_inst = S.inst[fail];
-        return H2_ERR_NOT_SPD;
+        return not_spd();
       }
       std::vector<GemmDesc> g1, g2;
       for (int b = 0; b < nb; ++b) {
@@ -516,8 +539,8 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         g2.push_back(gd(dLc + acco[b], sc[b], 1, dT2 + t1o[b], sc[b], 0, nullptr, 1,
                         dXid + xo[b] + sf[b], s[b], sc[b], S.m[b], sc[b], 1.0, 0.0));
       }
-      if ((e = run_gemm_tmp(g1, st)) != H2_OK) return e;
-      if ((e = run_gemm_tmp(g2, st)) != H2_OK) return e;
+      if ((e = run_gemm_tmp(c, g1, st)) != H2_OK) return e;
+      if ((e = run_gemm_tmp(c, g2, st)) != H2_OK) return e;
     }
     // ---- interpolative decomposition
     {
@@ -528,7 +551,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
                         fixed_ranks ? dFs + fsp : nullptr, s[b], S.m[b], fk[b], S.kcap[b]};
         fsp += fk[b];
       }
-      TmpBuf tid;
+      TmpBuf tid(c);
       IdDesc* did = nullptr;
       if (!upload_tmp(tid, did, idd, st)) return H2_ERR_ALLOC;
       HIPCHK(launch_cpqr_id(did, nb, prm->eps, prm->max_rank, nullptr, st));
@@ -555,7 +578,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
             q.U = S.Uptr[b];
             od.push_back(q);
           }
-          TmpBuf tod;
+          TmpBuf tod(c);
           IdDesc* dod = nullptr;
           if (!upload_tmp(tod, dod, od, st)) return H2_ERR_ALLOC;
           HIPCHK(launch_id_write_u(dod, (int)od.size(), st));

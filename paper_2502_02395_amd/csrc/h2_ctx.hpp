@@ -196,19 +196,33 @@ struct Ctx {
   int part_nrhs = 0;                       // right-hand sides dPart holds
   hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;  // caller stream <-> graph_stream ordering
 
+  // the caller's device allocator (h2_params.allocator); alloc == NULL means
+  // hipMalloc / hipFree
+  h2_allocator ua{};
+
   ~Ctx();
+  void* dev_alloc(size_t bytes) {
+    if (ua.alloc) return ua.alloc(bytes, ua.user);
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
+  void dev_free(void* p) {
+    if (ua.alloc) ua.free(p, ua.user);
+    else (void)hipFree(p);
+  }
   template <class T>
   T* alloc(size_t count) {
     if (count == 0) count = 1;
-    void* p = nullptr;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
+    void* p = dev_alloc(count * sizeof(T));
+    if (!p) return nullptr;
     allocs.push_back(p);
     return static_cast<T*>(p);
   }
+  // the device must have finished with p (callers synchronize first)
   void free_one(void* p) {
     for (size_t i = 0; i < allocs.size(); ++i)
       if (allocs[i] == p) {
-        (void)hipFree(p);
+        dev_free(p);
         allocs[i] = allocs.back();
         allocs.pop_back();
         return;

@@ -165,7 +165,8 @@ hipError_t launch_coldot(const double* a, int64_t lda, const double* b, int64_t 
 }
 
 // z = x + alpha[c] * y  (alpha per column from device memory if alphas != NULL,
-// scaled by sgn), all n x nrhs with their own leading dimensions.
+// divided by alphas_den[c] if given, scaled by sgn; a zero numerator or
+// denominator gives alpha = 0), all n x nrhs with their own leading dimensions.
 __global__ void axpby_kernel(double* z, int64_t ldz, const double* x, int64_t ldx, const double* y,
                              int64_t ldy, int64_t n, int nrhs, const double* alphas,
                              const double* alphas_den, double sgn) {
@@ -174,7 +175,9 @@ __global__ void axpby_kernel(double* z, int64_t ldz, const double* x, int64_t ld
     const int64_t r = e % n, c = e / n;
     double a = sgn;
     if (alphas) a *= alphas[c];
-    if (alphas_den) a /= alphas_den[c];
+    // a column whose ratio has a zero numerator or denominator (a zero or
+    // exactly converged right-hand side in CG) keeps its x, r and p
+    if (alphas_den) a = (alphas_den[c] != 0.0 && a != 0.0) ? a / alphas_den[c] : 0.0;
     z[r + c * ldz] = x[r + c * ldx] + a * y[r + c * ldy];
   }
 }

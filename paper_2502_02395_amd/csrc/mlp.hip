@@ -216,6 +216,22 @@ void box_features_host(const Ctx& c, int t, int l, int i, float* f) {
   f[7] = (float)(-std::log10(c.prm.eps > 0 ? c.prm.eps : 1e-300));
 }
 
+// One full-batch training step with the per-block partials in ws
+// (nblk * NP + nblk floats; every entry is written before it is read).
+static hipError_t mlp_train_launch(float* w, float* m, float* v, float* g, const float* x,
+                                   const float* t, int64_t n, int32_t step, float lr, float* loss,
+                                   float* ws, hipStream_t st) {
+  const int nblk = (int)((n + SPB - 1) / SPB);
+  hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(256), 0, st, w, x, t, n, ws,
+                     ws + (size_t)nblk * NP);
+  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, ws,
+                     ws + (size_t)nblk * NP, nblk, n, g, loss);
+  const float b1t = std::pow(0.9f, (float)step), b2t = std::pow(0.999f, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, w, m, v, g, NP, b1t, b2t,
+                     lr);
+  return hipGetLastError();
+}
+
 }  // namespace h2
 
 using namespace h2;
@@ -238,14 +254,7 @@ h2_status h2_mlp_train_step(float* w, float* m, float* v, float* g, const float*
   const int nblk = (int)((n + SPB - 1) / SPB);
   float* ws = nullptr;
   if (hipMalloc(&ws, sizeof(float) * ((size_t)nblk * NP + nblk)) != hipSuccess) return H2_ERR_ALLOC;
-  hipLaunchKernelGGL(mlp_grad_kernel, dim3(nblk), dim3(256), 0, st, w, x, t, n, ws,
-                     ws + (size_t)nblk * NP);
-  hipLaunchKernelGGL(mlp_reduce_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, ws,
-                     ws + (size_t)nblk * NP, nblk, n, g, loss);
-  const float b1t = std::pow(0.9f, (float)step), b2t = std::pow(0.999f, (float)step);
-  hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, st, w, m, v, g, NP, b1t, b2t,
-                     lr);
-  hipError_t e = hipGetLastError();
+  const hipError_t e = mlp_train_launch(w, m, v, g, x, t, n, step, lr, loss, ws, st);
   const hipError_t s2 = hipStreamSynchronize(st);
   (void)hipFree(ws);
   return (e == hipSuccess && s2 == hipSuccess) ? H2_OK : H2_ERR_HIP;

@@ -18,14 +18,72 @@ LIB_PATH = os.path.join(_HERE, "libh2.so")
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_SPD, ERR_STATE, ERR_NOCONV, ERR_UNSUPPORTED = range(8)
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 SYMBOLS = ["h2_build", "h2_build_batched", "h2_build_fixed", "h2_factor", "h2_solve", "h2_matvec",
-           "h2_stats", "h2_get_counts", "h2_get_structure", "h2_get_pairs", "h2_get_root",
-           "h2_mlp_forward", "h2_mlp_train_step", "h2_box_features", "h2_destroy", "h2_status_str"]
+           "h2_stats", "h2_get_counts", "h2_get_structure", "h2_get_pairs", "h2_get_basis",
+           "h2_get_root", "h2_mlp_forward", "h2_mlp_train_step", "h2_box_features",
+           "h2_destroy", "h2_status_str"]
 
 
 class H2Error(RuntimeError):
-    def __init__(self, status: int, what: str):
-        super().__init__(f"{what}: {_status_str(status)} ({status})")
+    def __init__(self, status: int, what: str, where: dict | None = None):
+        msg = f"{what}: {_status_str(status)} ({status})"
+        if where:
+            msg += " at level {fail_level}, box {fail_box}, instance {fail_inst}".format(**where)
+        super().__init__(msg)
         self.status = status
+        self.where = where
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    """h2_allocator: the device memory callbacks of a handle."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """PyTorch's caching allocator (on the current stream) behind h2_allocator.
+    ``fail_at`` (1-based) makes that allocation call fail, to exercise the
+    library's H2_ERR_ALLOC path; ``live`` counts outstanding allocations."""
+
+    def __init__(self, fail_at: int = 0):
+        self.fail_at = fail_at
+        self.calls = 0
+        self.live = 0
+        self._alloc = _ALLOC_FN(self._do_alloc)
+        self._free = _FREE_FN(self._do_free)
+        self.struct = Allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, user):
+        import torch
+        self.calls += 1
+        if self.fail_at and self.calls == self.fail_at:
+            return None
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:  # out of memory: the library reports H2_ERR_ALLOC
+            return None
+        self.live += 1
+        return p
+
+    def _do_free(self, ptr, user):
+        try:
+            import torch
+            torch.cuda.caching_allocator_delete(ptr)
+            self.live -= 1
+        except Exception:  # interpreter shutdown
+            pass
+
+
+_default_allocator = None
+
+
+def default_allocator() -> TorchAllocator:
+    global _default_allocator
+    if _default_allocator is None:
+        _default_allocator = TorchAllocator()
+    return _default_allocator
 
 
 class Kernel(ctypes.Structure):
@@ -41,7 +99,8 @@ class Params(ctypes.Structure):
                 ("use_pcg", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
                 ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32),
-                ("solve_prec", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32)]
+                ("solve_prec", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32),
+                ("allocator", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -97,6 +156,7 @@ def load() -> ctypes.CDLL:
     L.h2_get_counts.argtypes = [vp, P(i64), P(i64)]
     L.h2_get_structure.argtypes = [vp, vp, vp, vp, vp]
     L.h2_get_pairs.argtypes = [vp, i32, i32, vp, P(i64)]
+    L.h2_get_basis.argtypes = [vp, i32, i32, i32, vp, P(i32), P(i32)]
     L.h2_get_root.argtypes = [vp, i32, vp, P(i64)]
     L.h2_mlp_forward.argtypes = [vp, vp, vp, i64, vp]
     L.h2_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, i64, i32, ctypes.c_float, vp, vp]
@@ -137,17 +197,21 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
                 max_rank: int = 0, gemm_prec: int = PREC_FP64, ir_max_iter: int = 0,
                 ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
                 timing: bool = False, rank_model=None, rank_margin: float = 0.25,
-                autotune: bool = True, solve_prec: int = PREC_FP64, gs_sweeps: int = 0) -> Params:
+                autotune: bool = True, solve_prec: int = PREC_FP64, gs_sweeps: int = 0,
+                allocator=None) -> Params:
     """rank_model: numpy float32 array of the 4801 predictor weights (kept alive
-    by the caller for the duration of the build call)."""
+    by the caller for the duration of the build call).  allocator: a
+    TorchAllocator (or None: the library's hipMalloc); it must outlive the
+    handle."""
     ptr = None
     if rank_model is not None:
         assert rank_model.dtype == np.float32 and rank_model.size == 4801
         assert rank_model.flags["C_CONTIGUOUS"]
         ptr = rank_model.ctypes.data
+    aptr = None if allocator is None else ctypes.addressof(allocator.struct)
     return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
                   int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune),
-                  int(solve_prec), int(gs_sweeps))
+                  int(solve_prec), int(gs_sweeps), aptr)
 
 
 def _as_cols(t, n):
@@ -162,9 +226,10 @@ def _as_cols(t, n):
 class Handle:
     """An H^2 matrix built on the device (one instance or a batch)."""
 
-    def __init__(self, ptr: ctypes.c_void_p, n: int):
+    def __init__(self, ptr: ctypes.c_void_p, n: int, allocator=None):
         self._h = ptr
         self.n = n
+        self._allocator = allocator  # its callbacks must outlive the handle
 
     def close(self):
         if self._h:
@@ -236,6 +301,18 @@ class Handle:
                "h2_get_pairs")
         return [(int(buf[2 * q]), int(buf[2 * q + 1])) for q in range(cnt.value)]
 
+    def basis(self, level: int, box: int, inst: int = 0):
+        """(P, k): the two-sided basis [Q^S | Q^R L(r)^{-T}] (m x m) of a box
+        after factor, and its rank."""
+        L = load()
+        m, k = ctypes.c_int32(), ctypes.c_int32()
+        _check(L.h2_get_basis(self._h, inst, level, box, None, ctypes.byref(m), ctypes.byref(k)),
+               "h2_get_basis")
+        a = np.zeros((m.value, m.value))
+        _check(L.h2_get_basis(self._h, inst, level, box, a.ctypes.data, ctypes.byref(m),
+                              ctypes.byref(k)), "h2_get_basis")
+        return a.T.copy(), k.value  # column-major -> row-major
+
     def root(self, inst: int = 0) -> np.ndarray:
         L = load()
         n0 = ctypes.c_int64()
@@ -254,19 +331,42 @@ class Handle:
         return f
 
 
+def _built(status: int, out: ctypes.c_void_p, what: str, n: int, alloc) -> Handle:
+    """A successful build's handle; otherwise raise (a breakdown's failed-state
+    handle is read for the location, then destroyed)."""
+    if status == OK:
+        return Handle(out, n, alloc)
+    where = None
+    if status == ERR_NOT_SPD and out.value:
+        s = Stats()
+        if load().h2_stats(out, ctypes.byref(s)) == OK:
+            where = {"fail_level": s.fail_level, "fail_box": s.fail_box,
+                     "fail_inst": s.fail_inst}
+        load().h2_destroy(out)
+    raise H2Error(status, what, where)
+
+
+def _alloc_kw(kw: dict):
+    """The allocator a build uses: PyTorch's caching allocator unless the
+    caller passes one (allocator=None selects the library's hipMalloc)."""
+    if "allocator" not in kw:
+        kw["allocator"] = default_allocator()
+    return kw["allocator"]
+
+
 def build(points: np.ndarray, kernel, leaf: int, eta: float, eps: float, perm=None,
           s_far: int = -1, s_near: int = -1, stream=None, **kw) -> Handle:
     L = load()
     pts = np.ascontiguousarray(points, dtype=np.float64)
     n, dim = pts.shape
+    alloc = _alloc_kw(kw)
     prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
     k = make_kernel(kernel)
     pp = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
     out = ctypes.c_void_p()
-    _check(L.h2_build(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm),
-                      None if pp is None else pp.ctypes.data, _stream(stream), ctypes.byref(out)),
-           "h2_build")
-    return Handle(out, n)
+    s = L.h2_build(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm),
+                   None if pp is None else pp.ctypes.data, _stream(stream), ctypes.byref(out))
+    return _built(s, out, "h2_build", n, alloc)
 
 
 def build_fixed(points: np.ndarray, kernel, leaf: int, eta: float, eps: float, perm, ranks,
@@ -276,16 +376,16 @@ def build_fixed(points: np.ndarray, kernel, leaf: int, eta: float, eps: float, p
     L = load()
     pts = np.ascontiguousarray(points, dtype=np.float64)
     n, dim = pts.shape
+    alloc = _alloc_kw(kw)
     prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
     k = make_kernel(kernel)
     pp = np.ascontiguousarray(perm, dtype=np.int64)
     rk = np.ascontiguousarray(ranks, dtype=np.int32)
     sk = np.ascontiguousarray(skel, dtype=np.int32)
     out = ctypes.c_void_p()
-    _check(L.h2_build_fixed(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm), pp.ctypes.data,
-                            rk.ctypes.data, sk.ctypes.data, _stream(stream), ctypes.byref(out)),
-           "h2_build_fixed")
-    return Handle(out, n)
+    s = L.h2_build_fixed(pts.ctypes.data, n, ctypes.byref(k), ctypes.byref(prm), pp.ctypes.data,
+                         rk.ctypes.data, sk.ctypes.data, _stream(stream), ctypes.byref(out))
+    return _built(s, out, "h2_build_fixed", n, alloc)
 
 
 def build_batched(point_sets, kernels, leaf: int, eta: float, eps: float, perms=None,
@@ -294,6 +394,7 @@ def build_batched(point_sets, kernels, leaf: int, eta: float, eps: float, perms=
     pts = [np.ascontiguousarray(p, dtype=np.float64) for p in point_sets]
     ns = np.array([p.shape[0] for p in pts], dtype=np.int64)
     dim = pts[0].shape[1]
+    alloc = _alloc_kw(kw)
     prm = make_params(dim, leaf, eta, eps, s_far, s_near, **kw)
     ks = (Kernel * len(pts))(*[make_kernel(k) for k in kernels])
     pptr = (ctypes.c_void_p * len(pts))(*[p.ctypes.data for p in pts])
@@ -303,9 +404,9 @@ def build_batched(point_sets, kernels, leaf: int, eta: float, eps: float, perms=
     else:
         qptr = None
     out = ctypes.c_void_p()
-    _check(L.h2_build_batched(len(pts), pptr, ns.ctypes.data, ks, ctypes.byref(prm), qptr,
-                              _stream(stream), ctypes.byref(out)), "h2_build_batched")
-    h = Handle(out, int(ns.sum()))
+    s = L.h2_build_batched(len(pts), pptr, ns.ctypes.data, ks, ctypes.byref(prm), qptr,
+                           _stream(stream), ctypes.byref(out))
+    h = _built(s, out, "h2_build_batched", int(ns.sum()), alloc)
     h._keep = (pts, perms)
     return h
 
@@ -323,3 +424,4 @@ def mlp_train_step(w, m, v, g, x, t, step: int, lr: float, loss, stream=None):
     _check(load().h2_mlp_train_step(*(ctypes.c_void_p(a.data_ptr()) for a in (w, m, v, g, x, t)),
                                     x.shape[0], step, lr, ctypes.c_void_p(loss.data_ptr()),
                                     _stream(stream)), "h2_mlp_train_step")
+
