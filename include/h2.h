@@ -158,7 +158,14 @@ typedef struct {
                                transform, RR Cholesky + inverse, V and Schur
                                update, near-pair transforms, far couplings,
                                merge, root, FP32 copies for the substitution  */
+  int64_t gather_partials;  /* doubles of gather partial products that one
+                               right-hand side of a solve or matvec needs
+                               (h2_solve_noalloc: at most H2_NOALLOC_PARTIALS) */
 } h2_stats_t;
+
+/* Capacity, in doubles, of the fixed device array that h2_solve_noalloc uses
+ * for its gather partial products (64 MiB per GPU). */
+#define H2_NOALLOC_PARTIALS (1 << 23)
 
 /* Build the H^2 representation of one kernel matrix (Algorithm 1).
  *  pts:   host, n x dim row-major points (copied).
@@ -213,6 +220,24 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs,
  * dense near field).  x, y: device, n x nrhs, ld >= n, original order; x != y. */
 h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs,
                     int64_t ld, void* stream);
+
+/* h2_solve for callers that cannot allocate device memory during the call
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, same kernels and results as h2_solve (with
+ * the handle's params.timing ignored), but no hipMalloc, hipFree or other
+ * allocating call: the gather partial products go to a fixed device array of
+ * H2_NOALLOC_PARTIALS doubles (64 MiB), one per GPU, held until the process
+ * ends; right-hand sides are processed in passes of
+ * min(16, H2_NOALLOC_PARTIALS / h2_stats.gather_partials) columns.  The
+ * handle's own buffers come from its build.  Every call on one GPU shares that
+ * GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads, other handles) race and must be serialized by the caller.
+ * Errors: as h2_solve, plus H2_ERR_UNSUPPORTED when one right-hand side
+ * needs more than H2_NOALLOC_PARTIALS doubles of partials (the handle is
+ * unchanged), and H2_ERR_HIP if the array's device address cannot be
+ * looked up. */
+h2_status h2_solve_noalloc(h2_handle h, const double* b, double* x, int64_t nrhs,
+                           int64_t ld, void* stream);
 
 h2_status h2_stats(h2_handle h, h2_stats_t* out);
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "h2_ctx.hpp"
 
@@ -86,6 +87,36 @@ static void count_flops(Ctx& c) {
   c.st.flops_factor = ff;
   c.st.flops_solve = fs;
   c.st.bytes_factors = bytes;
+  c.st.gather_partials = c.part_len;
+}
+
+// ------------------------------------------------- no-allocation solve
+// The gather partials of h2_solve_noalloc live in this fixed array instead of
+// the handle's lazily grown buffer: every GPU the library runs on holds one
+// copy (H2_NOALLOC_PARTIALS doubles, 64 MiB) until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current.  No slot needs clearing between calls: every slot a reduction reads
+// is written by its chunk earlier in the same gather.
+static __device__ __align__(256) double scratch[H2_NOALLOC_PARTIALS];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[64] = {};
+
+static h2_status noalloc_partials(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return H2_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return H2_ERR_HIP;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return H2_OK;
 }
 
 extern "C" {
@@ -207,19 +238,15 @@ static h2_status colnorms(Ctx& c, const double* a, int nc, double* out, hipStrea
   return H2_OK;
 }
 
-h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_t ld, void* stream) {
-  if (!h || !h->c || !b || !x) return H2_ERR_ARG;
-  Ctx& c = *h->c;
-  if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
-  if (!c.factored || c.failed) return H2_ERR_STATE;
-  hipStream_t st = S(stream);
+// The solve of h2_solve and h2_solve_noalloc: right-hand sides in chunks of
+// at most `chunk` columns, gather partials in c.part_cur (sized by the caller
+// for part_len x chunk doubles).  time_gathers: record gather events (the
+// event pool is created on first use).
+static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, int64_t ld,
+                            hipStream_t st, int chunk, bool time_gathers) {
   const double t0 = now_seconds();
   const int maxit = c.prm.ir_max_iter;
-  {
-    h2_status e = ensure_partials(c, (int)std::min<int64_t>(NRHS_MAX, nrhs));
-    if (e != H2_OK) return e;
-  }
-  if (c.prm.timing) {
+  if (time_gathers) {
     if (c.gev.empty()) {
       c.gev.resize(3 * 2048, nullptr);
       for (auto& e : c.gev) HIPCHK(hipEventCreate(&e));
@@ -232,8 +259,8 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
   int iters_total = 0;
   double worst = 0.0;
   bool noconv = false;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += NRHS_MAX) {
-    const int nc = (int)std::min<int64_t>(NRHS_MAX, nrhs - c0);
+  for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
+    const int nc = (int)std::min<int64_t>(chunk, nrhs - c0);
     const double* bb = b + c0 * ld;
     double* xx = x + c0 * ld;
     // keep b (x may alias it)
@@ -243,10 +270,10 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
       if (e != H2_OK) return e;
     } else {
       double* sc = c.dScal;  // [0,16): r.r  [16,32): b.b  [32,48): rz  [48,64): pq  [64,80): rz_new
-      std::vector<double> hr(NRHS_MAX), hb(NRHS_MAX);
+      double hr[NRHS_MAX], hb[NRHS_MAX];
       h2_status e = colnorms(c, c.w_t, nc, sc + 16, st);
       if (e != H2_OK) return e;
-      HIPCHK(hipMemcpyAsync(hb.data(), sc + 16, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hb, sc + 16, nc * sizeof(double), hipMemcpyDeviceToHost, st));
       if ((e = solve_plain(c, c.w_t, c.w_x, nc, st)) != H2_OK) return e;
       // r = b - A x
       if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
@@ -261,7 +288,7 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
       double res = 0.0;
       for (;;) {
         if ((e = colnorms(c, c.w_r, nc, sc, st)) != H2_OK) return e;
-        HIPCHK(hipMemcpyAsync(hr.data(), sc, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hr, sc, nc * sizeof(double), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         res = 0.0;
         for (int q = 0; q < nc; ++q) {
@@ -318,6 +345,38 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
   return noconv ? H2_ERR_NOCONV : H2_OK;
 }
 
+h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_t ld, void* stream) {
+  if (!h || !h->c || !b || !x) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
+  if (!c.factored || c.failed) return H2_ERR_STATE;
+  {
+    h2_status e = ensure_partials(c, (int)std::min<int64_t>(NRHS_MAX, nrhs));
+    if (e != H2_OK) return e;
+  }
+  c.part_cur = c.dPart;
+  return solve_impl(c, b, x, nrhs, ld, S(stream), NRHS_MAX, c.prm.timing != 0);
+}
+
+h2_status h2_solve_noalloc(h2_handle h, const double* b, double* x, int64_t nrhs, int64_t ld,
+                           void* stream) {
+  if (!h || !h->c || !b || !x) return H2_ERR_ARG;
+  Ctx& c = *h->c;
+  if (nrhs < 1 || ld < c.N) return H2_ERR_ARG;
+  if (!c.factored || c.failed) return H2_ERR_STATE;
+  if (c.part_len > H2_NOALLOC_PARTIALS) return H2_ERR_UNSUPPORTED;
+  double* part = nullptr;
+  {
+    h2_status e = noalloc_partials(&part);
+    if (e != H2_OK) return e;
+  }
+  // as many columns per pass as the fixed array holds (at most NRHS_MAX)
+  const int64_t fit = c.part_len > 0 ? H2_NOALLOC_PARTIALS / c.part_len : NRHS_MAX;
+  const int chunk = (int)std::min<int64_t>(NRHS_MAX, fit);
+  c.part_cur = part;
+  return solve_impl(c, b, x, nrhs, ld, S(stream), chunk, false);
+}
+
 h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs, int64_t ld, void* stream) {
   if (!h || !h->c || !x || !y || x == y) return H2_ERR_ARG;
   Ctx& c = *h->c;
@@ -329,6 +388,7 @@ h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs, int64
   }
   for (int64_t c0 = 0; c0 < nrhs; c0 += NRHS_MAX) {
     const int nc = (int)std::min<int64_t>(NRHS_MAX, nrhs - c0);
+    c.part_cur = c.dPart;
     h2_status e = do_matvec_chunk(c, x + c0 * ld, ld, y + c0 * ld, ld, nc, st);
     if (e != H2_OK) return e;
   }

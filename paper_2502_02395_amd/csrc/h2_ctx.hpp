@@ -194,6 +194,9 @@ struct Ctx {
   double* dPart = nullptr;                 // gather partial products
   int64_t part_len = 0;                    // longest list's partials, one rhs
   int part_nrhs = 0;                       // right-hand sides dPart holds
+  double* part_cur = nullptr;              // partials the gathers of the current
+                                           // solve / matvec call use (dPart, or the
+                                           // no-allocation call's fixed array)
   hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;  // caller stream <-> graph_stream ordering
 
   // the caller's device allocator (h2_params.allocator); alloc == NULL means

@@ -105,10 +105,10 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.dPart, nrhs, L.f32, st, wide)) != hipSuccess)
+  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.f32, st, wide)) != hipSuccess)
     return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
-  if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.dPart, nrhs, st)) !=
+  if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st)) !=
       hipSuccess)
     return e;
   if (t) {

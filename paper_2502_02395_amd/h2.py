@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_SPD, ERR_STATE, ERR_NOCONV, ERR_UNSUPPORTED = range(8)
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
-SYMBOLS = ["h2_build", "h2_build_batched", "h2_build_fixed", "h2_factor", "h2_solve", "h2_matvec",
+SYMBOLS = ["h2_build", "h2_build_batched", "h2_build_fixed", "h2_factor", "h2_solve",
+           "h2_solve_noalloc", "h2_matvec",
            "h2_stats", "h2_get_counts", "h2_get_structure", "h2_get_pairs", "h2_get_basis",
            "h2_get_root", "h2_mlp_forward", "h2_mlp_train_step", "h2_box_features",
            "h2_destroy", "h2_status_str"]
@@ -120,7 +121,7 @@ class Stats(ctypes.Structure):
                 ("tuned_cfg_hist", ctypes.c_int32 * 4),
                 ("t_gather", ctypes.c_double * 3), ("bytes_gather", ctypes.c_double * 3),
                 ("gather_launches", ctypes.c_int32 * 3),
-                ("t_factor_phase", ctypes.c_double * 9)]
+                ("t_factor_phase", ctypes.c_double * 9), ("gather_partials", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -151,6 +152,7 @@ def load() -> ctypes.CDLL:
     L.h2_build_fixed.argtypes = [vp, i64, P(Kernel), P(Params), vp, vp, vp, vp, P(vp)]
     L.h2_factor.argtypes = [vp, vp]
     L.h2_solve.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.h2_solve_noalloc.argtypes = [vp, vp, vp, i64, i64, vp]
     L.h2_matvec.argtypes = [vp, vp, vp, i64, i64, vp]
     L.h2_stats.argtypes = [vp, P(Stats)]
     L.h2_get_counts.argtypes = [vp, P(i64), P(i64)]
@@ -263,6 +265,12 @@ class Handle:
         return load().h2_solve(self._h, ctypes.c_void_p(cols_b.data_ptr()),
                                ctypes.c_void_p(cols_x.data_ptr()), cols_b.shape[0], self.n,
                                _stream(stream))
+
+    def solve_noalloc_into(self, cols_b, cols_x, stream=None) -> int:
+        """h2_solve_noalloc on (nrhs, n) contiguous tensors; returns the status."""
+        return load().h2_solve_noalloc(self._h, ctypes.c_void_p(cols_b.data_ptr()),
+                                       ctypes.c_void_p(cols_x.data_ptr()), cols_b.shape[0],
+                                       self.n, _stream(stream))
 
     def matvec(self, x, stream=None):
         import torch

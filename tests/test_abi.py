@@ -57,6 +57,7 @@ def test_status_strings_and_argument_errors_without_gpu():
                           ctypes.byref(out)) == h2.ERR_ARG, kw
     assert L.h2_factor(None, None) == h2.ERR_ARG
     assert L.h2_solve(None, None, None, 1, 1, None) == h2.ERR_ARG
+    assert L.h2_solve_noalloc(None, None, None, 1, 1, None) == h2.ERR_ARG
 
 
 def test_graft_entry_has_build_and_smoke():
