@@ -4,11 +4,13 @@ One step = h2_factor + h2_solve (the parallel substitution as the
 preconditioner of CG against the FP64 H^2 operator, down to a relative
 residual of 1e-8) on a resident H^2 matrix of 2^20 points; the H^2
 construction runs once before the timed region.  The default run times the
-target path (rank-predicted basis buffers; basis-transform and Schur-update
-GEMMs on FP32 MFMA with FP32 accumulation, the near-pair transforms on FP32
-copies of the bases and near blocks, the substitution reading FP32 copies of
-the factors; Cholesky factors, root, H^2 matvec and refinement in FP64) next
-to the plain FP64 path and prints one JSON line with both.
+target path (rank-predicted basis buffers; the near-pair, diagonal and
+far-coupling transforms on FP32 copies of their operands in HBM, multiplied on
+the BF16 matrix cores with each operand split into BF16 high and low parts
+(three products per product, FP32 accumulation); the Schur update on FP32
+MFMA; the substitution reading FP32 copies of the factors; Cholesky factors,
+root, H^2 matvec and refinement in FP64) next to the plain FP64 path and
+prints one JSON line with both.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--path target|plain|custom]
 """
@@ -25,10 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector = matrix)
-# dense matrix peaks of the pair-transform GEMM by its precision
-PAIR_KERNEL = {0: ("gemm_f64_pair_kernel", FP64_PEAK_TFLOPS),
-               1: ("gemm_f32io_pair_kernel", 157.3),
-               2: ("gemm_bf16_kernel", 2500.0)}
+# The pair-transform GEMM by precision: kernel, dense matrix peak of the
+# instruction it runs, and matrix-core flops executed per algorithmic flop
+# (split BF16 does three BF16 products per product).
+PAIR_KERNEL = {0: ("gemm_f64_pair_kernel", FP64_PEAK_TFLOPS, 1),
+               1: ("gemm_f32io_pair_kernel", 157.3, 1),
+               2: ("gemm_bf16s_pair_kernel", 2500.0, 1),
+               3: ("gemm_bf16s_pair_kernel", 2500.0, 3)}
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE and, in a
@@ -133,8 +138,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
         bnp = np.concatenate([q.b() for q in p], axis=0)
         n_total = sum(q.n for q in p)
     else:
-        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
-                     s_near=p.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
+        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=a.s,
+                     s_near=a.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
                      gemm_prec=prec, rank_model=model, use_graph=a.graph,
                      use_pcg=not a.stationary, solve_prec=sprec)
         bnp = p.b()
@@ -193,9 +198,10 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     cands = []
     if t_pair > 0:
         tf = st["flops_pair_gemm"] * K / t_pair / 1e12
-        kname, peak = PAIR_KERNEL[prec]
-        cands.append({"bound": "mfma", "kernel": kname, "achieved": tf,
-                      "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+        kname, peak, mult = PAIR_KERNEL[prec]
+        cands.append({"bound": "mfma", "kernel": kname, "achieved": tf * mult,
+                      "peak": peak, "unit": "TFLOP/s", "frac": tf * mult / peak,
+                      "algorithmic_tflops": tf, "mfma_flops_per_flop": mult,
                       "traffic": None, "launches": st["pair_launches"] * K,
                       "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1),
                       "total_s": t_pair})
@@ -230,11 +236,12 @@ def main():
     ap.add_argument("--kernel", default="yukawa",
                     help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
-                    help="target: rank-predicted buffers, FP32 transform GEMMs and FP32 "
-                         "copies for the substitution, timed next to the plain FP64 path "
+                    help="target: rank-predicted buffers, split-BF16 transform GEMMs on FP32 "
+                         "copies and FP32 copies for the substitution, timed next to the "
+                         "plain FP64 path "
                          "(default); plain: the FP64 path "
                          "only; custom: --prec / --solve-prec / --rank-model as given")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"],
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="custom path: precision of the basis-transform and Schur-update GEMMs")
     ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32"],
                     help="custom path: precision of the factor copies the substitution reads "
@@ -248,6 +255,8 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--s", type=int, default=512)
+    ap.add_argument("--s-near", type=int, default=0,
+                    help="near-field sample size (0: the same as --s)")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -255,6 +264,8 @@ def main():
                     help="first run one plain 1 GiB device-to-device copy (the reference for "
                          "FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
+    if a.s_near <= 0:
+        a.s_near = a.s
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library implements the single-GPU H^2-ULV "
               "path; a distribution over several GPUs is not implemented.", file=sys.stderr)
@@ -269,7 +280,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    P = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16}
+    P = {"fp64": h2.PREC_FP64, "fp32": h2.PREC_FP32, "bf16": h2.PREC_BF16,
+         "bf16x3": h2.PREC_BF16X3}
     plain = None
     if a.path == "custom":
         model = train_rank_model(a, h2) if a.rank_model else None
@@ -281,8 +293,8 @@ def main():
     else:
         plain = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain fp64")
         model = train_rank_model(a, h2) if a.kernel != "gaussian_batch" else None
-        setting = ("fp32", "fp32", model is not None)
-        r = run_path(a, h2, h2.PREC_FP32, h2.PREC_FP32, model, "target")
+        setting = ("bf16x3", "fp32", model is not None)
+        r = run_path(a, h2, h2.PREC_BF16X3, h2.PREC_FP32, model, "target")
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20:
         for d in r["cands"]:  # traffic was measured on this workload and path
             d["traffic"] = measured_traffic(d["kernel"])
@@ -293,12 +305,14 @@ def main():
         "metric": "H2-ULV factor+solve TFLOP/s at N=2^20 (rel. residual <= 1e-8 vs FP64 H2 operator)",
         "value": r["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64+f32" if mixed else "f64",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64+f32" if mixed else "f64", "fp32": "f64+f32", "bf16": "f64+bf16",
+                  "bf16x3": "f64+bf16x3"}[setting[0]],
         "data": "synthetic",
         "config": {"workload": a.kernel if a.kernel == "gaussian_batch" else f"{a.kernel}_cube",
                    "path": a.path, "n": r["n_total"],
                    "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
-                   "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s, "nrhs": 1,
+                   "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s_near, "nrhs": 1,
                    "gemm_prec": setting[0], "solve_prec": setting[1], "rank_model": setting[2],
                    "graph": a.graph, "rank_fallbacks": st["rank_fallbacks"],
                    "basis_bytes": st["bytes_basis"], "autotuned_lists": st["tuned_lists"],

@@ -65,7 +65,16 @@ typedef struct {
   double delta, kappa, ell, nugget;
 } h2_kernel;
 
-typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_BF16 = 2 } h2_prec;
+/* Precision of the basis-transform GEMMs (h2_params.gemm_prec):
+ *   FP64    FP64 MFMA on the FP64 factors;
+ *   FP32    FP32 copies of the operands in HBM, FP32 MFMA, FP32 accumulation;
+ *   BF16    the same FP32 copies rounded to BF16 on their way into LDS, BF16
+ *           MFMA (16x16x32), FP32 accumulation (8-bit operands);
+ *   BF16X3  the same FP32 copies split into BF16 high and low parts, three
+ *           BF16 MFMAs per product (high*high + high*low + low*high), FP32
+ *           accumulation: about 17-bit operands at a third of the BF16 rate.
+ * The Cholesky factors, the root, the H^2 matvec and refinement stay FP64. */
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32 = 1, H2_PREC_BF16 = 2, H2_PREC_BF16X3 = 3 } h2_prec;
 
 /* Device memory of a handle.  Every device buffer the handle owns and every
  * temporary of the build comes from alloc(bytes, user), which returns NULL
@@ -87,11 +96,12 @@ typedef struct {
   double eps;             /* ID truncation: keep |R_jj| > eps |R_00|             */
   int32_t max_rank;       /* 0 = no cap                                          */
   int32_t s_far, s_near;  /* sample sizes per box; -1 = every candidate point    */
-  int32_t gemm_prec;      /* h2_prec of the basis-transform / Schur GEMMs.  FP32
-                             also keeps the near-pair transforms' operands and
-                             results in FP32 (FP32 copies of the bases and near
-                             blocks), so the substitution then reads the FP32
-                             copies whatever solve_prec says                   */
+  int32_t gemm_prec;      /* h2_prec of the basis-transform / Schur GEMMs.  Every
+                             reduced precision keeps the transforms' operands
+                             and results in FP32 (FP32 copies of the bases and
+                             near blocks), so the substitution then reads the
+                             FP32 copies whatever solve_prec says; the Schur
+                             update runs on FP32 MFMA                          */
   int32_t ir_max_iter;    /* 0 = plain direct solve                              */
   double ir_tol;          /* relative residual target of refinement              */
   int32_t use_pcg;        /* 1 = PCG instead of stationary refinement            */

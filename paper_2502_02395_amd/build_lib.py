@@ -21,7 +21,7 @@ BUILD = os.path.join(CSRC, "_build")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HIP_SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_gemm_f32.hip", "k_dense.hip", "k_vec.hip", "k_gather.hip", "mlp.hip"]
+HIP_SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_gemm_f32.hip", "k_gemm_bf16.hip", "k_dense.hip", "k_vec.hip", "k_gather.hip", "mlp.hip"]
 HOST_HIP_SOURCES = ["build.cpp", "solve.cpp", "gather_plan.cpp", "api.cpp"]
 PLAIN_SOURCES = ["tree.cpp"]
 

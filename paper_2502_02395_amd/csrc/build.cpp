@@ -36,6 +36,9 @@ Ctx::~Ctx() {
 }
 
 hipError_t run_gemm(const Batch<GemmDesc>& b, hipStream_t st, int tag) {
+  if (b.f32io && b.terms)
+    return launch_gemm_bf16s(b.d, b.toff, b.count, b.tiles, st, b.cfg, b.tA, b.tB, b.f32io == 2,
+                             b.terms);
   if (b.f32io)
     return launch_gemm_f32io(b.d, b.toff, b.count, b.tiles, st, b.cfg, b.tA, b.tB, b.f32io == 2);
   return launch_gemm(b.d, b.toff, b.count, b.tiles, st, tag, b.cfg, b.tA, b.tB);
@@ -200,7 +203,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   if (prm->solve_prec != H2_PREC_FP64 && prm->solve_prec != H2_PREC_FP32) return H2_ERR_ARG;
   if (prm->gs_sweeps < 0 || prm->gs_sweeps > 64) return H2_ERR_ARG;
   if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
-      prm->gemm_prec != H2_PREC_BF16)
+      prm->gemm_prec != H2_PREC_BF16 && prm->gemm_prec != H2_PREC_BF16X3)
     return H2_ERR_ARG;
   for (int t = 0; t < n_inst; ++t) {
     if (!pts[t] || ns[t] < 1) return H2_ERR_ARG;
@@ -737,7 +740,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     // only in FP32), far couplings, R factors, pair and far scratch; else the
     // FP64 scratch.  FP32 copies of F and P whenever the substitution reads
     // FP32.
-    const bool f32pair = c.prm.gemm_prec == H2_PREC_FP32;
+    const bool f32pair = c.prm.gemm_prec != H2_PREC_FP64;
     if (f32pair) {
       const int64_t ns = std::max<int64_t>(S.soff.back(), 1);
       S.dD32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
@@ -971,6 +974,11 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     if (f32pair) {
       S.g_pair1.f32io = S.g_pair2.f32io = S.g_far1.f32io = S.g_far2.f32io = S.g_diag1.f32io = 1;
       S.g_far3.f32io = S.g_diag2.f32io = 2;
+      // BF16 matrix cores: one term (BF16) or three (BF16X3)
+      const int terms = c.prm.gemm_prec == H2_PREC_BF16X3 ? 3 : c.prm.gemm_prec == H2_PREC_BF16 ? 1 : 0;
+      for (Batch<GemmDesc>* b : {&S.g_pair1, &S.g_pair2, &S.g_far1, &S.g_far2, &S.g_diag1,
+                                 &S.g_far3, &S.g_diag2})
+        b->terms = terms;
     }
     // blocked Cholesky + inverse of the RR blocks (A at TB + k + k m, ld m;
     // L^{-1} at Li, ld r; panel scratch in TA)

@@ -24,6 +24,8 @@ struct Batch {
   int cfg = 0;
   int tA = 0, tB = 0;      // transposes shared by every item of the list
   int f32io = 0;           // GEMM list on FP32 operands: 1 FP32 results, 2 FP64 results
+  int terms = 0;           // FP32-operand list on the BF16 matrix cores: 1 or 3 terms
+                           // (0: FP32 matrix cores)
   void use(int c) { cfg = c; toff = toffs[c]; tiles = tiles_c[c]; }
 };
 

@@ -83,8 +83,9 @@ constexpr int GEMM_BN[GEMM_NCFG] = {64, 64, 128, 64};
 // with one load.
 hipError_t launch_gemm(const GemmDesc* d_desc, const int* d_tile_map, int count,
                        int tiles, hipStream_t st, int tag, int cfg, int tA, int tB);
-// Same work lists in reduced precision (prec = H2_PREC_FP32 or H2_PREC_BF16,
-// FP32 accumulation, FP64 in and out), 64 x 64 tiles.
+// Same work lists on FP32 MFMA (prec = H2_PREC_FP32: operands rounded to FP32,
+// FP32 accumulation, FP64 in and out, 64 x 64 tiles; any other prec runs the
+// FP64 kernel).
 hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int count,
                           int tiles, int prec, hipStream_t st, int tag, int tA, int tB);
 // FP32 operands (pointers in the descriptors hold float arrays), FP32 MFMA
@@ -93,6 +94,12 @@ hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int cou
 hipError_t launch_gemm_f32io(const GemmDesc* d_desc, const int* d_tile_map, int count,
                              int tiles, hipStream_t st, int cfg, int tA, int tB,
                              bool out64 = false);
+// The same FP32-operand work lists on the BF16 matrix cores: each operand
+// element split into BF16 high and low parts; terms = 1 multiplies the high
+// parts only, terms = 3 adds both cross terms (about 17-bit operands); FP32
+// accumulation, results in FP32 (out64 = false) or FP64.
+hipError_t launch_gemm_bf16s(const GemmDesc* d_desc, const int* d_tile_map, int count, int tiles,
+                             hipStream_t st, int cfg, int tA, int tB, bool out64, int terms);
 // Host: the (item, tile) map of a work list for BM x BN tiles.
 inline std::vector<int> gemm_tile_map(const std::vector<GemmDesc>& v, int BM, int BN) {
   std::vector<int> map;

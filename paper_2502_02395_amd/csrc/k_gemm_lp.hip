@@ -1,26 +1,17 @@
-// Batched variable-size GEMM in reduced precision on CDNA4 matrix cores:
-// operands are read in FP64, rounded to FP32 or BF16 on their way into LDS,
-// multiplied by the FP32 or BF16 MFMA with FP32 accumulation, and written back
-// in FP64.  Same work-list format and tile mapping as the FP64 kernel
-// (k_gemm.hip); used for the basis transforms and the Schur update when the
-// handle's gemm_prec asks for it.  Rounding to BF16 is round-to-nearest-even.
+// Batched variable-size GEMM in FP32 on CDNA4 matrix cores for FP64
+// operands: read in FP64, rounded to FP32 on their way into LDS, multiplied by
+// the FP32 MFMA with FP32 accumulation, written back in FP64.  Same work-list
+// format and tile mapping as the FP64 kernel (k_gemm.hip); used for the Schur
+// update under every reduced gemm_prec.
 #include "h2_internal.hpp"
 
 namespace h2 {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
-typedef short s4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int xcd_remap_lp(int b, int nb) {
   const int per = (nb + 7) >> 3;
   return (b & 7) * per + (b >> 3);
-}
-
-__device__ __forceinline__ unsigned short to_bf16(double x) {
-  const float f = (float)x;
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
 }
 
 // Accumulator layout of the 16x16 FP32-output MFMAs (measured on gfx950):
@@ -107,119 +98,27 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const GemmDesc* __restric
       }
 }
 
-// ---------------------------------------------------------------- BF16 MFMA
-// Tiles are stored row-major in LDS (k contiguous) so that each lane fetches
-// its four consecutive k values of one row with a single 8-byte read.
 template <int TAG, int TA, int TB>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(const GemmDesc* __restrict__ descs,
-                                                        const int* __restrict__ tmap, int count,
-                                                        int tiles) {
-  constexpr int TK = 32, KP = TK + 4;
-  const int logical = xcd_remap_lp(blockIdx.x, gridDim.x);
-  if (logical >= tiles) return;
-  const int2 it = reinterpret_cast<const int2*>(tmap)[logical];
-  const int item = it.x;
-  const GemmDesc d = descs[item];
-  const int t = it.y;
-  const int tiles_m = (d.M + 63) / 64;
-  const int m0 = (t % tiles_m) * 64, n0 = (t / tiles_m) * 64;
-  __shared__ __attribute__((aligned(16))) unsigned short As[64][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[64][KP];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  f4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (f4){0.f, 0.f, 0.f, 0.f};
-  unsigned short ra[8], rb[8];
-  const int am = TA ? (tid >> 5) : (tid & 63), ak = TA ? (tid & 31) : (tid >> 6);
-  const int bn = TB ? (tid & 63) : (tid >> 5), bk = TB ? (tid >> 6) : (tid & 31);
-  const int M = d.M, N = d.N, K = d.K;
-  const int64_t lda = d.lda, ldb = d.ldb;
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int gm = m0 + am + (TA ? 8 * q : 0), gk = k0 + ak + (TA ? 0 : 4 * q);
-      ra[q] = to_bf16((gm < M && gk < K) ? (TA ? d.A[gk + gm * lda] : d.A[gm + gk * lda]) : 0.0);
-      const int gn = n0 + bn + (TB ? 0 : 8 * q), gk2 = k0 + bk + (TB ? 4 * q : 0);
-      rb[q] = to_bf16((gn < N && gk2 < K) ? (TB ? d.B[gn + gk2 * ldb] : d.B[gk2 + gn * ldb]) : 0.0);
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      As[am + (TA ? 8 * q : 0)][ak + (TA ? 0 : 4 * q)] = ra[q];
-      Bs[bn + (TB ? 0 : 8 * q)][bk + (TB ? 4 * q : 0)] = rb[q];
-    }
-  };
-  const int nk = (d.K + TK - 1) / TK;
-  if (nk > 0) load(0);
-  for (int kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (kt + 1 < nk) load((kt + 1) * TK);
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 16) {
-      const int c = lane & 15, g = (lane >> 4) * 4;
-      const s4 a0 = *reinterpret_cast<const s4*>(&As[wm + c][kk + g]);
-      const s4 a1 = *reinterpret_cast<const s4*>(&As[wm + 16 + c][kk + g]);
-      const s4 b0 = *reinterpret_cast<const s4*>(&Bs[wn + c][kk + g]);
-      const s4 b1 = *reinterpret_cast<const s4*>(&Bs[wn + 16 + c][kk + g]);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
-    }
-  }
-  const int col = lane & 15;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int gm = m0 + wm + 16 * i + ACC_ROW(e, lane);
-        const int gn = n0 + wn + 16 * j + col;
-        if (gm < d.M && gn < d.N) {
-          double v = d.alpha * (double)acc[i][j][e];
-          if (d.beta != 0.0) v += d.beta * d.C[gm + (int64_t)gn * d.ldc];
-          d.D[gm + (int64_t)gn * d.ldd] = v;
-        }
-      }
-}
-
-template <int P, int TAG, int TA, int TB>
 static void launch_lp(const GemmDesc* d, const int* o, int count, int tiles, hipStream_t st) {
   const int grid = (tiles + 7) & ~7;
-  if (P == H2_PREC_FP32)
-    hipLaunchKernelGGL((gemm_f32_kernel<TAG, TA, TB>), dim3(grid), dim3(256), 0, st, d, o, count, tiles);
-  else
-    hipLaunchKernelGGL((gemm_bf16_kernel<TAG, TA, TB>), dim3(grid), dim3(256), 0, st, d, o, count, tiles);
+  hipLaunchKernelGGL((gemm_f32_kernel<TAG, TA, TB>), dim3(grid), dim3(256), 0, st, d, o, count, tiles);
 }
 
-template <int P, int TAG>
+template <int TAG>
 static void launch_lp_t(const GemmDesc* d, const int* o, int count, int tiles, hipStream_t st,
                         int tA, int tB) {
-  if (!tA && !tB) launch_lp<P, TAG, 0, 0>(d, o, count, tiles, st);
-  else if (!tA && tB) launch_lp<P, TAG, 0, 1>(d, o, count, tiles, st);
-  else if (tA && !tB) launch_lp<P, TAG, 1, 0>(d, o, count, tiles, st);
-  else launch_lp<P, TAG, 1, 1>(d, o, count, tiles, st);
+  if (!tA && !tB) launch_lp<TAG, 0, 0>(d, o, count, tiles, st);
+  else if (!tA && tB) launch_lp<TAG, 0, 1>(d, o, count, tiles, st);
+  else if (tA && !tB) launch_lp<TAG, 1, 0>(d, o, count, tiles, st);
+  else launch_lp<TAG, 1, 1>(d, o, count, tiles, st);
 }
 
 hipError_t launch_gemm_lp(const GemmDesc* d_desc, const int* d_tile_map, int count, int tiles,
                           int prec, hipStream_t st, int tag, int tA, int tB) {
   if (count <= 0 || tiles <= 0) return hipSuccess;
-  if (prec == H2_PREC_FP32) {
-    if (tag == 1) launch_lp_t<H2_PREC_FP32, 1>(d_desc, d_tile_map, count, tiles, st, tA, tB);
-    else launch_lp_t<H2_PREC_FP32, 0>(d_desc, d_tile_map, count, tiles, st, tA, tB);
-  } else if (prec == H2_PREC_BF16) {
-    if (tag == 1) launch_lp_t<H2_PREC_BF16, 1>(d_desc, d_tile_map, count, tiles, st, tA, tB);
-    else launch_lp_t<H2_PREC_BF16, 0>(d_desc, d_tile_map, count, tiles, st, tA, tB);
-  } else {
-    return launch_gemm(d_desc, d_tile_map, count, tiles, st, tag, 0, tA, tB);
-  }
+  if (prec != H2_PREC_FP32) return launch_gemm(d_desc, d_tile_map, count, tiles, st, tag, 0, tA, tB);
+  if (tag == 1) launch_lp_t<1>(d_desc, d_tile_map, count, tiles, st, tA, tB);
+  else launch_lp_t<0>(d_desc, d_tile_map, count, tiles, st, tA, tB);
   return hipGetLastError();
 }
 

@@ -369,7 +369,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
     // all FP64 or all FP32); the matvec reads FP64.  FP32 pair transforms
     // leave the off-diagonal F in FP32 only, so they imply the FP32 reads.
     std::vector<Rebase> rb;
-    if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec == H2_PREC_FP32) {
+    if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec != H2_PREC_FP64) {
       rb.push_back({S.dF, S.poff.back(), S.dF32});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
     }
@@ -440,10 +440,12 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ factor
-// Basis transforms and Schur update in the handle's GEMM precision.
+// Basis transforms and Schur update in the handle's GEMM precision: the
+// FP32-operand lists carry their own kernel choice; the Schur update (FP64
+// operands) runs on FP32 MFMA under every reduced precision.
 static hipError_t run_gemm_p(const Ctx& c, const Batch<GemmDesc>& b, hipStream_t st, int tag = 0) {
   if (c.prm.gemm_prec == H2_PREC_FP64 || b.f32io) return run_gemm(b, st, tag);
-  return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], c.prm.gemm_prec, st, tag, b.tA, b.tB);
+  return launch_gemm_lp(b.d, b.toffs[0], b.count, b.tiles_c[0], H2_PREC_FP32, st, tag, b.tA, b.tB);
 }
 
 // Autotuner: every factor GEMM work list is timed with every tile shape (one
@@ -617,7 +619,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
   }
   HIPCHK(run_gemm(c.r_full, st));
   HIPCHK(done());
-  if (c.prm.solve_prec == H2_PREC_FP32 && c.prm.gemm_prec != H2_PREC_FP32) {
+  if (c.prm.solve_prec == H2_PREC_FP32 && c.prm.gemm_prec == H2_PREC_FP64) {
     HIPCHK(mark(FP_F32));
     for (auto& S : c.steps) {
       HIPCHK(launch_cvt_f32(S.dF, S.dF32, S.poff.back(), st));

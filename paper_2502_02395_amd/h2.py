@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libh2.so")
 
 OK, ERR_ARG, ERR_ALLOC, ERR_HIP, ERR_NOT_SPD, ERR_STATE, ERR_NOCONV, ERR_UNSUPPORTED = range(8)
-PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16, PREC_BF16X3 = 0, 1, 2, 3
 SYMBOLS = ["h2_build", "h2_build_batched", "h2_build_fixed", "h2_factor", "h2_solve",
            "h2_solve_noalloc", "h2_matvec",
            "h2_stats", "h2_get_counts", "h2_get_structure", "h2_get_pairs", "h2_get_basis",

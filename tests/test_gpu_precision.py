@@ -1,7 +1,7 @@
-"""Precision split: basis-transform, Schur-update and near-pair GEMMs in FP32
-or BF16 (FP32 accumulation), with the Cholesky factors, the root and the H^2
-matvec in FP64, against the FP64 oracle on the same H^2 matrix (the library
-gets the oracle's skeletons).
+"""Precision split: basis-transform, Schur-update and near-pair GEMMs in FP32,
+BF16 or split BF16 (FP32 accumulation), with the Cholesky factors, the root
+and the H^2 matvec in FP64, against the FP64 oracle on the same H^2 matrix
+(the library gets the oracle's skeletons).
 
 Unrefined bound (FP32), written before it was run: every transformed block
 is a product of two GEMMs over at most m_max terms whose inputs are rounded
@@ -14,6 +14,10 @@ dM with |dM| / |M| <= 8 L (u_p + m_max u_32), and
 |x_p - x_o| / |x_o| <= kappa(A~) |dM| / |M| to first order (M is within the
 dropped fill-ins of A~).  For BF16 inputs (u_p = 2^-8) this bound exceeds 1:
 only the refined result is claimed, and the unrefined error is reported.
+Split BF16 (three BF16 products per FP32 product, x = h + l with h = bf16(x),
+l = bf16(x - h)): |x - h - l| <= 2^-9 |x - h| <= 2^-18 |x|, and the dropped
+l_a l_b is below 2^-18 |a b|, so each product a b is formed to within
+3 2^-18 |a b| < 2^-16 |a b| before the FP32 sum: u_p = 2^-16.
 
 Refined bound: PCG against the FP64 H^2 operator stops at a relative residual
 res against the library's A~; with the oracle's PCG stopping at res_o against
@@ -29,7 +33,7 @@ from oracle import construct, h2matrix, ulv
 pytestmark = pytest.mark.gpu
 
 U32 = 2.0 ** -24
-U_IN = {1: 2.0 ** -24, 2: 2.0 ** -8}
+U_IN = {1: 2.0 ** -24, 2: 2.0 ** -8, 3: 2.0 ** -16}
 
 
 def _same_h2(p):
@@ -50,12 +54,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_precision_split_against_oracle(lib, prec):
     import torch
     # the mixed-precision configuration's kernel and RHS count at an oracle size
     p = W.yukawa_cube(n=4096, leaf=128, eps=1e-8, nrhs=4, s=256)
-    name = {1: "fp32", 2: "bf16"}[prec]
+    name = {1: "fp32", 2: "bf16", 3: "bf16x3"}[prec]
     print(f"[precision {name}] n={p.n} leaf={p.leaf} eps={p.eps}", flush=True)
     h2f, ranks, pos = _same_h2(p)
     fac = ulv.factor(h2f)
