@@ -8,8 +8,9 @@ target path (rank-predicted basis buffers; the near-pair, diagonal and
 far-coupling transforms on FP32 copies of their operands in HBM, multiplied on
 the BF16 matrix cores with each operand split into BF16 high and low parts
 (three products per product, FP32 accumulation); the Schur update on FP32
-MFMA; the substitution reading FP32 copies of the factors; Cholesky factors,
-root, H^2 matvec and refinement in FP64) next to the plain FP64 path and
+MFMA; the substitution reading BF16 copies of the factors, with FP64
+products and sums; Cholesky factors, root, H^2 matvec and refinement in
+FP64) next to the plain FP64 path and
 prints one JSON line with both.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--path target|plain|custom]
@@ -205,8 +206,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
                       "traffic": None, "launches": st["pair_launches"] * K,
                       "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1),
                       "total_s": t_pair})
-    for q, kname in ((0, "gchunk_kernel<f64>"), (1, "gchunk_kernel<f32>"),
-                     (2, "greduce_kernel")):
+    copies = "gchunk_kernel<bf16>" if sprec == h2.PREC_BF16 else "gchunk_kernel<f32>"
+    for q, kname in ((0, "gchunk_kernel<f64>"), (1, copies), (2, "greduce_kernel")):
         if n_g[q] == 0:
             continue
         gbs = b_g[q] / max(t_g[q], 1e-30) / 1e9
@@ -237,13 +238,13 @@ def main():
                     help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
                     help="target: rank-predicted buffers, split-BF16 transform GEMMs on FP32 "
-                         "copies and FP32 copies for the substitution, timed next to the "
+                         "copies and BF16 copies for the substitution, timed next to the "
                          "plain FP64 path "
                          "(default); plain: the FP64 path "
                          "only; custom: --prec / --solve-prec / --rank-model as given")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="custom path: precision of the basis-transform and Schur-update GEMMs")
-    ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32"],
+    ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="custom path: precision of the factor copies the substitution reads "
                          "(the H^2 matvec, the refinement and all arithmetic stay FP64)")
     ap.add_argument("--rank-model", action="store_true",
@@ -293,8 +294,8 @@ def main():
     else:
         plain = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain fp64")
         model = train_rank_model(a, h2) if a.kernel != "gaussian_batch" else None
-        setting = ("bf16x3", "fp32", model is not None)
-        r = run_path(a, h2, h2.PREC_BF16X3, h2.PREC_FP32, model, "target")
+        setting = ("bf16x3", "bf16", model is not None)
+        r = run_path(a, h2, h2.PREC_BF16X3, h2.PREC_BF16, model, "target")
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20:
         for d in r["cands"]:  # traffic was measured on this workload and path
             d["traffic"] = measured_traffic(d["kernel"])

@@ -110,11 +110,14 @@ typedef struct {
   double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
   int32_t timing;         /* 1 = time factor phases and solve gathers (events)   */
   int32_t no_autotune;    /* 1 = skip the tile-shape autotuner (64x64 tiles)     */
-  int32_t solve_prec;     /* h2_prec (FP64 or FP32) in which the substitution
-                             reads the factors: FP32 copies of the transformed
-                             near blocks and bases are made at the end of
-                             h2_factor; arithmetic, the root, the H^2 matvec
-                             and the refinement stay FP64                       */
+  int32_t solve_prec;     /* h2_prec (FP64, FP32 or BF16) in which the
+                             substitution reads the factors: FP32 or BF16
+                             copies of the transformed near blocks and bases
+                             are made at the end of h2_factor (with a reduced
+                             gemm_prec, FP32 copies exist anyway); products and
+                             sums, the root, the H^2 matvec and the refinement
+                             stay FP64.  The substitution is then a fixed
+                             symmetric preconditioner of PCG                  */
   int32_t gs_sweeps;      /* pre-factorization of h2_build (Section 3.5): 0 =
                              exact Cholesky solve with the near-sample block
                              A_cc; n > 0 = n Gauss-Seidel sweeps (from zero)

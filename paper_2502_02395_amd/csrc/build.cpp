@@ -200,7 +200,9 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   if (prm->dim != 2 && prm->dim != 3) return H2_ERR_ARG;
   if (prm->leaf < 2 || !(prm->eps >= 0.0) || !(prm->eta >= 0.0)) return H2_ERR_ARG;
   if (prm->s_far < -1 || prm->s_near < -1 || prm->max_rank < 0) return H2_ERR_ARG;
-  if (prm->solve_prec != H2_PREC_FP64 && prm->solve_prec != H2_PREC_FP32) return H2_ERR_ARG;
+  if (prm->solve_prec != H2_PREC_FP64 && prm->solve_prec != H2_PREC_FP32 &&
+      prm->solve_prec != H2_PREC_BF16)
+    return H2_ERR_ARG;
   if (prm->gs_sweeps < 0 || prm->gs_sweeps > 64) return H2_ERR_ARG;
   if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
       prm->gemm_prec != H2_PREC_BF16 && prm->gemm_prec != H2_PREC_BF16X3)
@@ -761,6 +763,11 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
       S.dP32 = c.alloc<float>(std::max<int64_t>(q, 1));
       ALLOCHK(S.dF32); ALLOCHK(S.dP32);
+    }
+    if (c.prm.solve_prec == H2_PREC_BF16) {
+      S.dF16 = c.alloc<unsigned short>(std::max<int64_t>(S.poff[np], 1));
+      S.dP16 = c.alloc<unsigned short>(std::max<int64_t>(q, 1));
+      ALLOCHK(S.dF16); ALLOCHK(S.dP16);
     }
   }
   // index of (instance, level-local box) in each step

@@ -15,12 +15,16 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
   if (seg < 0 || seg % 16 != 0) return false;
   const int W = seg > 0 ? seg : INT_MAX;
   out = GatherPlan();
-  out.f32 = !rb.empty();
-  const double esz = out.f32 ? 4.0 : 8.0;
-  // the FP32 copy of a block pointer, or nullptr
-  auto to32 = [&](const double* p) -> const float* {
+  out.esz = rb.empty() ? 8 : rb[0].esz;
+  for (const Rebase& r : rb)
+    if (r.esz != out.esz || (r.esz != 4 && r.esz != 2)) return false;
+  const bool copy = out.esz < 8;
+  const double esz = out.esz;
+  // the copy of a block pointer, or nullptr
+  auto to_copy = [&](const double* p) -> const char* {
     for (const Rebase& r : rb)
-      if (p >= r.base && p < r.base + r.n) return r.base32 + (p - r.base);
+      if (p >= r.base && p < r.base + r.n)
+        return static_cast<const char*>(r.copy) + (p - r.base) * r.esz;
     return nullptr;
   };
   struct Item {
@@ -72,12 +76,12 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
       item_of_t[q] = hit;
     }
   }
-  // Chunks of 64 rows, 128 for FP32 blocks (one or two rows per lane), or
-  // wide: the rows split evenly into the fewest chunks of at most 64 x
-  // GATHER_WIDE_RPL32 / GATHER_WIDE_RPL64 rows.  Boundaries depend only on the block's size, so
+  // Chunks of 64 rows, 128 for FP32 or BF16 copies (one or two rows per
+  // lane), or wide: the rows split evenly into the fewest chunks of at most
+  // 64 x GATHER_WIDE_RPL32 / GATHER_WIDE_RPL64 rows.  Boundaries depend only on the block's size, so
   // results are reproducible across handles and runs.
-  const int crows = wide ? 64 * (out.f32 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64)
-                         : out.f32 ? 128 : 64;
+  const int crows = wide ? 64 * (copy ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64)
+                         : copy ? 128 : 64;
   auto chunk_starts = [crows, wide](const Item& it) {
     std::vector<int> r;
     if (wide) {
@@ -102,15 +106,16 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
     const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
     const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
-    const float* M32 = out.f32 ? to32(it.M) : nullptr;
-    if (out.f32 && !M32) return false;
+    const char* Mc = copy ? to_copy(it.M) : nullptr;
+    if (copy && !Mc) return false;
     for (int c = 0; c < nck; ++c) {
       const int r0 = rs[c];
       for (int sg = 0; sg < nseg; ++sg) {
         const int c0 = sg * std::min(W, it.mc), c1 = std::min(it.mc, c0 + W);
         const int64_t e0 = r0 + (int64_t)c0 * it.ld;
         GChunk ch;
-        ch.M = out.f32 ? static_cast<const void*>(M32 + e0) : static_cast<const void*>(it.M + e0);
+        ch.M = copy ? static_cast<const void*>(Mc + e0 * out.esz)
+                    : static_cast<const void*>(it.M + e0);
         ch.xd = nd ? nd->x + c0 : nullptr;
         ch.xt = nt ? nt->x + r0 : nullptr;
         ch.ld = it.ld;

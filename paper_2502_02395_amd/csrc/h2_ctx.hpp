@@ -43,7 +43,8 @@ struct GList {
   GSet n;                                  // chunks of 64 rows (128 for FP32 copies)
   GSet w;                                  // wide chunks (up to 4 rows per lane) for
                                            // nrhs <= GATHER_WIDE_NR
-  bool f32 = false;                        // blocks read from FP32 copies
+  int esz = 8;                             // bytes per block element: 8, or 4 / 2
+                                           // for FP32 / BF16 copies
   bool has_w = false;
   const GSet& pick(int nrhs) const { return has_w && nrhs <= GATHER_WIDE_NR ? w : n; }
 };
@@ -84,6 +85,7 @@ struct Step {
   double* dW = nullptr;                    // QR workspace at qoff
   double* dTau = nullptr;                  // Householder scalars at koff
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
+  unsigned short *dF16 = nullptr, *dP16 = nullptr;  // BF16 copies (solve_prec BF16)
   float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)
   float *dR32 = nullptr, *dS32 = nullptr, *dT332 = nullptr;  // FP32 R, far couplings, scratch
   Batch<ConvDesc> cv_fii;                  // F_ii -> FP32 (diagonal blocks)
@@ -192,7 +194,7 @@ struct Ctx {
   size_t gev_used = 0;
   bool gtime = false;
   std::vector<double> gbytes;              // per timed gather: chunks, reduction
-  std::vector<int> gkind;                  // per timed gather: 0 FP64 blocks, 1 FP32
+  std::vector<int> gkind;                  // per timed gather: 0 FP64 blocks, 1 copies
   double* dPart = nullptr;                 // gather partial products
   int64_t part_len = 0;                    // longest list's partials, one rhs
   int part_nrhs = 0;                       // right-hand sides dPart holds

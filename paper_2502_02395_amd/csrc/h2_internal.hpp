@@ -182,8 +182,8 @@ hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 // cols x rows).  base == NULL means zero; base may alias y.  Lists are given
 // per box (GatherBox with neighbour ranges into a GatherNbr array) and are
 // planned (plan_gather) into
-//   * chunks: one wave per 64-row chunk (128 rows for FP32 copies, two rows
-//     per lane) and, where the plan asks for segments, per seg-column
+//   * chunks: one wave per 64-row chunk (128 rows for FP32 or BF16 copies,
+//     two rows per lane) and, where the plan asks for segments, per seg-column
 //     segment of each stored block M.  The wave reads its part of M once and
 //     forms the direct product M x_d for those rows and/or the transposed
 //     product M^T x_t over those rows; a block that is used directly by one
@@ -211,11 +211,11 @@ struct GatherNbr {
   int ldB, ldx, cols;       // cols: summation length
 };
 struct GChunk {
-  const void* M;            // first row of the chunk (column-major, ld; FP64 or FP32)
+  const void* M;            // first row of the chunk (column-major, ld; FP64, FP32 or BF16)
   const double* xd;         // direct x: mc entries per rhs (ld ldxd), or NULL
   const double* xt;         // trans x: this chunk's nr entries per rhs (ld ldxt), or NULL
   int ld, ldxd, ldxt;
-  int nr, mc;               // chunk rows (<= 64, <= 128 for FP32), columns of M
+  int nr, mc;               // chunk rows (<= 64, <= 128 for copies), columns of M
   int dlen, drow;           // direct slot length and this chunk's first row in it
   int tlen, tcol;           // trans slot length and this chunk's first column in it
   int rpl;                  // rows per lane: nr <= 64 rpl
@@ -228,7 +228,6 @@ struct GRed {
   double alpha;
   int s0, s1;               // slot range in the offset array
 };
-// A range of FP64 blocks with an FP32 copy at base32 (same offsets).
 // Column segments of the gathers at heights >= GATHER_SEG_FROM above the
 // leaves (measured: below that the lists have enough waves and the extra
 // direct slots cost more than the shorter waves gain).
@@ -242,8 +241,8 @@ constexpr int GATHER_SEG_THIN_FROM = 3;
 constexpr int GATHER_SEG_TOP = 32;       // the top levels: a few blocks each
 constexpr int GATHER_SEG_TOP_FROM = 8;
 // Wide chunks: a block's rows split evenly into chunks of at most 64 x RPL
-// rows (one wave each, up to RPL rows per lane: 4 for FP32 copies, 2 for
-// FP64 blocks), so that e.g. an FP32 block of 150 rows takes one wave with
+// rows (one wave each, up to RPL rows per lane: 4 for FP32 or BF16 copies,
+// 2 for FP64 blocks), so that e.g. an FP32 block of 150 rows takes one wave with
 // most lanes busy instead of two with most lanes of the second idle; used
 // for up to GATHER_WIDE_NR right-hand sides (the per-lane accumulators grow
 // with rows x rhs).
@@ -255,13 +254,16 @@ constexpr int GATHER_WIDE_RPL64 = 2;
 constexpr int GATHER_WIDE_NR = 2;
 constexpr int GATHER_WIDE_FROM = 1;
 constexpr int GATHER_WIDE_TO = 6;
+// A range of FP64 blocks with a reduced-precision copy (same element
+// offsets): esz 4 = FP32, esz 2 = BF16.
 struct Rebase {
   const double* base;
   int64_t n;
-  const float* base32;
+  const void* copy;
+  int esz;
 };
 struct GatherPlan {
-  bool f32 = false;           // blocks read from FP32 copies
+  int esz = 8;                // bytes per block element: 8 FP64, 4 FP32, 2 BF16 copies
   std::vector<GChunk> chunks;
   std::vector<GRed> reds;
   std::vector<int64_t> offs;  // slot offsets, grouped per box
@@ -273,16 +275,21 @@ struct GatherPlan {
   double bytes_red = 0.0;
 };
 // rb non-empty: every block must lie in one of its ranges and is read from
-// the FP32 copy (returns false otherwise).  seg > 0: column segments of at
+// that range's copy (all ranges of one plan share esz; returns false
+// otherwise).  seg > 0: column segments of at
 // most seg columns (a multiple of 16).  wide: wide chunks (see above).
 bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
                  GatherPlan& out, const std::vector<Rebase>& rb = {}, int seg = 0,
                  bool wide = false);
 // wide: the chunks come from a wide plan (nrhs <= GATHER_WIDE_NR required).
-hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
+// esz: bytes per block element (8, 4 or 2).
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
                           hipStream_t st, bool wide = false);
 // FP32 copy of n doubles.
 hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st);
+// BF16 copy (round to nearest even) of n doubles (esz_src 8) or floats (4).
+hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, int64_t n,
+                           hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 

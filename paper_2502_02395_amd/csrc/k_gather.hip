@@ -53,10 +53,16 @@ __device__ __forceinline__ double bcast(double v, int l) {
 }
 
 // Rows per lane: a chunk is 64 * RPL rows, lane l owns rows l + 64 t.  FP32
-// blocks take two rows per lane (the same bytes per load as one FP64 row, and
-// the transposed sums add both rows before the cross-lane reduction).
+// and BF16 copies take two rows per lane (the transposed sums add both rows
+// before the cross-lane reduction).  BF16 elements are held as their 16 bits
+// (unsigned short) and widened by a shift.
 template <typename T>
-constexpr int rows_per_lane() { return sizeof(T) == 4 ? 2 : 1; }
+constexpr int rows_per_lane() { return sizeof(T) < 8 ? 2 : 1; }
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return (double)v; }
+__device__ __forceinline__ double widen(unsigned short v) {
+  return (double)__uint_as_float((unsigned)v << 16);
+}
 
 // One batch of BW columns (8 or 16) starting at column sb (BW loads per row in
 // flight); xv[c] holds x_d of the current 64 columns, one per lane, and bo is
@@ -85,7 +91,7 @@ __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t
         if (FULL || sb + u < mc) {
           const double xu = bcast(xv[c], bo + u);
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) acc[t][c] += (double)bv[t][u] * xu;
+          for (int t = 0; t < RPL; ++t) acc[t][c] += widen(bv[t][u]) * xu;
         }
     }
   }
@@ -100,7 +106,7 @@ __device__ __forceinline__ void gchunk_cols(const gptr_t<T> (&col)[RPL], int64_t
         for (int u = 0; u < 8; ++u) {
           double s = 0.0;
 #pragma unroll
-          for (int t = 0; t < RPL; ++t) s += (double)bv[t][8 * h + u] * xt[t][c];
+          for (int t = 0; t < RPL; ++t) s += widen(bv[t][8 * h + u]) * xt[t][c];
           v[u] = s;
         }
         const double q = reduce8(v, lane);
@@ -227,7 +233,7 @@ static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hip
                              bool wide) {
   const dim3 grid((nch + 3) / 4), blk(256);
   constexpr int RN = rows_per_lane<T>();
-  constexpr int RW = sizeof(T) == 4 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64;
+  constexpr int RW = sizeof(T) < 8 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64;
   static_assert(GATHER_WIDE_NR == 2, "wide instantiations below");
   if (wide) {
     if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T, RW, 8>), grid, blk, 0, st, ch, nch, P, nrhs);
@@ -241,13 +247,15 @@ static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hip
   else hipLaunchKernelGGL((gchunk_kernel<16, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
 }
 
-hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, bool f32,
+hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
                           hipStream_t st, bool wide) {
   if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
   if (wide && nrhs > GATHER_WIDE_NR) return hipErrorInvalidValue;
-  if (f32) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide);
-  else launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);
+  if (esz == 8) launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);
+  else if (esz == 4) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide);
+  else if (esz == 2) launch_gchunks_t<unsigned short>(ch, nch, P, nrhs, st, wide);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

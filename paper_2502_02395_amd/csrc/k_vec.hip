@@ -89,6 +89,40 @@ hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t 
   return hipGetLastError();
 }
 
+// BF16 copies (round to nearest even through FP32), same access pattern.
+template <typename TS>
+__global__ __launch_bounds__(256) void cvt_bf16_kernel(const TS* __restrict__ src,
+                                                       unsigned short* __restrict__ dst,
+                                                       int64_t n) {
+  for (int64_t i0 = (int64_t)blockIdx.x * 1024 + threadIdx.x; i0 < n;
+       i0 += (int64_t)gridDim.x * 1024) {
+    TS v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i0 + 256 * u < n ? src[i0 + 256 * u] : TS(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i0 + 256 * u < n) {
+        const __bf16 h = (__bf16)(float)v[u];
+        dst[i0 + 256 * u] = __builtin_bit_cast(unsigned short, h);
+      }
+  }
+}
+
+hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, int64_t n,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 1023) / 1024, 65536);
+  if (esz_src == 8)
+    hipLaunchKernelGGL(cvt_bf16_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const double*>(src), dst, n);
+  else if (esz_src == 4)
+    hipLaunchKernelGGL(cvt_bf16_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const float*>(src), dst, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 __global__ void gather_rows_kernel(const int64_t* idx, int64_t n, int nrhs, const double* src,
                                    int64_t lds, double* dst, int64_t ldd) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n * nrhs;

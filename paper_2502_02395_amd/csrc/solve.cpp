@@ -67,7 +67,7 @@ static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
   auto up_set = [&](GSet& S, bool wide) {
     GatherPlan p;
     if (!plan_gather(B, Nv, p, rb, seg, wide)) return false;
-    L.f32 = p.f32;
+    L.esz = p.esz;
     S.max_rows = p.max_rows;
     S.plen = p.plen;
     S.bytes_ch_mat = p.bytes_chunks_mat;
@@ -105,7 +105,7 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.f32, st, wide)) != hipSuccess)
+  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, wide)) != hipSuccess)
     return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
   if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st)) !=
@@ -116,7 +116,7 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
     c.gev_used += 3;
     c.gbytes.push_back(S.bytes_ch_mat + S.bytes_ch_vec * nrhs);
     c.gbytes.push_back(S.bytes_rd * nrhs);
-    c.gkind.push_back(L.f32 ? 1 : 0);
+    c.gkind.push_back(L.esz < 8 ? 1 : 0);
   }
   return hipSuccess;
 }
@@ -365,13 +365,17 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         td.push_back(gd(U, m, 0, S.v_yh + S.koff[b], kld, 0, dst, cld, dst, cld, m, NR, k, 1.0, 1.0));
       }
     }
-    // the substitution may read FP32 copies of F and P (a gather list is
-    // all FP64 or all FP32); the matvec reads FP64.  FP32 pair transforms
-    // leave the off-diagonal F in FP32 only, so they imply the FP32 reads.
+    // the substitution may read FP32 or BF16 copies of F and P (a gather
+    // list reads one element type); the matvec reads FP64.  Reduced-precision
+    // pair transforms leave the off-diagonal F in FP32 only, so they imply at
+    // least the FP32 reads.
     std::vector<Rebase> rb;
-    if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec != H2_PREC_FP64) {
-      rb.push_back({S.dF, S.poff.back(), S.dF32});
-      rb.push_back({S.dP, S.qoff[S.nbox], S.dP32});
+    if (c.prm.solve_prec == H2_PREC_BF16) {
+      rb.push_back({S.dF, S.poff.back(), S.dF16, 2});
+      rb.push_back({S.dP, S.qoff[S.nbox], S.dP16, 2});
+    } else if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec != H2_PREC_FP64) {
+      rb.push_back({S.dF, S.poff.back(), S.dF32, 4});
+      rb.push_back({S.dP, S.qoff[S.nbox], S.dP32, 4});
     }
     const int sg = h >= GATHER_SEG_TOP_FROM ? GATHER_SEG_TOP
                  : h >= GATHER_SEG_FROM     ? GATHER_SEG
@@ -624,6 +628,18 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     for (auto& S : c.steps) {
       HIPCHK(launch_cvt_f32(S.dF, S.dF32, S.poff.back(), st));
       HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
+    }
+    HIPCHK(done());
+  }
+  if (c.prm.solve_prec == H2_PREC_BF16) {
+    // BF16 copies for the substitution: from the FP32 transforms' results
+    // (F_ii converted to FP32 above) or from the FP64 factors
+    HIPCHK(mark(FP_F32));
+    const bool from32 = c.prm.gemm_prec != H2_PREC_FP64;
+    for (auto& S : c.steps) {
+      if (from32) HIPCHK(launch_cvt_bf16(S.dF32, 4, S.dF16, S.poff.back(), st));
+      else HIPCHK(launch_cvt_bf16(S.dF, 8, S.dF16, S.poff.back(), st));
+      HIPCHK(launch_cvt_bf16(S.dP, 8, S.dP16, S.qoff[S.nbox], st));
     }
     HIPCHK(done());
   }

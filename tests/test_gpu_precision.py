@@ -107,10 +107,11 @@ def test_precision_split_against_oracle(lib, prec):
 
 
 def test_fp32_substitution_copies_against_oracle(lib):
-    """FP64 transforms with FP32 copies of the factors for the substitution: a
-    fixed symmetric preconditioner, so PCG against the FP64 H^2 operator
-    reaches the oracle's PCG solution to 2 kappa(A~) max(res, res_o) and needs
-    at most two more iterations than with the FP64 factors."""
+    """FP64 transforms with FP32 or BF16 copies of the factors for the
+    substitution: a fixed symmetric preconditioner, so PCG against the FP64
+    H^2 operator reaches the oracle's PCG solution to 2 kappa(A~)
+    max(res, res_o); with FP32 copies it needs at most two more iterations
+    than with the FP64 factors (BF16 copies: reported)."""
     import torch
     p = W.yukawa_cube(n=4096, leaf=128, eps=1e-8, nrhs=4, s=256)
     h2f, ranks, pos = _same_h2(p)
@@ -122,7 +123,7 @@ def test_fp32_substitution_copies_against_oracle(lib):
     res_o = np.linalg.norm(b - At @ xp, axis=0) / np.linalg.norm(b, axis=0)
     bt = torch.from_numpy(b).cuda()
     out = {}
-    for sp in (lib.PREC_FP64, lib.PREC_FP32):
+    for sp in (lib.PREC_FP64, lib.PREC_FP32, lib.PREC_BF16):
         H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
                             s_far=p.s_far, s_near=p.s_near, solve_prec=sp, ir_max_iter=100,
                             ir_tol=1e-10, use_pcg=True)
@@ -137,3 +138,32 @@ def test_fp32_substitution_copies_against_oracle(lib):
         assert res.max() <= 1.1e-10
         assert _rel(x, xp) <= 2 * kappa * max(res.max(), res_o.max())
     assert out[lib.PREC_FP32][1] <= out[lib.PREC_FP64][1] + 2
+
+
+def test_bf16_substitution_with_split_bf16_transforms(lib):
+    """The fastest combination: split-BF16 transforms and BF16 substitution
+    copies, PCG to 1e-10 against the FP64 H^2 operator on the oracle's H^2
+    matrix (Yukawa, 4 right-hand sides): the refined bound of the split
+    test, 2 kappa(A~) max(res, res_o)."""
+    import torch
+    p = W.yukawa_cube(n=4096, leaf=128, eps=1e-8, nrhs=4, s=256)
+    h2f, ranks, pos = _same_h2(p)
+    fac = ulv.factor(h2f)
+    b = p.b()
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    xp, its = ulv.pcg(fac, b, 1e-10, 100)
+    res_o = np.linalg.norm(b - At @ xp, axis=0) / np.linalg.norm(b, axis=0)
+    H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                        s_far=p.s_far, s_near=p.s_near, gemm_prec=lib.PREC_BF16X3,
+                        solve_prec=lib.PREC_BF16, ir_max_iter=100, ir_tol=1e-10, use_pcg=True)
+    H.factor()
+    x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    st = H.stats()
+    H.close()
+    res = np.linalg.norm(b - At @ x, axis=0) / np.linalg.norm(b, axis=0)
+    print(f"[bf16x3 + bf16 copies] iterations {st['ir_iters']} (oracle {max(its)}), residual "
+          f"{res.max():.2e}, x vs oracle PCG {_rel(x, xp):.2e}", flush=True)
+    assert st["ir_residual"] <= 1e-10
+    assert res.max() <= 1.1e-10
+    assert _rel(x, xp) <= 2 * kappa * max(res.max(), res_o.max())
