@@ -67,6 +67,66 @@ def measured_traffic(kernel: str):
     return m["bytes_per_launch"] if h.hexdigest() == m["sha256"] else None
 
 
+PHASES = ["basis_qr", "diag_transform", "rr_cholesky_inverse", "v_schur", "near_pair_transform",
+          "far_coupling", "merge", "root", "solve_copies"]
+
+
+def factor_roofline(st: dict, t_phase: list, t_factor: float, prec: int) -> dict:
+    """Precision-weighted roofline of the factorization: the time each phase's
+    canonical flops would take at the dense peak of the matrix instruction
+    that runs them (FP64 78.6 TF; FP32 157.3 TF; BF16 2500 TF, a third of it
+    for split BF16, which issues three products per product), summed over the
+    phases, divided by the measured factor time; per phase the same ratio."""
+    f64, f32 = FP64_PEAK_TFLOPS * 1e12, 157.3e12
+    tr = {0: f64, 1: f32, 2: 2500e12, 3: 2500e12 / 3}[prec]
+    schur = f64 if prec == 0 else f32
+    peak = [f64, tr, f64, None, tr, tr, None, f64, None]
+    total = 0.0
+    phases = {}
+    for q, name in enumerate(PHASES):
+        fl = st["flops_factor_phase"][q]
+        if fl <= 0:
+            continue
+        if q == 3:  # V and L(s) in FP64, the Schur update on the reduced GEMMs
+            ideal = (fl - st["flops_schur"]) / f64 + st["flops_schur"] / schur
+        else:
+            ideal = fl / peak[q]
+        total += ideal
+        t = t_phase[q]
+        phases[name] = {"gflop": fl / 1e9, "s": t,
+                        "tflops": fl / t / 1e12 if t > 0 else None,
+                        "frac": ideal / t if t > 0 else None}
+    return {"bound": "mfma", "ideal_s": total, "measured_s": t_factor,
+            "frac": total / t_factor if t_factor > 0 else None, "phases": phases}
+
+
+def matern_status(h2) -> dict:
+    """The rank-predictor configuration's kernel (Matern-3/2, l = 0.2, 1e-4
+    nugget, N = 2^20, leaf 256, eps 1e-6, 512-point samples) built and
+    factored on the FP64 path: the status of each call, and where a Cholesky
+    breakdown happened."""
+    import ctypes
+    import torch
+    import workloads as W
+    p = W.matern_cube(n=1 << 20, leaf=256, eps=1e-6, s=512)
+    out = {"workload": "matern_cube", "n": p.n, "leaf": p.leaf, "eps": p.eps, "s": 512,
+           "kernel": "matern32 l=0.2 nugget=1e-4"}
+    try:
+        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                     s_near=p.s_near)
+    except h2.H2Error as e:
+        out.update({"stage": "build", "status": h2._status_str(e.status), "where": e.where})
+        return out
+    s = h2.load().h2_factor(H._h, h2._stream(None))
+    st = H.stats()
+    out.update({"stage": "factor", "status": h2._status_str(s),
+                "where": {"fail_level": st["fail_level"], "fail_box": st["fail_box"]}
+                if s == h2.ERR_NOT_SPD else None})
+    H.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def workload(n: int, kernel: str, eps: float, leaf: int, s: int):
     import workloads as W
     if kernel == "gaussian_batch":
@@ -189,6 +249,7 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     dt = time.perf_counter() - t0
     st = H.stats()
     H.close()
+    torch.cuda.empty_cache()
     flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
     # Kernels of the timed steps with their work per launch over their average
     # launch time (HIP events on the launch stream), largest total time first:
@@ -221,10 +282,15 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
         "value": flops_step * K / dt / 1e12, "ms_per_step": 1e3 * dt / K, "n_total": n_total,
         "factor_s": t_fac / K, "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
         "build_s": t_build, "stats": st, "cands": cands,
-        "factor_phase_s": dict(zip(["basis_qr", "diag_transform", "rr_cholesky_inverse",
-                                    "v_schur", "near_pair_transform", "far_coupling", "merge",
-                                    "root", "solve_copies_fp32"],
-                                   [round(x / K, 5) for x in t_phase])),
+        "factor_phase_s": dict(zip(PHASES, [round(x / K, 5) for x in t_phase])),
+        "factor_roofline": factor_roofline(st, [x / K for x in t_phase], t_fac / K, prec),
+        # the solve's gathers: algorithmic bytes (every stored block and
+        # vector slice once per pass) over the whole solve's time
+        "solve_roofline": {"bound": "hbm", "gather_bytes": sum(b_g) / K,
+                           "s": t_sol / K,
+                           "achieved": sum(b_g) / max(t_sol, 1e-30) / 1e9,
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": sum(b_g) / max(t_sol, 1e-30) / 1e9 / HBM_PEAK_GBS},
     }
 
 
@@ -261,6 +327,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-Gaussian timing and the Matern status run")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (the reference for "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -321,6 +389,7 @@ def main():
                    "root_n": st["root_n"], "max_rank": st["max_rank_seen"],
                    "near_pairs": st["near_pairs"]},
         "factor_s": r["factor_s"], "factor_phase_s": r["factor_phase_s"],
+        "factor_roofline": r["factor_roofline"], "solve_roofline": r["solve_roofline"],
         "solve_s": r["solve_s"], "ir_iters": r["ir_iters"], "residual": r["residual"],
         "build_s": r["build_s"], "flops_factor": st["flops_factor"],
         "flops_solve": st["flops_solve"],
@@ -334,6 +403,34 @@ def main():
                              "basis_bytes": plain["stats"]["bytes_basis"],
                              "roofline": plain["cands"][0] if plain["cands"] else None}
         out["speedup_vs_plain_fp64"] = plain["ms_per_step"] / r["ms_per_step"]
+    if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20 and not a.no_extras:
+        # the batched configuration (64 independent 2-D Gaussian systems, one
+        # handle, factorization captured in a hipGraph; FP64 transforms: these
+        # covariance matrices break down under FP32 ones) and the status of
+        # the Matern configuration, beside the headline
+        import copy
+        import torch
+        b = copy.copy(a)
+        b.kernel, b.leaf, b.eps, b.s, b.s_near, b.graph = "gaussian_batch", 128, 1e-9, 512, 512, True
+        b.steps, b.warmup = min(a.steps, 10), 1
+        print("[bench] batched Gaussian instances", file=sys.stderr, flush=True)
+        try:
+            g = run_path(b, h2, h2.PREC_FP64, h2.PREC_FP64, None, "batched")
+            out["batched_gaussian"] = {
+                "instances": 64, "n_total": g["n_total"], "leaf": 128, "eps": 1e-9, "s": 512,
+                "gemm_prec": "fp64", "solve_prec": "fp64", "graph": True, "steps": b.steps,
+                "value": g["value"], "unit": "TFLOP/s", "ms_per_step": g["ms_per_step"],
+                "factor_s": g["factor_s"], "solve_s": g["solve_s"], "ir_iters": g["ir_iters"],
+                "residual": g["residual"]}
+        except h2.H2Error as e:
+            out["batched_gaussian"] = {"instances": 64, "status": str(e)}
+        torch.cuda.empty_cache()
+        print("[bench] Matern configuration status", file=sys.stderr, flush=True)
+        try:
+            out["matern_status"] = matern_status(h2)
+        except h2.H2Error as e:
+            out["matern_status"] = {"workload": "matern_cube", "status": str(e)}
+        torch.cuda.empty_cache()
     if not a.no_cpu_baseline and a.kernel != "gaussian_batch":
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(a.kernel, a.eps, a.leaf, a.s, a.cpu_sample)

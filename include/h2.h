@@ -174,6 +174,15 @@ typedef struct {
   int64_t gather_partials;  /* doubles of gather partial products that one
                                right-hand side of a solve or matvec needs
                                (h2_solve_noalloc: at most H2_NOALLOC_PARTIALS) */
+  double flops_factor_phase[9]; /* canonical flops of flops_factor by phase, in
+                               the order of t_factor_phase: GEQRF + ORGQR_full,
+                               4 m^3, r^3/3, m r^2 + k r^2 + k^2 r, near pairs
+                               (2 m_i m_j (m_i + m_j) + r_i r_j^2 + k_i r_j^2 +
+                               k_j r_i^2), far pairs k_i k_j (k_i + k_j), 0,
+                               n0^3/3, 0                                       */
+  double flops_schur;       /* the k^2 r of phase 3 (the Schur update SS -=
+                               L(s) L(s)^T, FP32 MFMA under a reduced
+                               gemm_prec)                                      */
 } h2_stats_t;
 
 /* Capacity, in doubles, of the fixed device array that h2_solve_noalloc uses

@@ -30,6 +30,9 @@ static double orgqr_full(double m, double k) {
 // Canonical algorithmic flop counts (unpadded sizes); see include/h2.h.
 static void count_flops(Ctx& c) {
   double ff = 0.0, fs = 0.0, bytes = 0.0;
+  double* ph = c.st.flops_factor_phase;
+  for (int q = 0; q < 9; ++q) ph[q] = 0.0;
+  c.st.flops_schur = 0.0;
   int64_t nboxes = 0, npairs = 0, nfar = 0, nnzb = 0;
   int maxk = 0, maxm = 0;
   c.st.flops_pair_gemm = 0.0;
@@ -41,6 +44,11 @@ static void count_flops(Ctx& c) {
       const double m = S.m[b], k = S.k[b], r = m - k;
       ff += geqrf(m, k) + orgqr_full(m, k) + 4.0 * m * m * m;
       ff += r * r * r / 3.0 + k * r * r + k * k * r + m * r * r;
+      ph[0] += geqrf(m, k) + orgqr_full(m, k);
+      ph[1] += 4.0 * m * m * m;
+      ph[2] += r * r * r / 3.0;
+      ph[3] += k * r * r + k * k * r + m * r * r;
+      c.st.flops_schur += k * k * r;
       fs += 4.0 * m * m + 4.0 * r * r;
       maxk = std::max(maxk, S.k[b]);
       maxm = std::max(maxm, S.m[b]);
@@ -59,17 +67,20 @@ static void count_flops(Ctx& c) {
       if (S.h == 0) nnzb += 2;
       ff += ki * rj * rj + kj * ri * ri;
       ff += 2.0 * mi * mj * (mi + mj) + ri * rj * rj;
+      ph[4] += ki * rj * rj + kj * ri * ri + 2.0 * mi * mj * (mi + mj) + ri * rj * rj;
       c.st.flops_pair_gemm += 2.0 * mi * mj * (mi + mj);
       fs += 4.0 * ki * rj + 4.0 * kj * ri + 4.0 * ri * rj;
     }
     for (size_t f = 0; f < S.fp_i.size(); ++f) {
       const double ki = S.k[S.fp_i[f]], kj = S.k[S.fp_j[f]];
       ff += ki * kj * (ki + kj);
+      ph[5] += ki * kj * (ki + kj);
       ++nfar;
     }
   }
   for (auto& in : c.ins) {
     ff += (double)in.n0 * in.n0 * in.n0 / 3.0;
+    ph[7] += (double)in.n0 * in.n0 * in.n0 / 3.0;
     fs += 2.0 * (double)in.n0 * in.n0;
     bytes += 8.0 * (double)in.n0 * in.n0;
     if (in.tree.L == 0) ++nnzb;

@@ -311,16 +311,211 @@ __global__ __launch_bounds__(256) void qr_diag_kernel(const BoxDev* __restrict__
   }
 }
 
+// ---------------------------------------------------- register-resident panel
+// The same panel with the panel in registers, owned by columns: TPC = 256 / W
+// threads hold one column each, thread s of the group the rows s + TPC i
+// (i < NR).  Householder step jj: the owners of column jj form the reflector
+// (norm and alpha summed over their TPC lanes) and publish v through LDS
+// (double-buffered, one barrier per step); every group then forms its
+// column's product with v (a TPC-lane sum, no cross-column reduction), which
+// is the update coefficient for later columns and, for earlier columns l, the
+// z_l = V_l^T v_jj of the forward recurrence T[0:j, j] = -tau_j T[0:j, 0:j] z,
+// T[j, j] = tau_j; the z are kept in LDS and T_p is formed after the steps,
+// each of its rows by one thread (a row only needs its own earlier entries).
+// U_p = V_p T_p goes through LDS in 64-row chunks.  Outputs as
+// qr_panel_kernel: V explicit in tmpA, R, tau, U_p.
+
+// Sum over aligned groups of TPC (8 or 16) lanes through DPP lane permutes
+// within a row of 16 lanes: quad_perm [1,0,3,2] (xor 1), quad_perm [2,3,0,1]
+// (xor 2), row_half_mirror (lane i of 8 <- lane 7 - i: the other quad's sum)
+// and, for 16, row_mirror (lane i <- lane 15 - i: the other half's sum).
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+  switch (ctrl_sel) {
+    case 0:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int TPC>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(TPC == 8 || TPC == 16, "lane group");
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  if constexpr (TPC == 16) v += dpp_f64(v, 3);
+  return v;
+}
+
+template <int W, int NR>
+__global__ __launch_bounds__(256, 2) void qr_panel_reg_kernel(const BoxDev* __restrict__ boxes,
+                                                              int J, int w) {
+  constexpr int TPC = 256 / W;
+  constexpr int RMAX = TPC * NR;      // rows the kernel holds
+  constexpr int CH = 64;              // rows per U_p chunk
+  __shared__ double vbuf[2][RMAX];   // v, row s + TPC i at i TPC + s (no bank conflicts)
+  __shared__ double Zs[W * W];        // z of step c in column c (rows l < c)
+  __shared__ double Tp[W * W];        // T_p, column-major
+  constexpr int VS = W + 1;          // odd row stride: no bank conflicts
+  __shared__ double Vc[CH * VS];      // a chunk of V_p, row-major
+  __shared__ double bet[W], tau_s[W];
+  const BoxDev b = boxes[blockIdx.x];
+  const int m = b.m, k = b.k;
+  if (m == 0 || k <= J) return;
+  const int wj = min(w, k - J), L = m - J;
+  const int tid = threadIdx.x;
+  const int col = tid / TPC, s = tid % TPC;
+  const double* __restrict__ Wm = b.W;
+  // rows s + TPC i of column col (clamped into the panel: rows past L and
+  // columns past wj hold copies and are never used or written out)
+  double a[NR];
+  {
+    const double* src = Wm + J + (int64_t)(J + min(col, wj - 1)) * m;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) a[i] = src[min(s + TPC * i, L - 1)];
+  }
+  for (int jj = 0; jj < wj; ++jj) {
+    const int bb = jj & 1;
+    if (col == jj) {
+      // four independent accumulators: the FP64 chains are a quarter as long
+      double sg4[4] = {0.0, 0.0, 0.0, 0.0}, al = 0.0;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int r = s + TPC * i;
+        if (r > jj && r < L) sg4[i & 3] += a[i] * a[i];
+        if (r == jj) al = a[i];
+      }
+      double sg = group_sum<TPC>((sg4[0] + sg4[1]) + (sg4[2] + sg4[3]));
+      al = group_sum<TPC>(al);
+      double tau = 0.0, beta = al, scal = 0.0;
+      if (sg != 0.0) {
+        beta = -copysign(sqrt(al * al + sg), al);
+        tau = (beta - al) / beta;
+        scal = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int r = s + TPC * i;
+        const double v = (r == jj) ? 1.0 : ((r > jj && r < L) ? a[i] * scal : 0.0);
+        vbuf[bb][i * TPC + s] = v;
+        if (r > jj) a[i] = v;  // the column becomes V below the diagonal
+      }
+      if (s == 0) {
+        tau_s[jj] = tau;
+        bet[jj] = beta;
+      }
+    }
+    __syncthreads();
+    if (col != jj) {
+      double v[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) v[i] = vbuf[bb][i * TPC + s];
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < NR; ++i) p4[i & 3] += v[i] * a[i];
+      const double p = group_sum<TPC>((p4[0] + p4[1]) + (p4[2] + p4[3]));
+      if (col > jj) {
+        const double wc = tau_s[jj] * p;
+#pragma unroll
+        for (int i = 0; i < NR; ++i) a[i] -= v[i] * wc;
+      } else if (s == 0) {
+        Zs[col + jj * W] = p;
+      }
+    }
+  }
+  __syncthreads();
+  // T_p row tid: T[i][c] = -tau_c sum_{i <= l < c} T[i][l] z_l(c)
+  if (tid < wj) {
+    double trow[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < c; ++l) acc += (l >= tid) ? trow[l] * Zs[l + c * W] : 0.0;
+      const double t = (tid < c) ? -tau_s[c] * acc : (tid == c ? tau_s[c] : 0.0);
+      trow[c] = t;
+      if (c < wj) Tp[tid + c * W] = t;
+    }
+  }
+  // R column J + col (every row of R: it is used as a full k x k matrix),
+  // V explicit in tmpA, tau
+  if (col < wj) {
+    double* Rc = b.Rf + (int64_t)(J + col) * k;
+    for (int r = s; r < J; r += TPC) Rc[r] = Wm[r + (int64_t)(J + col) * m];
+    double* V = b.tmpA + (int64_t)(J + col) * m;
+    for (int r = s; r < J; r += TPC) V[r] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = s + TPC * i;
+      if (r < k - J) Rc[J + r] = (r < col) ? a[i] : (r == col ? bet[col] : 0.0);
+      if (r < L) V[J + r] = (r < col) ? 0.0 : (r == col ? 1.0 : a[i]);
+    }
+    if (s == 0) b.tau[J + col] = tau_s[col];
+  }
+  if (J + wj >= k) return;
+  __syncthreads();  // T_p complete
+  // U_p = V_p T_p, rows J .. m-1 of tmpB (ld m), in chunks of CH rows
+  for (int r0 = 0; r0 < L; r0 += CH) {
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int r = s + TPC * i;
+      if (r >= r0 && r < r0 + CH)
+        Vc[(r - r0) * VS + col] = (r < col) ? 0.0 : (r == col ? 1.0 : a[i]);
+    }
+    __syncthreads();
+    if (col < wj) {
+      double tc[W];
+#pragma unroll
+      for (int l = 0; l < W; ++l) tc[l] = (l <= col) ? Tp[l + col * W] : 0.0;
+      for (int rr = s; rr < CH && r0 + rr < L; rr += TPC) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < W; ++l) acc += Vc[rr * VS + l] * tc[l];
+        b.tmpB[J + r0 + rr + (int64_t)col * m] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Panel width of a level: the register kernel's 32 columns up to 256 rows, 16
+// up to 768 rows (the panel held in at most 96 registers per thread); beyond,
+// the LDS kernel's (its panel must fit in LDS).
 int qr_panel_width(int max_m) {
   if (max_m <= 0) return QR_PW;
+  if (max_m <= 256) return 32;
+  if (max_m <= 768) return 16;
   return std::max(1, std::min(QR_PW, QR_PAN / (max_m + 1)));  // + 1: odd column stride
 }
 
 hipError_t launch_qr_panel(const BoxDev* boxes, int nbox, int max_m, int J, int w,
                            hipStream_t st) {
   if (nbox <= 0) return hipSuccess;
-  if (w < 1 || w > QR_PW || (int64_t)(max_m + 1) * w > QR_PAN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(qr_panel_kernel, dim3(nbox), dim3(256), 0, st, boxes, J, w);
+  if (max_m <= 256 && w <= 32)
+    hipLaunchKernelGGL((qr_panel_reg_kernel<32, 32>), dim3(nbox), dim3(256), 0, st, boxes, J, w);
+  else if (max_m <= 512 && w <= 16)
+    hipLaunchKernelGGL((qr_panel_reg_kernel<16, 32>), dim3(nbox), dim3(256), 0, st, boxes, J, w);
+  else if (max_m <= 768 && w <= 16)
+    hipLaunchKernelGGL((qr_panel_reg_kernel<16, 48>), dim3(nbox), dim3(256), 0, st, boxes, J, w);
+  else if (w >= 1 && w <= QR_PW && (int64_t)(max_m + 1) * w <= QR_PAN)
+    hipLaunchKernelGGL(qr_panel_kernel, dim3(nbox), dim3(256), 0, st, boxes, J, w);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -121,12 +121,14 @@ class Stats(ctypes.Structure):
                 ("tuned_cfg_hist", ctypes.c_int32 * 4),
                 ("t_gather", ctypes.c_double * 3), ("bytes_gather", ctypes.c_double * 3),
                 ("gather_launches", ctypes.c_int32 * 3),
-                ("t_factor_phase", ctypes.c_double * 9), ("gather_partials", ctypes.c_int64)]
+                ("t_factor_phase", ctypes.c_double * 9), ("gather_partials", ctypes.c_int64),
+                ("flops_factor_phase", ctypes.c_double * 9), ("flops_schur", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["tuned_cfg_hist"] = list(self.tuned_cfg_hist)
-        for f in ("t_gather", "bytes_gather", "gather_launches", "t_factor_phase"):
+        for f in ("t_gather", "bytes_gather", "gather_launches", "t_factor_phase",
+                  "flops_factor_phase"):
             d[f] = list(getattr(self, f))
         return d
 
