@@ -126,12 +126,14 @@ def matern_status(h2, n: int) -> dict:
     return out
 
 
-def workload(n: int, kernel: str, eps: float, leaf: int, s: int):
+def workload(n: int, kernel: str, eps: float, leaf: int, s: int, nrhs: int = 1):
     import workloads as W
     if kernel == "gaussian_batch":
         return W.gaussian_batch(n_inst=64, leaf=leaf, eps=eps, s=s)
     if kernel == "yukawa":
-        return W.yukawa_cube(n=n, leaf=leaf, eps=eps, nrhs=1, s=s)
+        return W.yukawa_cube(n=n, leaf=leaf, eps=eps, nrhs=nrhs, s=s)
+    if kernel == "laplace_sphere":
+        return W.laplace_sphere(n=n, leaf=leaf, eps=eps, nrhs=nrhs, s=s)
     if kernel == "laplace":
         return W.laplace_cube(n=n, leaf=leaf, eps=eps, s=s)
     if kernel == "matern":
@@ -187,7 +189,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     """Build once (untimed), W warm-up steps, then time K steps of factor +
     solve with the inputs resident in HBM."""
     import torch
-    p = workload(a.n, a.kernel, a.eps, a.leaf, a.s)
+    nrhs = getattr(a, "nrhs", 1)
+    p = workload(a.n, a.kernel, a.eps, a.leaf, a.s, nrhs)
     t0 = time.perf_counter()
     if a.kernel == "gaussian_batch":
         import numpy as np
@@ -249,7 +252,7 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     st = H.stats()
     H.close()
     torch.cuda.empty_cache()
-    flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
+    flops_step = st["flops_factor"] + st["flops_solve"] * nrhs * (1 + iters / K)
     # Kernels of the timed steps with their work per launch over their average
     # launch time (HIP events on the launch stream), largest total time first:
     # the neighbour gathers of the substitution and the matvec (HBM-bound; FP64
@@ -300,7 +303,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--kernel", default="yukawa",
-                    help="yukawa (default) | laplace | matern | gaussian_batch (64 instances)")
+                    help="yukawa (default) | laplace | laplace_sphere | matern | gaussian_batch "
+                         "(64 instances)")
+    ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per solve")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
                     help="target: rank-predicted buffers, split-BF16 transform GEMMs on FP32 "
                          "copies and BF16 copies for the substitution, timed next to the "
@@ -377,10 +382,11 @@ def main():
         "dtype": {"fp64": "f64+f32" if mixed else "f64", "fp32": "f64+f32", "bf16": "f64+bf16",
                   "bf16x3": "f64+bf16x3"}[setting[0]],
         "data": "synthetic",
-        "config": {"workload": a.kernel if a.kernel == "gaussian_batch" else f"{a.kernel}_cube",
+        "config": {"workload": a.kernel if a.kernel in ("gaussian_batch", "laplace_sphere")
+                   else f"{a.kernel}_cube",
                    "path": a.path, "n": r["n_total"],
                    "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
-                   "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s_near, "nrhs": 1,
+                   "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s_near, "nrhs": a.nrhs,
                    "gemm_prec": setting[0], "solve_prec": setting[1], "rank_model": setting[2],
                    "graph": a.graph, "rank_fallbacks": st["rank_fallbacks"],
                    "basis_bytes": st["bytes_basis"], "autotuned_lists": st["tuned_lists"],
@@ -390,7 +396,8 @@ def main():
         "factor_s": r["factor_s"], "factor_phase_s": r["factor_phase_s"],
         "factor_roofline": r["factor_roofline"], "solve_roofline": r["solve_roofline"],
         "solve_s": r["solve_s"], "ir_iters": r["ir_iters"], "residual": r["residual"],
-        "build_s": r["build_s"], "flops_factor": st["flops_factor"],
+        "build_s": r["build_s"], "build_id_s": st["t_build_id"],
+        "flops_factor": st["flops_factor"],
         "flops_solve": st["flops_solve"],
         "roofline": r["cands"][0] if r["cands"] else None,
         "roofline_other": r["cands"][1:],
@@ -400,6 +407,8 @@ def main():
                              "factor_s": plain["factor_s"], "solve_s": plain["solve_s"],
                              "ir_iters": plain["ir_iters"], "residual": plain["residual"],
                              "basis_bytes": plain["stats"]["bytes_basis"],
+                             "build_s": plain["build_s"],
+                             "build_id_s": plain["stats"]["t_build_id"],
                              "roofline": plain["cands"][0] if plain["cands"] else None}
         out["speedup_vs_plain_fp64"] = plain["ms_per_step"] / r["ms_per_step"]
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20 and not a.no_extras:
@@ -424,6 +433,33 @@ def main():
         except h2.H2Error as e:
             out["batched_gaussian"] = {"instances": 64, "status": str(e)}
         torch.cuda.empty_cache()
+        # the sphere configuration (Laplace, N=65536 on the unit sphere, leaf
+        # 256, eps 1e-8, 16 right-hand sides, FP64) and the mixed-precision
+        # cube (Yukawa, N=262144, leaf 256, eps 1e-8, 4 right-hand sides,
+        # refined to 1e-10 against the FP64 H^2 operator) on reduced-precision
+        # transforms
+        extra = [("sphere_16rhs", "laplace_sphere", 1 << 16, 16, h2.PREC_FP64, h2.PREC_FP64, 1e-8),
+                 ("mixed_4rhs_bf16x3", "yukawa", 1 << 18, 4, h2.PREC_BF16X3, h2.PREC_BF16, 1e-10),
+                 ("mixed_4rhs_bf16", "yukawa", 1 << 18, 4, h2.PREC_BF16, h2.PREC_FP32, 1e-10)]
+        names = {h2.PREC_FP64: "fp64", h2.PREC_FP32: "fp32", h2.PREC_BF16: "bf16",
+                 h2.PREC_BF16X3: "bf16x3"}
+        for key, kern, n, nrhs, gp, sp, tol in extra:
+            c = copy.copy(a)
+            c.kernel, c.n, c.nrhs, c.leaf, c.eps, c.s, c.s_near, c.tol = kern, n, nrhs, 256, 1e-8, 256, 256, tol
+            c.steps, c.warmup, c.graph = min(a.steps, 3), 1, False
+            print(f"[bench] {key}", file=sys.stderr, flush=True)
+            try:
+                g = run_path(c, h2, gp, sp, None, key)
+                out[key] = {"workload": kern, "n": n, "nrhs": nrhs, "leaf": 256, "eps": 1e-8,
+                            "s": 256, "gemm_prec": names[gp], "solve_prec": names[sp],
+                            "ir_tol": tol, "steps": c.steps, "value": g["value"],
+                            "unit": "TFLOP/s", "ms_per_step": g["ms_per_step"],
+                            "factor_s": g["factor_s"], "solve_s": g["solve_s"],
+                            "ir_iters": g["ir_iters"], "residual": g["residual"],
+                            "build_s": g["build_s"], "max_rank": g["stats"]["max_rank_seen"]}
+            except h2.H2Error as e:
+                out[key] = {"workload": kern, "n": n, "nrhs": nrhs, "status": str(e)}
+            torch.cuda.empty_cache()
         print("[bench] Matern configuration status", file=sys.stderr, flush=True)
         out["matern_status"] = []
         for n in (1 << 20, 1 << 18):  # the configuration, and a size that fits

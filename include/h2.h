@@ -183,6 +183,13 @@ typedef struct {
   double flops_schur;       /* the k^2 r of phase 3 (the Schur update SS -=
                                L(s) L(s)^T, FP32 MFMA under a reduced
                                gemm_prec)                                      */
+  double t_build_id;        /* seconds of the build spent in the pivoted-QR IDs
+                               (host clock around each level's launch and the
+                               rank readback that ends it)                     */
+  double flops_prefactor;   /* canonical flops of the build's pre-factorization
+                               (Section 3.5), summed over boxes with a near
+                               sample of size c: c^3/3 + 2 c^2 m, or
+                               2 c^2 m per Gauss-Seidel sweep                  */
 } h2_stats_t;
 
 /* Capacity, in doubles, of the fixed device array that h2_solve_noalloc uses

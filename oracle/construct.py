@@ -39,6 +39,7 @@ class BoxBasis:
     U: np.ndarray          # m x k interpolation basis, identity rows at the skeleton
     piv: np.ndarray        # CPQR pivot order (positions into B), length m
     R_diag: np.ndarray     # |R_jj| of the pivoted QR (diagnostics)
+    sc: int = 0            # size of the near-field sample S_C (pre-factorization)
 
     @property
     def m(self) -> int:
@@ -167,7 +168,7 @@ def construct(X: np.ndarray, kernel, leaf: int, eta: float, eps: float,
             else:
                 piv, k, T, rd = interpolative_decomposition(M, eps, max_rank)
             U = build_basis(piv, k, T, Bi.size)
-            lvl.append(BoxBasis(Bi, Bi[piv[:k]], U, piv, rd))
+            lvl.append(BoxBasis(Bi, Bi[piv[:k]], U, piv, rd, sc=int(SC.size)))
         basis[l] = lvl
         for (i, j) in tree.far[l]:
             S[(l, i, j)] = kernels.evaluate(kernel, X[lvl[i].SK], X[lvl[j].SK],

@@ -18,6 +18,13 @@ reflectors: 4 m n k - 2 (m + n) k^2 + 4/3 k^3, here with n = m).  The solve,
 per right-hand side: 4 m^2 + 4 r^2 per box, 4 r_i r_j per near pair i > j,
 4 k_i r_j per ordered near pair (i == j included), 2 n_0^2 at the root.
 
+The pre-factorization of the construction (Section 3.5, Algorithm 1), per
+box with a near-field sample S_C of size c and m active points: the
+Cholesky factorization of A_cc (c^3 / 3) and two triangular solves with the
+m columns of G(S_C, B_i) (2 c^2 m), or, with Gauss-Seidel sweeps in place of
+the factorization, 2 c^2 m per sweep (every off-diagonal entry of A_cc once
+per column; Section 3.5's iterative variant).
+
 Pinned by tests/test_oracle_flops.py against the operations that running
 Householder QR, Q accumulation, Cholesky and triangular-solve loops perform.
 """
@@ -68,3 +75,19 @@ def count_h2(h2, nrhs: int = 1):
     ks = [None] + [[bb.k for bb in h2.basis[l]] for l in range(1, t.L + 1)]
     n0 = len(h2.root_B)
     return count(ms, ks, t.near, t.far, n0, nrhs)
+
+
+def prefactor_box(c: int, m: int, gs_sweeps: int = 0) -> float:
+    """Pre-factorization flops of one box (see the module docstring)."""
+    if c == 0:
+        return 0.0
+    if gs_sweeps > 0:
+        return gs_sweeps * 2.0 * c * c * m
+    return c ** 3 / 3.0 + 2.0 * c * c * m
+
+
+def count_prefactor(h2, gs_sweeps: int = 0) -> float:
+    """Pre-factorization flops of a whole construction (every level)."""
+    t = h2.tree
+    return sum(prefactor_box(bb.sc, bb.m, gs_sweeps)
+               for l in range(1, t.L + 1) for bb in h2.basis[l])

@@ -424,6 +424,13 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       sc[b] = (int)SC[b].size();
       s[b] = sf[b] + sc[b];
       if (sc[b] > CHOL_NMAX) return H2_ERR_UNSUPPORTED;
+      // pre-factorization flops (Section 3.5): chol(A_cc) and two triangular
+      // solves with the m columns of G(S_C, B_i), or 2 c^2 m per sweep
+      if (sc[b] > 0) {
+        const double cc = sc[b], mm = S.m[b];
+        c.st.flops_prefactor += prm->gs_sweeps > 0 ? prm->gs_sweeps * 2.0 * cc * cc * mm
+                                                   : cc * cc * cc / 3.0 + 2.0 * cc * cc * mm;
+      }
       sfo[b + 1] = sfo[b] + sf[b];
       sco[b + 1] = sco[b] + sc[b];
       acco[b + 1] = acco[b] + (int64_t)sc[b] * sc[b];
@@ -559,12 +566,16 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       TmpBuf tid(c);
       IdDesc* did = nullptr;
       if (!upload_tmp(tid, did, idd, st)) return H2_ERR_ALLOC;
-      HIPCHK(launch_cpqr_id(did, nb, prm->eps, prm->max_rank, nullptr, st));
+      const int max_m = nb > 0 ? *std::max_element(S.m.begin(), S.m.end()) : 1;
+      HIPCHK(hipStreamSynchronize(st));
+      const double t_id = now_seconds();
+      HIPCHK(launch_cpqr_id(did, nb, prm->eps, prm->max_rank, max_m, st));
       S.k.assign(nb, 0);
       std::vector<int32_t> piv(S.sum_m);
       HIPCHK(hipMemcpyAsync(S.k.data(), dK, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipMemcpyAsync(piv.data(), dPiv, S.sum_m * sizeof(int32_t), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
+      c.st.t_build_id += now_seconds() - t_id;
       // fallback: ranks above the predicted capacity get a buffer of their own
       {
         std::vector<int> over;

@@ -170,8 +170,9 @@ struct IdDesc {
   int s, m, kforced;
   int kcap;                 // U capacity in columns (0 = unlimited)
 };
+// max_m: the largest m of the list (sizes the LDS; at most 4096).
 hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps,
-                          int max_rank, double* norm_ws, hipStream_t st);
+                          int max_rank, int max_m, hipStream_t st);
 // Write U for IDs whose rank exceeded the capacity given to cpqr_id.
 hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st);
 

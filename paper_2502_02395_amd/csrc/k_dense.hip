@@ -532,7 +532,7 @@ hipError_t launch_qr_diag(const BoxDev* boxes, int nbox, hipStream_t st) {
 }
 
 // ------------------------------------------------------------- pivoted QR ID
-constexpr int ID_MMAX = 4096;
+constexpr int ID_MMAX = 4096;  // largest m: the column norms and pivots live in LDS
 
 // U (m x k, ld m) from T = R_11^{-1} R_12 stored in rows 0..k-1 of columns
 // k..m-1 of X (ld s) and the pivot order piv (LDS or global).
@@ -548,10 +548,11 @@ __device__ void write_u(const double* X, int s, int m, int k, const int* piv, do
 }
 
 __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__ descs, double eps,
-                                                      int max_rank) {
+                                                      int max_rank, int id_m_lds) {
+  // column norms and pivot order, sized by the launch to the level's largest
+  // m (12 bytes per column), so that small boxes keep many workgroups per CU
+  extern __shared__ double id_lds[];
   __shared__ double sh[4];
-  __shared__ double norms[ID_MMAX];
-  __shared__ int piv[ID_MMAX];
   __shared__ double bestv[4];
   __shared__ int besti[4];
   __shared__ int kfinal;
@@ -560,6 +561,8 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const IdDesc* __restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* X = d.X;
   const bool forced = d.skel != nullptr;
+  double* norms = id_lds;
+  int* piv = reinterpret_cast<int*>(id_lds + id_m_lds);
 
   for (int c = threadIdx.x; c < m; c += 256) piv[c] = c;
   for (int c = wave; c < m; c += 4) {
@@ -679,11 +682,12 @@ hipError_t launch_id_write_u(const IdDesc* d_desc, int count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps, int max_rank,
-                          double* norm_ws, hipStream_t st) {
-  (void)norm_ws;
+hipError_t launch_cpqr_id(const IdDesc* d_desc, int count, double eps, int max_rank, int max_m,
+                          hipStream_t st) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(cpqr_id_kernel, dim3(count), dim3(256), 0, st, d_desc, eps, max_rank);
+  if (max_m < 1 || max_m > ID_MMAX) return hipErrorInvalidValue;
+  const size_t lds = (size_t)max_m * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(cpqr_id_kernel, dim3(count), dim3(256), lds, st, d_desc, eps, max_rank, max_m);
   return hipGetLastError();
 }
 

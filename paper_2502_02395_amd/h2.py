@@ -122,7 +122,8 @@ class Stats(ctypes.Structure):
                 ("t_gather", ctypes.c_double * 3), ("bytes_gather", ctypes.c_double * 3),
                 ("gather_launches", ctypes.c_int32 * 3),
                 ("t_factor_phase", ctypes.c_double * 9), ("gather_partials", ctypes.c_int64),
-                ("flops_factor_phase", ctypes.c_double * 9), ("flops_schur", ctypes.c_double)]
+                ("flops_factor_phase", ctypes.c_double * 9), ("flops_schur", ctypes.c_double),
+                ("t_build_id", ctypes.c_double), ("flops_prefactor", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}

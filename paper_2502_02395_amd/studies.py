@@ -5,11 +5,12 @@ measurements of this library only):
 
   scaling  -- build, factor and solve time, factor TFLOP/s and the number of
               near (dense, non-zero) and far blocks vs N (O(N) behaviour);
-  eta      -- factor flops, near / far blocks, ranks and times vs the
-              admissibility eta at a fixed N;
-  hss      -- HSS (eta = 0, weak admissibility) vs H^2 (eta = 1): ranks,
-              factor flops and the accuracy of the H^2 operator and of the
-              unrefined solve against the dense kernel matrix;
+  eta      -- the flop counts of the construction's pre-factorization and
+              of the factorization (Fig. 17), near / far blocks, ranks and
+              times vs the admissibility eta at a fixed N;
+  hss      -- HSS (eta = 0, weak admissibility) vs H^2 (eta = 1) at fixed
+              ranks without far-field sampling (Figs. 18-19): the unrefined
+              solve's error against the dense solve, and time to solution;
   prefactor -- the pre-factorization of the construction (Section 3.5):
               exact near-sample solve vs Gauss-Seidel sweeps, on the Yukawa
               cube of the headline configuration (build time, ranks, PCG
@@ -18,8 +19,8 @@ measurements of this library only):
     python -m paper_2502_02395_amd.studies [scaling|eta|hss|prefactor|all] [--max-n N]
 
 Every line printed is one JSON record.  The dense reference of the hss
-study is the kernel matrix formed with plain torch operations on the GPU
-(N = 8192), not the library.
+study is the FP64 solve of the kernel matrix formed with plain torch
+operations on the GPU (N = 8192), not the library.
 """
 from __future__ import annotations
 
@@ -72,43 +73,77 @@ def scaling(h2, max_n: int, prec):
 
 
 def eta_sweep(h2, n: int, prec):
+    """Fig. 17: FP64 operation counts of the construction's pre-factorization
+    (Section 3.5) and of the ULV factorization vs eta; the counts come from
+    the build, the times from a factor + solve where the factorization holds."""
     import workloads as W
     for eta in (0.0, 0.5, 1.0, 1.5, 2.0, 3.0):
         p = W.laplace_sphere(n=n, leaf=256, eps=1e-8, eta=eta, nrhs=1)
+        H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                     s_near=p.s_near, gemm_prec=prec, solve_prec=prec, ir_max_iter=100,
+                     ir_tol=1e-8, use_pcg=True)
+        st = H.stats()
+        rec = {"study": "eta", "n": p.n, "leaf": p.leaf, "eta": eta, "eps": p.eps,
+               "s": p.s_far, "near_pairs": st["near_pairs"], "far_pairs": st["far_pairs"],
+               "leaf_near_blocks": st["leaf_near_blocks"], "max_rank": st["max_rank_seen"],
+               "flops_prefactor": st["flops_prefactor"], "flops_factor": st["flops_factor"],
+               "prefactor_share": st["flops_prefactor"] /
+               (st["flops_prefactor"] + st["flops_factor"]), "build_s": st["t_build"]}
         try:
-            H, _, _, rec = _run(h2, p, prec, prec)
-            H.close()
+            import torch
+            b = torch.from_numpy(p.b()).cuda()
+            H.factor()
+            H.solve(b)
+            H.factor()
+            H.solve(b)
+            st = H.stats()
+            rec.update({"factor_s": st["t_factor"], "solve_s": st["t_solve"],
+                        "ir_iters": st["ir_iters"], "residual": st["ir_residual"]})
         except h2.H2Error as e:  # e.g. a Cholesky breakdown: recorded, not fatal
-            rec = {"n": p.n, "leaf": p.leaf, "eta": eta, "eps": p.eps, "error": str(e)}
-        rec["study"] = "eta"
+            rec["error"] = str(e)
+        H.close()
         print(json.dumps(rec), flush=True)
 
 
-def hss_vs_h2(h2):
+def hss_vs_h2(h2, ranks=(25, 50, 100, 200, 400)):
+    """Figs. 18-19: HSS (eta = 0) vs H^2 (eta = 1) at fixed ranks, N = 8192,
+    leaf 512, every far-field point used (no far sampling; near samples of
+    2048 points): the unrefined solve's error against the dense FP64 solve,
+    and the time to solution (factor + solve)."""
     import torch
     import workloads as W
-    # HSS with every candidate point sampled, then HSS and H^2 with 1024-point
-    # samples
-    for eta, s in ((0.0, -1), (0.0, 1024), (1.0, 1024)):
-        p = W.laplace_sphere(n=8192, leaf=512, eps=1e-8, eta=eta, nrhs=1, s=s)
-        try:
-            H, b, x, rec = _run(h2, p, h2.PREC_FP64, h2.PREC_FP64, refine=False)
-        except h2.H2Error as e:
-            print(json.dumps({"study": "hss" if eta == 0.0 else "h2", "n": p.n, "eta": eta,
-                              "s": s, "error": str(e)}), flush=True)
-            continue
-        X = torch.from_numpy(p.points).cuda()
-        A = 1.0 / (torch.cdist(X, X) + p.kernel.delta)
-        gen = torch.Generator(device="cuda").manual_seed(3)
-        v = torch.randn(p.n, 1, dtype=torch.float64, device="cuda", generator=gen)
-        y = H.matvec(v)
-        rec["matvec_rel_err"] = float(torch.linalg.norm(y - A @ v) / torch.linalg.norm(A @ v))
-        rec["solve_rel_residual_dense"] = float(torch.linalg.norm(b - A @ x) /
-                                                torch.linalg.norm(b))
-        H.close()
-        rec["study"] = "hss" if eta == 0.0 else "h2"
-        rec["s"] = s
-        print(json.dumps(rec), flush=True)
+    p0 = W.laplace_sphere(n=8192, leaf=512, eps=0.0, eta=1.0, nrhs=1, s=-1)
+    X = torch.from_numpy(p0.points).cuda()
+    A = 1.0 / (torch.cdist(X, X) + p0.kernel.delta)
+    b = torch.from_numpy(p0.b()).cuda()
+    xd = torch.linalg.solve(A, b)
+    del A
+    torch.cuda.empty_cache()
+    for eta in (0.0, 1.0):
+        for r in ranks:
+            rec = {"study": "hss" if eta == 0.0 else "h2", "n": p0.n, "leaf": 512, "eta": eta,
+                   "max_rank": r, "s_far": -1, "s_near": 2048}
+            try:
+                H = h2.build(p0.points, p0.kernel, 512, eta, 0.0, p0.perm(), s_far=-1,
+                             s_near=2048, max_rank=r)
+                st = H.stats()
+                rec.update({"max_rank_seen": st["max_rank_seen"], "root_n": st["root_n"],
+                            "near_pairs": st["near_pairs"], "far_pairs": st["far_pairs"],
+                            "flops_factor": st["flops_factor"], "build_s": st["t_build"]})
+                H.factor()
+                x = H.solve(b)
+                H.factor()
+                x = H.solve(b)
+                torch.cuda.synchronize()
+                st = H.stats()
+                rec.update({"factor_s": st["t_factor"], "solve_s": st["t_solve"],
+                            "time_to_solution_s": st["t_factor"] + st["t_solve"],
+                            "rel_err_vs_dense": float(torch.linalg.norm(x - xd) /
+                                                      torch.linalg.norm(xd))})
+                H.close()
+            except h2.H2Error as e:
+                rec["error"] = str(e)
+            print(json.dumps(rec), flush=True)
 
 
 def prefactor(h2, n: int):

@@ -140,3 +140,66 @@ def test_count_composes_the_step_counts():
     es = sum(4.0 * m * m + 4.0 * (m - k) ** 2 for m, k in zip(ms[1], ks[1]))
     es += 4.0 * (k0 * r0 + k0 * r1 + k1 * r0 + k1 * r1) + 4.0 * r1 * r0 + 2.0 * 25 ** 2
     assert abs(fs - es) <= 1e-9 * es
+
+
+def _lower_solve(L, B):
+    """Y = L^{-1} B by forward substitution, column by column."""
+    c, m = B.shape
+    Y = np.zeros_like(B)
+    f = 0
+    for q in range(m):
+        for i in range(c):
+            Y[i, q] = (B[i, q] - L[i, :i] @ Y[:i, q]) / L[i, i]
+            f += 2 * i + 1
+    return Y, f
+
+
+@pytest.mark.parametrize("c,m", [(30, 40), (64, 16), (17, 50)])
+def test_prefactor_counts(c, m):
+    """Section 3.5's pre-factorization of one box: Cholesky of A_cc and two
+    triangular solves with the m columns of G(S_C, B_i), counted by loops
+    that really solve A_cc X = G (checked against scipy), or Gauss-Seidel
+    sweeps counted by a loop that reproduces oracle.construct.gauss_seidel."""
+    from oracle import construct
+    rng = np.random.default_rng(c * 100 + m)
+    G = rng.standard_normal((c, c))
+    A = G @ G.T + c * np.eye(c)
+    B = rng.standard_normal((c, m))
+    L, fc = _cholesky(A)
+    Y, f1 = _lower_solve(L, B)
+    Xr, f2 = _lower_solve(L[::-1, ::-1].T.copy(), Y[::-1].copy())   # L^T X = Y, reversed
+    X = Xr[::-1]
+    assert np.allclose(X, sla.cho_solve((sla.cholesky(A, lower=True), True), B), atol=1e-12)
+    f = fc + f1 + f2
+    assert abs(f - flops.prefactor_box(c, m)) <= 2 * c * c + 2 * c * m
+    for sweeps in (1, 2, 3):
+        Xg = np.zeros_like(B)
+        fg = 0
+        for _ in range(sweeps):
+            for i in range(c):
+                Xg[i] = (B[i] - A[i, :i] @ Xg[:i] - A[i, i + 1:] @ Xg[i + 1:]) / A[i, i]
+                fg += (2 * (c - 1) + 1) * m
+        assert np.allclose(Xg, construct.gauss_seidel(A, B, sweeps), rtol=1e-12, atol=1e-12)
+        assert abs(fg - flops.prefactor_box(c, m, sweeps)) <= sweeps * c * m
+
+
+def test_count_prefactor_follows_the_near_samples():
+    """The per-box sample sizes the count uses are those the sampling rule
+    gives (the first s_near candidates of the near boxes' active points, or
+    all of them), and the total is the per-box formula summed over levels."""
+    import workloads as W
+    from oracle import construct
+    p = W.laplace_cube(n=1024, leaf=64, eps=1e-6, s=96)
+    h = construct.construct(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), p.s_far,
+                            p.s_near)
+    t = h.tree
+    tot = 0.0
+    for l in range(1, t.L + 1):
+        near = t.near_of(l)
+        for i, bb in enumerate(h.basis[l]):
+            cands = sum(h.basis[l][j].m for j in near[i] if j != i)
+            assert bb.sc == min(cands, p.s_near)
+            tot += bb.sc ** 3 / 3.0 + 2.0 * bb.sc ** 2 * bb.m
+    assert any(bb.sc == p.s_near for bb in h.basis[t.L])      # the sample bounds some boxes
+    assert abs(flops.count_prefactor(h) - tot) <= 1e-9 * tot
+    assert flops.count_prefactor(h, 2) > 0
