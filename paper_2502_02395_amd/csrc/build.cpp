@@ -683,6 +683,49 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
 }
 
 // ------------------------------------------------------------- factor plan
+// Packed BF16 copies of what the substitution reads (its gathers only):
+// for every near pair (i, j) the rows [0, k_i) of F_ij from column k_j on
+// (L(s)_ij), and for i != j the rows [k_i, m_i) over every column (L(s)_ji^T
+// and L(r)_ij); for every box the whole P_i.  The S x S part of F_ij is not
+// copied.  Segments are laid out one after another, each with its row count
+// rounded up to 8 as leading dimension (a multiple of 8 elements: every
+// segment and column starts on a 16-byte boundary).
+static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtSeg>& sF,
+                             std::vector<CvtSeg>& sP) {
+  auto r8 = [](int64_t x) { return (x + 7) / 8 * 8; };
+  S.cmF.clear();
+  S.cmP.clear();
+  int64_t off = 0;
+  for (size_t p = 0; p < S.np_i.size(); ++p) {
+    const int i = S.np_i[p], j = S.np_j[p];
+    const int mi = S.m[i], mj = S.m[j], ki = S.k[i], kj = S.k[j];
+    CopyMap cm{S.dF + S.poff[p], mi, mi, mj, ki, kj, -1, 1, -1, 1};
+    if (ki > 0 && mj > kj) {
+      cm.top = off;
+      cm.ld_top = r8(ki);
+      sF.push_back({S.poff[p] + (int64_t)kj * mi, off, mi, ki, mj - kj, (int)cm.ld_top});
+      off += cm.ld_top * (mj - kj);
+    }
+    if (i != j && mi > ki && mj > 0) {
+      cm.bot = off;
+      cm.ld_bot = r8(mi - ki);
+      sF.push_back({S.poff[p] + ki, off, mi, mi - ki, mj, (int)cm.ld_bot});
+      off += cm.ld_bot * mj;
+    }
+    S.cmF.push_back(cm);
+  }
+  nF = off;
+  off = 0;
+  for (int b = 0; b < S.nbox; ++b) {
+    const int m = S.m[b];
+    CopyMap cm{S.dP + S.qoff[b], m, m, m, m, 0, off, r8(m), -1, 1};
+    if (m > 0) sP.push_back({S.qoff[b], off, m, m, m, (int)cm.ld_top});
+    off += cm.ld_top * m;
+    S.cmP.push_back(cm);
+  }
+  nP = off;
+}
+
 h2_status plan_factor(Ctx& c, hipStream_t st) {
   // root buffers
   int max_n0 = 0;
@@ -776,9 +819,15 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       ALLOCHK(S.dF32); ALLOCHK(S.dP32);
     }
     if (c.prm.solve_prec == H2_PREC_BF16) {
-      S.dF16 = c.alloc<unsigned short>(std::max<int64_t>(S.poff[np], 1));
-      S.dP16 = c.alloc<unsigned short>(std::max<int64_t>(q, 1));
+      int64_t nF = 0, nP = 0;
+      std::vector<CvtSeg> sF, sP;
+      plan_bf16_copies(S, nF, nP, sF, sP);
+      S.dF16 = c.alloc<unsigned short>(std::max<int64_t>(nF, 1));
+      S.dP16 = c.alloc<unsigned short>(std::max<int64_t>(nP, 1));
       ALLOCHK(S.dF16); ALLOCHK(S.dP16);
+      if (!upload(c, S.cvF16, sF, st) || !upload(c, S.cvP16, sP, st)) return H2_ERR_ALLOC;
+      for (const CvtSeg& g : sF) S.cvF16_cols = std::max(S.cvF16_cols, g.cols);
+      for (const CvtSeg& g : sP) S.cvP16_cols = std::max(S.cvP16_cols, g.cols);
     }
   }
   // index of (instance, level-local box) in each step

@@ -20,11 +20,35 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (r.esz != out.esz || (r.esz != 4 && r.esz != 2)) return false;
   const bool copy = out.esz < 8;
   const double esz = out.esz;
-  // the copy of a block pointer, or nullptr
-  auto to_copy = [&](const double* p) -> const char* {
-    for (const Rebase& r : rb)
-      if (p >= r.base && p < r.base + r.n)
-        return static_cast<const char*>(r.copy) + (p - r.base) * r.esz;
+  bool packed = copy;
+  for (const Rebase& r : rb) packed = packed && r.map != nullptr;
+  if (packed && out.esz != 2) return false;
+  // The copy of a sub-block that starts at p and spans `rows` rows, and its
+  // leading dimension (*ld); nullptr when p lies in no range, or when a
+  // packed copy does not hold those rows in one segment.
+  auto to_copy = [&](const double* p, int rows, int64_t* ld) -> const char* {
+    for (const Rebase& r : rb) {
+      if (!(p >= r.base && p < r.base + r.n)) continue;
+      const char* cp = static_cast<const char*>(r.copy);
+      if (!r.map) return cp + (p - r.base) * r.esz;
+      const std::vector<CopyMap>& mp = *r.map;
+      // last block whose source starts at or before p
+      auto it = std::upper_bound(mp.begin(), mp.end(), p,
+                                 [](const double* a, const CopyMap& b) { return a < b.src; });
+      if (it == mp.begin()) return nullptr;
+      const CopyMap& b = *(it - 1);
+      const int64_t e = p - b.src;
+      if (e >= b.ld * b.cols) return nullptr;
+      const int64_t row = e % b.ld, col = e / b.ld;
+      if (row < b.split) {
+        if (b.top < 0 || col < b.top_c0 || row + rows > b.split) return nullptr;
+        *ld = b.ld_top;
+        return cp + (b.top + (col - b.top_c0) * b.ld_top + row) * r.esz;
+      }
+      if (b.bot < 0 || row + rows > b.rows) return nullptr;
+      *ld = b.ld_bot;
+      return cp + (b.bot + col * b.ld_bot + (row - b.split)) * r.esz;
+    }
     return nullptr;
   };
   struct Item {
@@ -106,7 +130,8 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (it.tq >= 0) { it.ot0 = off; off += (int64_t)nck * it.mc; }
     const GatherNbr* nd = it.dq >= 0 ? &Nv[it.dq] : nullptr;
     const GatherNbr* nt = it.tq >= 0 ? &Nv[it.tq] : nullptr;
-    const char* Mc = copy ? to_copy(it.M) : nullptr;
+    int64_t ldc = it.ld;
+    const char* Mc = copy ? to_copy(it.M, it.mr, &ldc) : nullptr;
     if (copy && !Mc) return false;
     for (int c = 0; c < nck; ++c) {
       const int r0 = rs[c];
@@ -114,11 +139,11 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
         const int c0 = sg * std::min(W, it.mc), c1 = std::min(it.mc, c0 + W);
         const int64_t e0 = r0 + (int64_t)c0 * it.ld;
         GChunk ch;
-        ch.M = copy ? static_cast<const void*>(Mc + e0 * out.esz)
+        ch.M = copy ? static_cast<const void*>(Mc + (r0 + (int64_t)c0 * ldc) * out.esz)
                     : static_cast<const void*>(it.M + e0);
         ch.xd = nd ? nd->x + c0 : nullptr;
         ch.xt = nt ? nt->x + r0 : nullptr;
-        ch.ld = it.ld;
+        ch.ld = (int)ldc;
         ch.ldxd = nd ? nd->ldx : 1;
         ch.ldxt = nt ? nt->ldx : 1;
         ch.nr = rs[c + 1] - r0;
@@ -138,6 +163,12 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (nt) out.bytes_chunks_vec += 8.0 * (it.mr + (double)nck * it.mc);    // x_t, slots
   }
   out.plen = off;
+  // packed BF16: every chunk 16-byte aligned with ld a multiple of 8 and a
+  // first row that is a multiple of 8 (rows past the segment are zeros)
+  out.v16 = packed && !wide;
+  for (const GChunk& ch : out.chunks)
+    if (out.v16 && (reinterpret_cast<uintptr_t>(ch.M) % 16 != 0 || ch.ld % 8 != 0 || ch.nr > 128))
+      out.v16 = false;
   for (size_t bx = 0; bx < B.size(); ++bx) {
     const GatherBox& g = B[bx];
     GRed r;

@@ -46,6 +46,7 @@ struct GList {
   int esz = 8;                             // bytes per block element: 8, or 4 / 2
                                            // for FP32 / BF16 copies
   bool has_w = false;
+  bool v16 = false;                        // n reads packed BF16 copies (GatherPlan::v16)
   const GSet& pick(int nrhs) const { return has_w && nrhs <= GATHER_WIDE_NR ? w : n; }
 };
 
@@ -85,7 +86,10 @@ struct Step {
   double* dW = nullptr;                    // QR workspace at qoff
   double* dTau = nullptr;                  // Householder scalars at koff
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
-  unsigned short *dF16 = nullptr, *dP16 = nullptr;  // BF16 copies (solve_prec BF16)
+  unsigned short *dF16 = nullptr, *dP16 = nullptr;  // packed BF16 copies (solve_prec BF16)
+  std::vector<CopyMap> cmF, cmP;           // their layout (sorted by source block)
+  Batch<CvtSeg> cvF16, cvP16;              // their conversion segments
+  int cvF16_cols = 0, cvP16_cols = 0;      // widest segment of each
   float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)
   float *dR32 = nullptr, *dS32 = nullptr, *dT332 = nullptr;  // FP32 R, far couplings, scratch
   Batch<ConvDesc> cv_fii;                  // F_ii -> FP32 (diagonal blocks)

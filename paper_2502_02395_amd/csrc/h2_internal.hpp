@@ -255,13 +255,37 @@ constexpr int GATHER_WIDE_RPL64 = 2;
 constexpr int GATHER_WIDE_NR = 2;
 constexpr int GATHER_WIDE_FROM = 1;
 constexpr int GATHER_WIDE_TO = 6;
-// A range of FP64 blocks with a reduced-precision copy (same element
-// offsets): esz 4 = FP32, esz 2 = BF16.
+// Where the packed BF16 copy of one FP64 block lives.  The block (rows x
+// cols, column-major, ld) is kept as up to two segments: its rows
+// [0, split) from column top_c0 on (the top segment), and its rows
+// [split, rows) over every column (the bottom segment; bot < 0: none).  Each
+// segment is column-major with a leading dimension that is a multiple of 8
+// elements, starts on a 16-byte boundary, and holds zeros below its rows, so
+// that a gather can read eight rows of a column with one 16-byte load.
+struct CopyMap {
+  const double* src;
+  int64_t ld;
+  int rows, cols, split, top_c0;
+  int64_t top, ld_top;      // element offsets into the copy
+  int64_t bot, ld_bot;
+};
+// One segment of a packed copy for the conversion kernel: source element
+// offset (into the FP64 or FP32 arena) and ld, rows, columns; destination
+// offset and ld (rows up to dst_ld are written, zeros below `rows`).
+struct CvtSeg {
+  int64_t src_off;
+  int64_t dst_off;
+  int src_ld, rows, cols, dst_ld;
+};
+// A range of FP64 blocks with a reduced-precision copy: esz 4 = FP32, esz 2
+// = BF16.  Without a map the copy has the same element offsets; with one
+// (BF16 only, sorted by src) it is packed as the map says.
 struct Rebase {
   const double* base;
   int64_t n;
   const void* copy;
   int esz;
+  const std::vector<CopyMap>* map = nullptr;
 };
 struct GatherPlan {
   int esz = 8;                // bytes per block element: 8 FP64, 4 FP32, 2 BF16 copies
@@ -274,6 +298,9 @@ struct GatherPlan {
   // and partial traffic per rhs
   double bytes_chunks_mat = 0.0, bytes_chunks_vec = 0.0;
   double bytes_red = 0.0;
+  // every chunk reads a packed BF16 copy: 16-byte aligned, ld a multiple of
+  // 8, zero rows below the chunk up to the next multiple of 8
+  bool v16 = false;
 };
 // rb non-empty: every block must lie in one of its ranges and is read from
 // that range's copy (all ranges of one plan share esz; returns false
@@ -283,14 +310,22 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
                  GatherPlan& out, const std::vector<Rebase>& rb = {}, int seg = 0,
                  bool wide = false);
 // wide: the chunks come from a wide plan (nrhs <= GATHER_WIDE_NR required).
-// esz: bytes per block element (8, 4 or 2).
+// esz: bytes per block element (8, 4 or 2).  v16: the plan's v16 (BF16
+// chunks of 128 rows read with 16-byte loads, for one right-hand side;
+// more fall back to the two-rows-per-lane kernel, which reads the packed
+// copies too).
+constexpr int GV16_NR = 1;
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
-                          hipStream_t st, bool wide = false);
+                          hipStream_t st, bool wide = false, bool v16 = false);
 // FP32 copy of n doubles.
 hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // BF16 copy (round to nearest even) of n doubles (esz_src 8) or floats (4).
 hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, int64_t n,
                            hipStream_t st);
+// Packed BF16 copy: every segment of segs (device, count) from src (FP64 or
+// FP32 arena, esz_src 8 or 4) into dst, zero-padded; max_cols the widest.
+hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs, int count,
+                                int max_cols, unsigned short* dst, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 

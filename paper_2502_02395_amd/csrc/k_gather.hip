@@ -195,6 +195,173 @@ __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ 
   gchunk_one<NR, T, 1, BW>(ch, P, nrhs, lane);
 }
 
+// ------------------------------------------------------ packed BF16 chunks
+// Chunks of the packed BF16 copies (GatherPlan::v16): the leading dimension
+// is a multiple of 8 elements and every chunk starts on a 16-byte boundary,
+// so lane (g, q) = (lane >> 4, lane & 15) reads rows 8q..8q+7 of one column
+// with a single 16-byte load, and one load instruction of the wave moves
+// four columns of 128 rows (1 KiB).  Columns 4u + g of each batch of 4U
+// columns belong to lane group g.  Direct sums (rows) are reduced over the
+// four groups at the end of the chunk, transposed sums (columns) over the
+// sixteen row groups after each batch; both in a fixed order.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int T>
+__device__ __forceinline__ double bf16_at(const u32x4& v) {
+  const unsigned w = v[T >> 1];
+  return (double)__uint_as_float((T & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+
+// Sum of v[0..N) over the 16 lanes of each lane group (lanes with equal
+// lane >> 4), halving the values a lane carries at each exchange: on return
+// lane q of the group holds the total of value q (N = 16) or of value q >> 1
+// (N = 8).
+template <int N>
+__device__ __forceinline__ double reduce_group16(const double (&v)[N], int lane) {
+  static_assert(N == 16 || N == 8, "16 or 8 values");
+  constexpr int H = N / 2;
+  double a[H];
+  const bool b3 = (lane >> 3) & 1;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double send = b3 ? v[j] : v[H + j];
+    const double keep = b3 ? v[H + j] : v[j];
+    a[j] = keep + __shfl_xor(send, 8, 64);
+  }
+  constexpr int Q = H / 2;
+  double b[Q];
+  const bool b2 = (lane >> 2) & 1;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const double send = b2 ? a[j] : a[Q + j];
+    const double keep = b2 ? a[Q + j] : a[j];
+    b[j] = keep + __shfl_xor(send, 4, 64);
+  }
+  const bool b1 = (lane >> 1) & 1;
+  if constexpr (N == 16) {
+    double c[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double send = b1 ? b[j] : b[2 + j];
+      const double keep = b1 ? b[2 + j] : b[j];
+      c[j] = keep + __shfl_xor(send, 2, 64);
+    }
+    const bool b0 = lane & 1;
+    return (b0 ? c[1] : c[0]) + __shfl_xor(b0 ? c[0] : c[1], 1, 64);
+  } else {
+    const double c = (b1 ? b[1] : b[0]) + __shfl_xor(b1 ? b[0] : b[1], 2, 64);
+    return c + __shfl_xor(c, 1, 64);
+  }
+}
+
+template <int NR, int U>
+__global__ __launch_bounds__(256) void gv16_kernel(const GChunk* __restrict__ chunks, int nch,
+                                                   double* __restrict__ P, int nrhs) {
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (w >= nch) return;
+  const GChunk& ch = chunks[w];
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
+  const bool dir = ch.od >= 0, tr = ch.ot >= 0;
+  const int nr = ch.nr, mc = ch.mc;
+  const int64_t colb = (int64_t)ch.ld * 2;  // bytes per column
+  // row groups past the chunk read group 0 (in bounds); their x_t is zero
+  // and their direct sums are never stored
+  const bool live = 8 * q < nr;
+  const char* base = static_cast<const char*>(ch.M) + 16 * (live ? q : 0);
+  double xt[8][NR], acc[8][NR];
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      acc[t][c] = 0.0;
+      xt[t][c] = (tr && c < nrhs && 8 * q + t < nr)
+                     ? as_global(ch.xt)[8 * q + t + (int64_t)c * ch.ldxt]
+                     : 0.0;
+    }
+  for (int s0 = 0; s0 < mc; s0 += 4 * U) {
+    double xv[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+      xv[c] = (dir && c < nrhs && lane < 4 * U && s0 + lane < mc)
+                  ? as_global(ch.xd)[s0 + lane + (int64_t)c * ch.ldxd]
+                  : 0.0;
+    u32x4 d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // columns past the chunk read its last column; x_d is zero there and
+      // their transposed sums are not stored
+      const int cc = min(s0 + 4 * u + g, mc - 1);
+      d[u] = __builtin_nontemporal_load(
+          reinterpret_cast<gptr_t<u32x4>>(as_global(base + (int64_t)cc * colb)));
+    }
+    if (dir) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        if (c < nrhs) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const double xu = __shfl(xv[c], 4 * u + g, 64);
+            acc[0][c] += bf16_at<0>(d[u]) * xu;
+            acc[1][c] += bf16_at<1>(d[u]) * xu;
+            acc[2][c] += bf16_at<2>(d[u]) * xu;
+            acc[3][c] += bf16_at<3>(d[u]) * xu;
+            acc[4][c] += bf16_at<4>(d[u]) * xu;
+            acc[5][c] += bf16_at<5>(d[u]) * xu;
+            acc[6][c] += bf16_at<6>(d[u]) * xu;
+            acc[7][c] += bf16_at<7>(d[u]) * xu;
+          }
+        }
+      }
+    }
+    if (tr) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        if (c < nrhs) {
+          double pt[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            pt[u] = bf16_at<0>(d[u]) * xt[0][c] + bf16_at<1>(d[u]) * xt[1][c] +
+                    bf16_at<2>(d[u]) * xt[2][c] + bf16_at<3>(d[u]) * xt[3][c] +
+                    bf16_at<4>(d[u]) * xt[4][c] + bf16_at<5>(d[u]) * xt[5][c] +
+                    bf16_at<6>(d[u]) * xt[6][c] + bf16_at<7>(d[u]) * xt[7][c];
+          const double tot = reduce_group16<U>(pt, lane);
+          const int uu = U == 16 ? q : (q >> 1);
+          const int col = s0 + 4 * uu + g;
+          if (col < mc && (U == 16 || (q & 1) == 0))
+            P[ch.ot * nrhs + (int64_t)c * ch.tlen + ch.tcol + col] = tot;
+        }
+      }
+    }
+  }
+  if (dir) {
+    // rows 8q..8q+7 summed over the four lane groups: lane (q, g) keeps rows
+    // 8q + 4 (g & 1) + 2 (g >> 1) + {0, 1}
+    const bool g0 = g & 1, g1 = (g >> 1) & 1;
+    const int r0 = 8 * q + 4 * g0 + 2 * g1;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      if (c < nrhs) {
+        double a[4], b[2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double send = g0 ? acc[j][c] : acc[4 + j][c];
+          const double keep = g0 ? acc[4 + j][c] : acc[j][c];
+          a[j] = keep + __shfl_xor(send, 16, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double send = g1 ? a[j] : a[2 + j];
+          const double keep = g1 ? a[2 + j] : a[j];
+          b[j] = keep + __shfl_xor(send, 32, 64);
+        }
+        double* dst = P + ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow;
+        if (r0 < nr) dst[r0] = b[0];
+        if (r0 + 1 < nr) dst[r0 + 1] = b[1];
+      }
+    }
+  }
+}
+
 template <int NR>
 __global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ reds,
                                                       const int64_t* __restrict__ offs,
@@ -248,10 +415,16 @@ static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hip
 }
 
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
-                          hipStream_t st, bool wide) {
+                          hipStream_t st, bool wide, bool v16) {
   if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
   if (wide && nrhs > GATHER_WIDE_NR) return hipErrorInvalidValue;
+  if (v16 && esz == 2 && !wide && nrhs <= GV16_NR) {
+    static_assert(GV16_NR == 1, "instantiation below");
+    const dim3 grid((nch + 3) / 4), blk(256);
+    hipLaunchKernelGGL((gv16_kernel<1, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+    return hipGetLastError();
+  }
   if (esz == 8) launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);
   else if (esz == 4) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide);
   else if (esz == 2) launch_gchunks_t<unsigned short>(ch, nch, P, nrhs, st, wide);

@@ -64,10 +64,14 @@ static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
                       const std::vector<GatherNbr>& Nv, hipStream_t st,
                       const std::vector<Rebase>& rb, int seg, bool wide) {
+  // packed BF16 copies take the 16-byte-load chunks instead of wide ones
+  for (const Rebase& r : rb)
+    if (r.map) wide = false;
   auto up_set = [&](GSet& S, bool wide) {
     GatherPlan p;
     if (!plan_gather(B, Nv, p, rb, seg, wide)) return false;
     L.esz = p.esz;
+    if (!wide) L.v16 = p.v16;
     S.max_rows = p.max_rows;
     S.plen = p.plen;
     S.bytes_ch_mat = p.bytes_chunks_mat;
@@ -105,7 +109,8 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, wide)) != hipSuccess)
+  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, wide,
+                         L.v16 && !wide)) != hipSuccess)
     return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
   if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st)) !=
@@ -371,8 +376,8 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
     // least the FP32 reads.
     std::vector<Rebase> rb;
     if (c.prm.solve_prec == H2_PREC_BF16) {
-      rb.push_back({S.dF, S.poff.back(), S.dF16, 2});
-      rb.push_back({S.dP, S.qoff[S.nbox], S.dP16, 2});
+      rb.push_back({S.dF, S.poff.back(), S.dF16, 2, &S.cmF});
+      rb.push_back({S.dP, S.qoff[S.nbox], S.dP16, 2, &S.cmP});
     } else if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec != H2_PREC_FP64) {
       rb.push_back({S.dF, S.poff.back(), S.dF32, 4});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32, 4});
@@ -637,9 +642,11 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(mark(FP_F32));
     const bool from32 = c.prm.gemm_prec != H2_PREC_FP64;
     for (auto& S : c.steps) {
-      if (from32) HIPCHK(launch_cvt_bf16(S.dF32, 4, S.dF16, S.poff.back(), st));
-      else HIPCHK(launch_cvt_bf16(S.dF, 8, S.dF16, S.poff.back(), st));
-      HIPCHK(launch_cvt_bf16(S.dP, 8, S.dP16, S.qoff[S.nbox], st));
+      if (from32)
+        HIPCHK(launch_cvt_bf16_segs(S.dF32, 4, S.cvF16.d, S.cvF16.count, S.cvF16_cols, S.dF16, st));
+      else
+        HIPCHK(launch_cvt_bf16_segs(S.dF, 8, S.cvF16.d, S.cvF16.count, S.cvF16_cols, S.dF16, st));
+      HIPCHK(launch_cvt_bf16_segs(S.dP, 8, S.cvP16.d, S.cvP16.count, S.cvP16_cols, S.dP16, st));
     }
     HIPCHK(done());
   }

@@ -140,16 +140,20 @@ def test_fp32_substitution_copies_against_oracle(lib):
     assert out[lib.PREC_FP32][1] <= out[lib.PREC_FP64][1] + 2
 
 
-def test_bf16_substitution_with_split_bf16_transforms(lib):
+@pytest.mark.parametrize("nrhs", [1, 2, 4])
+def test_bf16_substitution_with_split_bf16_transforms(lib, nrhs):
     """The fastest combination: split-BF16 transforms and BF16 substitution
     copies, PCG to 1e-10 against the FP64 H^2 operator on the oracle's H^2
-    matrix (Yukawa, 4 right-hand sides): the refined bound of the split
-    test, 2 kappa(A~) max(res, res_o)."""
+    matrix (Yukawa): the refined bound of the split test, 2 kappa(A~)
+    max(res, res_o).  One right-hand side takes the 16-byte-load chunks of
+    the packed BF16 copies, two and four the two-rows-per-lane chunks on the
+    same copies."""
     import torch
     p = W.yukawa_cube(n=4096, leaf=128, eps=1e-8, nrhs=4, s=256)
+    print(f"[bf16x3 + bf16 copies] nrhs={nrhs}", flush=True)
     h2f, ranks, pos = _same_h2(p)
     fac = ulv.factor(h2f)
-    b = p.b()
+    b = p.b()[:, :nrhs].copy()
     At = h2matrix.assemble_dense(h2f)
     kappa = np.linalg.cond(At)
     xp, its = ulv.pcg(fac, b, 1e-10, 100)
