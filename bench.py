@@ -46,12 +46,12 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "9e7b18558982c239297fc0b243fec7649526dad4f49f2137d1a9ca3a21ccc822",
-                           "bytes_per_launch": 1.9693e9 + 0.0375e9},
-    "gchunk_kernel<bf16>": {"src": GATHER_SRC, "sha256": "9e7b18558982c239297fc0b243fec7649526dad4f49f2137d1a9ca3a21ccc822",
-                            "bytes_per_launch": 0.4131e9 + 0.0095e9},
-    "greduce_kernel": {"src": GATHER_SRC, "sha256": "9e7b18558982c239297fc0b243fec7649526dad4f49f2137d1a9ca3a21ccc822",
-                       "bytes_per_launch": 0.0179e9 + 0.0013e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
+                           "bytes_per_launch": 1.9949e9 + 0.0375e9},
+    "gv16_kernel<bf16>": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
+                          "bytes_per_launch": 0.3866e9 + 0.0114e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
+                       "bytes_per_launch": 0.0193e9 + 0.0013e9},
 }
 
 
@@ -269,7 +269,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
                       "traffic": None, "launches": st["pair_launches"] * K,
                       "avg_launch_ms": 1e3 * t_pair / K / max(st["pair_launches"], 1),
                       "total_s": t_pair})
-    copies = "gchunk_kernel<bf16>" if sprec == h2.PREC_BF16 else "gchunk_kernel<f32>"
+    # one right-hand side on BF16 copies: the 16-byte-load chunks (gv16_kernel)
+    copies = "gv16_kernel<bf16>" if sprec == h2.PREC_BF16 else "gchunk_kernel<f32>"
     for q, kname in ((0, "gchunk_kernel<f64>"), (1, copies), (2, "greduce_kernel")):
         if n_g[q] == 0:
             continue

@@ -703,13 +703,13 @@ static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtS
     if (ki > 0 && mj > kj) {
       cm.top = off;
       cm.ld_top = r8(ki);
-      sF.push_back({S.poff[p] + (int64_t)kj * mi, off, mi, ki, mj - kj, (int)cm.ld_top});
+      sF.push_back({S.poff[p] + (int64_t)kj * mi, off, 0, mi, ki, mj - kj, (int)cm.ld_top});
       off += cm.ld_top * (mj - kj);
     }
     if (i != j && mi > ki && mj > 0) {
       cm.bot = off;
       cm.ld_bot = r8(mi - ki);
-      sF.push_back({S.poff[p] + ki, off, mi, mi - ki, mj, (int)cm.ld_bot});
+      sF.push_back({S.poff[p] + ki, off, 0, mi, mi - ki, mj, (int)cm.ld_bot});
       off += cm.ld_bot * mj;
     }
     S.cmF.push_back(cm);
@@ -719,11 +719,19 @@ static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtS
   for (int b = 0; b < S.nbox; ++b) {
     const int m = S.m[b];
     CopyMap cm{S.dP + S.qoff[b], m, m, m, m, 0, off, r8(m), -1, 1};
-    if (m > 0) sP.push_back({S.qoff[b], off, m, m, m, (int)cm.ld_top});
+    if (m > 0) sP.push_back({S.qoff[b], off, 0, m, m, m, (int)cm.ld_top});
     off += cm.ld_top * m;
     S.cmP.push_back(cm);
   }
   nP = off;
+  // group prefixes (8 rows of one column per group)
+  for (auto* v : {&sF, &sP}) {
+    int64_t g = 0;
+    for (CvtSeg& x : *v) {
+      x.g0 = g;
+      g += (int64_t)(x.dst_ld / 8) * x.cols;
+    }
+  }
 }
 
 h2_status plan_factor(Ctx& c, hipStream_t st) {
@@ -826,8 +834,8 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       S.dP16 = c.alloc<unsigned short>(std::max<int64_t>(nP, 1));
       ALLOCHK(S.dF16); ALLOCHK(S.dP16);
       if (!upload(c, S.cvF16, sF, st) || !upload(c, S.cvP16, sP, st)) return H2_ERR_ALLOC;
-      for (const CvtSeg& g : sF) S.cvF16_cols = std::max(S.cvF16_cols, g.cols);
-      for (const CvtSeg& g : sP) S.cvP16_cols = std::max(S.cvP16_cols, g.cols);
+      S.cvF16_groups = sF.empty() ? 0 : sF.back().g0 + (int64_t)(sF.back().dst_ld / 8) * sF.back().cols;
+      S.cvP16_groups = sP.empty() ? 0 : sP.back().g0 + (int64_t)(sP.back().dst_ld / 8) * sP.back().cols;
     }
   }
   // index of (instance, level-local box) in each step

@@ -220,6 +220,9 @@ struct GChunk {
   int dlen, drow;           // direct slot length and this chunk's first row in it
   int tlen, tcol;           // trans slot length and this chunk's first column in it
   int rpl;                  // rows per lane: nr <= 64 rpl
+  int vec;                  // 1: FP64 chunk of <= 64 rows of a narrow plan: with
+                            // one right-hand side it is read two rows per lane
+                            // with 16-byte loads (8-byte aligned is enough)
   int64_t od, ot;           // slot offsets (one-rhs units); -1 = no such product
 };
 struct GRed {
@@ -275,6 +278,7 @@ struct CopyMap {
 struct CvtSeg {
   int64_t src_off;
   int64_t dst_off;
+  int64_t g0;               // first of its 8-row groups in the list (prefix)
   int src_ld, rows, cols, dst_ld;
 };
 // A range of FP64 blocks with a reduced-precision copy: esz 4 = FP32, esz 2
@@ -322,10 +326,11 @@ hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t 
 // BF16 copy (round to nearest even) of n doubles (esz_src 8) or floats (4).
 hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, int64_t n,
                            hipStream_t st);
-// Packed BF16 copy: every segment of segs (device, count) from src (FP64 or
-// FP32 arena, esz_src 8 or 4) into dst, zero-padded; max_cols the widest.
+// Packed BF16 copy: every segment of segs (device, count, g0 ascending) from
+// src (FP64 or FP32 arena, esz_src 8 or 4) into dst, zero-padded; groups:
+// the total number of 8-row groups.
 hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs, int count,
-                                int max_cols, unsigned short* dst, hipStream_t st);
+                                int64_t groups, unsigned short* dst, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 

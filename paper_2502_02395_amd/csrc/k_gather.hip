@@ -174,6 +174,93 @@ __device__ __forceinline__ void gchunk_one(const GChunk& ch, double* __restrict_
           P[ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow + lane + 64 * t] = acc[t][c];
 }
 
+// FP64 chunks with GChunk::vec, one right-hand side: lane (g, q) = (lane >> 5,
+// lane & 31) reads rows 2q, 2q+1 of the columns 2u + g of each batch of 2U
+// columns with one 16-byte load (8-byte alignment suffices on this part; a
+// wave moves two columns of 64 rows per load).  With an odd row count the
+// lane of the last row reads that row alone.  Direct sums are reduced over
+// the two lane halves at the end, the transposed ones over the 32 lanes of
+// each half after every batch; both in a fixed order that does not depend
+// on the chunk's address.
+typedef double f64x2a8 __attribute__((ext_vector_type(2), aligned(8)));
+
+template <bool TAIL>
+__device__ __forceinline__ f64x2a8 load_rows2(const double* p, bool both) {
+  if (!TAIL || both)
+    return __builtin_nontemporal_load(reinterpret_cast<gptr_t<f64x2a8>>(as_global(p)));
+  f64x2a8 v;
+  v.x = __builtin_nontemporal_load(as_global(p));
+  v.y = 0.0;
+  return v;
+}
+
+template <int U, bool TAIL>
+__device__ __forceinline__ void gv64_body(const GChunk& ch, double* __restrict__ P, int lane) {
+  static_assert(U == 16, "32 columns per batch");
+  const int q = lane & 31, g = lane >> 5;
+  const bool dir = ch.od >= 0, tr = ch.ot >= 0;
+  const int nr = ch.nr, mc = ch.mc;
+  const int64_t ld = ch.ld;
+  const bool live = 2 * q < nr;
+  const int qe = live ? q : 0;
+  const bool both = 2 * qe + 1 < nr;
+  const double* base = static_cast<const double*>(ch.M) + 2 * qe;
+  const double xt0 = (tr && 2 * q < nr) ? as_global(ch.xt)[2 * q] : 0.0;
+  const double xt1 = (tr && 2 * q + 1 < nr) ? as_global(ch.xt)[2 * q + 1] : 0.0;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int s0 = 0; s0 < mc; s0 += 2 * U) {
+    const double xv = (dir && lane < 2 * U && s0 + lane < mc) ? as_global(ch.xd)[s0 + lane] : 0.0;
+    f64x2a8 d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int cc = min(s0 + 2 * u + g, mc - 1);
+      d[u] = load_rows2<TAIL>(base + (int64_t)cc * ld, both);
+    }
+    if (dir) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double xu = __shfl(xv, 2 * u + g, 64);
+        acc0 += d[u].x * xu;
+        acc1 += d[u].y * xu;
+      }
+    }
+    if (tr) {
+      // sums over the 32 lanes of each half: exchanges at distances 16, 8,
+      // 4, 2 halve the values a lane carries, the last one adds the pair
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = d[u].x * xt0 + d[u].y * xt1;
+      double a[8], b[4], c[2];
+      const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1,
+                 b1 = (lane >> 1) & 1;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        a[j] = (b4 ? v[8 + j] : v[j]) + __shfl_xor(b4 ? v[j] : v[8 + j], 16, 64);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        b[j] = (b3 ? a[4 + j] : a[j]) + __shfl_xor(b3 ? a[j] : a[4 + j], 8, 64);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        c[j] = (b2 ? b[2 + j] : b[j]) + __shfl_xor(b2 ? b[j] : b[2 + j], 4, 64);
+      double e = (b1 ? c[1] : c[0]) + __shfl_xor(b1 ? c[0] : c[1], 2, 64);
+      e += __shfl_xor(e, 1, 64);
+      // lane q holds value (q >> 1): column s0 + 2 (q >> 1) + g
+      const int col = s0 + 2 * (q >> 1) + g;
+      if ((q & 1) == 0 && col < mc) P[ch.ot + ch.tcol + col] = e;
+    }
+  }
+  if (dir) {
+    // rows 2q, 2q+1 summed over the two halves: lane (q, g) keeps row 2q + g
+    const double r = (g ? acc1 : acc0) + __shfl_xor(g ? acc0 : acc1, 32, 64);
+    if (2 * q + g < nr) P[ch.od + ch.drow + 2 * q + g] = r;
+  }
+}
+
+__device__ __forceinline__ void gv64_one(const GChunk& ch, double* __restrict__ P, int lane) {
+  if (__builtin_amdgcn_readfirstlane(ch.nr) & 1) gv64_body<16, true>(ch, P, lane);
+  else gv64_body<16, false>(ch, P, lane);
+}
+
 // RMAX: the largest rows-per-lane of the plan the chunks come from; each
 // chunk runs the variant of its own row count (wave-uniform).  BW: columns
 // per batch; 8 keeps the wide variants at four or more waves per SIMD.
@@ -185,6 +272,9 @@ __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ 
   const GChunk& ch = chunks[w];
   const int rpl = __builtin_amdgcn_readfirstlane(ch.rpl);
   const int lane = threadIdx.x & 63;
+  if constexpr (NR == 1 && sizeof(T) == 8 && RMAX == 1) {
+    if (__builtin_amdgcn_readfirstlane(ch.vec)) { gv64_one(ch, P, lane); return; }
+  }
   if constexpr (RMAX >= 4) {
     if (rpl >= 4) { gchunk_one<NR, T, 4, BW>(ch, P, nrhs, lane); return; }
     if (rpl == 3) { gchunk_one<NR, T, 3, BW>(ch, P, nrhs, lane); return; }

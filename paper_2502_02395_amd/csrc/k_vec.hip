@@ -1,4 +1,6 @@
 // Kernel-matrix evaluation and vector utilities.
+#include <climits>
+
 #include "h2_internal.hpp"
 
 namespace h2 {
@@ -123,51 +125,63 @@ hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, in
   return hipGetLastError();
 }
 
-// Packed BF16 copies: block x = segment, the threads of the y blocks stride
-// over its (column, 8-row group) pairs; each thread converts eight rows of a
-// column (rounded like cvt_bf16_kernel: to FP32, then to BF16, nearest even)
-// and writes them with one 16-byte store; rows from `rows` up to dst_ld are
-// written as zeros.
+// Packed BF16 copies: one thread per 8-row group of a column over the whole
+// list; the block's first segment is found once by binary search on the
+// group prefix, each thread then steps forward to its own (a block of 256
+// groups spans few segments).  Each thread converts eight rows (rounded like
+// cvt_bf16_kernel: to FP32, then to BF16, nearest even) and writes them with
+// one 16-byte store; rows from `rows` up to dst_ld are written as zeros.
 template <typename TS>
 __global__ __launch_bounds__(256) void cvt_bf16_segs_kernel(const TS* __restrict__ src,
                                                             const CvtSeg* __restrict__ segs,
+                                                            int count, int64_t groups,
                                                             unsigned short* __restrict__ dst) {
-  const CvtSeg g = segs[blockIdx.x];
-  const int groups = g.dst_ld / 8;
-  const int64_t work = (int64_t)groups * g.cols;
-  for (int64_t e = threadIdx.x + 256 * (int64_t)blockIdx.y; e < work; e += 256 * (int64_t)gridDim.y) {
-    const int col = (int)(e / groups), rg = (int)(e % groups);
-    const TS* sc = src + g.src_off + (int64_t)col * g.src_ld;
-    unsigned short* dc = dst + g.dst_off + (int64_t)col * g.dst_ld;
-    {
-      unsigned short h[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int r = 8 * rg + t;
-        const __bf16 b = (__bf16)(float)(r < g.rows ? sc[r] : TS(0));
-        h[t] = __builtin_bit_cast(unsigned short, b);
-      }
-      uint4 v;
-      v.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
-      v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
-      v.z = (unsigned)h[4] | ((unsigned)h[5] << 16);
-      v.w = (unsigned)h[6] | ((unsigned)h[7] << 16);
-      *reinterpret_cast<uint4*>(dc + 8 * rg) = v;
+  __shared__ int first;
+  const int64_t e0 = (int64_t)blockIdx.x * 256;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = count - 1;  // last segment with g0 <= e0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].g0 <= e0) lo = mid; else hi = mid - 1;
     }
+    first = lo;
   }
+  __syncthreads();
+  const int64_t e = e0 + threadIdx.x;
+  if (e >= groups) return;
+  int sg = first;
+  while (sg + 1 < count && segs[sg + 1].g0 <= e) ++sg;
+  const CvtSeg g = segs[sg];
+  const int per_col = g.dst_ld / 8;
+  const int64_t le = e - g.g0;
+  const int col = (int)(le / per_col), rg = (int)(le % per_col);
+  const TS* sc = src + g.src_off + (int64_t)col * g.src_ld;
+  unsigned short h[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int r = 8 * rg + t;
+    const __bf16 b = (__bf16)(float)(r < g.rows ? sc[r] : TS(0));
+    h[t] = __builtin_bit_cast(unsigned short, b);
+  }
+  uint4 v;
+  v.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+  v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+  v.z = (unsigned)h[4] | ((unsigned)h[5] << 16);
+  v.w = (unsigned)h[6] | ((unsigned)h[7] << 16);
+  *reinterpret_cast<uint4*>(dst + g.dst_off + (int64_t)col * g.dst_ld + 8 * rg) = v;
 }
 
 hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs, int count,
-                                int max_cols, unsigned short* dst, hipStream_t st) {
-  if (count <= 0 || max_cols <= 0) return hipSuccess;
-  // max_cols columns of up to 96 groups (768 rows): a few y blocks suffice
-  const dim3 grid((unsigned)count, (unsigned)std::min((max_cols + 15) / 16, 8)), blk(256);
+                                int64_t groups, unsigned short* dst, hipStream_t st) {
+  if (count <= 0 || groups <= 0) return hipSuccess;
+  if ((groups + 255) / 256 > INT_MAX) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)((groups + 255) / 256);
   if (esz_src == 8)
-    hipLaunchKernelGGL(cvt_bf16_segs_kernel<double>, grid, blk, 0, st,
-                       static_cast<const double*>(src), segs, dst);
+    hipLaunchKernelGGL(cvt_bf16_segs_kernel<double>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const double*>(src), segs, count, groups, dst);
   else if (esz_src == 4)
-    hipLaunchKernelGGL(cvt_bf16_segs_kernel<float>, grid, blk, 0, st,
-                       static_cast<const float*>(src), segs, dst);
+    hipLaunchKernelGGL(cvt_bf16_segs_kernel<float>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const float*>(src), segs, count, groups, dst);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
