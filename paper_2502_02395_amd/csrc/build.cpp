@@ -836,6 +836,20 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       if (!upload(c, S.cvF16, sF, st) || !upload(c, S.cvP16, sP, st)) return H2_ERR_ALLOC;
       S.cvF16_groups = sF.empty() ? 0 : sF.back().g0 + (int64_t)(sF.back().dst_ld / 8) * sF.back().cols;
       S.cvP16_groups = sP.empty() ? 0 : sP.back().g0 + (int64_t)(sP.back().dst_ld / 8) * sP.back().cols;
+      // the segment of the first group of every 256-group block
+      auto firsts = [](const std::vector<CvtSeg>& v, int64_t groups) {
+        std::vector<int> f((size_t)((groups + 255) / 256));
+        size_t sg = 0;
+        for (size_t b = 0; b < f.size(); ++b) {
+          const int64_t e = (int64_t)b * 256;
+          while (sg + 1 < v.size() && v[sg + 1].g0 <= e) ++sg;
+          f[b] = (int)sg;
+        }
+        return f;
+      };
+      if (!upload(c, S.cvF16_first, firsts(sF, S.cvF16_groups), st) ||
+          !upload(c, S.cvP16_first, firsts(sP, S.cvP16_groups), st))
+        return H2_ERR_ALLOC;
     }
   }
   // index of (instance, level-local box) in each step

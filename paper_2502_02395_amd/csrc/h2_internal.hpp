@@ -328,9 +328,11 @@ hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, in
                            hipStream_t st);
 // Packed BF16 copy: every segment of segs (device, count, g0 ascending) from
 // src (FP64 or FP32 arena, esz_src 8 or 4) into dst, zero-padded; groups:
-// the total number of 8-row groups.
-hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs, int count,
-                                int64_t groups, unsigned short* dst, hipStream_t st);
+// the total number of 8-row groups; first (device, one per 256 groups): the
+// segment holding group 256 b.
+hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs,
+                                const int* first, int count, int64_t groups,
+                                unsigned short* dst, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
                           const double* P, int nrhs, hipStream_t st);
 

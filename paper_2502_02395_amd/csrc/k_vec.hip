@@ -126,30 +126,20 @@ hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, in
 }
 
 // Packed BF16 copies: one thread per 8-row group of a column over the whole
-// list; the block's first segment is found once by binary search on the
-// group prefix, each thread then steps forward to its own (a block of 256
-// groups spans few segments).  Each thread converts eight rows (rounded like
+// list; first[b] is the segment of block b's first group (planned on the
+// host), each thread steps forward from it to its own (a block of 256 groups
+// spans few segments).  Each thread converts eight rows (rounded like
 // cvt_bf16_kernel: to FP32, then to BF16, nearest even) and writes them with
 // one 16-byte store; rows from `rows` up to dst_ld are written as zeros.
 template <typename TS>
 __global__ __launch_bounds__(256) void cvt_bf16_segs_kernel(const TS* __restrict__ src,
                                                             const CvtSeg* __restrict__ segs,
+                                                            const int* __restrict__ first,
                                                             int count, int64_t groups,
                                                             unsigned short* __restrict__ dst) {
-  __shared__ int first;
-  const int64_t e0 = (int64_t)blockIdx.x * 256;
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = count - 1;  // last segment with g0 <= e0
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].g0 <= e0) lo = mid; else hi = mid - 1;
-    }
-    first = lo;
-  }
-  __syncthreads();
-  const int64_t e = e0 + threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= groups) return;
-  int sg = first;
+  int sg = first[blockIdx.x];
   while (sg + 1 < count && segs[sg + 1].g0 <= e) ++sg;
   const CvtSeg g = segs[sg];
   const int per_col = g.dst_ld / 8;
@@ -171,17 +161,18 @@ __global__ __launch_bounds__(256) void cvt_bf16_segs_kernel(const TS* __restrict
   *reinterpret_cast<uint4*>(dst + g.dst_off + (int64_t)col * g.dst_ld + 8 * rg) = v;
 }
 
-hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs, int count,
-                                int64_t groups, unsigned short* dst, hipStream_t st) {
+hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs,
+                                const int* first, int count, int64_t groups,
+                                unsigned short* dst, hipStream_t st) {
   if (count <= 0 || groups <= 0) return hipSuccess;
   if ((groups + 255) / 256 > INT_MAX) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((groups + 255) / 256);
   if (esz_src == 8)
     hipLaunchKernelGGL(cvt_bf16_segs_kernel<double>, dim3(grid), dim3(256), 0, st,
-                       static_cast<const double*>(src), segs, count, groups, dst);
+                       static_cast<const double*>(src), segs, first, count, groups, dst);
   else if (esz_src == 4)
     hipLaunchKernelGGL(cvt_bf16_segs_kernel<float>, dim3(grid), dim3(256), 0, st,
-                       static_cast<const float*>(src), segs, count, groups, dst);
+                       static_cast<const float*>(src), segs, first, count, groups, dst);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
