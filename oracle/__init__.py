@@ -22,7 +22,11 @@ no blocking, fusion or reordering beyond what the paper states:
   flops.py      the canonical algorithmic flop count
   mlp.py        FP64 reference of the rank-predictor MLP (forward, backward,
                 Adam) used to check the GPU training kernels
+  ulv_lu.py     the LU variant of the factorization and substitution for
+                non-symmetric kernel matrices (the paper states the method for
+                symmetric positive definite matrices only; this variant keeps
+                its structure with a pivot-free LU of the redundant blocks)
 
-Readings of passages the paper leaves silent or garbled are listed in
-the design doc; each function's docstring cites the passage it follows.
+Each function's docstring cites the passage it follows and states the
+reading it takes where the paper is silent or garbled.
 """

@@ -122,9 +122,18 @@ def construct(X: np.ndarray, kernel, leaf: int, eta: float, eps: float,
     running the pivoted QR; the remaining rows follow in increasing position.
     Used to build an H^2 matrix with a prescribed skeleton selection.
     ``gs_sweeps`` > 0 replaces the exact solve with A_cc by that many
-    Gauss-Seidel sweeps (Section 3.5)."""
+    Gauss-Seidel sweeps (Section 3.5).
+
+    Non-symmetric kernels (the LU variant; the paper treats symmetric
+    matrices only): box i keeps one basis for its rows and its columns, so the
+    interpolative decomposition runs on [G(B_i,S_F), G(S_F,B_i)^T,
+    G(B_i,S_C) A_cc^{-1}, (A_cc^{-1} G(S_C,B_i))^T], the far field and the
+    fill-in seen from both sides (A_cc by an LU factorization, or Gauss-Seidel
+    sweeps on A_cc^T and A_cc); couplings and near blocks are evaluated for
+    every ordered pair, as for symmetric kernels."""
     tree = ClusterTree(X, leaf, eta)
     L = tree.L
+    sym = kernels.symmetric(kernel)
     n = X.shape[0]
     pirank = np.empty(n, dtype=np.int64)
     pirank[pi] = np.arange(n)
@@ -151,14 +160,31 @@ def construct(X: np.ndarray, kernel, leaf: int, eta: float, eps: float,
             if SC.size:
                 A_cc = kernels.evaluate(kernel, X[SC], X[SC], SC, SC)
                 G_bc = kernels.evaluate(kernel, X[Bi], X[SC], Bi, SC)
-                if gs_sweeps > 0:
+                if not sym:
+                    # the column side of the fill-in, A_cc^{-1} G(S_C, B_i)
+                    G_cb = kernels.evaluate(kernel, X[SC], X[Bi], SC, Bi)
+                    if gs_sweeps > 0:
+                        A_close = gauss_seidel(A_cc.T, G_bc.T, gs_sweeps).T
+                        A_close_c = gauss_seidel(A_cc, G_cb, gs_sweeps).T
+                    else:
+                        lf = sla.lu_factor(A_cc)
+                        A_close = sla.lu_solve(lf, G_bc.T, trans=1).T   # G(B_i,S_C) A_cc^{-1}
+                        A_close_c = sla.lu_solve(lf, G_cb).T            # (A_cc^{-1} G(S_C,B_i))^T
+                elif gs_sweeps > 0:
                     A_close = gauss_seidel(A_cc, G_bc.T, gs_sweeps).T
                 else:
                     cf = sla.cho_factor(A_cc, lower=True)
                     A_close = sla.cho_solve(cf, G_bc.T).T   # G(B_i,S_C) A_cc^{-1}
             else:
                 A_close = np.zeros((Bi.size, 0))
-            M = np.hstack([A_far, A_close])
+                A_close_c = np.zeros((Bi.size, 0))
+            if sym:
+                M = np.hstack([A_far, A_close])
+            else:
+                # one shared basis for the rows and the columns of box i: the
+                # far field seen from both sides and both sides of the fill-in
+                A_far_c = kernels.evaluate(kernel, X[SF], X[Bi], SF, Bi).T
+                M = np.hstack([A_far, A_far_c, A_close, A_close_c])
             if skeletons is not None:
                 sk = np.asarray(skeletons[(l, i)], dtype=np.int64)
                 k = sk.size

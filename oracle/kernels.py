@@ -8,6 +8,15 @@ Matern-3/2 covariance kernels take a nugget added where the two point indices
 are equal (by index, not by distance).
 
 Distance: r = sqrt(sum_d (x_d - y_d)^2), summed over axes 0..d-1 in order.
+
+A non-symmetric kernel for the LU variant (not in the paper, whose method is
+stated for symmetric positive definite matrices): the Yukawa kernel with a
+drift along the first axis,
+    G(x, y) = exp(-kappa r) / (r + delta) * (1 + beta (x_0 - y_0) / (r + delta)).
+Its symmetric part is the Yukawa kernel and the rest is skew-symmetric, so
+x^T A x = x^T A_sym x: where the Yukawa matrix is positive definite, every
+leading principal block of A is non-singular and an LU factorization without
+pivoting exists.
 """
 from __future__ import annotations
 
@@ -15,7 +24,12 @@ import math
 
 import numpy as np
 
-LAPLACE, YUKAWA, GAUSSIAN, MATERN32 = 0, 1, 2, 3
+LAPLACE, YUKAWA, GAUSSIAN, MATERN32, YUKAWA_DRIFT = 0, 1, 2, 3, 4
+
+
+def symmetric(kernel) -> bool:
+    """Whether G(x, y) = G(y, x) for this kernel."""
+    return kernel.id != YUKAWA_DRIFT or getattr(kernel, "beta", 0.0) == 0.0
 
 
 def distances(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
@@ -45,6 +59,9 @@ def evaluate(kernel, X: np.ndarray, Y: np.ndarray,
     elif kid == MATERN32:
         a = math.sqrt(3.0) * r / kernel.ell
         v = (1.0 + a) * np.exp(-a)
+    elif kid == YUKAWA_DRIFT:
+        dx = X[:, 0][:, None] - Y[:, 0][None, :]
+        v = np.exp(-kernel.kappa * r) / (r + kernel.delta) * (1.0 + kernel.beta * dx / (r + kernel.delta))
     else:
         raise ValueError(f"unknown kernel id {kid}")
     if kernel.nugget != 0.0 and ix is not None and iy is not None:

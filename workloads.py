@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-LAPLACE, YUKAWA, GAUSSIAN, MATERN32 = 0, 1, 2, 3
+LAPLACE, YUKAWA, GAUSSIAN, MATERN32, YUKAWA_DRIFT = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass(frozen=True)
@@ -37,6 +37,7 @@ class Kernel:
     kappa: float = 1.0
     ell: float = 1.0
     nugget: float = 0.0
+    beta: float = 0.0    # drift strength of the non-symmetric kernel (id 4)
 
 
 def cube_points(n: int, dim: int = 3, seed: int = 0) -> np.ndarray:
@@ -121,6 +122,16 @@ def yukawa_cube(n: int = 262144, leaf: int = 256, eps: float = 1e-8,
         s = 2 * leaf
     return Problem("yukawa_cube", cube_points(n, 3, 0),
                    Kernel(YUKAWA, delta=1e-3, kappa=1.0), leaf, eta, eps, nrhs, s, s)
+
+
+def yukawa_drift_cube(n: int = 4096, leaf: int = 128, eps: float = 1e-8, beta: float = 0.5,
+                      eta: float = 1.0, nrhs: int = 1, s: int | None = None) -> Problem:
+    """Uniform cube, the non-symmetric Yukawa kernel with a drift of strength
+    beta along the first axis (the LU variant's test problem)."""
+    if s is None:
+        s = 2 * leaf
+    return Problem("yukawa_drift_cube", cube_points(n, 3, 0),
+                   Kernel(YUKAWA_DRIFT, delta=1e-3, kappa=1.0, beta=beta), leaf, eta, eps, nrhs, s, s)
 
 
 def matern_cube(n: int = 1 << 20, leaf: int = 256, eps: float = 1e-6,
