@@ -185,7 +185,7 @@ def train_rank_model(a, h2):
     return model
 
 
-def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
+def run_path(a, h2, prec: int, sprec: int, model, label: str, mvprec: int = 0) -> dict:
     """Build once (untimed), W warm-up steps, then time K steps of factor +
     solve with the inputs resident in HBM."""
     import torch
@@ -204,7 +204,7 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
         H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=a.s,
                      s_near=a.s_near, ir_max_iter=100, ir_tol=a.tol, timing=True,
                      gemm_prec=prec, rank_model=model, use_graph=a.graph,
-                     use_pcg=not a.stationary, solve_prec=sprec)
+                     use_pcg=not a.stationary, solve_prec=sprec, matvec_prec=mvprec)
         bnp = p.b()
         n_total = p.n
     t_build = time.perf_counter() - t0
@@ -226,8 +226,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     K = a.steps
     t_fac = t_sol = t_pair = 0.0
     t_phase = [0.0] * 9
-    t_g, b_g, n_g = [0.0] * 3, [0.0] * 3, [0] * 3
-    iters = 0
+    t_g, b_g, n_g = [0.0] * 4, [0.0] * 4, [0] * 4
+    iters = fp64_mv = 0
     res = 0.0
     t0 = time.perf_counter()
     for k in range(K):
@@ -245,7 +245,11 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
             t_g[q] += st["t_gather"][q]
             b_g[q] += st["bytes_gather"][q]
             n_g[q] += st["gather_launches"][q]
+        t_g[3] += st["t_gather_mv32"]
+        b_g[3] += st["bytes_gather_mv32"]
+        n_g[3] += st["gather_launches_mv32"]
         iters += st["ir_iters"]
+        fp64_mv += st["ir_fp64_matvecs"]
         res = max(res, st["ir_residual"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -271,7 +275,8 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
                       "total_s": t_pair})
     # one right-hand side on BF16 copies: the 16-byte-load chunks (gv16_kernel)
     copies = "gv16_kernel<bf16>" if sprec == h2.PREC_BF16 else "gchunk_kernel<f32>"
-    for q, kname in ((0, "gchunk_kernel<f64>"), (1, copies), (2, "greduce_kernel")):
+    for q, kname in ((0, "gchunk_kernel<f64>"), (1, copies), (2, "greduce_kernel"),
+                     (3, "gchunk_kernel<f32> (PCG products)")):
         if n_g[q] == 0:
             continue
         gbs = b_g[q] / max(t_g[q], 1e-30) / 1e9
@@ -284,6 +289,7 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str) -> dict:
     return {
         "value": flops_step * K / dt / 1e12, "ms_per_step": 1e3 * dt / K, "n_total": n_total,
         "factor_s": t_fac / K, "solve_s": t_sol / K, "ir_iters": iters / K, "residual": res,
+        "fp64_matvecs": fp64_mv / K,
         "build_s": t_build, "stats": st, "cands": cands,
         "factor_phase_s": dict(zip(PHASES, [round(x / K, 5) for x in t_phase])),
         "factor_roofline": factor_roofline(st, [x / K for x in t_phase], t_fac / K, prec),
@@ -309,12 +315,16 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per solve")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
                     help="target: rank-predicted buffers, split-BF16 transform GEMMs on FP32 "
-                         "copies and BF16 copies for the substitution, timed next to the "
-                         "plain FP64 path "
-                         "(default); plain: the FP64 path "
-                         "only; custom: --prec / --solve-prec / --rank-model as given")
+                         "copies, packed BF16 copies for the substitution and PCG products on "
+                         "FP32 copies of the near blocks and couplings (stopped by the FP64 "
+                         "operator's residual), timed next to the plain FP64 path (default); "
+                         "plain: the FP64 path only; custom: --prec / --solve-prec / --mv-prec / "
+                         "--rank-model as given")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16", "bf16x3"],
                     help="custom path: precision of the basis-transform and Schur-update GEMMs")
+    ap.add_argument("--mv-prec", default="fp64", choices=["fp64", "fp32"],
+                    help="custom path: precision of the near blocks and couplings PCG's "
+                         "products read (the residual that stops it is the FP64 operator's)")
     ap.add_argument("--solve-prec", default="fp64", choices=["fp64", "fp32", "bf16"],
                     help="custom path: precision of the factor copies the substitution reads "
                          "(the H^2 matvec, the refinement and all arithmetic stay FP64)")
@@ -359,16 +369,16 @@ def main():
     plain = None
     if a.path == "custom":
         model = train_rank_model(a, h2) if a.rank_model else None
-        setting = (a.prec, a.solve_prec, a.rank_model)
-        r = run_path(a, h2, P[a.prec], P[a.solve_prec], model, "custom")
+        setting = (a.prec, a.solve_prec, a.rank_model, a.mv_prec)
+        r = run_path(a, h2, P[a.prec], P[a.solve_prec], model, "custom", P[a.mv_prec])
     elif a.path == "plain":
-        setting = ("fp64", "fp64", False)
+        setting = ("fp64", "fp64", False, "fp64")
         r = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain")
     else:
         plain = run_path(a, h2, h2.PREC_FP64, h2.PREC_FP64, None, "plain fp64")
         model = train_rank_model(a, h2) if a.kernel != "gaussian_batch" else None
-        setting = ("bf16x3", "bf16", model is not None)
-        r = run_path(a, h2, h2.PREC_BF16X3, h2.PREC_BF16, model, "target")
+        setting = ("bf16x3", "bf16", model is not None, "fp32")
+        r = run_path(a, h2, h2.PREC_BF16X3, h2.PREC_BF16, model, "target", h2.PREC_FP32)
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20:
         for d in r["cands"]:  # traffic was measured on this workload and path
             d["traffic"] = measured_traffic(d["kernel"])
@@ -389,6 +399,7 @@ def main():
                    "dim": 2 if a.kernel == "gaussian_batch" else 3, "leaf": a.leaf,
                    "eta": 1.0, "eps": a.eps, "s_far": a.s, "s_near": a.s_near, "nrhs": a.nrhs,
                    "gemm_prec": setting[0], "solve_prec": setting[1], "rank_model": setting[2],
+                   "matvec_prec": setting[3],
                    "graph": a.graph, "rank_fallbacks": st["rank_fallbacks"],
                    "basis_bytes": st["bytes_basis"], "autotuned_lists": st["tuned_lists"],
                    "tile_choice": st["tuned_cfg_hist"], "ir_tol": a.tol, "levels": st["levels"],
@@ -397,6 +408,7 @@ def main():
         "factor_s": r["factor_s"], "factor_phase_s": r["factor_phase_s"],
         "factor_roofline": r["factor_roofline"], "solve_roofline": r["solve_roofline"],
         "solve_s": r["solve_s"], "ir_iters": r["ir_iters"], "residual": r["residual"],
+        "fp64_matvecs": r["fp64_matvecs"],
         "build_s": r["build_s"], "build_id_s": st["t_build_id"],
         "flops_factor": st["flops_factor"],
         "flops_solve": st["flops_solve"],

@@ -127,6 +127,15 @@ typedef struct {
                              with the box in h2_stats                          */
   const h2_allocator* allocator; /* host; copied at build; NULL = hipMalloc and
                              hipFree                                          */
+  int32_t matvec_prec;    /* h2_prec (FP64 or FP32) of the leaf near blocks and
+                             couplings that PCG's iterations multiply with.
+                             FP32: FP32 copies made at build, products and sums
+                             FP64; when PCG's own residual reaches ir_tol the
+                             residual is recomputed with the FP64 H^2 operator,
+                             and PCG restarts from it while that one is above
+                             ir_tol (at most 8 restarts).  The returned
+                             residual is always the FP64 operator's.  Stationary
+                             refinement ignores it                            */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -190,6 +199,14 @@ typedef struct {
                                (Section 3.5), summed over boxes with a near
                                sample of size c: c^3/3 + 2 c^2 m, or
                                2 c^2 m per Gauss-Seidel sweep                  */
+  int32_t ir_fp64_matvecs;  /* FP64 H^2 products of the last solve (PCG with
+                               matvec_prec FP32: the initial and every
+                               recomputed residual)                            */
+  double t_gather_mv32;     /* as t_gather, bytes_gather, gather_launches for
+                               the products on FP32 copies of the near blocks
+                               and couplings (matvec_prec FP32)                */
+  double bytes_gather_mv32;
+  int32_t gather_launches_mv32;
 } h2_stats_t;
 
 /* Capacity, in doubles, of the fixed device array that h2_solve_noalloc uses

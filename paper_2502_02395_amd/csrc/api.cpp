@@ -268,6 +268,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
     c.gkind.clear();
   }
   int iters_total = 0;
+  int fp64_mv = 0;
   double worst = 0.0;
   bool noconv = false;
   for (int64_t c0 = 0; c0 < nrhs; c0 += chunk) {
@@ -290,6 +291,11 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
       if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
       HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
       const bool pcg = c.prm.use_pcg != 0;
+      // PCG on FP32 copies of the near blocks and couplings: its own
+      // residual decides when to look at the FP64 operator's
+      const bool lowp = pcg && c.prm.matvec_prec == H2_PREC_FP32;
+      int restarts = 0;
+      ++fp64_mv;
       if (pcg) {
         if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
         HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
@@ -307,6 +313,29 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
           if (!(rel <= res)) res = rel;  // a NaN column makes res NaN
         }
         if (!std::isfinite(res)) { noconv = true; break; }
+        if (res <= c.prm.ir_tol && lowp) {
+          // the FP64 operator's residual r = b - A x; restart PCG from it
+          // while it is above the target
+          if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          ++fp64_mv;
+          HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
+          if ((e = colnorms(c, c.w_r, nc, sc, st)) != H2_OK) return e;
+          HIPCHK(hipMemcpyAsync(hr, sc, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          res = 0.0;
+          for (int q = 0; q < nc; ++q) {
+            const double rel = hb[q] > 0 ? std::sqrt(hr[q] / hb[q]) : std::sqrt(hr[q]);
+            if (!(rel <= res)) res = rel;
+          }
+          if (!std::isfinite(res)) { noconv = true; break; }
+          if (res <= c.prm.ir_tol) break;
+          if (restarts >= 8 || it >= maxit) { noconv = true; break; }
+          ++restarts;
+          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
+          HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 32, st));
+          continue;
+        }
         if (res <= c.prm.ir_tol) break;
         if (it >= maxit) { noconv = true; break; }
         ++it;
@@ -314,9 +343,11 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
           if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
           HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 1.0, st));
           if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          ++fp64_mv;
           HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
         } else {
-          if ((e = do_matvec_chunk(c, c.w_p, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          if ((e = do_matvec_chunk(c, c.w_p, c.N, c.w_q, c.N, nc, st, lowp)) != H2_OK) return e;
+          if (!lowp) ++fp64_mv;
           HIPCHK(launch_coldot(c.w_p, c.N, c.w_q, c.N, c.N, nc, c.dWs, sc + 48, st));
           HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_p, c.N, c.N, nc, sc + 32, sc + 48, 1.0, st));
           HIPCHK(launch_axpby(c.w_r, c.N, c.w_r, c.N, c.w_q, c.N, c.N, nc, sc + 32, sc + 48, -1.0, st));
@@ -335,8 +366,8 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
   c.st.t_solve = now_seconds() - t0;
   if (c.gtime) {
     c.gtime = false;
-    double tt[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
-    int nl[3] = {0, 0, 0};
+    double tt[4] = {0.0, 0.0, 0.0, 0.0}, bb[4] = {0.0, 0.0, 0.0, 0.0};
+    int nl[4] = {0, 0, 0, 0};
     for (size_t q = 0; q + 3 <= c.gev_used; q += 3) {
       float ms0 = 0.f, ms1 = 0.f;
       HIPCHK(hipEventElapsedTime(&ms0, c.gev[q], c.gev[q + 1]));
@@ -350,7 +381,11 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
       c.st.bytes_gather[q] = bb[q];
       c.st.gather_launches[q] = nl[q];
     }
+    c.st.t_gather_mv32 = tt[3];
+    c.st.bytes_gather_mv32 = bb[3];
+    c.st.gather_launches_mv32 = nl[3];
   }
+  c.st.ir_fp64_matvecs = fp64_mv;
   c.st.ir_iters = iters_total;
   c.st.ir_residual = worst;
   return noconv ? H2_ERR_NOCONV : H2_OK;

@@ -204,6 +204,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       prm->solve_prec != H2_PREC_BF16)
     return H2_ERR_ARG;
   if (prm->gs_sweeps < 0 || prm->gs_sweeps > 64) return H2_ERR_ARG;
+  if (prm->matvec_prec != H2_PREC_FP64 && prm->matvec_prec != H2_PREC_FP32) return H2_ERR_ARG;
   if (prm->gemm_prec != H2_PREC_FP64 && prm->gemm_prec != H2_PREC_FP32 &&
       prm->gemm_prec != H2_PREC_BF16 && prm->gemm_prec != H2_PREC_BF16X3)
     return H2_ERR_ARG;
@@ -820,6 +821,17 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       S.dT2 = c.alloc<double>(S.poff[np]);
       S.dT3 = c.alloc<double>(S.soff.back());
       ALLOCHK(S.dT2); ALLOCHK(S.dT3);
+      if (c.prm.matvec_prec == H2_PREC_FP32) {
+        // FP32 copies of the operator's stored blocks for PCG's products
+        S.dS32 = c.alloc<float>(std::max<int64_t>(S.soff.back(), 1));
+        ALLOCHK(S.dS32);
+        HIPCHK(launch_cvt_f32(S.dS, S.dS32, S.soff.back(), st));
+        if (h == 0) {
+          S.dD32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
+          ALLOCHK(S.dD32);
+          HIPCHK(launch_cvt_f32(S.dD, S.dD32, S.poff[np], st));
+        }
+      }
     }
     if (f32pair || c.prm.solve_prec == H2_PREC_FP32) {
       S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));

@@ -47,6 +47,7 @@ struct GList {
                                            // for FP32 / BF16 copies
   bool has_w = false;
   bool v16 = false;                        // n reads packed BF16 copies (GatherPlan::v16)
+  int kind = -1;                           // timing class (h2_stats); -1: by esz
   const GSet& pick(int nrhs) const { return has_w && nrhs <= GATHER_WIDE_NR ? w : n; }
 };
 
@@ -180,6 +181,8 @@ struct Ctx {
   double *vt_in = nullptr, *vt_out = nullptr;
   Batch<CopyDesc> r_in, r_out;             // root-only instances <-> v_root
   GList t_root;                            // root-only instances: matvec
+  GList g_mv32;                            // the same list on FP32 copies of the leaf
+                                           // near blocks and couplings (matvec_prec FP32)
   GList g_mv;                              // matvec: couplings y^ = S x^ of every level
                                            // and the leaf near field y = D x
   // refinement vectors (N x NRHS_MAX)
@@ -303,7 +306,7 @@ h2_status do_factor(Ctx& c, hipStream_t st);
 h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
                          hipStream_t st);
 h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs,
-                          hipStream_t st);
+                          hipStream_t st, bool lowp = false);
 double now_seconds();
 
 hipError_t launch_set_int(int* p, int v, hipStream_t st);

@@ -121,7 +121,7 @@ static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
     c.gev_used += 3;
     c.gbytes.push_back(S.bytes_ch_mat + S.bytes_ch_vec * nrhs);
     c.gbytes.push_back(S.bytes_rd * nrhs);
-    c.gkind.push_back(L.esz < 8 ? 1 : 0);
+    c.gkind.push_back(L.kind >= 0 ? L.kind : L.esz < 8 ? 1 : 0);
   }
   return hipSuccess;
 }
@@ -416,6 +416,16 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       Nv.insert(Nv.end(), mv_n[q].begin(), mv_n[q].end());
     }
     if (!up_gather(c, c.g_mv, B, Nv, st)) return H2_ERR_ALLOC;
+    if (c.prm.matvec_prec == H2_PREC_FP32) {
+      // the same products on the FP32 copies (PCG's inner products)
+      std::vector<Rebase> rb32;
+      for (const Step& S : c.steps)
+        if (S.dS32 && S.soff.back() > 0) rb32.push_back({S.dS, S.soff.back(), S.dS32, 4});
+      const Step& S0 = c.steps[0];
+      if (S0.dD32 && S0.poff.back() > 0) rb32.push_back({S0.dD, S0.poff.back(), S0.dD32, 4});
+      if (!up_gather(c, c.g_mv32, B, Nv, st, rb32)) return H2_ERR_ALLOC;
+      c.g_mv32.kind = 3;
+    }
   }
   // root solves and root-only instances
   {
@@ -690,10 +700,12 @@ h2_status do_solve_chunk(Ctx& c, const double* b, int64_t ldb, double* x, int64_
 }
 
 h2_status do_matvec_chunk(Ctx& c, const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs,
-                          hipStream_t st) {
+                          hipStream_t st, bool lowp) {
+  if (lowp && c.g_mv32.n.rd.count == 0 && c.g_mv.n.rd.count > 0) return H2_ERR_STATE;
   HIPCHK(launch_gather_rows(c.dPermG, c.N, nrhs, x, ldx, c.vt_in, c.N, st));
   for (int h = 0; h < c.H; ++h) HIPCHK(gather(c, c.steps[h].t_up, nrhs, st));
-  HIPCHK(gather(c, c.g_mv, nrhs, st));  // couplings of every level, leaf near field
+  // couplings of every level, leaf near field
+  HIPCHK(gather(c, lowp ? c.g_mv32 : c.g_mv, nrhs, st));
   for (int h = c.H - 1; h >= 0; --h) HIPCHK(gather(c, c.steps[h].t_down, nrhs, st));
   HIPCHK(gather(c, c.t_root, nrhs, st));
   HIPCHK(launch_scatter_rows(c.dPermG, c.N, nrhs, c.vt_out, c.N, y, ldy, st));

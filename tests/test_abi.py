@@ -51,7 +51,8 @@ def test_status_strings_and_argument_errors_without_gpu():
     assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
                       ctypes.byref(out)) == h2.ERR_ARG
     # Gauss-Seidel sweeps outside 0..64, unknown precisions
-    for kw in ({"gs_sweeps": -1}, {"gs_sweeps": 65}, {"gemm_prec": 7}, {"solve_prec": 3}):
+    for kw in ({"gs_sweeps": -1}, {"gs_sweeps": 65}, {"gemm_prec": 7}, {"solve_prec": 3},
+               {"matvec_prec": 2}):
         prm = h2.make_params(3, 8, 1.0, 1e-6, **kw)
         assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
                           ctypes.byref(out)) == h2.ERR_ARG, kw

@@ -171,3 +171,41 @@ def test_bf16_substitution_with_split_bf16_transforms(lib, nrhs):
     assert st["ir_residual"] <= 1e-10
     assert res.max() <= 1.1e-10
     assert _rel(x, xp) <= 2 * kappa * max(res.max(), res_o.max())
+
+
+def test_pcg_on_fp32_operator_copies_stops_on_the_fp64_residual(lib):
+    """matvec_prec FP32: PCG multiplies with FP32 copies of the leaf near
+    blocks and couplings; the residual that ends it is recomputed with the
+    FP64 H^2 operator.  On the oracle's H^2 matrix (Yukawa, target-path
+    precisions, 1 and 4 right-hand sides) the returned residual must be the
+    FP64 operator's (checked against the oracle's dense A~) and reach 1e-10,
+    and x must meet the refined bound 2 kappa(A~) max(res, res_o) of the
+    oracle's PCG solution."""
+    import torch
+    p = W.yukawa_cube(n=4096, leaf=128, eps=1e-8, nrhs=4, s=256)
+    h2f, ranks, pos = _same_h2(p)
+    fac = ulv.factor(h2f)
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    for nrhs in (1, 4):
+        b = p.b()[:, :nrhs].copy()
+        xp, its = ulv.pcg(fac, b, 1e-10, 100)
+        res_o = np.linalg.norm(b - At @ xp, axis=0) / np.linalg.norm(b, axis=0)
+        H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                            s_far=p.s_far, s_near=p.s_near, gemm_prec=lib.PREC_BF16X3,
+                            solve_prec=lib.PREC_BF16, matvec_prec=lib.PREC_FP32,
+                            ir_max_iter=100, ir_tol=1e-10, use_pcg=True)
+        H.factor()
+        x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+        st = H.stats()
+        H.close()
+        res = np.linalg.norm(b - At @ x, axis=0) / np.linalg.norm(b, axis=0)
+        print(f"[pcg fp32 products] nrhs={nrhs} iterations {st['ir_iters']} (oracle {max(its)}), "
+              f"FP64 products {st['ir_fp64_matvecs']}, residual {res.max():.2e} (reported "
+              f"{st['ir_residual']:.2e}), x vs oracle PCG {_rel(x, xp):.2e}", flush=True)
+        assert st["ir_fp64_matvecs"] >= 2
+        assert st["ir_residual"] <= 1e-10
+        assert res.max() <= 1.1e-10
+        # the reported residual is the FP64 operator's: it matches the dense A~
+        assert abs(res.max() - st["ir_residual"]) <= 0.05 * res.max() + 1e-14
+        assert _rel(x, xp) <= 2 * kappa * max(res.max(), res_o.max())
