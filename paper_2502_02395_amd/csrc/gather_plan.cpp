@@ -11,9 +11,8 @@
 namespace h2 {
 
 bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
-                 GatherPlan& out, const std::vector<Rebase>& rb, int seg, bool wide, bool v16) {
+                 GatherPlan& out, const std::vector<Rebase>& rb, int seg, bool wide) {
   if (seg < 0 || seg % 16 != 0) return false;
-  if (v16 && wide) return false;
   const int W = seg > 0 ? seg : INT_MAX;
   out = GatherPlan();
   out.esz = rb.empty() ? 8 : rb[0].esz;
@@ -24,7 +23,6 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
   bool packed = copy;
   for (const Rebase& r : rb) packed = packed && r.map != nullptr;
   if (packed && out.esz != 2) return false;
-  if (v16 && !packed) return false;
   // The copy of a sub-block that starts at p and spans `rows` rows, and its
   // leading dimension (*ld); nullptr when p lies in no range, or when a
   // packed copy does not hold those rows in one segment.
@@ -107,8 +105,7 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
   // 64 x GATHER_WIDE_RPL32 / GATHER_WIDE_RPL64 rows.  Boundaries depend only on the block's size, so
   // results are reproducible across handles and runs.
   const int crows = wide ? 64 * (copy ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64)
-                 : v16  ? 256
-                 : copy ? 128 : 64;
+                         : copy ? 128 : 64;
   auto chunk_starts = [crows, wide](const Item& it) {
     std::vector<int> r;
     if (wide) {
@@ -167,13 +164,12 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
     if (nt) out.bytes_chunks_vec += 8.0 * (it.mr + (double)nck * it.mc);    // x_t, slots
   }
   out.plen = off;
-  // v16: every chunk 16-byte aligned with ld a multiple of 8 (so its first
-  // row is a multiple of 8 in its segment, and the rows up to the next
-  // multiple of 8 stay inside the column)
-  out.v16 = v16;
+  // packed BF16: every chunk 16-byte aligned with ld a multiple of 8 and a
+  // first row that is a multiple of 8 (rows past the segment are zeros)
+  out.v16 = packed && !wide;
   for (const GChunk& ch : out.chunks)
-    if (v16 && (reinterpret_cast<uintptr_t>(ch.M) % 16 != 0 || ch.ld % 8 != 0 || ch.nr > 256))
-      return false;
+    if (out.v16 && (reinterpret_cast<uintptr_t>(ch.M) % 16 != 0 || ch.ld % 8 != 0 || ch.nr > 128))
+      out.v16 = false;
   for (size_t bx = 0; bx < B.size(); ++bx) {
     const GatherBox& g = B[bx];
     GRed r;

@@ -46,11 +46,9 @@ struct GList {
   int esz = 8;                             // bytes per block element: 8, or 4 / 2
                                            // for FP32 / BF16 copies
   bool has_w = false;
-  bool w_v16 = false;                      // w is a v16 plan (packed BF16 copies,
-                                           // gv16_kernel) instead of a wide one
+  bool v16 = false;                        // n reads packed BF16 copies (GatherPlan::v16)
   int kind = -1;                           // timing class (h2_stats); -1: by esz
-  bool use_w(int nrhs) const { return has_w && nrhs <= (w_v16 ? GV16_NR : GATHER_WIDE_NR); }
-  const GSet& pick(int nrhs) const { return use_w(nrhs) ? w : n; }
+  const GSet& pick(int nrhs) const { return has_w && nrhs <= GATHER_WIDE_NR ? w : n; }
 };
 
 // One height step h above the leaves: level L_t - h of every instance t with

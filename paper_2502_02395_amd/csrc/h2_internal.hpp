@@ -302,24 +302,22 @@ struct GatherPlan {
   // and partial traffic per rhs
   double bytes_chunks_mat = 0.0, bytes_chunks_vec = 0.0;
   double bytes_red = 0.0;
-  // a v16 plan: every chunk reads a packed BF16 copy, 16-byte aligned, ld a
-  // multiple of 8, up to 256 rows
+  // every chunk reads a packed BF16 copy: 16-byte aligned, ld a multiple of
+  // 8, zero rows below the chunk up to the next multiple of 8
   bool v16 = false;
 };
 // rb non-empty: every block must lie in one of its ranges and is read from
 // that range's copy (all ranges of one plan share esz; returns false
 // otherwise).  seg > 0: column segments of at
 // most seg columns (a multiple of 16).  wide: wide chunks (see above).
-// v16: chunks of up to 256 rows of packed BF16 copies for gv16_kernel (one
-// right-hand side; every range of rb needs a map; not with wide).
 bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& Nv,
                  GatherPlan& out, const std::vector<Rebase>& rb = {}, int seg = 0,
-                 bool wide = false, bool v16 = false);
+                 bool wide = false);
 // wide: the chunks come from a wide plan (nrhs <= GATHER_WIDE_NR required).
-// esz: bytes per block element (8, 4 or 2).  v16: the chunks come from a v16
-// plan (BF16 chunks of up to 256 rows read with 16-byte loads, nrhs <=
-// GV16_NR; more right-hand sides use a plan of 128-row chunks of the same
-// packed copies with the two-rows-per-lane kernel).
+// esz: bytes per block element (8, 4 or 2).  v16: the plan's v16 (BF16
+// chunks of 128 rows read with 16-byte loads, for one right-hand side;
+// more fall back to the two-rows-per-lane kernel, which reads the packed
+// copies too).
 constexpr int GV16_NR = 1;
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
                           hipStream_t st, bool wide = false, bool v16 = false);

@@ -344,113 +344,112 @@ __device__ __forceinline__ double reduce_group16(const double (&v)[N], int lane)
   }
 }
 
-// One right-hand side.  R = 1 or 2 passes of 128 rows: lane (g, q) owns rows
-// 128 p + 8q .. +7 for p < R (a chunk of up to 256 rows is one wave, so a
-// column segment of a packed block is read by one wave, front to back).
-template <int U, int R>
-__device__ __forceinline__ void gv16_body(const GChunk& ch, double* __restrict__ P, int lane) {
-  const int q = lane & 15, g = lane >> 4;
+template <int NR, int U>
+__global__ __launch_bounds__(256) void gv16_kernel(const GChunk* __restrict__ chunks, int nch,
+                                                   double* __restrict__ P, int nrhs) {
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (w >= nch) return;
+  const GChunk& ch = chunks[w];
+  const int lane = threadIdx.x & 63, q = lane & 15, g = lane >> 4;
   const bool dir = ch.od >= 0, tr = ch.ot >= 0;
   const int nr = ch.nr, mc = ch.mc;
   const int64_t colb = (int64_t)ch.ld * 2;  // bytes per column
-  // row groups past the chunk read its first group (in bounds); their x_t is
-  // zero and their direct sums are never stored
-  const char* base[R];
-  double xt[R][8], acc[R][8];
+  // row groups past the chunk read group 0 (in bounds); their x_t is zero
+  // and their direct sums are never stored
+  const bool live = 8 * q < nr;
+  const char* base = static_cast<const char*>(ch.M) + 16 * (live ? q : 0);
+  double xt[8][NR], acc[8][NR];
 #pragma unroll
-  for (int p = 0; p < R; ++p) {
-    const int r0 = 128 * p + 8 * q;
-    base[p] = static_cast<const char*>(ch.M) + 2 * (r0 < nr ? r0 : 0);
+  for (int t = 0; t < 8; ++t)
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      acc[p][t] = 0.0;
-      xt[p][t] = (tr && r0 + t < nr) ? as_global(ch.xt)[r0 + t] : 0.0;
+    for (int c = 0; c < NR; ++c) {
+      acc[t][c] = 0.0;
+      xt[t][c] = (tr && c < nrhs && 8 * q + t < nr)
+                     ? as_global(ch.xt)[8 * q + t + (int64_t)c * ch.ldxt]
+                     : 0.0;
     }
-  }
   for (int s0 = 0; s0 < mc; s0 += 4 * U) {
-    const double xv = (dir && lane < 4 * U && s0 + lane < mc) ? as_global(ch.xd)[s0 + lane] : 0.0;
-    u32x4 d[U][R];
+    double xv[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c)
+      xv[c] = (dir && c < nrhs && lane < 4 * U && s0 + lane < mc)
+                  ? as_global(ch.xd)[s0 + lane + (int64_t)c * ch.ldxd]
+                  : 0.0;
+    u32x4 d[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       // columns past the chunk read its last column; x_d is zero there and
       // their transposed sums are not stored
       const int cc = min(s0 + 4 * u + g, mc - 1);
-#pragma unroll
-      for (int p = 0; p < R; ++p)
-        d[u][p] = __builtin_nontemporal_load(
-            reinterpret_cast<gptr_t<u32x4>>(as_global(base[p] + (int64_t)cc * colb)));
+      d[u] = __builtin_nontemporal_load(
+          reinterpret_cast<gptr_t<u32x4>>(as_global(base + (int64_t)cc * colb)));
     }
     if (dir) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double xu = __shfl(xv, 4 * u + g, 64);
+      for (int c = 0; c < NR; ++c) {
+        if (c < nrhs) {
 #pragma unroll
-        for (int p = 0; p < R; ++p) {
-          acc[p][0] += bf16_at<0>(d[u][p]) * xu;
-          acc[p][1] += bf16_at<1>(d[u][p]) * xu;
-          acc[p][2] += bf16_at<2>(d[u][p]) * xu;
-          acc[p][3] += bf16_at<3>(d[u][p]) * xu;
-          acc[p][4] += bf16_at<4>(d[u][p]) * xu;
-          acc[p][5] += bf16_at<5>(d[u][p]) * xu;
-          acc[p][6] += bf16_at<6>(d[u][p]) * xu;
-          acc[p][7] += bf16_at<7>(d[u][p]) * xu;
+          for (int u = 0; u < U; ++u) {
+            const double xu = __shfl(xv[c], 4 * u + g, 64);
+            acc[0][c] += bf16_at<0>(d[u]) * xu;
+            acc[1][c] += bf16_at<1>(d[u]) * xu;
+            acc[2][c] += bf16_at<2>(d[u]) * xu;
+            acc[3][c] += bf16_at<3>(d[u]) * xu;
+            acc[4][c] += bf16_at<4>(d[u]) * xu;
+            acc[5][c] += bf16_at<5>(d[u]) * xu;
+            acc[6][c] += bf16_at<6>(d[u]) * xu;
+            acc[7][c] += bf16_at<7>(d[u]) * xu;
+          }
         }
       }
     }
     if (tr) {
-      double pt[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        double v = 0.0;
+      for (int c = 0; c < NR; ++c) {
+        if (c < nrhs) {
+          double pt[U];
 #pragma unroll
-        for (int p = 0; p < R; ++p)
-          v += bf16_at<0>(d[u][p]) * xt[p][0] + bf16_at<1>(d[u][p]) * xt[p][1] +
-               bf16_at<2>(d[u][p]) * xt[p][2] + bf16_at<3>(d[u][p]) * xt[p][3] +
-               bf16_at<4>(d[u][p]) * xt[p][4] + bf16_at<5>(d[u][p]) * xt[p][5] +
-               bf16_at<6>(d[u][p]) * xt[p][6] + bf16_at<7>(d[u][p]) * xt[p][7];
-        pt[u] = v;
+          for (int u = 0; u < U; ++u)
+            pt[u] = bf16_at<0>(d[u]) * xt[0][c] + bf16_at<1>(d[u]) * xt[1][c] +
+                    bf16_at<2>(d[u]) * xt[2][c] + bf16_at<3>(d[u]) * xt[3][c] +
+                    bf16_at<4>(d[u]) * xt[4][c] + bf16_at<5>(d[u]) * xt[5][c] +
+                    bf16_at<6>(d[u]) * xt[6][c] + bf16_at<7>(d[u]) * xt[7][c];
+          const double tot = reduce_group16<U>(pt, lane);
+          const int uu = U == 16 ? q : (q >> 1);
+          const int col = s0 + 4 * uu + g;
+          if (col < mc && (U == 16 || (q & 1) == 0))
+            P[ch.ot * nrhs + (int64_t)c * ch.tlen + ch.tcol + col] = tot;
+        }
       }
-      const double tot = reduce_group16<U>(pt, lane);
-      const int uu = U == 16 ? q : (q >> 1);
-      const int col = s0 + 4 * uu + g;
-      if (col < mc && (U == 16 || (q & 1) == 0)) P[ch.ot + ch.tcol + col] = tot;
     }
   }
   if (dir) {
-    // rows 128 p + 8q .. +7 summed over the four lane groups: lane (q, g)
-    // keeps rows 128 p + 8q + 4 (g & 1) + 2 (g >> 1) + {0, 1}
+    // rows 8q..8q+7 summed over the four lane groups: lane (q, g) keeps rows
+    // 8q + 4 (g & 1) + 2 (g >> 1) + {0, 1}
     const bool g0 = g & 1, g1 = (g >> 1) & 1;
-    double* dst = P + ch.od + ch.drow;
+    const int r0 = 8 * q + 4 * g0 + 2 * g1;
 #pragma unroll
-    for (int p = 0; p < R; ++p) {
-      double a[4], b[2];
+    for (int c = 0; c < NR; ++c) {
+      if (c < nrhs) {
+        double a[4], b[2];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double send = g0 ? acc[p][j] : acc[p][4 + j];
-        const double keep = g0 ? acc[p][4 + j] : acc[p][j];
-        a[j] = keep + __shfl_xor(send, 16, 64);
+        for (int j = 0; j < 4; ++j) {
+          const double send = g0 ? acc[j][c] : acc[4 + j][c];
+          const double keep = g0 ? acc[4 + j][c] : acc[j][c];
+          a[j] = keep + __shfl_xor(send, 16, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double send = g1 ? a[j] : a[2 + j];
+          const double keep = g1 ? a[2 + j] : a[j];
+          b[j] = keep + __shfl_xor(send, 32, 64);
+        }
+        double* dst = P + ch.od * nrhs + (int64_t)c * ch.dlen + ch.drow;
+        if (r0 < nr) dst[r0] = b[0];
+        if (r0 + 1 < nr) dst[r0 + 1] = b[1];
       }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const double send = g1 ? a[j] : a[2 + j];
-        const double keep = g1 ? a[2 + j] : a[j];
-        b[j] = keep + __shfl_xor(send, 32, 64);
-      }
-      const int r0 = 128 * p + 8 * q + 4 * g0 + 2 * g1;
-      if (r0 < nr) dst[r0] = b[0];
-      if (r0 + 1 < nr) dst[r0 + 1] = b[1];
     }
   }
-}
-
-__global__ __launch_bounds__(256) void gv16_kernel(const GChunk* __restrict__ chunks, int nch,
-                                                   double* __restrict__ P) {
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-  if (w >= nch) return;
-  const GChunk& ch = chunks[w];
-  const int lane = threadIdx.x & 63;
-  if (__builtin_amdgcn_readfirstlane(ch.nr) <= 128) gv16_body<16, 1>(ch, P, lane);
-  else gv16_body<8, 2>(ch, P, lane);
 }
 
 template <int NR>
@@ -511,9 +510,9 @@ hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int es
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
   if (wide && nrhs > GATHER_WIDE_NR) return hipErrorInvalidValue;
   if (v16 && esz == 2 && !wide && nrhs <= GV16_NR) {
-    static_assert(GV16_NR == 1, "one right-hand side");
+    static_assert(GV16_NR == 1, "instantiation below");
     const dim3 grid((nch + 3) / 4), blk(256);
-    hipLaunchKernelGGL(gv16_kernel, grid, blk, 0, st, ch, nch, P);
+    hipLaunchKernelGGL((gv16_kernel<1, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
     return hipGetLastError();
   }
   if (esz == 8) launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);

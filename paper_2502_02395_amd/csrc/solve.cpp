@@ -64,15 +64,14 @@ static bool up_thin(Ctx& c, GList& L, const std::vector<GemmDesc>& v, hipStream_
 static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
                       const std::vector<GatherNbr>& Nv, hipStream_t st,
                       const std::vector<Rebase>& rb, int seg, bool wide) {
-  // packed BF16 copies: a v16 plan for one right-hand side instead of a wide
-  // one, 128-row chunks of the same copies for more
-  bool packed = false;
+  // packed BF16 copies take the 16-byte-load chunks instead of wide ones
   for (const Rebase& r : rb)
-    if (r.map) packed = true;
-  auto up_set = [&](GSet& S, bool wide, bool v16) {
+    if (r.map) wide = false;
+  auto up_set = [&](GSet& S, bool wide) {
     GatherPlan p;
-    if (!plan_gather(B, Nv, p, rb, seg, wide, v16)) return false;
+    if (!plan_gather(B, Nv, p, rb, seg, wide)) return false;
     L.esz = p.esz;
+    if (!wide) L.v16 = p.v16;
     S.max_rows = p.max_rows;
     S.plen = p.plen;
     S.bytes_ch_mat = p.bytes_chunks_mat;
@@ -82,12 +81,8 @@ static bool up_gather(Ctx& c, GList& L, const std::vector<GatherBox>& B,
     return upload(c, S.ch, p.chunks, st) && upload(c, S.rd, p.reds, st) &&
            upload(c, S.offs, p.offs, st);
   };
-  if (packed) {
-    L.has_w = L.w_v16 = true;
-    return up_set(L.n, false, false) && up_set(L.w, false, true);
-  }
   L.has_w = wide;
-  return up_set(L.n, false, false) && (!wide || up_set(L.w, true, false));
+  return up_set(L.n, false) && (!wide || up_set(L.w, true));
 }
 
 // The partial buffer holds the longest list's partial products for nrhs
@@ -108,14 +103,14 @@ h2_status ensure_partials(Ctx& c, int nrhs) {
 // Chunks then reduction; with timing on, HIP events around each (the event
 // pool is sized once; gathers beyond it run untimed).
 static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
-  const bool use_w = L.use_w(nrhs);
+  const bool wide = L.has_w && nrhs <= GATHER_WIDE_NR;
   const GSet& S = L.pick(nrhs);
   if (S.rd.count == 0) return hipSuccess;
   const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
   hipError_t e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
-  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, use_w && !L.w_v16,
-                         use_w && L.w_v16)) != hipSuccess)
+  if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, wide,
+                         L.v16 && !wide)) != hipSuccess)
     return e;
   if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
   if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st)) !=
