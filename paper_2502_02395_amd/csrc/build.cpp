@@ -691,8 +691,8 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
 // copied.  Segments are laid out one after another, each with its row count
 // rounded up to 8 as leading dimension (a multiple of 8 elements: every
 // segment and column starts on a 16-byte boundary).
-static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtSeg>& sF,
-                             std::vector<CvtSeg>& sP) {
+static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtBlk>& sF,
+                             std::vector<CvtBlk>& sP) {
   auto r8 = [](int64_t x) { return (x + 7) / 8 * 8; };
   S.cmF.clear();
   S.cmP.clear();
@@ -701,26 +701,28 @@ static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtS
     const int i = S.np_i[p], j = S.np_j[p];
     const int mi = S.m[i], mj = S.m[j], ki = S.k[i], kj = S.k[j];
     CopyMap cm{S.dF + S.poff[p], mi, mi, mj, ki, kj, -1, 1, -1, 1};
+    CvtBlk cb{S.poff[p], -1, -1, 0, mi, mi, ki, kj, mj, 0, 0};
     if (ki > 0 && mj > kj) {
-      cm.top = off;
+      cm.top = cb.top = off;
       cm.ld_top = r8(ki);
-      sF.push_back({S.poff[p] + (int64_t)kj * mi, off, 0, mi, ki, mj - kj, (int)cm.ld_top});
+      cb.gt = (int)(cm.ld_top / 8);
       off += cm.ld_top * (mj - kj);
     }
     if (i != j && mi > ki && mj > 0) {
-      cm.bot = off;
+      cm.bot = cb.bot = off;
       cm.ld_bot = r8(mi - ki);
-      sF.push_back({S.poff[p] + ki, off, 0, mi, mi - ki, mj, (int)cm.ld_bot});
+      cb.gb = (int)(cm.ld_bot / 8);
       off += cm.ld_bot * mj;
     }
     S.cmF.push_back(cm);
+    if (cb.gt + cb.gb > 0) sF.push_back(cb);
   }
   nF = off;
   off = 0;
   for (int b = 0; b < S.nbox; ++b) {
     const int m = S.m[b];
     CopyMap cm{S.dP + S.qoff[b], m, m, m, m, 0, off, r8(m), -1, 1};
-    if (m > 0) sP.push_back({S.qoff[b], off, 0, m, m, m, (int)cm.ld_top});
+    if (m > 0) sP.push_back({S.qoff[b], off, -1, 0, m, m, m, 0, m, (int)(r8(m) / 8), 0});
     off += cm.ld_top * m;
     S.cmP.push_back(cm);
   }
@@ -728,9 +730,9 @@ static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtS
   // group prefixes (8 rows of one column per group)
   for (auto* v : {&sF, &sP}) {
     int64_t g = 0;
-    for (CvtSeg& x : *v) {
+    for (CvtBlk& x : *v) {
       x.g0 = g;
-      g += (int64_t)(x.dst_ld / 8) * x.cols;
+      g += (int64_t)x.c_top * x.gb + (int64_t)(x.cols - x.c_top) * (x.gt + x.gb);
     }
   }
 }
@@ -840,16 +842,21 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     }
     if (c.prm.solve_prec == H2_PREC_BF16) {
       int64_t nF = 0, nP = 0;
-      std::vector<CvtSeg> sF, sP;
+      std::vector<CvtBlk> sF, sP;
       plan_bf16_copies(S, nF, nP, sF, sP);
       S.dF16 = c.alloc<unsigned short>(std::max<int64_t>(nF, 1));
       S.dP16 = c.alloc<unsigned short>(std::max<int64_t>(nP, 1));
       ALLOCHK(S.dF16); ALLOCHK(S.dP16);
       if (!upload(c, S.cvF16, sF, st) || !upload(c, S.cvP16, sP, st)) return H2_ERR_ALLOC;
-      S.cvF16_groups = sF.empty() ? 0 : sF.back().g0 + (int64_t)(sF.back().dst_ld / 8) * sF.back().cols;
-      S.cvP16_groups = sP.empty() ? 0 : sP.back().g0 + (int64_t)(sP.back().dst_ld / 8) * sP.back().cols;
+      auto total = [](const std::vector<CvtBlk>& v) -> int64_t {
+        if (v.empty()) return 0;
+        const CvtBlk& x = v.back();
+        return x.g0 + (int64_t)x.c_top * x.gb + (int64_t)(x.cols - x.c_top) * (x.gt + x.gb);
+      };
+      S.cvF16_groups = total(sF);
+      S.cvP16_groups = total(sP);
       // the segment of the first group of every 256-group block
-      auto firsts = [](const std::vector<CvtSeg>& v, int64_t groups) {
+      auto firsts = [](const std::vector<CvtBlk>& v, int64_t groups) {
         std::vector<int> f((size_t)((groups + 255) / 256));
         size_t sg = 0;
         for (size_t b = 0; b < f.size(); ++b) {

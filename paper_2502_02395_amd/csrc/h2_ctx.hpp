@@ -89,7 +89,7 @@ struct Step {
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
   unsigned short *dF16 = nullptr, *dP16 = nullptr;  // packed BF16 copies (solve_prec BF16)
   std::vector<CopyMap> cmF, cmP;           // their layout (sorted by source block)
-  Batch<CvtSeg> cvF16, cvP16;              // their conversion segments
+  Batch<CvtBlk> cvF16, cvP16;              // their conversion blocks
   Batch<int> cvF16_first, cvP16_first;     // segment of each 256-group block
   int64_t cvF16_groups = 0, cvP16_groups = 0;  // their 8-row column groups
   float *dD32 = nullptr, *dT232 = nullptr; // FP32 near blocks and pair scratch (FP32 pairs)

@@ -272,14 +272,16 @@ struct CopyMap {
   int64_t top, ld_top;      // element offsets into the copy
   int64_t bot, ld_bot;
 };
-// One segment of a packed copy for the conversion kernel: source element
-// offset (into the FP64 or FP32 arena) and ld, rows, columns; destination
-// offset and ld (rows up to dst_ld are written, zeros below `rows`).
-struct CvtSeg {
-  int64_t src_off;
-  int64_t dst_off;
-  int64_t g0;               // first of its 8-row groups in the list (prefix)
-  int src_ld, rows, cols, dst_ld;
+// One block of a packed copy for the conversion kernel (see CopyMap): source
+// element offset (into the FP64 or FP32 arena) and ld; its top segment (rows
+// [0, split) of columns [c_top, cols), gt groups of 8 rows per column, at
+// top) and its bottom segment (rows [split, rows) of every column, gb groups
+// per column, at bot; gb = 0: none).  Its 8-row groups are numbered column by
+// column from g0 (a column's top groups, then its bottom groups), so that the
+// threads converting the two parts of one column are neighbours.
+struct CvtBlk {
+  int64_t src_off, top, bot, g0;
+  int src_ld, rows, split, c_top, cols, gt, gb;
 };
 // A range of FP64 blocks with a reduced-precision copy: esz 4 = FP32, esz 2
 // = BF16.  Without a map the copy has the same element offsets; with one
@@ -326,11 +328,11 @@ hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t 
 // BF16 copy (round to nearest even) of n doubles (esz_src 8) or floats (4).
 hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, int64_t n,
                            hipStream_t st);
-// Packed BF16 copy: every segment of segs (device, count, g0 ascending) from
+// Packed BF16 copy: every block of blks (device, count, g0 ascending) from
 // src (FP64 or FP32 arena, esz_src 8 or 4) into dst, zero-padded; groups:
 // the total number of 8-row groups; first (device, one per 256 groups): the
-// segment holding group 256 b.
-hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs,
+// block holding group 256 b.
+hipError_t launch_cvt_bf16_blks(const void* src, int esz_src, const CvtBlk* blks,
                                 const int* first, int count, int64_t groups,
                                 unsigned short* dst, hipStream_t st);
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,

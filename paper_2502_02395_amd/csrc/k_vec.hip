@@ -125,32 +125,64 @@ hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, in
   return hipGetLastError();
 }
 
-// Packed BF16 copies: one thread per 8-row group of a column over the whole
-// list; first[b] is the segment of block b's first group (planned on the
-// host), each thread steps forward from it to its own (a block of 256 groups
-// spans few segments).  Each thread converts eight rows (rounded like
-// cvt_bf16_kernel: to FP32, then to BF16, nearest even) and writes them with
-// one 16-byte store; rows from `rows` up to dst_ld are written as zeros.
+// Packed BF16 copies: one thread per 8-row group over the whole list;
+// first[b] is the block of block b's first group (planned on the host), each
+// thread steps forward from it to its own.  Groups run column by column (a
+// column's top groups, then its bottom groups), so the two parts of a column
+// are converted by neighbouring threads and the cache line they share is
+// read once.  Each thread converts eight rows (to FP32, then to BF16,
+// nearest even) and writes them with one 16-byte store; rows past the
+// segment's end up to its leading dimension are written as zeros.
 template <typename TS>
-__global__ __launch_bounds__(256) void cvt_bf16_segs_kernel(const TS* __restrict__ src,
-                                                            const CvtSeg* __restrict__ segs,
+__global__ __launch_bounds__(256) void cvt_bf16_blks_kernel(const TS* __restrict__ src,
+                                                            const CvtBlk* __restrict__ blks,
                                                             const int* __restrict__ first,
                                                             int count, int64_t groups,
                                                             unsigned short* __restrict__ dst) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= groups) return;
   int sg = first[blockIdx.x];
-  while (sg + 1 < count && segs[sg + 1].g0 <= e) ++sg;
-  const CvtSeg g = segs[sg];
-  const int per_col = g.dst_ld / 8;
-  const int64_t le = e - g.g0;
-  const int col = (int)(le / per_col), rg = (int)(le % per_col);
-  const TS* sc = src + g.src_off + (int64_t)col * g.src_ld;
+  while (sg + 1 < count && blks[sg + 1].g0 <= e) ++sg;
+  const CvtBlk g = blks[sg];
+  int64_t le = e - g.g0;
+  int col, r;
+  bool top;
+  const int64_t lead = (int64_t)g.c_top * g.gb;  // columns with a bottom part only
+  if (le < lead) {
+    col = (int)(le / g.gb);
+    r = (int)(le % g.gb);
+    top = false;
+  } else {
+    le -= lead;
+    const int per = g.gt + g.gb;
+    col = g.c_top + (int)(le / per);
+    r = (int)(le % per);
+    top = r < g.gt;
+    if (!top) r -= g.gt;
+  }
+  const int r_lo = top ? 0 : g.split;          // the segment's first source row
+  const int r_hi = top ? g.split : g.rows;     // and its end
+  const TS* sc = src + g.src_off + (int64_t)col * g.src_ld + r_lo + 8 * r;
+  TS x[8];
+  if (r_lo + 8 * r + 8 <= r_hi) {
+    // a full group: 32 or 64 contiguous bytes, read as 16-byte vectors (the
+    // element alignment suffices on this part)
+    typedef TS tv __attribute__((ext_vector_type(16 / sizeof(TS)), aligned(sizeof(TS))));
+    constexpr int NV = 8 * sizeof(TS) / 16, PV = 16 / sizeof(TS);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const tv y = *reinterpret_cast<const tv*>(sc + PV * v);
+#pragma unroll
+      for (int t = 0; t < PV; ++t) x[PV * v + t] = y[t];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) x[t] = r_lo + 8 * r + t < r_hi ? sc[t] : TS(0);
+  }
   unsigned short h[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const int r = 8 * rg + t;
-    const __bf16 b = (__bf16)(float)(r < g.rows ? sc[r] : TS(0));
+    const __bf16 b = (__bf16)(float)x[t];
     h[t] = __builtin_bit_cast(unsigned short, b);
   }
   uint4 v;
@@ -158,21 +190,23 @@ __global__ __launch_bounds__(256) void cvt_bf16_segs_kernel(const TS* __restrict
   v.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
   v.z = (unsigned)h[4] | ((unsigned)h[5] << 16);
   v.w = (unsigned)h[6] | ((unsigned)h[7] << 16);
-  *reinterpret_cast<uint4*>(dst + g.dst_off + (int64_t)col * g.dst_ld + 8 * rg) = v;
+  unsigned short* dc = top ? dst + g.top + (int64_t)(col - g.c_top) * (8 * g.gt)
+                           : dst + g.bot + (int64_t)col * (8 * g.gb);
+  *reinterpret_cast<uint4*>(dc + 8 * r) = v;
 }
 
-hipError_t launch_cvt_bf16_segs(const void* src, int esz_src, const CvtSeg* segs,
+hipError_t launch_cvt_bf16_blks(const void* src, int esz_src, const CvtBlk* blks,
                                 const int* first, int count, int64_t groups,
                                 unsigned short* dst, hipStream_t st) {
   if (count <= 0 || groups <= 0) return hipSuccess;
   if ((groups + 255) / 256 > INT_MAX) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)((groups + 255) / 256);
   if (esz_src == 8)
-    hipLaunchKernelGGL(cvt_bf16_segs_kernel<double>, dim3(grid), dim3(256), 0, st,
-                       static_cast<const double*>(src), segs, first, count, groups, dst);
+    hipLaunchKernelGGL(cvt_bf16_blks_kernel<double>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const double*>(src), blks, first, count, groups, dst);
   else if (esz_src == 4)
-    hipLaunchKernelGGL(cvt_bf16_segs_kernel<float>, dim3(grid), dim3(256), 0, st,
-                       static_cast<const float*>(src), segs, first, count, groups, dst);
+    hipLaunchKernelGGL(cvt_bf16_blks_kernel<float>, dim3(grid), dim3(256), 0, st,
+                       static_cast<const float*>(src), blks, first, count, groups, dst);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -653,10 +653,10 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     const bool from32 = c.prm.gemm_prec != H2_PREC_FP64;
     for (auto& S : c.steps) {
       if (from32)
-        HIPCHK(launch_cvt_bf16_segs(S.dF32, 4, S.cvF16.d, S.cvF16_first.d, S.cvF16.count, S.cvF16_groups, S.dF16, st));
+        HIPCHK(launch_cvt_bf16_blks(S.dF32, 4, S.cvF16.d, S.cvF16_first.d, S.cvF16.count, S.cvF16_groups, S.dF16, st));
       else
-        HIPCHK(launch_cvt_bf16_segs(S.dF, 8, S.cvF16.d, S.cvF16_first.d, S.cvF16.count, S.cvF16_groups, S.dF16, st));
-      HIPCHK(launch_cvt_bf16_segs(S.dP, 8, S.cvP16.d, S.cvP16_first.d, S.cvP16.count, S.cvP16_groups, S.dP16, st));
+        HIPCHK(launch_cvt_bf16_blks(S.dF, 8, S.cvF16.d, S.cvF16_first.d, S.cvF16.count, S.cvF16_groups, S.dF16, st));
+      HIPCHK(launch_cvt_bf16_blks(S.dP, 8, S.cvP16.d, S.cvP16_first.d, S.cvP16.count, S.cvP16_groups, S.dP16, st));
     }
     HIPCHK(done());
   }
