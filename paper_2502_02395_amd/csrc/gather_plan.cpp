@@ -153,7 +153,7 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
         ch.tlen = it.mc;
         ch.tcol = c0;
         ch.rpl = (ch.nr + 63) / 64;
-        ch.vec = (!copy && !wide && ch.nr <= 64) ? 1 : 0;
+        ch.vec = (!wide && ((!copy && ch.nr <= 64) || (out.esz == 4 && ch.nr <= 128))) ? 1 : 0;
         ch.od = nd ? it.od + (int64_t)sg * it.mr : -1;
         ch.ot = nt ? it.ot0 + (int64_t)c * it.mc : -1;
         out.chunks.push_back(ch);

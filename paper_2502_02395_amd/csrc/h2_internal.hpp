@@ -220,9 +220,10 @@ struct GChunk {
   int dlen, drow;           // direct slot length and this chunk's first row in it
   int tlen, tcol;           // trans slot length and this chunk's first column in it
   int rpl;                  // rows per lane: nr <= 64 rpl
-  int vec;                  // 1: FP64 chunk of <= 64 rows of a narrow plan: with
-                            // one right-hand side it is read two rows per lane
-                            // with 16-byte loads (8-byte aligned is enough)
+  int vec;                  // 1: FP64 chunk of <= 64 rows or FP32 chunk of <= 128
+                            // rows of a narrow plan: with one right-hand side it
+                            // is read two (FP64) or four (FP32) rows per lane
+                            // with 16-byte loads (element alignment is enough)
   int64_t od, ot;           // slot offsets (one-rhs units); -1 = no such product
 };
 struct GRed {

@@ -261,6 +261,101 @@ __device__ __forceinline__ void gv64_one(const GChunk& ch, double* __restrict__ 
   else gv64_body<16, false>(ch, P, lane);
 }
 
+// FP32 chunks with GChunk::vec (128 rows), one right-hand side: lane (g, q) =
+// (lane >> 5, lane & 31) reads rows 4q..4q+3 of the columns 2u + g of each
+// batch of 2U = 16 columns with one 16-byte load (4-byte alignment suffices on
+// this part; a wave moves two columns of 128 rows per load).  The lane of a
+// row group that the chunk ends inside reads its rows one by one.  Direct
+// sums are reduced over the two lane halves at the end, the transposed ones
+// over the 32 lanes of each half after every batch, in a fixed order that
+// does not depend on the chunk's address.
+typedef float f32x4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <bool TAIL>
+__device__ __forceinline__ f32x4a4 load_rows4(const float* p, int valid) {
+  if (!TAIL || valid >= 4)
+    return __builtin_nontemporal_load(reinterpret_cast<gptr_t<f32x4a4>>(as_global(p)));
+  f32x4a4 v;
+  v.x = valid > 0 ? __builtin_nontemporal_load(as_global(p)) : 0.f;
+  v.y = valid > 1 ? __builtin_nontemporal_load(as_global(p + 1)) : 0.f;
+  v.z = valid > 2 ? __builtin_nontemporal_load(as_global(p + 2)) : 0.f;
+  v.w = 0.f;
+  return v;
+}
+
+template <int U, bool TAIL>
+__device__ __forceinline__ void gv32_body(const GChunk& ch, double* __restrict__ P, int lane,
+                                          int nrhs) {
+  static_assert(U == 8, "16 columns per batch");
+  const int q = lane & 31, g = lane >> 5;
+  const bool dir = ch.od >= 0, tr = ch.ot >= 0;
+  const int nr = ch.nr, mc = ch.mc;
+  const int64_t ld = ch.ld;
+  const bool live = 4 * q < nr;
+  const int qe = live ? q : 0;
+  const int valid = nr - 4 * qe;  // rows of the group inside the chunk (>= 1)
+  const float* base = static_cast<const float*>(ch.M) + 4 * qe;
+  double xt[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) xt[t] = (tr && 4 * q + t < nr) ? as_global(ch.xt)[4 * q + t] : 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < mc; s0 += 2 * U) {
+    const double xv = (dir && lane < 2 * U && s0 + lane < mc) ? as_global(ch.xd)[s0 + lane] : 0.0;
+    f32x4a4 d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int cc = min(s0 + 2 * u + g, mc - 1);
+      d[u] = load_rows4<TAIL>(base + (int64_t)cc * ld, valid);
+    }
+    if (dir && nrhs == 1) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double xu = __shfl(xv, 2 * u + g, 64);
+        acc[0] += (double)d[u].x * xu;
+        acc[1] += (double)d[u].y * xu;
+        acc[2] += (double)d[u].z * xu;
+        acc[3] += (double)d[u].w * xu;
+      }
+    }
+    if (tr && nrhs == 1) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        v[u] = (double)d[u].x * xt[0] + (double)d[u].y * xt[1] + (double)d[u].z * xt[2] +
+               (double)d[u].w * xt[3];
+      double a[4], b[2];
+      const bool b4 = (lane >> 4) & 1, b3 = (lane >> 3) & 1, b2 = (lane >> 2) & 1;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        a[j] = (b4 ? v[4 + j] : v[j]) + __shfl_xor(b4 ? v[j] : v[4 + j], 16, 64);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = (b3 ? a[2 + j] : a[j]) + __shfl_xor(b3 ? a[j] : a[2 + j], 8, 64);
+      double e = (b2 ? b[1] : b[0]) + __shfl_xor(b2 ? b[0] : b[1], 4, 64);
+      e += __shfl_xor(e, 2, 64);
+      e += __shfl_xor(e, 1, 64);
+      // lane q holds value (q >> 2): column s0 + 2 (q >> 2) + g
+      const int col = s0 + 2 * (q >> 2) + g;
+      if ((q & 3) == 0 && col < mc) P[ch.ot + ch.tcol + col] = e;
+    }
+  }
+  if (dir && nrhs == 1) {
+    // rows 4q..4q+3 summed over the two halves: lane (q, g) keeps rows
+    // 4q + 2g + {0, 1}
+    const double r0 = (g ? acc[2] : acc[0]) + __shfl_xor(g ? acc[0] : acc[2], 32, 64);
+    const double r1 = (g ? acc[3] : acc[1]) + __shfl_xor(g ? acc[1] : acc[3], 32, 64);
+    const int rr = 4 * q + 2 * g;
+    if (rr < nr) P[ch.od + ch.drow + rr] = r0;
+    if (rr + 1 < nr) P[ch.od + ch.drow + rr + 1] = r1;
+  }
+}
+
+__device__ __forceinline__ void gv32_one(const GChunk& ch, double* __restrict__ P, int lane,
+                                         int nrhs) {
+  if (__builtin_amdgcn_readfirstlane(ch.nr) & 3) gv32_body<8, true>(ch, P, lane, nrhs);
+  else gv32_body<8, false>(ch, P, lane, nrhs);
+}
+
 // RMAX: the largest rows-per-lane of the plan the chunks come from; each
 // chunk runs the variant of its own row count (wave-uniform).  BW: columns
 // per batch; 8 keeps the wide variants at four or more waves per SIMD.
@@ -274,6 +369,11 @@ __global__ __launch_bounds__(256) void gchunk_kernel(const GChunk* __restrict__ 
   const int lane = threadIdx.x & 63;
   if constexpr (NR == 1 && sizeof(T) == 8 && RMAX == 1) {
     if (__builtin_amdgcn_readfirstlane(ch.vec)) { gv64_one(ch, P, lane); return; }
+  }
+  if constexpr (NR == 1 && sizeof(T) == 4 && RMAX == 2) {
+    // nrhs (1 here) stays a run-time value: the compiler keeps the direct and
+    // transposed products apart and needs fewer registers
+    if (__builtin_amdgcn_readfirstlane(ch.vec)) { gv32_one(ch, P, lane, nrhs); return; }
   }
   if constexpr (RMAX >= 4) {
     if (rpl >= 4) { gchunk_one<NR, T, 4, BW>(ch, P, nrhs, lane); return; }
