@@ -46,7 +46,8 @@ typedef enum {
   H2_ERR_ARG = 1,         /* invalid argument (synchronous, handle unchanged)   */
   H2_ERR_ALLOC = 2,       /* device or host allocation failed                   */
   H2_ERR_HIP = 3,         /* a HIP runtime call failed                          */
-  H2_ERR_NOT_SPD = 4,     /* Cholesky breakdown; h2_stats gives (level, box)    */
+  H2_ERR_NOT_SPD = 4,     /* Cholesky breakdown (LU variant: a zero or
+                             non-finite pivot); h2_stats gives (level, box)    */
   H2_ERR_STATE = 5,       /* call out of order (e.g. solve before factor)       */
   H2_ERR_NOCONV = 6,      /* refinement did not reach the tolerance             */
   H2_ERR_UNSUPPORTED = 7  /* option not available in this library               */
@@ -57,12 +58,16 @@ typedef enum {
   H2_K_LAPLACE_REG = 0,   /* 1/(r + delta)                                       */
   H2_K_YUKAWA_REG = 1,    /* exp(-kappa r)/(r + delta)                           */
   H2_K_GAUSSIAN = 2,      /* exp(-r^2/ell^2) + nugget [i == j]                   */
-  H2_K_MATERN32 = 3       /* (1 + sqrt3 r/ell) exp(-sqrt3 r/ell) + nugget [i==j] */
+  H2_K_MATERN32 = 3,      /* (1 + sqrt3 r/ell) exp(-sqrt3 r/ell) + nugget [i==j] */
+  H2_K_YUKAWA_DRIFT = 4   /* exp(-kappa r)/(r + delta) (1 + beta (x_0 - y_0)/(r + delta)):
+                             the Yukawa kernel plus a skew part along the first
+                             axis; non-symmetric for beta != 0                 */
 } h2_kernel_id;
 
 typedef struct {
   int32_t id;             /* h2_kernel_id */
   double delta, kappa, ell, nugget;
+  double beta;            /* H2_K_YUKAWA_DRIFT only (ignored otherwise)          */
 } h2_kernel;
 
 /* Precision of the basis-transform GEMMs (h2_params.gemm_prec):
@@ -136,6 +141,24 @@ typedef struct {
                              ir_tol (at most 8 restarts).  The returned
                              residual is always the FP64 operator's.  Stationary
                              refinement ignores it                            */
+  int32_t factor_lu;      /* 1 = the LU variant of the factorization and the
+                             substitution (below) for a symmetric kernel too;
+                             a handle with any non-symmetric kernel
+                             (H2_K_YUKAWA_DRIFT, beta != 0) always uses it.
+                             LU variant (the method stated for non-symmetric
+                             matrices): one basis per box for its rows and
+                             columns, from an interpolative decomposition of
+                             the far field and the fill-in seen from both
+                             sides; a pivot-free LU of every redundant block
+                             with left and right bases
+                             P_i = [Q_i^S | Q_i^R L(r)_ii^{-T}] and
+                             P'_i = [Q_i^S | Q_i^R U(r)_ii^{-1}]; near blocks,
+                             couplings and factors stored for every ordered
+                             pair; the forward sweep of Eq. 31 with the lower
+                             and the backward sweep with the upper factor.
+                             It requires gemm_prec, solve_prec and matvec_prec
+                             FP64 and use_pcg 0 (refinement is stationary),
+                             else H2_ERR_ARG                                  */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;
@@ -207,6 +230,7 @@ typedef struct {
                                and couplings (matvec_prec FP32)                */
   double bytes_gather_mv32;
   int32_t gather_launches_mv32;
+  int32_t lu_variant;       /* 1 if the handle uses the LU variant (factor_lu) */
 } h2_stats_t;
 
 /* Capacity, in doubles, of the fixed device array that h2_solve_noalloc uses
@@ -250,8 +274,10 @@ h2_status h2_build_fixed(const double* pts, int64_t n, const h2_kernel* kernel,
                          const int32_t* ranks, const int32_t* skel,
                          void* stream, h2_handle* out);
 
-/* Factor (Algorithm 4).  Returns H2_ERR_NOT_SPD with the location in h2_stats
- * if a redundant diagonal block or the root is not positive definite. */
+/* Factor (Algorithm 4; the LU variant for handles with factor_lu).  Returns
+ * H2_ERR_NOT_SPD with the location in h2_stats if a redundant diagonal block
+ * or the root is not positive definite (LU variant: meets a zero or
+ * non-finite pivot). */
 h2_status h2_factor(h2_handle h, void* stream);
 
 /* x = A~^{-1} b through the parallel substitution (Eq. 31 and its transpose);
@@ -306,7 +332,8 @@ h2_status h2_get_pairs(h2_handle h, int32_t level, int32_t far, int32_t* pairs,
  * column-major into host `p` (pass NULL to query m and k only).  Q_i is the
  * orthogonal completion of D_i U_i (Section 4.4, Eq. 32), so the last m - k
  * columns are V_i = Q_i^R L(r)_ii^{-T} of Algorithm 4.  H2_ERR_STATE before
- * a successful h2_factor. */
+ * a successful h2_factor.  LU variant: the left basis P_i (the right one,
+ * [Q_i^S | Q_i^R U(r)_ii^{-1}], is not exported). */
 h2_status h2_get_basis(h2_handle h, int32_t inst, int32_t level, int32_t box, double* p,
                        int32_t* m, int32_t* k);
 /* The root matrix after factor: A_00 (before Cholesky) of instance t, n0 x n0

@@ -27,6 +27,57 @@ static double orgqr_full(double m, double k) {
   return 4.0 * m * m * k - 4.0 * m * k * k + 4.0 / 3.0 * k * k * k;
 }
 
+// The LU variant's counts for one step: per box the same QR and diagonal
+// transform, the LU of the redundant block 2 r^3/3, L(s)_ii and U(s)_ii
+// (k r^2 each), the Schur update 2 k^2 r and both bases (m r^2 each); per
+// ordered near pair i != j the transform 2 m_i m_j (m_i + m_j), L(s)_ij
+// (k_i r_j^2), U(s)_ij (r_i^2 k_j) and L(r)_ij (r_i r_j^2, i > j) or U(r)_ij
+// (r_i^2 r_j, i < j); per ordered far pair k_i k_j (k_i + k_j).  A solve
+// takes the same per-block products as the symmetric path.  Pair counts are
+// reported unordered, dense leaf blocks ordered.
+static void count_flops_lu(Ctx& c, const Step& S, double& ff, double& fs, double& bytes,
+                           int64_t& npairs, int64_t& nfar, int64_t& nnzb, int& maxk, int& maxm) {
+  double* ph = c.st.flops_factor_phase;
+  for (int b = 0; b < S.nbox; ++b) {
+    const double m = S.m[b], k = S.k[b], r = m - k;
+    const double qr = geqrf(m, k) + orgqr_full(m, k), lu = 2.0 * r * r * r / 3.0;
+    const double vs = 2.0 * k * r * r + 2.0 * k * k * r + 2.0 * m * r * r;
+    ff += qr + 4.0 * m * m * m + lu + vs;
+    ph[0] += qr;
+    ph[1] += 4.0 * m * m * m;
+    ph[2] += lu;
+    ph[3] += vs;
+    c.st.flops_schur += 2.0 * k * k * r;
+    fs += 4.0 * m * m + 4.0 * r * r;
+    maxk = std::max(maxk, S.k[b]);
+    maxm = std::max(maxm, S.m[b]);
+    bytes += 16.0 * m * m;  // P and P'
+  }
+  for (size_t p = 0; p < S.np_i.size(); ++p) {
+    const int i = S.np_i[p], j = S.np_j[p];
+    const double mi = S.m[i], mj = S.m[j], ki = S.k[i], kj = S.k[j], ri = mi - ki, rj = mj - kj;
+    bytes += 8.0 * mi * mj;
+    if (S.h == 0) ++nnzb;
+    if (i >= j) ++npairs;
+    if (i == j) {
+      fs += 4.0 * ki * ri;
+      continue;
+    }
+    const double t = 2.0 * mi * mj * (mi + mj);
+    const double tri = ki * rj * rj + ri * ri * kj + (i > j ? ri * rj * rj : ri * ri * rj);
+    ff += t + tri;
+    ph[4] += t + tri;
+    c.st.flops_pair_gemm += t;
+    fs += 2.0 * ki * rj + 2.0 * ri * kj + 2.0 * ri * rj;
+  }
+  for (size_t f = 0; f < S.fp_i.size(); ++f) {
+    const double ki = S.k[S.fp_i[f]], kj = S.k[S.fp_j[f]];
+    ff += ki * kj * (ki + kj);
+    ph[5] += ki * kj * (ki + kj);
+    if (S.fp_i[f] > S.fp_j[f]) ++nfar;
+  }
+}
+
 // Canonical algorithmic flop counts (unpadded sizes); see include/h2.h.
 static void count_flops(Ctx& c) {
   double ff = 0.0, fs = 0.0, bytes = 0.0;
@@ -40,6 +91,10 @@ static void count_flops(Ctx& c) {
   for (auto& S : c.steps) {
     if (S.g_pair1.count > 0) c.st.pair_launches += 2;
     nboxes += S.nbox;
+    if (c.lu) {
+      count_flops_lu(c, S, ff, fs, bytes, npairs, nfar, nnzb, maxk, maxm);
+      continue;
+    }
     for (int b = 0; b < S.nbox; ++b) {
       const double m = S.m[b], k = S.k[b], r = m - k;
       ff += geqrf(m, k) + orgqr_full(m, k) + 4.0 * m * m * m;
@@ -79,8 +134,9 @@ static void count_flops(Ctx& c) {
     }
   }
   for (auto& in : c.ins) {
-    ff += (double)in.n0 * in.n0 * in.n0 / 3.0;
-    ph[7] += (double)in.n0 * in.n0 * in.n0 / 3.0;
+    const double rc = (c.lu ? 2.0 : 1.0) * (double)in.n0 * in.n0 * in.n0 / 3.0;  // LU / Cholesky
+    ff += rc;
+    ph[7] += rc;
     fs += 2.0 * (double)in.n0 * in.n0;
     bytes += 8.0 * (double)in.n0 * in.n0;
     if (in.tree.L == 0) ++nnzb;

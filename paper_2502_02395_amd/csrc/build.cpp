@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <thread>
@@ -179,6 +180,96 @@ static h2_status blocked_chol_inv(Ctx& c, const std::vector<CholJob>& jobs, int*
   return H2_OK;
 }
 
+// Blocked pivot-free LU of the near-sample blocks A (n x n, ld n) for the LU
+// variant, with the explicit inverses of both factors: per 64-wide panel the
+// diagonal block's LU and the inverses of its factors in LDS
+// (lu_panel_kernel), L_21 = A_21 U_pp^{-1}, U_12 = L_pp^{-1} A_12, the trailing
+// update A_22 -= L_21 U_12; then the block rows of L^{-1},
+// X_{p,<p} = -X_pp (L_{p,<p} X_{<p,<p}), and the block columns of U^{-1},
+// Y_{<p,p} = -(Y_{<p,<p} U_{<p,p}) Y_pp.  A is overwritten by L (unit, below
+// the diagonal) and U; Linv and Uinv (ld n) must hold zeros on entry.  A zero
+// or non-finite pivot writes the job's code to fail.
+struct LuJob {
+  double* A;
+  double* Linv;
+  double* Uinv;
+  int n, code;
+};
+static h2_status blocked_lu_inv(Ctx& c, const std::vector<LuJob>& jobs, int* fail,
+                                hipStream_t st) {
+  if (jobs.empty()) return H2_OK;
+  int nmax = 0;
+  std::vector<int64_t> so(jobs.size() + 1, 0);  // scratch: 128 n per job
+  for (size_t q = 0; q < jobs.size(); ++q) {
+    nmax = std::max(nmax, jobs[q].n);
+    so[q + 1] = so[q] + 128 * (int64_t)std::max(jobs[q].n, 0);
+  }
+  TmpBuf tsc(c);
+  double* dS = tsc.get<double>(so.back());
+  ALLOCHK(dS);
+  const int np = (nmax + 63) / 64;
+  for (int pi = 0; pi < np; ++pi) {
+    const int p0 = 64 * pi;
+    std::vector<PanelDesc> pd;
+    std::vector<GemmDesc> tr, up;
+    std::vector<CopyDesc> bk;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      const LuJob& j = jobs[q];
+      const int n = j.n;
+      if (n <= p0) continue;
+      const int w = std::min(64, n - p0), rows = n - p0 - w;
+      double* Lp = j.Linv + p0 + (int64_t)p0 * n;
+      double* Up = j.Uinv + p0 + (int64_t)p0 * n;
+      pd.push_back({j.A + p0 + (int64_t)p0 * n, n, w, Lp, n, j.code, Up, n});
+      if (rows > 0) {
+        double* A21 = j.A + p0 + w + (int64_t)p0 * n;
+        double* A12 = j.A + p0 + (int64_t)(p0 + w) * n;
+        double* A22 = A21 + (int64_t)w * n;
+        double* S1 = dS + so[q];                    // rows x w, ld n
+        double* S2 = dS + so[q] + 64 * (int64_t)n;  // w x rows, ld 64
+        tr.push_back(gd(A21, n, 0, Up, n, 0, nullptr, 1, S1, n, rows, w, w, 1.0, 0.0));
+        tr.push_back(gd(Lp, n, 0, A12, n, 0, nullptr, 1, S2, 64, w, rows, w, 1.0, 0.0));
+        up.push_back(gd(S1, n, 0, S2, 64, 0, A22, n, A22, n, rows, rows, w, -1.0, 1.0));
+        bk.push_back({S1, A21, rows, w, n, n, 0});
+        bk.push_back({S2, A12, w, rows, 64, n, 0});
+      }
+    }
+    TmpBuf tp(c), tb(c);
+    PanelDesc* dpd = nullptr;
+    CopyDesc* dbk = nullptr;
+    if (!upload_tmp(tp, dpd, pd, st) || !upload_tmp(tb, dbk, bk, st)) return H2_ERR_ALLOC;
+    HIPCHK(launch_lu_panel(dpd, (int)pd.size(), fail, st));
+    h2_status e = run_gemm_tmp(c, tr, st);
+    if (e == H2_OK) e = run_gemm_tmp(c, up, st);
+    if (e != H2_OK) return e;
+    HIPCHK(launch_copy(dbk, (int)bk.size(), st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  for (int pi = 1; pi < np; ++pi) {
+    const int p0 = 64 * pi;
+    std::vector<GemmDesc> i1, i2;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      const LuJob& j = jobs[q];
+      const int n = j.n;
+      if (n <= p0) continue;
+      const int w = std::min(64, n - p0);
+      double* T1 = dS + so[q];                    // w x p0, ld 64
+      double* T2 = dS + so[q] + 64 * (int64_t)n;  // p0 x w, ld n
+      i1.push_back(gd(j.A + p0, n, 0, j.Linv, n, 0, nullptr, 1, T1, 64, w, p0, p0, 1.0, 0.0));
+      i1.push_back(gd(j.Uinv, n, 0, j.A + (int64_t)p0 * n, n, 0, nullptr, 1, T2, n, p0, w, p0, 1.0,
+                      0.0));
+      i2.push_back(gd(j.Linv + p0 + (int64_t)p0 * n, n, 0, T1, 64, 0, nullptr, 1, j.Linv + p0, n,
+                      w, p0, w, -1.0, 0.0));
+      i2.push_back(gd(T2, n, 0, j.Uinv + p0 + (int64_t)p0 * n, n, 0, nullptr, 1,
+                      j.Uinv + (int64_t)p0 * n, n, p0, w, w, -1.0, 0.0));
+    }
+    h2_status e = run_gemm_tmp(c, i1, st);
+    if (e == H2_OK) e = run_gemm_tmp(c, i2, st);
+    if (e != H2_OK) return e;
+  }
+  return H2_OK;
+}
+
 static h2_status run_gemm_tmp(Ctx& c, const std::vector<GemmDesc>& g, hipStream_t st) {
   if (g.empty()) return H2_OK;
   TmpBuf tb1(c), tb2(c);
@@ -211,10 +302,20 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   for (int t = 0; t < n_inst; ++t) {
     if (!pts[t] || ns[t] < 1) return H2_ERR_ARG;
     const h2_kernel& k = kerns[t];
-    if (k.id < 0 || k.id > 3) return H2_ERR_ARG;
-    if ((k.id <= 1 && !(k.delta > 0.0)) || (k.id >= 2 && !(k.ell > 0.0))) return H2_ERR_ARG;
+    if (k.id < 0 || k.id > 4) return H2_ERR_ARG;
+    const bool reg = k.id <= 1 || k.id == 4;
+    if ((reg && !(k.delta > 0.0)) || (!reg && !(k.ell > 0.0))) return H2_ERR_ARG;
     if (k.nugget < 0.0) return H2_ERR_ARG;
+    if (k.id == 4 && !std::isfinite(k.beta)) return H2_ERR_ARG;
   }
+  // the LU variant: forced, or any non-symmetric kernel
+  bool lu = prm->factor_lu != 0;
+  for (int t = 0; t < n_inst; ++t)
+    if (kerns[t].id == 4 && kerns[t].beta != 0.0) lu = true;
+  if (prm->factor_lu != 0 && prm->factor_lu != 1) return H2_ERR_ARG;
+  if (lu && (prm->gemm_prec != H2_PREC_FP64 || prm->solve_prec != H2_PREC_FP64 ||
+             prm->matvec_prec != H2_PREC_FP64 || prm->use_pcg))
+    return H2_ERR_ARG;
   if (fixed_ranks && n_inst != 1) return H2_ERR_ARG;
   if (prm->allocator && (!prm->allocator->alloc || !prm->allocator->free)) return H2_ERR_ARG;
 
@@ -235,6 +336,8 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   c.prm.allocator = nullptr;
   c.n_inst = n_inst;
   c.dim = prm->dim;
+  c.lu = lu;
+  c.st.lu_variant = lu ? 1 : 0;
   c.ins.resize(n_inst);
   const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 
@@ -245,7 +348,7 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     in.pbase = N;
     N += ns[t];
     const h2_kernel& k = kerns[t];
-    in.kern = KernelDev{k.id, k.delta, k.kappa, k.ell, k.nugget};
+    in.kern = KernelDev{k.id, k.delta, k.kappa, k.ell, k.nugget, k.id == 4 ? k.beta : 0.0};
     in.rank.assign(in.n, 0);
     if (perms && perms[t]) {
       std::vector<char> seen(in.n, 0);
@@ -282,11 +385,17 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     c.dX = c.alloc<double>(X.size());
     ALLOCHK(c.dX);
     HIPCHK(hipMemcpy(c.dX, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<KernelDev> kd(n_inst);
-    for (int t = 0; t < n_inst; ++t) kd[t] = c.ins[t].kern;
-    c.dKern = c.alloc<KernelDev>(n_inst);
+    // entry n_inst + t: the transposed kernel G^T(x, y) = G(y, x) of instance
+    // t (the drift kernel with -beta; the symmetric kernels unchanged)
+    std::vector<KernelDev> kd(2 * n_inst);
+    for (int t = 0; t < n_inst; ++t) {
+      kd[t] = c.ins[t].kern;
+      kd[n_inst + t] = c.ins[t].kern;
+      kd[n_inst + t].beta = -kd[n_inst + t].beta;
+    }
+    c.dKern = c.alloc<KernelDev>(2 * n_inst);
     ALLOCHK(c.dKern);
-    HIPCHK(hipMemcpy(c.dKern, kd.data(), n_inst * sizeof(KernelDev), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.dKern, kd.data(), 2 * n_inst * sizeof(KernelDev), hipMemcpyHostToDevice));
     std::vector<int64_t> pg(N);
     for (int t = 0; t < n_inst; ++t)
       for (int64_t q = 0; q < c.ins[t].n; ++q) pg[c.ins[t].pbase + q] = c.ins[t].pbase + c.ins[t].tree.perm[q];
@@ -377,15 +486,16 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     for (int t = 0; t < n_inst; ++t) {
       if (base[t] < 0) continue;
       const int l = c.ins[t].tree.L - h;
+      // unordered pairs (i >= j), or every ordered pair for the LU variant
       for (auto& pr : c.ins[t].tree.near[l]) {
         near_loc[base[t] + pr.first].push_back(pr.second);
-        if (pr.first >= pr.second) {
+        if (lu || pr.first >= pr.second) {
           S.np_i.push_back(base[t] + pr.first);
           S.np_j.push_back(base[t] + pr.second);
         }
       }
       for (auto& pr : c.ins[t].tree.far[l])
-        if (pr.first > pr.second) {
+        if (lu ? pr.first != pr.second : pr.first > pr.second) {
           S.fp_i.push_back(base[t] + pr.first);
           S.fp_j.push_back(base[t] + pr.second);
         }
@@ -423,14 +533,21 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     for (int b = 0; b < nb; ++b) {
       sf[b] = (int)SF[b].size();
       sc[b] = (int)SC[b].size();
-      s[b] = sf[b] + sc[b];
+      // the LU variant samples both sides: [G^T(S_F, B_i); G(S_F, B_i);
+      // A_cc^{-T} G^T(S_C, B_i); A_cc^{-1} G(S_C, B_i)]
+      s[b] = lu ? 2 * (sf[b] + sc[b]) : sf[b] + sc[b];
       if (sc[b] > CHOL_NMAX) return H2_ERR_UNSUPPORTED;
       // pre-factorization flops (Section 3.5): chol(A_cc) and two triangular
-      // solves with the m columns of G(S_C, B_i), or 2 c^2 m per sweep
+      // solves with the m columns of G(S_C, B_i), or 2 c^2 m per sweep; the
+      // LU variant: LU(A_cc) and two solves on each side, or sweeps on both
       if (sc[b] > 0) {
         const double cc = sc[b], mm = S.m[b];
-        c.st.flops_prefactor += prm->gs_sweeps > 0 ? prm->gs_sweeps * 2.0 * cc * cc * mm
-                                                   : cc * cc * cc / 3.0 + 2.0 * cc * cc * mm;
+        if (lu)
+          c.st.flops_prefactor += prm->gs_sweeps > 0 ? prm->gs_sweeps * 4.0 * cc * cc * mm
+                                                     : 2.0 * cc * cc * cc / 3.0 + 4.0 * cc * cc * mm;
+        else
+          c.st.flops_prefactor += prm->gs_sweeps > 0 ? prm->gs_sweeps * 2.0 * cc * cc * mm
+                                                     : cc * cc * cc / 3.0 + 2.0 * cc * cc * mm;
       }
       sfo[b + 1] = sfo[b] + sf[b];
       sco[b + 1] = sco[b] + sc[b];
@@ -461,12 +578,22 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
       fixed_box += nb;
     }
     TmpBuf tf(c), tc(c), tacc(c), tlc(c), tt1(c), tt2(c), tx(c), tpiv(c), tk(c), tfs(c);
+    TmpBuf tuc(c), tt1t(c), tt2t(c);  // the LU variant's second side
     int64_t *dF = nullptr, *dC = nullptr;
     if (!upload_tmp(tf, dF, ids_f, st) || !upload_tmp(tc, dC, ids_c, st)) return H2_ERR_ALLOC;
     double* dAcc = tacc.get<double>(acco[nb]);
     double* dLc = tlc.get<double>(acco[nb]);
     double* dT1 = tt1.get<double>(t1o[nb]);
     double* dT2 = tt2.get<double>(t1o[nb]);
+    // LU variant: U^{-1} of A_cc (or A_cc^T for the sweeps), G^T(S_C, B_i) and
+    // its partial solve
+    double *dUc = nullptr, *dT1t = nullptr, *dT2t = nullptr;
+    if (lu) {
+      dUc = tuc.get<double>(acco[nb]);
+      dT1t = tt1t.get<double>(t1o[nb]);
+      dT2t = tt2t.get<double>(t1o[nb]);
+      ALLOCHK(dUc); ALLOCHK(dT1t); ALLOCHK(dT2t);
+    }
     double* dXid = tx.get<double>(xo[nb]);
     int32_t* dPiv = tpiv.get<int32_t>(S.sum_m);
     int32_t* dK = tk.get<int32_t>(nb);
@@ -496,12 +623,26 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     std::vector<EvalDesc> ev;
     for (int b = 0; b < nb; ++b) {
       const int64_t* Bb = S.dB + S.boff[b];
-      const int t = S.inst[b];
+      const int t = S.inst[b], tt = n_inst + t;  // tt: the transposed kernel
       if (sc[b] > 0) {
         ev.push_back({dC + sco[b], dC + sco[b], dAcc + acco[b], sc[b], sc[b], sc[b], t});
         ev.push_back({dC + sco[b], Bb, dT1 + t1o[b], sc[b], S.m[b], sc[b], t});
+        if (lu) {
+          ev.push_back({dC + sco[b], Bb, dT1t + t1o[b], sc[b], S.m[b], sc[b], tt});
+          // the sweeps read row i of their matrix as column i of its storage:
+          // A_cc^T's storage for the solves with A_cc
+          if (prm->gs_sweeps > 0)
+            ev.push_back({dC + sco[b], dC + sco[b], dUc + acco[b], sc[b], sc[b], sc[b], tt});
+        }
       }
-      if (sf[b] > 0) ev.push_back({dF + sfo[b], Bb, dXid + xo[b], sf[b], S.m[b], s[b], t});
+      if (sf[b] > 0) {
+        if (lu) {
+          ev.push_back({dF + sfo[b], Bb, dXid + xo[b], sf[b], S.m[b], s[b], tt});
+          ev.push_back({dF + sfo[b], Bb, dXid + xo[b] + sf[b], sf[b], S.m[b], s[b], t});
+        } else {
+          ev.push_back({dF + sfo[b], Bb, dXid + xo[b], sf[b], S.m[b], s[b], t});
+        }
+      }
     }
     h2_status e = run_eval(c, ev, st);
     if (e != H2_OK) return e;
@@ -509,10 +650,20 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     if (prm->gs_sweeps > 0) {
       std::vector<GsDesc> gsd;
       // the row-major iterates reuse the (unused) second product buffer
-      for (int b = 0; b < nb; ++b)
-        if (sc[b] > 0)
+      for (int b = 0; b < nb; ++b) {
+        if (sc[b] == 0) continue;
+        if (lu) {
+          // A_cc X = G(S_C, B_i) and A_cc^T X = G^T(S_C, B_i)
+          double* X = dXid + xo[b] + 2 * sf[b];
+          gsd.push_back({dUc + acco[b], dT1 + t1o[b], X + sc[b], dT2 + t1o[b], sc[b], S.m[b],
+                         sc[b], sc[b], s[b], b});
+          gsd.push_back({dAcc + acco[b], dT1t + t1o[b], X, dT2t + t1o[b], sc[b], S.m[b], sc[b],
+                         sc[b], s[b], b});
+        } else {
           gsd.push_back({dAcc + acco[b], dT1 + t1o[b], dXid + xo[b] + sf[b], dT2 + t1o[b], sc[b],
                          S.m[b], sc[b], sc[b], s[b], b});
+        }
+      }
       TmpBuf tgs(c);
       GsDesc* dgs = nullptr;
       if (!upload_tmp(tgs, dgs, gsd, st)) return H2_ERR_ALLOC;
@@ -527,6 +678,42 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
         c.st.fail_inst = S.inst[fail];
         return not_spd();
       }
+    } else if (lu) {
+    // ... or exactly, LU variant: U_c^{-1} (L_c^{-1} G(S_C, B_i)) and
+    // L_c^{-T} (U_c^{-T} G^T(S_C, B_i))
+      std::vector<LuJob> lj;
+      for (int b = 0; b < nb; ++b)
+        if (sc[b] > 0) lj.push_back({dAcc + acco[b], dLc + acco[b], dUc + acco[b], sc[b], b});
+      const size_t ab = (size_t)std::max<int64_t>(acco[nb], 1) * sizeof(double);
+      HIPCHK(hipMemsetAsync(dLc, 0, ab, st));
+      HIPCHK(hipMemsetAsync(dUc, 0, ab, st));
+      HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
+      if ((e = blocked_lu_inv(c, lj, c.dFail, st)) != H2_OK) return e;
+      int fail = INT_MAX;
+      HIPCHK(hipMemcpyAsync(&fail, c.dFail, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (fail != INT_MAX) {
+        c.st.fail_level = c.ins[S.inst[fail]].tree.L - h;
+        c.st.fail_box = S.idx[fail];
+        c.st.fail_inst = S.inst[fail];
+        return not_spd();
+      }
+      std::vector<GemmDesc> g1, g1t, g2, g2t;
+      for (int b = 0; b < nb; ++b) {
+        const int n = sc[b], m = S.m[b];
+        if (n == 0) continue;
+        double* X = dXid + xo[b] + 2 * sf[b];
+        g1.push_back(gd(dLc + acco[b], n, 0, dT1 + t1o[b], n, 0, nullptr, 1, dT2 + t1o[b], n, n, m,
+                        n, 1.0, 0.0));
+        g1t.push_back(gd(dUc + acco[b], n, 1, dT1t + t1o[b], n, 0, nullptr, 1, dT2t + t1o[b], n,
+                         n, m, n, 1.0, 0.0));
+        g2.push_back(gd(dUc + acco[b], n, 0, dT2 + t1o[b], n, 0, nullptr, 1, X + n, s[b], n, m, n,
+                        1.0, 0.0));
+        g2t.push_back(gd(dLc + acco[b], n, 1, dT2t + t1o[b], n, 0, nullptr, 1, X, s[b], n, m, n,
+                         1.0, 0.0));
+      }
+      for (auto* g : {&g1, &g1t, &g2, &g2t})
+        if ((e = run_gemm_tmp(c, *g, st)) != H2_OK) return e;
     } else {
     // ... or exactly: Lc^{-T} (Lc^{-1} G(S_C, B_i))
       std::vector<CholJob> cj;
@@ -746,11 +933,16 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     in.dRootA = c.alloc<double>((size_t)n0 * n0);
     in.dRootX = c.alloc<double>((size_t)n0 * n0);
     in.dRinv = c.alloc<double>((size_t)n0 * n0);
-    in.dPan = c.alloc<double>((size_t)n0 * 64);
+    in.dPan = c.alloc<double>((size_t)n0 * (c.lu ? 128 : 64));
     ALLOCHK(in.dRoot); ALLOCHK(in.dRootA); ALLOCHK(in.dRootX); ALLOCHK(in.dRinv); ALLOCHK(in.dPan);
     // L^{-1}: the panels write the diagonal blocks, the inverse block rows
-    // the blocks below them; the blocks above stay zero
+    // the blocks below them; the blocks above stay zero (U^{-1} likewise)
     HIPCHK(hipMemsetAsync(in.dRootX, 0, (size_t)n0 * n0 * sizeof(double), st));
+    if (c.lu) {
+      in.dRootUi = c.alloc<double>((size_t)n0 * n0);
+      ALLOCHK(in.dRootUi);
+      HIPCHK(hipMemsetAsync(in.dRootUi, 0, (size_t)n0 * n0 * sizeof(double), st));
+    }
     max_n0 = std::max(max_n0, in.n0);
   }
   // L == 0 instances: the dense kernel block is the whole matrix
@@ -796,6 +988,12 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     S.dTau = c.alloc<double>(std::max<int64_t>(S.koff[nb], 1));
     ALLOCHK(S.dQ); ALLOCHK(S.dP); ALLOCHK(S.dTA); ALLOCHK(S.dTB); ALLOCHK(S.dW); ALLOCHK(S.dTau);
     ALLOCHK(S.dR); ALLOCHK(S.dLi);
+    if (c.lu) {
+      S.dPr = c.alloc<double>(q);
+      S.dUi = c.alloc<double>(std::max<int64_t>(S.lioff[nb], 1));
+      S.dLUs = c.alloc<double>(std::max<int64_t>(128 * S.roff[nb], 1));
+      ALLOCHK(S.dPr); ALLOCHK(S.dUi); ALLOCHK(S.dLUs);
+    }
     // near blocks of upper steps (m = k_2I + k_2I+1 is known now)
     const size_t np = S.np_i.size();
     S.poff.assign(np + 1, 0);
@@ -916,7 +1114,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
   for (int h = 0; h < c.H; ++h) {
     Step& S = c.steps[h];
     const int nb = S.nbox;
-    std::vector<GemmDesc> gw, gq1, gq2, gq3, gd1, gd2, gv, gs, gp1, gp2, gf1, gf2;
+    std::vector<GemmDesc> gw, gq1, gq2, gq3, gd1, gd2, gv, gv2, gs, gp1, gp2, gf1, gf2;
     std::vector<CopyDesc> cw, cps, cm;
     std::vector<ConvDesc> cvd;  // FP32 transforms: D_ii -> FP32 above the leaves
     std::vector<BoxDev> qr(nb);
@@ -965,6 +1163,28 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gd2.push_back(gd(Q, m, 1, TA, m, 0, nullptr, 1, TB, m, m, m, m, 1.0, 0.0));
       }
       if (m * k > 0) cps.push_back({Q, P, m, k, m, m, 0});
+      if (c.lu) {
+        // LU variant: P = [Q^S | Q^R L^{-T}], P' = [Q^S | Q^R U^{-1}],
+        // L(s)_ii = SR U^{-1}, U(s)_ii = L^{-1} RS, SS -= L(s)_ii U(s)_ii
+        double* Pr = S.dPr + S.qoff[b];
+        double* Ui = S.dUi + S.lioff[b];
+        if (m * k > 0) cps.push_back({Q, Pr, m, k, m, m, 0});
+        if (r > 0) {
+          gv.push_back(gd(Q + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, P + (int64_t)k * m, m, m,
+                          r, r, 1.0, 0.0));
+          gv2.push_back(gd(Q + (int64_t)k * m, m, 0, Ui, r, 0, nullptr, 1, Pr + (int64_t)k * m, m,
+                           m, r, r, 1.0, 0.0));
+          if (k > 0) {
+            gv2.push_back(gd(TB + (int64_t)k * m, m, 0, Ui, r, 0, nullptr, 1, Fii + (int64_t)k * m,
+                             m, k, r, r, 1.0, 0.0));
+            gv2.push_back(gd(Li, r, 0, TB + k, m, 0, nullptr, 1, Fii + k, m, r, k, r, 1.0, 0.0));
+          }
+        }
+        if (k > 0)
+          gs.push_back(gd(Fii + (int64_t)k * m, m, 0, Fii + k, m, 0, TB, m, Fii, m, k, k, r, -1.0,
+                          1.0));
+        continue;
+      }
       if (r > 0) {
         gv.push_back(gd(Q + (int64_t)k * m, m, 0, Li, r, 1, nullptr, 1, P + (int64_t)k * m, m, m, r,
                         r, 1.0, 0.0));
@@ -995,8 +1215,9 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gp2.push_back(gd(asd(S.dP32 + S.qoff[i]), mi, 1, asd(S.dT232 + S.poff[p]), mi, 0, nullptr,
                          1, asd(S.dF32 + S.poff[p]), mi, mi, mj, mi, 1.0, 0.0));
       } else {
-        gp1.push_back(gd(S.dD + S.poff[p], mi, 0, S.dP + S.qoff[j], mj, 0, nullptr, 1,
-                         S.dT2 + S.poff[p], mi, mi, mj, mj, 1.0, 0.0));
+        // (LU variant: the right basis P'_j on the right)
+        gp1.push_back(gd(S.dD + S.poff[p], mi, 0, (c.lu ? S.dPr : S.dP) + S.qoff[j], mj, 0,
+                         nullptr, 1, S.dT2 + S.poff[p], mi, mi, mj, mj, 1.0, 0.0));
         gp2.push_back(gd(S.dP + S.qoff[i], mi, 1, S.dT2 + S.poff[p], mi, 0, nullptr, 1,
                          S.dF + S.poff[p], mi, mi, mj, mi, 1.0, 0.0));
       }
@@ -1037,7 +1258,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gf3.push_back(gd(asd(S.dT332 + S.soff[f]), ki, 0, asd(S.dR32 + S.rkoff[j]), kj, 1, nullptr,
                          1, dst, ldp, ki, kj, kj, 1.0, 0.0));
       const bool sib = (S.idx[i] >> 1) == (S.idx[j] >> 1);
-      if (sib && ki * kj > 0) {
+      if (sib && ki * kj > 0 && !c.lu) {  // (the LU variant has both orders)
         // transposed copy inside the parent's diagonal block
         cm.push_back({dst, dst - S.k[j] + (int64_t)S.k[j] * ldp, kj, ki, ldp, ldp, 1});
       }
@@ -1060,7 +1281,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       }
       std::vector<CopyDesc>& out = from32 ? cm32 : cm;
       out.push_back({src, dst, ka, kb, S.m[a], ldp, 0});
-      if (a != b && (S.idx[a] >> 1) == (S.idx[b] >> 1)) {
+      if (a != b && (S.idx[a] >> 1) == (S.idx[b] >> 1) && !c.lu) {
         // sibling block (2I+1, 2I): also write (2I, 2I+1) = transpose
         double* base = dst - kb;  // row offset of a is k_b; back to the parent origin row
         out.push_back({src, base + (int64_t)kb * ldp, kb, ka, S.m[a], ldp, 1});
@@ -1070,7 +1291,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       return upload_gemm(c, B, v, st);
     };
     if (!up_g(S.g_w, gw) || !up_g(S.g_qr1, gq1) || !up_g(S.g_qr2, gq2) || !up_g(S.g_qr3, gq3) ||
-        !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) ||
+        !up_g(S.g_diag1, gd1) || !up_g(S.g_diag2, gd2) || !up_g(S.g_v, gv) || !up_g(S.g_v2, gv2) ||
         !up_g(S.g_schur, gs) || !up_g(S.g_pair1, gp1) || !up_g(S.g_pair2, gp2) ||
         !up_g(S.g_far1, gf1) || !up_g(S.g_far2, gf2) || !up_g(S.g_far3, gf3))
       return H2_ERR_ALLOC;
@@ -1108,6 +1329,35 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         double* TA = S.dTA + S.qoff[b];
         double* Li = S.dLi + S.lioff[b];
         double* Dp = Li + p0 + (int64_t)p0 * r;
+        if (c.lu) {
+          // LU variant: L_21 = A_21 U_pp^{-1}, U_12 = L_pp^{-1} A_12 (into the
+          // scratch, then back), A_22 -= L_21 U_12; inverse block rows of
+          // L^{-1} and block columns of U^{-1}
+          double* Ui = S.dUi + S.lioff[b];
+          double* Up = Ui + p0 + (int64_t)p0 * r;
+          double* S1 = S.dLUs + 128 * S.roff[b];  // rows x w, ld r / w x p0, ld 64
+          double* S2 = S1 + 64 * (int64_t)r;       // w x rows, ld 64 / p0 x w, ld r
+          pd.push_back({A + p0 + (int64_t)p0 * m, m, w, Dp, r, h * (1 << 20) + b, Up, r});
+          if (rows > 0) {
+            double* A21 = A + p0 + w + (int64_t)p0 * m;
+            double* A12 = A + p0 + (int64_t)(p0 + w) * m;
+            double* A22 = A + p0 + w + (int64_t)(p0 + w) * m;
+            tr.push_back(gd(A21, m, 0, Up, r, 0, nullptr, 1, S1, r, rows, w, w, 1.0, 0.0));
+            tr.push_back(gd(Dp, r, 0, A12, m, 0, nullptr, 1, S2, 64, w, rows, w, 1.0, 0.0));
+            sy.push_back(gd(S1, r, 0, S2, 64, 0, A22, m, A22, m, rows, rows, w, -1.0, 1.0));
+            bk.push_back({S1, A21, rows, w, r, m, 0});
+            bk.push_back({S2, A12, w, rows, 64, m, 0});
+          }
+          if (p0 > 0) {
+            i1.push_back(gd(A + p0, m, 0, Li, r, 0, nullptr, 1, S1, 64, w, p0, p0, 1.0, 0.0));
+            i1.push_back(gd(Ui, r, 0, A + (int64_t)p0 * m, m, 0, nullptr, 1, S2, r, p0, w, p0, 1.0,
+                            0.0));
+            i2.push_back(gd(Dp, r, 0, S1, 64, 0, nullptr, 1, Li + p0, r, w, p0, w, -1.0, 0.0));
+            i2.push_back(gd(S2, r, 0, Up, r, 0, nullptr, 1, Ui + (int64_t)p0 * r, r, p0, w, w, -1.0,
+                            0.0));
+          }
+          continue;
+        }
         pd.push_back({A + p0 + (int64_t)p0 * m, m, w, Dp, r, h * (1 << 20) + b});
         if (rows > 0) {
           double* A21 = A + p0 + w + (int64_t)p0 * m;
@@ -1206,8 +1456,25 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         const int nbk = std::min(64, n - p);
         double* A = in.dRoot;
         double* Xpp = in.dRootX + p + (int64_t)p * n;  // L_pp^{-1}, ld n
-        pd.push_back({A + p + (int64_t)p * n, n, nbk, Xpp, n, (1023 << 20) + t});
         const int rows = n - p - nbk;
+        if (c.lu) {
+          double* Upp = in.dRootUi + p + (int64_t)p * n;  // U_pp^{-1}, ld n
+          pd.push_back({A + p + (int64_t)p * n, n, nbk, Xpp, n, (1023 << 20) + t, Upp, n});
+          if (rows > 0) {
+            double* A21 = A + (p + nbk) + (int64_t)p * n;
+            double* A12 = A + p + (int64_t)(p + nbk) * n;
+            double* A22 = A + (p + nbk) + (int64_t)(p + nbk) * n;
+            double* S1 = in.dPan;                     // rows x nbk, ld n
+            double* S2 = in.dPan + 64 * (int64_t)n;   // nbk x rows, ld 64
+            tr.push_back(gd(A21, n, 0, Upp, n, 0, nullptr, 1, S1, n, rows, nbk, nbk, 1.0, 0.0));
+            tr.push_back(gd(Xpp, n, 0, A12, n, 0, nullptr, 1, S2, 64, nbk, rows, nbk, 1.0, 0.0));
+            sy.push_back(gd(S1, n, 0, S2, 64, 0, A22, n, A22, n, rows, rows, nbk, -1.0, 1.0));
+            bk.push_back({S1, A21, rows, nbk, n, n, 0});
+            bk.push_back({S2, A12, nbk, rows, 64, n, 0});
+          }
+          continue;
+        }
+        pd.push_back({A + p + (int64_t)p * n, n, nbk, Xpp, n, (1023 << 20) + t});
         if (rows > 0) {
           double* A21 = A + (p + nbk) + (int64_t)p * n;
           double* A22 = A + (p + nbk) + (int64_t)(p + nbk) * n;
@@ -1232,16 +1499,30 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
                         1.0, 0.0));
         i2.push_back(gd(in.dRootX + p + (int64_t)p * n, n, 0, in.dPan, 64, 0, nullptr, 1,
                         in.dRootX + p, n, nbk, p, nbk, -1.0, 0.0));
+        if (c.lu) {
+          // block column p of U^{-1}: Y_{<p,p} = -(Y_{<p,<p} U_{<p,p}) Y_pp
+          double* T2 = in.dPan + 64 * (int64_t)n;  // p x nbk, ld n
+          i1.push_back(gd(in.dRootUi, n, 0, in.dRoot + (int64_t)p * n, n, 0, nullptr, 1, T2, n, p,
+                          nbk, p, 1.0, 0.0));
+          i2.push_back(gd(T2, n, 0, in.dRootUi + p + (int64_t)p * n, n, 0, nullptr, 1,
+                          in.dRootUi + (int64_t)p * n, n, p, nbk, nbk, -1.0, 0.0));
+        }
       }
       if (!upload_gemm(c, c.r_inv1[pi], i1, st) || !upload_gemm(c, c.r_inv2[pi], i2, st))
         return H2_ERR_ALLOC;
     }
-    // root^{-1} = X^T X: the root solve of the substitution is one product
+    // root^{-1} = X^T X (LU variant: U^{-1} L^{-1}): the root solve of the
+    // substitution is one product
     std::vector<GemmDesc> fl;
     for (auto& in : c.ins)
-      if (in.n0 > 0)
-        fl.push_back(gd(in.dRootX, in.n0, 1, in.dRootX, in.n0, 0, nullptr, 1, in.dRinv, in.n0,
-                        in.n0, in.n0, in.n0, 1.0, 0.0));
+      if (in.n0 > 0) {
+        if (c.lu)
+          fl.push_back(gd(in.dRootUi, in.n0, 0, in.dRootX, in.n0, 0, nullptr, 1, in.dRinv, in.n0,
+                          in.n0, in.n0, in.n0, 1.0, 0.0));
+        else
+          fl.push_back(gd(in.dRootX, in.n0, 1, in.dRootX, in.n0, 0, nullptr, 1, in.dRinv, in.n0,
+                          in.n0, in.n0, in.n0, 1.0, 0.0));
+      }
     if (!upload_gemm(c, c.r_full, fl, st)) return H2_ERR_ALLOC;
   }
   return H2_OK;

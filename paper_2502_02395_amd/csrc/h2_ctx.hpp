@@ -100,6 +100,9 @@ struct Step {
   Batch<CopyDesc> c_merge3232;             // FP32 blocks into FP32 parent near blocks
   double* dR = nullptr;                    // at rkoff
   double* dLi = nullptr;                   // at lioff
+  // LU variant: right basis P'_i = [Q^S | Q^R U(r)_ii^{-1}] (at qoff), U(r)^{-1}
+  // (at lioff), panel scratch (128 r per box, at 128 roff)
+  double *dPr = nullptr, *dUi = nullptr, *dLUs = nullptr;
   // factor work lists
   Batch<GemmDesc> g_w;                     // W = D_i U_i (upper steps)
   Batch<GemmDesc> g_qr1, g_qr2, g_qr3;     // compact-WY Q: V^T V, T V^T, -V (T V^T)
@@ -118,6 +121,7 @@ struct Step {
   std::vector<Batch<CopyDesc>> ch_back;
   Batch<CopyDesc> c_ps;                    // P^S = Q^S
   Batch<GemmDesc> g_v;                     // V = Q^R Linv^T, L(s)_ii
+  Batch<GemmDesc> g_v2;                    // LU variant: Q^R U^{-1}, L(s)_ii, U(s)_ii
   Batch<GemmDesc> g_schur;                 // SS_ii -= L(s) L(s)^T
   Batch<GemmDesc> g_pair1, g_pair2;        // D_ij P_j, P_i^T (.)
   Batch<GemmDesc> g_far1, g_far2;          // R_i S_ij, (.) R_j^T into the parent
@@ -144,6 +148,8 @@ struct Instance {
   double* dRootOrig = nullptr;             // L == 0: the dense kernel block
   double* dRootX = nullptr;                // n0 x n0: L^{-1} of the root Cholesky factor
   double* dRinv = nullptr;                 // n0 x n0: root^{-1} = L^{-T} L^{-1}
+                                           // (LU variant: U^{-1} L^{-1})
+  double* dRootUi = nullptr;               // LU variant: n0 x n0 U^{-1} of the root
   double* dPan = nullptr;                  // n0 x 64 panel scratch
   double* v_root = nullptr;                // n0 x NRHS_MAX
 };
@@ -156,6 +162,7 @@ struct Ctx {
   int dim = 3;
   int64_t N = 0;
   int H = 0;                               // max levels
+  bool lu = false;                         // the LU variant (params.factor_lu)
   std::vector<Instance> ins;
   std::vector<Step> steps;                 // h = 0 .. H-1
   double* dX = nullptr;                    // N x dim points (original order per instance)

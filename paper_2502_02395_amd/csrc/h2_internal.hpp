@@ -17,6 +17,7 @@ namespace h2 {
 struct KernelDev {          // kernel function parameters of one instance
   int id;
   double delta, kappa, ell, nugget;
+  double beta;              // drift kernel: skew strength (its transpose: -beta)
 };
 
 // One item of a batched GEMM:  D = alpha * op(A) op(B) + beta * C
@@ -345,11 +346,16 @@ hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t*
 struct PanelDesc {
   double* A;                // diagonal block pointer
   int lda, nb;
-  double* dinv;             // nb x nb inverse of the panel's factor
+  double* dinv;             // nb x nb inverse of the panel's factor (LU: of L)
   int ldd;                  // leading dimension of dinv
   int code;
+  double* uinv;             // LU panels: nb x nb inverse of U (ld ldu)
+  int ldu;
 };
 hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st);
+// Pivot-free LU of each nb x nb diagonal block (unit lower L below the
+// diagonal, U on and above it, in place) and the inverses of L and U.
+hipError_t launch_lu_panel(const PanelDesc* d, int count, int* fail, hipStream_t st);
 
 // Vector permutations: dst[r + c*ldd] = src[idx[r] + c*lds]  (gather)
 hipError_t launch_gather_rows(const int64_t* idx, int64_t n, int nrhs,

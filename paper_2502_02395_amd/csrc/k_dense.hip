@@ -832,4 +832,95 @@ hipError_t launch_panel(const PanelDesc* d, int count, int* fail, hipStream_t st
   return hipGetLastError();
 }
 
+// Inverse of the lower triangle of a (unit diagonal if UNIT) into x, which
+// must hold zeros: 16 x 16 diagonal blocks by forward substitution (thread =
+// column), then the block recursion of panel_inv_merge.
+template <bool UNIT>
+__device__ __forceinline__ void panel_inv_lower(const double* __restrict__ a, double* __restrict__ x,
+                                                double* __restrict__ t) {
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    const int o = tid & ~15, j = tid;
+    for (int i = o; i < o + 16; ++i) {
+      double s = i == j ? 1.0 : 0.0;
+      for (int q = o; q < i; ++q) s -= a[i + q * PLD] * x[q + j * PLD];
+      x[i + j * PLD] = UNIT ? s : s / a[i + i * PLD];
+    }
+  }
+  __syncthreads();
+  panel_inv_merge<16>(a, x, t);
+  panel_inv_merge<32>(a, x, t);
+}
+
+// Pivot-free LU of an nb x nb diagonal block (nb <= 64), padded to 64 x 64
+// with the identity: right-looking, one barrier per column (the update of
+// step j uses the unscaled column j and the pivot's reciprocal; column j is
+// scaled after the barrier, when no later step reads it).  A zero or
+// non-finite pivot writes the job's code to fail and continues with 1.  Then
+// L^{-1} (unit lower) and U^{-1}: the latter as the transpose of the inverse
+// of U^T, formed in the lower triangle of a after L has been written out.
+__global__ __launch_bounds__(256) void lu_panel_kernel(const PanelDesc* __restrict__ descs,
+                                                       int* fail) {
+  __shared__ double a[64 * PLD];
+  __shared__ double x[64 * PLD];
+  __shared__ double t[32 * 32];
+  const PanelDesc d = descs[blockIdx.x];
+  const int n = d.nb;
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    a[r + c * PLD] = (r < n && c < n) ? d.A[r + (int64_t)c * d.lda] : (r == c ? 1.0 : 0.0);
+    x[r + c * PLD] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < 64; ++j) {
+    double p = a[j + j * PLD];
+    if (!(fabs(p) > 0.0) || !isfinite(p)) {
+      if (tid == 0) atomicMin(fail, d.code);
+      p = 1.0;
+    }
+    const double rp = 1.0 / p;
+    // a[i, c] -= a[i, j] (a[j, c] / p) for i, c > j
+    for (int c = j + 1 + wave; c < 64; c += 4) {
+      const double ujc = a[j + c * PLD] * rp;
+      const int i = j + 1 + lane;
+      if (i < 64) a[i + c * PLD] -= a[i + j * PLD] * ujc;
+    }
+    __syncthreads();
+    if (tid > j && tid < 64) a[tid + j * PLD] *= rp;
+  }
+  __syncthreads();
+  // L and U back in place
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    d.A[r + (int64_t)c * d.lda] = a[r + c * PLD];
+  }
+  panel_inv_lower<true>(a, x, t);
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    d.dinv[r + (int64_t)c * d.ldd] = x[r + c * PLD];
+  }
+  __syncthreads();
+  // lower triangle of a <- U^T (diagonal kept), x <- 0
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    if (r > c) a[r + c * PLD] = a[c + r * PLD];
+    x[r + c * PLD] = 0.0;
+  }
+  __syncthreads();
+  panel_inv_lower<false>(a, x, t);
+  // U^{-1} = ((U^T)^{-1})^T
+  for (int e = tid; e < n * n; e += 256) {
+    const int r = e % n, c = e / n;
+    d.uinv[r + (int64_t)c * d.ldu] = x[c + r * PLD];
+  }
+}
+
+hipError_t launch_lu_panel(const PanelDesc* d, int count, int* fail, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lu_panel_kernel, dim3(count), dim3(256), 0, st, d, fail);
+  return hipGetLastError();
+}
+
 }  // namespace h2

@@ -7,13 +7,18 @@ namespace h2 {
 
 // ---------------------------------------------------------- kernel function
 // Eq. 35 / Eq. 36 with the regularisation 1/(r + delta) (value 1/delta on the
-// diagonal) and the covariance kernels with a nugget added where the two
-// point indices coincide.
-__device__ __forceinline__ double kernel_value(const KernelDev& k, double r, bool same) {
+// diagonal), the covariance kernels with a nugget added where the two point
+// indices coincide, and the Yukawa kernel with a drift along the first axis
+// (dx0 = x_0 - y_0; its transpose is the same kernel with -beta).
+__device__ __forceinline__ double kernel_value(const KernelDev& k, double r, double dx0, bool same) {
   switch (k.id) {
     case 0: return 1.0 / (r + k.delta);
     case 1: return exp(-k.kappa * r) / (r + k.delta);
     case 2: return exp(-(r * r) / (k.ell * k.ell)) + (same ? k.nugget : 0.0);
+    case 4: {
+      const double q = 1.0 / (r + k.delta);
+      return exp(-k.kappa * r) * q * (1.0 + k.beta * dx0 * q) + (same ? k.nugget : 0.0);
+    }
     default: {
       const double a = 1.7320508075688772 * r / k.ell;
       return (1.0 + a) * exp(-a) + (same ? k.nugget : 0.0);
@@ -51,12 +56,13 @@ __global__ __launch_bounds__(256) void eval_kernel(const EvalDesc* __restrict__ 
     const int c = c0 + cc;
     if (c >= d.nc) break;
     const int64_t pc = d.cols[c];
-    double s = 0.0;
+    double s = 0.0, dx0 = 0.0;
     for (int a = 0; a < dim; ++a) {
       const double df = xr[a] - X[pc * dim + a];
+      if (a == 0) dx0 = df;
       s += df * df;
     }
-    d.out[r + (int64_t)c * d.ld] = kernel_value(k, sqrt(s), pr == pc);
+    d.out[r + (int64_t)c * d.ld] = kernel_value(k, sqrt(s), dx0, pr == pc);
   }
 }
 

@@ -197,18 +197,25 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
     const int vld = (int)S.vld;
     const int rld = (int)std::max<int64_t>(S.sum_r, 1);
     const int kld = (int)std::max<int64_t>(S.sum_k, 1);
-    // neighbour lists from the unordered near pairs
-    std::vector<std::vector<std::pair<int, int>>> lower(nb), upper(nb);  // (other, pair)
+    // neighbour lists (other, pair) from the unordered near pairs: lower[i]
+    // the pairs (i, j < i), upper[j] the same pairs seen from j (read
+    // transposed); LU variant (every ordered pair stored): lower[i] the pairs
+    // (i, j < i), higher[i] the pairs (i, j > i), all read directly
+    std::vector<std::vector<std::pair<int, int>>> lower(nb), upper(nb), higher(nb);
     for (size_t p = 0; p < S.np_i.size(); ++p) {
       const int i = S.np_i[p], j = S.np_j[p];
       if (i == j) continue;
-      lower[i].push_back({j, (int)p});
-      upper[j].push_back({i, (int)p});
+      if (c.lu) {
+        (j < i ? lower[i] : higher[i]).push_back({j, (int)p});
+      } else {
+        lower[i].push_back({j, (int)p});
+        upper[j].push_back({i, (int)p});
+      }
     }
     std::vector<std::vector<std::pair<int, int>>> flo(nb), fup(nb);
     for (size_t f = 0; f < S.fp_i.size(); ++f) {
       flo[S.fp_i[f]].push_back({S.fp_j[f], (int)f});
-      fup[S.fp_j[f]].push_back({S.fp_i[f], (int)f});
+      if (!c.lu) fup[S.fp_j[f]].push_back({S.fp_i[f], (int)f});
     }
     auto F = [&](int p) { return S.dF + S.poff[p]; };
     std::vector<GemmDesc> tf, tb, tu, td;
@@ -248,6 +255,10 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
           const int j = jp.first, rj = S.m[j] - S.k[j];
           if (rj > 0) n2.push_back({F(jp.second) + (int64_t)S.k[j] * m, S.v_yr + S.roff[j], m, rld, rj});
         }
+        for (auto& jp : higher[b]) {  // LU variant: L(s)_ij = F_ij^SR, j > i
+          const int j = jp.first, rj = S.m[j] - S.k[j];
+          if (rj > 0) n2.push_back({F(jp.second) + (int64_t)S.k[j] * m, S.v_yr + S.roff[j], m, rld, rj});
+        }
         g.d1 = (int)n2.size();
         g.t0 = (int)n2.size();
         for (auto& jp : upper[b]) {
@@ -276,10 +287,22 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
             parent_slice(h, i, true, xsi, xldi);
             n3.push_back({F(ip.second) + k, xsi, m, xldi, ki});
           }
+          const double* Fjj = S.dF + S.poff[S.diag_pair[b]];
+          if (c.lu) {
+            // U(s)_ji = F_ji^RS for i = j and i > j, read directly
+            if (k > 0) n3.push_back({Fjj + k, xs, m, xld, k});
+            for (auto& ip : higher[b]) {
+              const int i = ip.first, ki = S.k[i];
+              if (ki == 0) continue;
+              double* xsi;
+              int xldi;
+              parent_slice(h, i, true, xsi, xldi);
+              n3.push_back({F(ip.second) + k, xsi, m, xldi, ki});
+            }
+          }
           g.d1 = (int)n3.size();
           g.t0 = (int)n3.size();
-          const double* Fjj = S.dF + S.poff[S.diag_pair[b]];
-          if (k > 0) n3.push_back({Fjj + (int64_t)k * m, xs, m, xld, k});
+          if (k > 0 && !c.lu) n3.push_back({Fjj + (int64_t)k * m, xs, m, xld, k});
           for (auto& ip : upper[b]) {
             const int i = ip.first, ki = S.k[i];
             if (ki == 0) continue;
@@ -299,7 +322,13 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
       }
       // s_j = t_j - sum_{i>j} Lt_ij^T t_i, into d_j[k:]
       if (r > 0) {
-        GatherBox g{vd + k, tv, r, vld, rld, -1.0, (int)n4.size(), (int)n4.size(), (int)n4.size(), 0};
+        GatherBox g{vd + k, tv, r, vld, rld, -1.0, (int)n4.size(), 0, 0, 0};
+        for (auto& ip : higher[b]) {  // LU variant: U(r)_ji read directly from F_ji^RR
+          const int i = ip.first, ri = S.m[i] - S.k[i];
+          if (ri > 0)
+            n4.push_back({F(ip.second) + k + (int64_t)S.k[i] * m, S.v_t + S.roff[i], m, rld, ri});
+        }
+        g.d1 = g.t0 = (int)n4.size();
         for (auto& ip : upper[b]) {
           const int i = ip.first, ri = S.m[i] - S.k[i];
           if (ri > 0)
@@ -308,8 +337,9 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         g.t1 = (int)n4.size();
         b4.push_back(g);
       }
-      // x_j = P_j d_j
-      tb.push_back(gd(P, m, 0, vd, vld, 0, nullptr, 1, vout, vld, m, NR, m, 1.0, 0.0));
+      // x_j = P_j d_j (LU variant: the right basis P'_j)
+      const double* Pb = c.lu ? S.dPr + S.qoff[b] : P;
+      tb.push_back(gd(Pb, m, 0, vd, vld, 0, nullptr, 1, vout, vld, m, NR, m, 1.0, 0.0));
 
       // ---- matvec: upward U^T x
       const double* U = S.Uptr[b];
@@ -351,6 +381,10 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
         GatherBox g{c.vt_out + S.voff[b], nullptr, m, vld, vld, 1.0, (int)nn.size(), 0, 0, 0};
         nn.push_back({S.dD + S.poff[S.diag_pair[b]], c.vt_in + S.voff[b], m, vld, m});
         for (auto& jp : lower[b]) {
+          const int j = jp.first;
+          nn.push_back({S.dD + S.poff[jp.second], c.vt_in + S.voff[j], m, vld, S.m[j]});
+        }
+        for (auto& jp : higher[b]) {
           const int j = jp.first;
           nn.push_back({S.dD + S.poff[jp.second], c.vt_in + S.voff[j], m, vld, S.m[j]});
         }
@@ -586,8 +620,10 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(done());
     HIPCHK(mark(FP_CHOL));
     HIPCHK(launch_fill(S.dLi, S.lioff.back(), 0.0, st));
+    if (c.lu) HIPCHK(launch_fill(S.dUi, S.lioff.back(), 0.0, st));
     for (size_t p = 0; p < S.ch_panel.size(); ++p) {
-      HIPCHK(launch_panel(S.ch_panel[p].d, S.ch_panel[p].count, c.dFail, st));
+      if (c.lu) HIPCHK(launch_lu_panel(S.ch_panel[p].d, S.ch_panel[p].count, c.dFail, st));
+      else HIPCHK(launch_panel(S.ch_panel[p].d, S.ch_panel[p].count, c.dFail, st));
       HIPCHK(run_gemm(S.ch_trsm[p], st));
       HIPCHK(run_gemm(S.ch_syrk[p], st));
       HIPCHK(run_copy(S.ch_back[p], st));
@@ -600,6 +636,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(mark(FP_VS));
     HIPCHK(run_copy(S.c_ps, st));
     HIPCHK(run_gemm(S.g_v, st));
+    HIPCHK(run_gemm(S.g_v2, st));
     HIPCHK(run_gemm_p(c, S.g_schur, st));
     HIPCHK(done());
     if (S.dD32) {  // FP32 pair transforms: operands and finished F_ii to FP32
@@ -627,7 +664,8 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
   HIPCHK(mark(FP_ROOT));
   HIPCHK(run_copy(c.r_save, st));
   for (size_t p = 0; p < c.r_panel.size(); ++p) {
-    HIPCHK(launch_panel(c.r_panel[p].d, c.r_panel[p].count, c.dFail, st));
+    if (c.lu) HIPCHK(launch_lu_panel(c.r_panel[p].d, c.r_panel[p].count, c.dFail, st));
+    else HIPCHK(launch_panel(c.r_panel[p].d, c.r_panel[p].count, c.dFail, st));
     HIPCHK(run_gemm(c.r_trsm[p], st));
     HIPCHK(run_gemm(c.r_syrk[p], st));
     HIPCHK(run_copy(c.r_back[p], st));

@@ -89,7 +89,7 @@ def default_allocator() -> TorchAllocator:
 
 class Kernel(ctypes.Structure):
     _fields_ = [("id", ctypes.c_int32), ("delta", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("ell", ctypes.c_double), ("nugget", ctypes.c_double)]
+                ("ell", ctypes.c_double), ("nugget", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class Params(ctypes.Structure):
@@ -101,7 +101,8 @@ class Params(ctypes.Structure):
                 ("rank_model", ctypes.c_void_p), ("rank_margin", ctypes.c_double),
                 ("timing", ctypes.c_int32), ("no_autotune", ctypes.c_int32),
                 ("solve_prec", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32),
-                ("allocator", ctypes.c_void_p), ("matvec_prec", ctypes.c_int32)]
+                ("allocator", ctypes.c_void_p), ("matvec_prec", ctypes.c_int32),
+                ("factor_lu", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -125,7 +126,8 @@ class Stats(ctypes.Structure):
                 ("flops_factor_phase", ctypes.c_double * 9), ("flops_schur", ctypes.c_double),
                 ("t_build_id", ctypes.c_double), ("flops_prefactor", ctypes.c_double),
                 ("ir_fp64_matvecs", ctypes.c_int32), ("t_gather_mv32", ctypes.c_double),
-                ("bytes_gather_mv32", ctypes.c_double), ("gather_launches_mv32", ctypes.c_int32)]
+                ("bytes_gather_mv32", ctypes.c_double), ("gather_launches_mv32", ctypes.c_int32),
+                ("lu_variant", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -197,7 +199,8 @@ def _stream(stream=None):
 
 
 def make_kernel(k) -> Kernel:
-    return Kernel(int(k.id), float(k.delta), float(k.kappa), float(k.ell), float(k.nugget))
+    return Kernel(int(k.id), float(k.delta), float(k.kappa), float(k.ell), float(k.nugget),
+                  float(getattr(k, "beta", 0.0)))
 
 
 def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_near: int = -1,
@@ -205,7 +208,7 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
                 ir_tol: float = 1e-10, use_pcg: bool = False, use_graph: bool = False,
                 timing: bool = False, rank_model=None, rank_margin: float = 0.25,
                 autotune: bool = True, solve_prec: int = PREC_FP64, gs_sweeps: int = 0,
-                allocator=None, matvec_prec: int = PREC_FP64) -> Params:
+                allocator=None, matvec_prec: int = PREC_FP64, factor_lu: bool = False) -> Params:
     """rank_model: numpy float32 array of the 4801 predictor weights (kept alive
     by the caller for the duration of the build call).  allocator: a
     TorchAllocator (or None: the library's hipMalloc); it must outlive the
@@ -218,7 +221,7 @@ def make_params(dim: int, leaf: int, eta: float, eps: float, s_far: int = -1, s_
     aptr = None if allocator is None else ctypes.addressof(allocator.struct)
     return Params(dim, leaf, eta, eps, max_rank, s_far, s_near, gemm_prec, ir_max_iter, ir_tol,
                   int(use_pcg), int(use_graph), ptr, rank_margin, int(timing), int(not autotune),
-                  int(solve_prec), int(gs_sweeps), aptr, int(matvec_prec))
+                  int(solve_prec), int(gs_sweeps), aptr, int(matvec_prec), int(factor_lu))
 
 
 def _as_cols(t, n):

@@ -1,0 +1,201 @@
+"""The LU variant on the GPU (non-symmetric kernels) against the oracle's LU
+variant, through the C ABI.
+
+Same-H^2 cases give the library the oracle's skeleton selection
+(h2_build_fixed) for the drift kernel, so both sides factor the same
+non-symmetric H^2 matrix with the same pivot-free LU steps: x agrees to
+max(1e-10, 100 kappa(A~) u) relative, in norm and element by element, the
+residual against A~ matches the oracle's, and the matvec agrees to 1e-12
+(norm, and component by component against the rounding bound of a product).
+The forced LU variant on a symmetric kernel must reproduce the Cholesky
+path's x.  The free build picks its own skeletons from the two-sided sample;
+its structure must equal the oracle's and its ranks agree almost everywhere.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import construct, h2matrix, kernels, ulv_lu
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(p, skeletons=None, gs_sweeps=0):
+    return construct.construct(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), p.s_far,
+                               p.s_near, skeletons=skeletons, gs_sweeps=gs_sweeps)
+
+
+def _skeletons(h2):
+    sk, ranks, pos = {}, [], []
+    for l in range(h2.tree.L, 0, -1):
+        for i, bb in enumerate(h2.basis[l]):
+            sk[(l, i)] = bb.piv[:bb.k]
+            ranks.append(bb.k)
+            pos.extend(bb.piv[:bb.k].tolist())
+    return sk, np.array(ranks, dtype=np.int32), np.array(pos, dtype=np.int32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+CASES = {
+    # name: (problem factory, nrhs)
+    "drift2048_sampled": (lambda: W.yukawa_drift_cube(n=2048, leaf=64, eps=1e-6, beta=0.5, s=128), 2),
+    "drift_ragged": (lambda: W.yukawa_drift_cube(n=3001, leaf=100, eps=1e-7, beta=0.8, s=150), 1),
+    "drift_unsampled": (lambda: W.yukawa_drift_cube(n=1024, leaf=64, eps=1e-6, beta=0.5, s=-1), 3),
+    "drift_hss": (lambda: W.yukawa_drift_cube(n=1024, leaf=64, eps=1e-6, beta=0.5, eta=0.0, s=-1), 1),
+    # wide boxes: the redundant blocks span several 64-wide LU panels
+    "drift_leaf256": (lambda: W.yukawa_drift_cube(n=4096, leaf=256, eps=1e-7, beta=0.5, s=256), 1),
+    "drift_root_only": (lambda: W.yukawa_drift_cube(n=100, leaf=128, eps=1e-8, beta=0.5), 2),
+}
+
+
+def _same_h2(lib, p, nrhs, name, gs_sweeps=0):
+    import torch
+    print(f"[case {name}] n={p.n} leaf={p.leaf} eps={p.eps} eta={p.eta} "
+          f"beta={p.kernel.beta} gs={gs_sweeps}", flush=True)
+    h2o = _oracle(p, gs_sweeps=gs_sweeps)
+    sk, ranks, pos = _skeletons(h2o)
+    h2f = _oracle(p, skeletons=sk, gs_sweeps=gs_sweeps)
+    fac = ulv_lu.factor(h2f)
+    b = W.rhs(p.n, nrhs, 1)
+    xo = ulv_lu.solve(fac, b)
+    H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                        s_far=p.s_far, s_near=p.s_near, gs_sweeps=gs_sweeps)
+    assert H.stats()["lu_variant"] == 1
+    perm, gr, gm, gsk = H.structure()
+    assert np.array_equal(perm, h2o.tree.perm)
+    assert np.array_equal(gr, ranks)
+    H.factor()
+    bt = torch.from_numpy(b).cuda()
+    x = H.solve(bt).cpu().numpy()
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    u = np.finfo(float).eps / 2
+    tol = max(1e-10, 100 * kappa * 2 * u)
+    ew = float(np.abs(x - xo).max() / np.abs(xo).max())
+    print(f"[{name}] x: norm {_rel(x, xo):.2e} element-wise {ew:.2e} (tol {tol:.1e}, "
+          f"kappa {kappa:.1f})", flush=True)
+    assert _rel(x, xo) < tol, (_rel(x, xo), kappa)
+    assert ew < tol, (ew, kappa)
+    res_g = np.linalg.norm(b - At @ x) / np.linalg.norm(b)
+    res_o = np.linalg.norm(b - At @ xo) / np.linalg.norm(b)
+    assert res_g <= max(10 * res_o, 1e-13), (res_g, res_o)
+    # the non-symmetric H^2 operator
+    y = H.matvec(bt).cpu().numpy()
+    yo = h2matrix.matvec(h2f, b)
+    assert _rel(y, yo) < 1e-12, _rel(y, yo)
+    cw = float(np.max(np.abs(y - yo) / (np.abs(At) @ np.abs(b))))
+    assert cw < 1e-12, cw
+    H.close()
+    return h2f
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_same_h2_lu_matches_oracle(lib, name):
+    factory, nrhs = CASES[name]
+    _same_h2(lib, factory(), nrhs, name)
+
+
+def test_same_h2_lu_gauss_seidel(lib):
+    """The pre-factorization by Gauss-Seidel sweeps on both sides of the
+    fill-in (A_cc and A_cc^T), the same sweeps on both sides."""
+    p = W.yukawa_drift_cube(n=2048, leaf=64, eps=1e-6, beta=0.5, s=128)
+    _same_h2(lib, p, 1, "drift_gs2", gs_sweeps=2)
+
+
+def test_lu_refinement_matches_oracle(lib):
+    """Stationary refinement to 1e-12 against A~ on both sides."""
+    import torch
+    p = W.yukawa_drift_cube(n=2048, leaf=64, eps=1e-5, beta=0.5, s=128)
+    h2o = _oracle(p)
+    sk, ranks, pos = _skeletons(h2o)
+    h2f = _oracle(p, skeletons=sk)
+    b = W.rhs(p.n, 2, 3)
+    xo, hist = ulv_lu.refine(ulv_lu.factor(h2f), b, 1e-12, 30)
+    assert hist[-1] <= 1e-12
+    H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                        s_far=p.s_far, s_near=p.s_near, ir_max_iter=30, ir_tol=1e-12)
+    H.factor()
+    x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    st = H.stats()
+    print(f"[refine] gpu {st['ir_iters']} iterations residual {st['ir_residual']:.2e}; "
+          f"oracle {len(hist) - 1} iterations", flush=True)
+    assert H.last_solve_status == lib.OK
+    assert st["ir_residual"] <= 1e-12
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    # both solutions are within kappa times their residual of A~^{-1} b
+    assert _rel(x, xo) < 2 * kappa * 1e-12 + 1e-13, _rel(x, xo)
+    H.close()
+
+
+def test_forced_lu_on_symmetric_kernel_matches_cholesky(lib):
+    """The LU variant reduces to the Cholesky variant on a symmetric matrix:
+    the same H^2 matrix factored both ways gives the same x."""
+    import torch
+    p = W.yukawa_cube(n=4096, leaf=64, eps=1e-7, s=128)
+    h2o = _oracle(p)
+    sk, ranks, pos = _skeletons(h2o)
+    b = W.rhs(p.n, 2, 1)
+    bt = torch.from_numpy(b).cuda()
+    xs = {}
+    for lu in (False, True):
+        H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                            s_far=p.s_far, s_near=p.s_near, factor_lu=lu)
+        assert H.stats()["lu_variant"] == int(lu)
+        H.factor()
+        xs[lu] = H.solve(bt).cpu().numpy()
+        H.close()
+    h2f = _oracle(p, skeletons=sk)
+    xo = ulv_lu.solve(ulv_lu.factor(h2f), b)
+    kappa = np.linalg.cond(h2matrix.assemble_dense(h2f))
+    tol = max(1e-10, 100 * kappa * np.finfo(float).eps)
+    print(f"[forced lu] vs cholesky {_rel(xs[True], xs[False]):.2e}, vs oracle "
+          f"{_rel(xs[True], xo):.2e} (tol {tol:.1e})", flush=True)
+    assert _rel(xs[True], xs[False]) < tol
+    assert _rel(xs[True], xo) < tol
+
+
+def test_free_lu_build_end_to_end(lib):
+    """The library's own two-sided construction (pivoted QR on the stacked
+    row and column samples) against the oracle's free construction."""
+    import torch
+    p = W.yukawa_drift_cube(n=4096, leaf=64, eps=1e-7, beta=0.5, s=128)
+    h2o = _oracle(p)
+    H = lib.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=p.s_far,
+                  s_near=p.s_near)
+    perm, ranks, ms, skel = H.structure()
+    assert np.array_equal(perm, h2o.tree.perm)
+    o_ranks = np.array([bb.k for l in range(h2o.tree.L, 0, -1) for bb in h2o.basis[l]])
+    print(f"[free lu] rank agreement {np.mean(ranks == o_ranks):.3f}, max diff "
+          f"{np.max(np.abs(ranks - o_ranks))}", flush=True)
+    assert np.mean(ranks == o_ranks) > 0.7
+    assert np.max(np.abs(ranks - o_ranks)) <= 3
+    H.factor()
+    b = W.rhs(p.n, 1, 2)
+    x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    A = kernels.dense(p.kernel, p.points)
+    res_g = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    xo = ulv_lu.solve(ulv_lu.factor(h2o), b)
+    res_o = np.linalg.norm(b - A @ xo) / np.linalg.norm(b)
+    print(f"[free lu] residual vs dense: gpu {res_g:.2e} oracle {res_o:.2e}", flush=True)
+    assert res_g <= max(10 * res_o, 1e-12), (res_g, res_o)
+    H.close()
+
+
+def test_lu_rejects_reduced_precision_and_pcg(lib):
+    p = W.yukawa_drift_cube(n=512, leaf=64, eps=1e-6, beta=0.5)
+    for kw in ({"gemm_prec": lib.PREC_FP32}, {"solve_prec": lib.PREC_BF16},
+               {"matvec_prec": lib.PREC_FP32}, {"use_pcg": True}):
+        with pytest.raises(lib.H2Error) as ei:
+            lib.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), **kw)
+        assert ei.value.status == lib.ERR_ARG
+    # beta = 0: the drift kernel is symmetric and takes the Cholesky path
+    q = dataclasses.replace(p, kernel=dataclasses.replace(p.kernel, beta=0.0))
+    H = lib.build(q.points, q.kernel, q.leaf, q.eta, q.eps, q.perm())
+    assert H.stats()["lu_variant"] == 0
+    H.close()
