@@ -138,6 +138,8 @@ def workload(n: int, kernel: str, eps: float, leaf: int, s: int, nrhs: int = 1):
         return W.laplace_cube(n=n, leaf=leaf, eps=eps, s=s)
     if kernel == "matern":
         return W.matern_cube(n=n, leaf=leaf, eps=eps, s=s)
+    if kernel == "yukawa_drift":
+        return W.yukawa_drift_cube(n=n, leaf=leaf, eps=eps, beta=0.5, nrhs=nrhs, s=s)
     raise SystemExit(f"unknown kernel {kernel}")
 
 
@@ -311,7 +313,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--kernel", default="yukawa",
                     help="yukawa (default) | laplace | laplace_sphere | matern | gaussian_batch "
-                         "(64 instances)")
+                         "(64 instances) | yukawa_drift (non-symmetric: the LU variant, "
+                         "stationary refinement, FP64)")
     ap.add_argument("--nrhs", type=int, default=1, help="right-hand sides per solve")
     ap.add_argument("--path", default="target", choices=["target", "plain", "custom"],
                     help="target: rank-predicted buffers, split-BF16 transform GEMMs on FP32 "
@@ -350,6 +353,11 @@ def main():
     a = ap.parse_args()
     if a.s_near <= 0:
         a.s_near = a.s
+    if a.kernel == "yukawa_drift":
+        # the LU variant runs in FP64 with stationary refinement only
+        if a.path == "target":
+            a.path = "plain"
+        a.stationary = True
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library implements the single-GPU H^2-ULV "
               "path; a distribution over several GPUs is not implemented.", file=sys.stderr)
@@ -473,6 +481,28 @@ def main():
             except h2.H2Error as e:
                 out[key] = {"workload": kern, "n": n, "nrhs": nrhs, "status": str(e)}
             torch.cuda.empty_cache()
+        # the LU variant: the non-symmetric drift kernel (beta 0.5) on the
+        # cube, N=262144, leaf 256, eps 1e-6, 512-point samples, FP64,
+        # stationary refinement to 1e-8 against the FP64 H^2 operator
+        c = copy.copy(a)
+        c.kernel, c.n, c.nrhs, c.leaf, c.eps, c.s, c.s_near, c.tol = "yukawa_drift", 1 << 18, 1, 256, 1e-6, 512, 512, 1e-8
+        c.steps, c.warmup, c.graph, c.stationary = min(a.steps, 3), 1, False, True
+        print("[bench] lu_drift", file=sys.stderr, flush=True)
+        try:
+            g = run_path(c, h2, h2.PREC_FP64, h2.PREC_FP64, None, "lu_drift")
+            out["lu_drift"] = {"workload": "yukawa_drift_cube", "beta": 0.5, "n": c.n, "nrhs": 1,
+                               "leaf": 256, "eps": 1e-6, "s": 512, "gemm_prec": "fp64",
+                               "solve_prec": "fp64", "refinement": "stationary", "ir_tol": 1e-8,
+                               "steps": c.steps, "value": g["value"], "unit": "TFLOP/s",
+                               "ms_per_step": g["ms_per_step"], "factor_s": g["factor_s"],
+                               "solve_s": g["solve_s"], "ir_iters": g["ir_iters"],
+                               "residual": g["residual"], "build_s": g["build_s"],
+                               "max_rank": g["stats"]["max_rank_seen"],
+                               "lu_variant": g["stats"]["lu_variant"],
+                               "factor_phase_s": g["factor_phase_s"]}
+        except h2.H2Error as e:
+            out["lu_drift"] = {"workload": "yukawa_drift_cube", "n": c.n, "status": str(e)}
+        torch.cuda.empty_cache()
         print("[bench] Matern configuration status", file=sys.stderr, flush=True)
         out["matern_status"] = []
         for n in (1 << 20, 1 << 18):  # the configuration, and a size that fits
