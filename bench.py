@@ -46,12 +46,12 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
-                           "bytes_per_launch": 1.9949e9 + 0.0375e9},
-    "gv16_kernel<bf16>": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
-                          "bytes_per_launch": 0.3866e9 + 0.0114e9},
-    "greduce_kernel": {"src": GATHER_SRC, "sha256": "70a757892a67eaba733919fb304eb4d6372eef28038e0dd053be3d7f483b119b",
-                       "bytes_per_launch": 0.0193e9 + 0.0013e9},
+    "gv16_kernel<bf16>": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
+                          "bytes_per_launch": 0.3858e9 + 0.0114e9},
+    "gchunk_kernel<f32> (PCG products)": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
+                                          "bytes_per_launch": 22.7027e9 + 0.6236e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
+                           "bytes_per_launch": 0.4719e9 + 0.0069e9},
 }
 
 

@@ -315,7 +315,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
   const int maxit = c.prm.ir_max_iter;
   if (time_gathers) {
     if (c.gev.empty()) {
-      c.gev.resize(3 * 2048, nullptr);
+      c.gev.resize(4 * 2048, nullptr);
       for (auto& e : c.gev) HIPCHK(hipEventCreate(&e));
     }
     c.gtime = true;
@@ -424,11 +424,11 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
     c.gtime = false;
     double tt[4] = {0.0, 0.0, 0.0, 0.0}, bb[4] = {0.0, 0.0, 0.0, 0.0};
     int nl[4] = {0, 0, 0, 0};
-    for (size_t q = 0; q + 3 <= c.gev_used; q += 3) {
+    for (size_t q = 0; q + 4 <= c.gev_used; q += 4) {
       float ms0 = 0.f, ms1 = 0.f;
       HIPCHK(hipEventElapsedTime(&ms0, c.gev[q], c.gev[q + 1]));
-      HIPCHK(hipEventElapsedTime(&ms1, c.gev[q + 1], c.gev[q + 2]));
-      const int g = q / 3, kind = c.gkind[g];
+      HIPCHK(hipEventElapsedTime(&ms1, c.gev[q + 2], c.gev[q + 3]));
+      const int g = q / 4, kind = c.gkind[g];
       tt[kind] += 1e-3 * ms0; bb[kind] += c.gbytes[2 * g]; ++nl[kind];
       tt[2] += 1e-3 * ms1; bb[2] += c.gbytes[2 * g + 1]; ++nl[2];
     }

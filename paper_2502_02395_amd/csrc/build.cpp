@@ -925,6 +925,10 @@ static void plan_bf16_copies(Step& S, int64_t& nF, int64_t& nP, std::vector<CvtB
 }
 
 h2_status plan_factor(Ctx& c, hipStream_t st) {
+  // FP32 transforms (a reduced gemm_prec); the FP32 copies of the leaf near
+  // blocks that PCG's products read under matvec_prec FP32 alone do not
+  // select them
+  const bool f32t = c.prm.gemm_prec != H2_PREC_FP64;
   // root buffers
   int max_n0 = 0;
   for (auto& in : c.ins) {
@@ -1108,7 +1112,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
     const int pp = pmap[h + 1].at((int64_t)pI * P.nbox + pJ);
     ld = P.m[pI];
     ptr = P.dD + P.poff[pp] + ro + (int64_t)co * ld;
-    if (P.dD32 && pI != pJ) ptr32 = P.dD32 + P.poff[pp] + ro + (int64_t)co * ld;
+    if (f32t && pI != pJ) ptr32 = P.dD32 + P.poff[pp] + ro + (int64_t)co * ld;
   };
 
   for (int h = 0; h < c.H; ++h) {
@@ -1147,7 +1151,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gq2.push_back(gd(P, k, 0, TA, m, 1, nullptr, 1, TB, k, k, m, k, 1.0, 0.0));
         gq3.push_back(gd(TA, m, 0, TB, k, 0, nullptr, 1, Q, m, m, m, k, -1.0, 0.0));
       }
-      if (S.dD32) {
+      if (f32t) {
         // FP32 transforms: D_ii and Q_i from their FP32 copies (Q32 in the
         // P32 buffer, free until P exists), the product in TA's memory as
         // FP32, F_ii = Q^T (.) in FP64 for the Cholesky of its RR part
@@ -1196,7 +1200,7 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
         gs.push_back(gd(Fii + (int64_t)k * m, m, 0, Fii + (int64_t)k * m, m, 1, TB, m, Fii, m, k, k, r,
                         -1.0, 1.0));
     }
-    const bool f32pair = S.dD32 != nullptr;
+    const bool f32pair = f32t;
     // FP32 arrays travel in the double-typed descriptors (the FP32 kernels
     // read them back as float)
     auto asd = [](float* p) { return reinterpret_cast<double*>(p); };

@@ -200,8 +200,9 @@ struct Ctx {
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
   hipStream_t graph_stream = nullptr;      // capture and replay (never the null stream)
-  // gather timing (params.timing): event triples around the two halves of
-  // each gather, and the bytes each timed launch moves
+  // gather timing (params.timing): per gather four events, the start and end
+  // of its chunk launch and of its reduction launch (marked by the launches'
+  // own dispatches), and the bytes each timed launch moves
   std::vector<hipEvent_t> fev;             // factor phases: (before, after) pairs
   std::vector<int> fev_phase;
   size_t fev_used = 0;

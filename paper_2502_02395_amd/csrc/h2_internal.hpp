@@ -321,10 +321,13 @@ bool plan_gather(const std::vector<GatherBox>& B, const std::vector<GatherNbr>& 
 // esz: bytes per block element (8, 4 or 2).  v16: the plan's v16 (BF16
 // chunks of 128 rows read with 16-byte loads, for one right-hand side;
 // more fall back to the two-rows-per-lane kernel, which reads the packed
-// copies too).
+// copies too).  e0, e1: if set, events that the kernel's own dispatch marks
+// at its start and end (its duration without a separate marker on the
+// stream); the call must launch (nch > 0).
 constexpr int GV16_NR = 1;
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
-                          hipStream_t st, bool wide = false, bool v16 = false);
+                          hipStream_t st, bool wide = false, bool v16 = false,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // FP32 copy of n doubles.
 hipError_t launch_cvt_f32(const double* src, float* dst, int64_t n, hipStream_t st);
 // BF16 copy (round to nearest even) of n doubles (esz_src 8) or floats (4).
@@ -337,8 +340,10 @@ hipError_t launch_cvt_bf16(const void* src, int esz_src, unsigned short* dst, in
 hipError_t launch_cvt_bf16_blks(const void* src, int esz_src, const CvtBlk* blks,
                                 const int* first, int count, int64_t groups,
                                 unsigned short* dst, hipStream_t st);
+// e0, e1 as for launch_gchunks (nred > 0 and max_rows > 0).
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
-                          const double* P, int nrhs, hipStream_t st);
+                          const double* P, int nrhs, hipStream_t st, hipEvent_t e0 = nullptr,
+                          hipEvent_t e1 = nullptr);
 
 // Blocked Cholesky panel (nb <= 64; the root and the redundant blocks):
 // factor the nb x nb diagonal block in place (L below, zeros above) and write

@@ -1,6 +1,8 @@
 // Neighbour gathers of the substitution (Eq. 31 and its transpose) and of
 // the H^2 matrix-vector product: block-chunk products into partial slots and
 // the per-box reductions (see GatherPlan).
+#include <hip/hip_ext.h>
+
 #include "h2_internal.hpp"
 
 namespace h2 {
@@ -587,51 +589,52 @@ __global__ __launch_bounds__(256) void greduce_kernel(const GRed* __restrict__ r
 
 template <typename T>
 static void launch_gchunks_t(const GChunk* ch, int nch, double* P, int nrhs, hipStream_t st,
-                             bool wide) {
+                             bool wide, hipEvent_t e0, hipEvent_t e1) {
   const dim3 grid((nch + 3) / 4), blk(256);
   constexpr int RN = rows_per_lane<T>();
   constexpr int RW = sizeof(T) < 8 ? GATHER_WIDE_RPL32 : GATHER_WIDE_RPL64;
   static_assert(GATHER_WIDE_NR == 2, "wide instantiations below");
   if (wide) {
-    if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T, RW, 8>), grid, blk, 0, st, ch, nch, P, nrhs);
-    else hipLaunchKernelGGL((gchunk_kernel<2, T, RW, 8>), grid, blk, 0, st, ch, nch, P, nrhs);
+    if (nrhs == 1) hipExtLaunchKernelGGL((gchunk_kernel<1, T, RW, 8>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
+    else hipExtLaunchKernelGGL((gchunk_kernel<2, T, RW, 8>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
     return;
   }
-  if (nrhs == 1) hipLaunchKernelGGL((gchunk_kernel<1, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 2) hipLaunchKernelGGL((gchunk_kernel<2, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 4) hipLaunchKernelGGL((gchunk_kernel<4, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else if (nrhs <= 8) hipLaunchKernelGGL((gchunk_kernel<8, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
-  else hipLaunchKernelGGL((gchunk_kernel<16, T, RN, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+  if (nrhs == 1) hipExtLaunchKernelGGL((gchunk_kernel<1, T, RN, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
+  else if (nrhs <= 2) hipExtLaunchKernelGGL((gchunk_kernel<2, T, RN, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
+  else if (nrhs <= 4) hipExtLaunchKernelGGL((gchunk_kernel<4, T, RN, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
+  else if (nrhs <= 8) hipExtLaunchKernelGGL((gchunk_kernel<8, T, RN, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
+  else hipExtLaunchKernelGGL((gchunk_kernel<16, T, RN, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
 }
 
 hipError_t launch_gchunks(const GChunk* ch, int nch, double* P, int nrhs, int esz,
-                          hipStream_t st, bool wide, bool v16) {
+                          hipStream_t st, bool wide, bool v16, hipEvent_t e0, hipEvent_t e1) {
   if (nch <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
   if (wide && nrhs > GATHER_WIDE_NR) return hipErrorInvalidValue;
   if (v16 && esz == 2 && !wide && nrhs <= GV16_NR) {
     static_assert(GV16_NR == 1, "instantiation below");
     const dim3 grid((nch + 3) / 4), blk(256);
-    hipLaunchKernelGGL((gv16_kernel<1, 16>), grid, blk, 0, st, ch, nch, P, nrhs);
+    hipExtLaunchKernelGGL((gv16_kernel<1, 16>), grid, blk, 0, st, e0, e1, 0, ch, nch, P, nrhs);
     return hipGetLastError();
   }
-  if (esz == 8) launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide);
-  else if (esz == 4) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide);
-  else if (esz == 2) launch_gchunks_t<unsigned short>(ch, nch, P, nrhs, st, wide);
+  if (esz == 8) launch_gchunks_t<double>(ch, nch, P, nrhs, st, wide, e0, e1);
+  else if (esz == 4) launch_gchunks_t<float>(ch, nch, P, nrhs, st, wide, e0, e1);
+  else if (esz == 2) launch_gchunks_t<unsigned short>(ch, nch, P, nrhs, st, wide, e0, e1);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_greduce(const GRed* rd, int nred, int max_rows, const int64_t* offs,
-                          const double* P, int nrhs, hipStream_t st) {
+                          const double* P, int nrhs, hipStream_t st, hipEvent_t e0,
+                          hipEvent_t e1) {
   if (nred <= 0 || max_rows <= 0) return hipSuccess;
   if (nrhs > GNR || nrhs < 1) return hipErrorInvalidValue;
   const dim3 grid(nred, (max_rows + 255) / 256), blk(256);
-  if (nrhs == 1) hipLaunchKernelGGL(greduce_kernel<1>, grid, blk, 0, st, rd, offs, P, nrhs);
-  else if (nrhs <= 2) hipLaunchKernelGGL(greduce_kernel<2>, grid, blk, 0, st, rd, offs, P, nrhs);
-  else if (nrhs <= 4) hipLaunchKernelGGL(greduce_kernel<4>, grid, blk, 0, st, rd, offs, P, nrhs);
-  else if (nrhs <= 8) hipLaunchKernelGGL(greduce_kernel<8>, grid, blk, 0, st, rd, offs, P, nrhs);
-  else hipLaunchKernelGGL(greduce_kernel<16>, grid, blk, 0, st, rd, offs, P, nrhs);
+  if (nrhs == 1) hipExtLaunchKernelGGL(greduce_kernel<1>, grid, blk, 0, st, e0, e1, 0, rd, offs, P, nrhs);
+  else if (nrhs <= 2) hipExtLaunchKernelGGL(greduce_kernel<2>, grid, blk, 0, st, e0, e1, 0, rd, offs, P, nrhs);
+  else if (nrhs <= 4) hipExtLaunchKernelGGL(greduce_kernel<4>, grid, blk, 0, st, e0, e1, 0, rd, offs, P, nrhs);
+  else if (nrhs <= 8) hipExtLaunchKernelGGL(greduce_kernel<8>, grid, blk, 0, st, e0, e1, 0, rd, offs, P, nrhs);
+  else hipExtLaunchKernelGGL(greduce_kernel<16>, grid, blk, 0, st, e0, e1, 0, rd, offs, P, nrhs);
   return hipGetLastError();
 }
 

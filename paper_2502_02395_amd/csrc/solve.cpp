@@ -100,25 +100,33 @@ h2_status ensure_partials(Ctx& c, int nrhs) {
   return H2_OK;
 }
 
-// Chunks then reduction; with timing on, HIP events around each (the event
-// pool is sized once; gathers beyond it run untimed).
+// Chunks then reduction; with timing on, each launch marks a start and an
+// end event through its own dispatch (no marker between the launches; the
+// event pool is sized once, gathers beyond it run untimed).
 static hipError_t gather(Ctx& c, const GList& L, int nrhs, hipStream_t st) {
   const bool wide = L.has_w && nrhs <= GATHER_WIDE_NR;
   const GSet& S = L.pick(nrhs);
   if (S.rd.count == 0) return hipSuccess;
-  const bool t = c.gtime && c.gev_used + 3 <= c.gev.size();
+  const bool t = c.gtime && c.gev_used + 4 <= c.gev.size();
+  hipEvent_t* ev = t ? &c.gev[c.gev_used] : nullptr;
   hipError_t e;
-  if (t && (e = hipEventRecord(c.gev[c.gev_used], st)) != hipSuccess) return e;
+  if (t && S.ch.count == 0) {  // nothing to launch: an empty interval
+    if ((e = hipEventRecord(ev[0], st)) != hipSuccess || (e = hipEventRecord(ev[1], st)) != hipSuccess)
+      return e;
+  }
   if ((e = launch_gchunks(S.ch.d, S.ch.count, c.part_cur, nrhs, L.esz, st, wide,
-                         L.v16 && !wide)) != hipSuccess)
-    return e;
-  if (t && (e = hipEventRecord(c.gev[c.gev_used + 1], st)) != hipSuccess) return e;
-  if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st)) !=
+                          L.v16 && !wide, t ? ev[0] : nullptr, t ? ev[1] : nullptr)) !=
       hipSuccess)
     return e;
+  if (t && S.max_rows <= 0) {
+    if ((e = hipEventRecord(ev[2], st)) != hipSuccess || (e = hipEventRecord(ev[3], st)) != hipSuccess)
+      return e;
+  }
+  if ((e = launch_greduce(S.rd.d, S.rd.count, S.max_rows, S.offs.d, c.part_cur, nrhs, st,
+                          t ? ev[2] : nullptr, t ? ev[3] : nullptr)) != hipSuccess)
+    return e;
   if (t) {
-    if ((e = hipEventRecord(c.gev[c.gev_used + 2], st)) != hipSuccess) return e;
-    c.gev_used += 3;
+    c.gev_used += 4;
     c.gbytes.push_back(S.bytes_ch_mat + S.bytes_ch_vec * nrhs);
     c.gbytes.push_back(S.bytes_rd * nrhs);
     c.gkind.push_back(L.kind >= 0 ? L.kind : L.esz < 8 ? 1 : 0);
@@ -570,6 +578,7 @@ enum FactorPhase {
 
 h2_status do_factor(Ctx& c, hipStream_t st) {
   HIPCHK(launch_set_int(c.dFail, INT_MAX, st));
+  const bool f32t = c.prm.gemm_prec != H2_PREC_FP64;  // FP32 transforms
   const bool timing = c.prm.timing != 0 && !c.prm.use_graph;
   if (timing && c.fev.empty()) {
     c.fev.resize(2 * FP_N * (c.H + 2), nullptr);
@@ -608,7 +617,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(S.g_qr3, st));
     HIPCHK(launch_qr_diag(S.qr.d, S.qr.count, st));
     HIPCHK(done());
-    if (S.dD32) {  // FP32 transforms: Q_i and (above the leaves) D_ii to FP32
+    if (f32t) {  // FP32 transforms: Q_i and (above the leaves) D_ii to FP32
       HIPCHK(mark(FP_F32));
       HIPCHK(launch_cvt_f32(S.dQ, S.dP32, S.qoff[S.nbox], st));
       HIPCHK(launch_cvt_list(S.cv_dii.d, S.cv_dii.count, st));
@@ -639,7 +648,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     HIPCHK(run_gemm(S.g_v2, st));
     HIPCHK(run_gemm_p(c, S.g_schur, st));
     HIPCHK(done());
-    if (S.dD32) {  // FP32 pair transforms: operands and finished F_ii to FP32
+    if (f32t) {  // FP32 pair transforms: operands and finished F_ii to FP32
       HIPCHK(mark(FP_F32));
       HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
       HIPCHK(launch_cvt_f32(S.dR, S.dR32, S.rkoff[S.nbox], st));
