@@ -25,8 +25,19 @@ m columns of G(S_C, B_i) (2 c^2 m), or, with Gauss-Seidel sweeps in place of
 the factorization, 2 c^2 m per sweep (every off-diagonal entry of A_cc once
 per column; Section 3.5's iterative variant).
 
+The LU variant (oracle/ulv_lu.py; count_lu): per box the same QR and
+diagonal transform, 2 r^3/3 for the pivot-free LU of the redundant block,
+2 k r^2 for L(s)_ii = SR U^{-1} and U(s)_ii = L^{-1} RS, 2 k^2 r for
+SS -= L(s)_ii U(s)_ii and 2 m r^2 for the two bases; per ordered near pair
+i != j the transform 2 m_i m_j (m_i + m_j), k_i r_j^2 (L(s)_ij), r_i^2 k_j
+(U(s)_ij) and r_i r_j^2 (i > j, L(r)_ij) or r_i^2 r_j (i < j, U(r)_ij); per
+ordered far pair k_i k_j (k_i + k_j); the root 2 n_0^3 / 3.  Its solve, per
+right-hand side: 4 m^2 + 4 r^2 per box, 4 k_i r_i per diagonal block, and
+2 k_i r_j + 2 r_i k_j + 2 r_i r_j per ordered near pair i != j.
+
 Pinned by tests/test_oracle_flops.py against the operations that running
-Householder QR, Q accumulation, Cholesky and triangular-solve loops perform.
+Householder QR, Q accumulation, Cholesky, pivot-free LU and triangular-solve
+loops perform.
 """
 from __future__ import annotations
 
@@ -67,6 +78,39 @@ def count(ms: list, ks: list, near: list, far: list, n0: int, nrhs: int = 1):
     ff += n0 ** 3 / 3.0
     fs += 2.0 * n0 * n0
     return ff, fs * nrhs
+
+
+def count_lu(ms: list, ks: list, near: list, far: list, n0: int, nrhs: int = 1):
+    """The LU variant's counts on the same inputs as count()."""
+    ff = 0.0
+    fs = 0.0
+    for l in range(1, len(ms)):
+        m, k = ms[l], ks[l]
+        for i in range(len(m)):
+            r = m[i] - k[i]
+            ff += geqrf(m[i], k[i]) + orgqr_full(m[i], k[i]) + 4.0 * m[i] ** 3
+            ff += 2.0 * r ** 3 / 3.0 + 2.0 * k[i] * r * r + 2.0 * k[i] * k[i] * r + 2.0 * m[i] * r * r
+            fs += 4.0 * m[i] ** 2 + 4.0 * r * r
+        for (i, j) in near[l]:
+            ri, rj = m[i] - k[i], m[j] - k[j]
+            if i == j:
+                fs += 4.0 * k[i] * ri
+                continue
+            ff += 2.0 * m[i] * m[j] * (m[i] + m[j]) + k[i] * rj * rj + ri * ri * k[j]
+            ff += ri * rj * rj if i > j else ri * ri * rj
+            fs += 2.0 * k[i] * rj + 2.0 * ri * k[j] + 2.0 * ri * rj
+        for (i, j) in far[l]:
+            ff += k[i] * k[j] * (k[i] + k[j])
+    ff += 2.0 * n0 ** 3 / 3.0
+    fs += 2.0 * n0 * n0
+    return ff, fs * nrhs
+
+
+def count_h2_lu(h2, nrhs: int = 1):
+    t = h2.tree
+    ms = [None] + [[bb.m for bb in h2.basis[l]] for l in range(1, t.L + 1)]
+    ks = [None] + [[bb.k for bb in h2.basis[l]] for l in range(1, t.L + 1)]
+    return count_lu(ms, ks, t.near, t.far, len(h2.root_B), nrhs)
 
 
 def count_h2(h2, nrhs: int = 1):

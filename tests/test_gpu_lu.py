@@ -5,8 +5,9 @@ Same-H^2 cases give the library the oracle's skeleton selection
 (h2_build_fixed) for the drift kernel, so both sides factor the same
 non-symmetric H^2 matrix with the same pivot-free LU steps: x agrees to
 max(1e-10, 100 kappa(A~) u) relative, in norm and element by element, the
-residual against A~ matches the oracle's, and the matvec agrees to 1e-12
-(norm, and component by component against the rounding bound of a product).
+residual against A~ matches the oracle's, the matvec agrees to 1e-12
+(norm, and component by component against the rounding bound of a product),
+and the library's canonical flop counts equal the oracle's LU counts.
 The forced LU variant on a symmetric kernel must reproduce the Cholesky
 path's x.  The free build picks its own skeletons from the two-sided sample;
 its structure must equal the oracle's and its ranks agree almost everywhere.
@@ -17,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import construct, h2matrix, kernels, ulv_lu
+from oracle import construct, flops, h2matrix, kernels, ulv_lu
 
 pytestmark = pytest.mark.gpu
 
@@ -90,6 +91,11 @@ def _same_h2(lib, p, nrhs, name, gs_sweeps=0):
     assert _rel(y, yo) < 1e-12, _rel(y, yo)
     cw = float(np.max(np.abs(y - yo) / (np.abs(At) @ np.abs(b))))
     assert cw < 1e-12, cw
+    # the library's canonical LU flop counts against the oracle's
+    st = H.stats()
+    ff_o, fs_o = flops.count_h2_lu(h2f)
+    assert abs(st["flops_factor"] - ff_o) <= 1e-12 * ff_o, (st["flops_factor"], ff_o)
+    assert abs(st["flops_solve"] - fs_o) <= 1e-12 * fs_o, (st["flops_solve"], fs_o)
     H.close()
     return h2f
 

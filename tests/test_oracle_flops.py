@@ -203,3 +203,90 @@ def test_count_prefactor_follows_the_near_samples():
     assert any(bb.sc == p.s_near for bb in h.basis[t.L])      # the sample bounds some boxes
     assert abs(flops.count_prefactor(h) - tot) <= 1e-9 * tot
     assert flops.count_prefactor(h, 2) > 0
+
+
+def _lu_nopivot(A):
+    """Doolittle elimination without row exchanges; returns (L, U, flops)."""
+    U = A.copy()
+    r = U.shape[0]
+    L = np.eye(r)
+    f = 0
+    for j in range(r):
+        if j + 1 < r:
+            L[j + 1:, j] = U[j + 1:, j] / U[j, j]; f += r - j - 1
+            U[j + 1:, j:] -= np.outer(L[j + 1:, j], U[j, j:]); f += 2 * (r - j - 1) * (r - j)
+            U[j + 1:, j] = 0.0
+    return L, np.triu(U), f
+
+
+def _left_unit_lower_solve(L, B):
+    """Y = L^{-1} B for unit lower L, by forward substitution."""
+    r, k = B.shape
+    Y = np.zeros_like(B)
+    f = 0
+    for i in range(r):
+        Y[i] = B[i] - L[i, :i] @ Y[:i]
+        f += 2 * i * k
+    return Y, f
+
+
+def _right_upper_solve(B, U):
+    """X = B U^{-1}: column j of X from the columns before it."""
+    k, r = B.shape
+    X = np.zeros_like(B)
+    f = 0
+    for j in range(r):
+        X[:, j] = (B[:, j] - X[:, :j] @ U[:j, j]) / U[j, j]
+        f += k * (2 * j + 1)
+    return X, f
+
+
+@pytest.mark.parametrize("k,r", [(10, 40), (32, 64), (80, 30)])
+def test_lu_and_its_triangular_solve_counts(k, r):
+    """The LU variant's per-box steps: a pivot-free LU of the redundant block
+    (checked against the oracle's and against L U = A), U(s) = L^{-1} RS and
+    L(s) = SR U^{-1}, counted by the loops that perform them."""
+    from oracle import ulv_lu
+    rng = np.random.default_rng(k * 100 + r + 7)
+    A = rng.standard_normal((r, r)) + r * np.eye(r)
+    L, U, fl = _lu_nopivot(A)
+    Lo, Uo = ulv_lu.lu_nopivot(A)
+    assert np.allclose(L, Lo, atol=1e-13) and np.allclose(U, Uo, atol=1e-12)
+    assert np.allclose(L @ U, A, atol=1e-12 * r)
+    RS = rng.standard_normal((r, k))
+    SR = rng.standard_normal((k, r))
+    Y, f1 = _left_unit_lower_solve(L, RS)
+    X, f2 = _right_upper_solve(SR, U)
+    assert np.allclose(L @ Y, RS, atol=1e-11) and np.allclose(X @ U, SR, atol=1e-11)
+    assert abs(fl - 2.0 * r ** 3 / 3.0) <= 2 * r * r
+    assert abs(f1 - k * r * r) <= k * r and abs(f2 - k * r * r) <= k * r
+
+
+def test_count_lu_composes_the_step_counts():
+    """count_lu on one level with two boxes (m, k) = (60, 20), (50, 30), both
+    orders of their near pair and root n0 = 25, against the per-step counts
+    summed by hand (each ordered pair transformed on its own; L(s), U(s)
+    and one of L(r) / U(r) per ordered pair; LU and both bases per box)."""
+    ms, ks = [None, [60, 50]], [None, [20, 30]]
+    near = [None, [(0, 0), (0, 1), (1, 0), (1, 1)]]
+    far = [None, []]
+    ff, fs = flops.count_lu(ms, ks, near, far, n0=25)
+    exp = 0.0
+    for m, k in zip(ms[1], ks[1]):
+        r = m - k
+        exp += flops.geqrf(m, k) + flops.orgqr_full(m, k) + 4.0 * m ** 3
+        exp += 2 * r ** 3 / 3 + 2 * k * r * r + 2 * k * k * r + 2 * m * r * r
+    (m0, k0), (m1, k1) = (60, 20), (50, 30)
+    r0, r1 = m0 - k0, m1 - k1
+    exp += 2 * (2.0 * m1 * m0 * (m1 + m0))            # P_1^T A_10 P'_0 and P_0^T A_01 P'_1
+    exp += k1 * r0 * r0 + r1 * r1 * k0 + r1 * r0 * r0  # (1, 0): L(s), U(s), L(r)
+    exp += k0 * r1 * r1 + r0 * r0 * k1 + r0 * r0 * r1  # (0, 1): L(s), U(s), U(r)
+    exp += 2 * 25 ** 3 / 3.0
+    assert abs(ff - exp) <= 1e-9 * exp
+    es = sum(4.0 * m * m + 4.0 * (m - k) ** 2 + 4.0 * k * (m - k) for m, k in zip(ms[1], ks[1]))
+    es += 2 * (2.0 * k1 * r0 + 2.0 * r1 * k0 + 2.0 * r1 * r0) + 2.0 * 25 ** 2
+    assert abs(fs - es) <= 1e-9 * es
+    # on a symmetric structure the LU count exceeds the Cholesky count by the
+    # extra triangular work and the second transform of every pair
+    fc, _ = flops.count(ms, ks, near, far, n0=25)
+    assert ff > fc
