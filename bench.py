@@ -46,12 +46,14 @@ HBM_PEAK_GBS = 8000.0
 GATHER_SRC = ['paper_2502_02395_amd/csrc/k_gather.hip', 'paper_2502_02395_amd/csrc/gather_plan.cpp',
               'paper_2502_02395_amd/csrc/h2_internal.hpp']
 MEASURED_TRAFFIC = {
-    "gv16_kernel<bf16>": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
-                          "bytes_per_launch": 0.3858e9 + 0.0114e9},
-    "gchunk_kernel<f32> (PCG products)": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
-                                          "bytes_per_launch": 22.7027e9 + 0.6236e9},
-    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "33e356d3981f07cc276af054dc09804ec8ac2883b2eb3a1776b8e232748071cc",
-                           "bytes_per_launch": 0.4719e9 + 0.0069e9},
+    "gv16_kernel<bf16>": {"src": GATHER_SRC, "sha256": "cfd79b81529fae76baeb9a8fb9eb92a39b5c7c791f0d54b12b3b4f182eb2e13e",
+                          "bytes_per_launch": 0.3867e9 + 0.0114e9},
+    "gchunk_kernel<f32> (PCG products)": {"src": GATHER_SRC, "sha256": "cfd79b81529fae76baeb9a8fb9eb92a39b5c7c791f0d54b12b3b4f182eb2e13e",
+                                          "bytes_per_launch": 22.6678e9 + 0.6242e9},
+    "gchunk_kernel<f64>": {"src": GATHER_SRC, "sha256": "cfd79b81529fae76baeb9a8fb9eb92a39b5c7c791f0d54b12b3b4f182eb2e13e",
+                           "bytes_per_launch": 0.4720e9 + 0.0069e9},
+    "greduce_kernel": {"src": GATHER_SRC, "sha256": "cfd79b81529fae76baeb9a8fb9eb92a39b5c7c791f0d54b12b3b4f182eb2e13e",
+                       "bytes_per_launch": 0.0171e9 + 0.0013e9},
 }
 
 
