@@ -125,8 +125,10 @@ typedef struct {
                              symmetric preconditioner of PCG                  */
   int32_t gs_sweeps;      /* pre-factorization of h2_build (Section 3.5): 0 =
                              exact Cholesky solve with the near-sample block
-                             A_cc; n > 0 = n Gauss-Seidel sweeps (from zero)
-                             approximating A_Close = G(B_i, S_C) A_cc^{-1}.
+                             A_cc (LU variant: pivot-free LU); n > 0 = n
+                             Gauss-Seidel sweeps (from zero) approximating
+                             A_Close = G(B_i, S_C) A_cc^{-1} (LU variant: and
+                             the column side with A_cc^T).
                              Range 0..64 (else H2_ERR_ARG); a non-positive
                              diagonal entry of A_cc returns H2_ERR_NOT_SPD
                              with the box in h2_stats                          */
@@ -172,7 +174,8 @@ typedef struct {
   int64_t far_pairs;      /* unordered far pairs, all levels                     */
   int64_t leaf_near_blocks; /* ordered dense near blocks at the leaves (N_NZB)   */
   int32_t max_rank_seen, max_m_seen, root_n;
-  double flops_factor;    /* canonical algorithmic flops of one factorization    */
+  double flops_factor;    /* canonical algorithmic flops of one factorization
+                             (LU variant: the LU counts, every ordered pair)    */
   double flops_solve;     /* canonical flops of one solve, per right-hand side   */
   double bytes_factors;   /* bytes of the stored factors                         */
   double t_build, t_factor, t_solve; /* seconds of the last call (host clock)    */
@@ -183,7 +186,8 @@ typedef struct {
   double t_pair_gemm;     /* seconds in the near-pair transform launches of the
                              last factor (HIP events; params.timing = 1)         */
   double flops_pair_gemm; /* canonical flops of those launches: sum over
-                             unordered near pairs of 2 m_i m_j (m_i + m_j)      */
+                             unordered near pairs of 2 m_i m_j (m_i + m_j)
+                             (LU variant: over ordered pairs)                  */
   int32_t pair_launches;  /* number of those launches per factor                */
   double bytes_basis;     /* bytes allocated for the bases U_i (predicted
                              capacities plus fallbacks, or m_i^2 per box)       */
@@ -211,7 +215,9 @@ typedef struct {
                                4 m^3, r^3/3, m r^2 + k r^2 + k^2 r, near pairs
                                (2 m_i m_j (m_i + m_j) + r_i r_j^2 + k_i r_j^2 +
                                k_j r_i^2), far pairs k_i k_j (k_i + k_j), 0,
-                               n0^3/3, 0                                       */
+                               n0^3/3, 0.  LU variant: 2 r^3/3, 2 m r^2 +
+                               2 k r^2 + 2 k^2 r, every ordered near and far
+                               pair, 2 n0^3/3                                  */
   double flops_schur;       /* the k^2 r of phase 3 (the Schur update SS -=
                                L(s) L(s)^T, FP32 MFMA under a reduced
                                gemm_prec)                                      */
@@ -246,7 +252,8 @@ typedef struct {
  *         an allocator without both callbacks;
  *         H2_ERR_ALLOC when a device allocation fails (everything allocated
  *         so far is freed);
- *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD: then
+ *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD (LU
+ *         variant: its pivot-free LU meets a zero or non-finite pivot): then
  *         *out receives a handle in the failed state whose h2_stats give the
  *         (level, box, instance); it accepts only h2_stats and h2_destroy.
  *         On every other error *out is NULL. */
