@@ -484,27 +484,30 @@ def main():
                 out[key] = {"workload": kern, "n": n, "nrhs": nrhs, "status": str(e)}
             torch.cuda.empty_cache()
         # the LU variant: the non-symmetric drift kernel (beta 0.5) on the
-        # cube, N=262144, leaf 256, eps 1e-6, 512-point samples, FP64,
-        # stationary refinement to 1e-8 against the FP64 H^2 operator
-        c = copy.copy(a)
-        c.kernel, c.n, c.nrhs, c.leaf, c.eps, c.s, c.s_near, c.tol = "yukawa_drift", 1 << 18, 1, 256, 1e-6, 512, 512, 1e-8
-        c.steps, c.warmup, c.graph, c.stationary = min(a.steps, 3), 1, False, True
-        print("[bench] lu_drift", file=sys.stderr, flush=True)
-        try:
-            g = run_path(c, h2, h2.PREC_FP64, h2.PREC_FP64, None, "lu_drift")
-            out["lu_drift"] = {"workload": "yukawa_drift_cube", "beta": 0.5, "n": c.n, "nrhs": 1,
-                               "leaf": 256, "eps": 1e-6, "s": 512, "gemm_prec": "fp64",
-                               "solve_prec": "fp64", "refinement": "stationary", "ir_tol": 1e-8,
-                               "steps": c.steps, "value": g["value"], "unit": "TFLOP/s",
-                               "ms_per_step": g["ms_per_step"], "factor_s": g["factor_s"],
-                               "solve_s": g["solve_s"], "ir_iters": g["ir_iters"],
-                               "residual": g["residual"], "build_s": g["build_s"],
-                               "max_rank": g["stats"]["max_rank_seen"],
-                               "lu_variant": g["stats"]["lu_variant"],
-                               "factor_phase_s": g["factor_phase_s"]}
-        except h2.H2Error as e:
-            out["lu_drift"] = {"workload": "yukawa_drift_cube", "n": c.n, "status": str(e)}
-        torch.cuda.empty_cache()
+        # cube, N=262144, leaf 256, eps 1e-6, 512-point samples, stationary
+        # refinement to 1e-8 against the FP64 H^2 operator; FP64, and with
+        # split-BF16 transforms and FP32 substitution copies
+        for key, gp, sp in (("lu_drift", h2.PREC_FP64, h2.PREC_FP64),
+                            ("lu_drift_bf16x3", h2.PREC_BF16X3, h2.PREC_FP32)):
+            c = copy.copy(a)
+            c.kernel, c.n, c.nrhs, c.leaf, c.eps, c.s, c.s_near, c.tol = "yukawa_drift", 1 << 18, 1, 256, 1e-6, 512, 512, 1e-8
+            c.steps, c.warmup, c.graph, c.stationary = min(a.steps, 3), 1, False, True
+            print(f"[bench] {key}", file=sys.stderr, flush=True)
+            try:
+                g = run_path(c, h2, gp, sp, None, key)
+                out[key] = {"workload": "yukawa_drift_cube", "beta": 0.5, "n": c.n, "nrhs": 1,
+                            "leaf": 256, "eps": 1e-6, "s": 512, "gemm_prec": names[gp],
+                            "solve_prec": names[sp], "refinement": "stationary", "ir_tol": 1e-8,
+                            "steps": c.steps, "value": g["value"], "unit": "TFLOP/s",
+                            "ms_per_step": g["ms_per_step"], "factor_s": g["factor_s"],
+                            "solve_s": g["solve_s"], "ir_iters": g["ir_iters"],
+                            "residual": g["residual"], "build_s": g["build_s"],
+                            "max_rank": g["stats"]["max_rank_seen"],
+                            "lu_variant": g["stats"]["lu_variant"],
+                            "factor_phase_s": g["factor_phase_s"]}
+            except h2.H2Error as e:
+                out[key] = {"workload": "yukawa_drift_cube", "n": c.n, "status": str(e)}
+            torch.cuda.empty_cache()
         print("[bench] Matern configuration status", file=sys.stderr, flush=True)
         out["matern_status"] = []
         for n in (1 << 20, 1 << 18):  # the configuration, and a size that fits

@@ -158,9 +158,10 @@ typedef struct {
                              couplings and factors stored for every ordered
                              pair; the forward sweep of Eq. 31 with the lower
                              and the backward sweep with the upper factor.
-                             It requires gemm_prec, solve_prec and matvec_prec
-                             FP64 and use_pcg 0 (refinement is stationary),
-                             else H2_ERR_ARG                                  */
+                             It takes any gemm_prec, solve_prec FP64 or FP32
+                             (the right basis has its own FP32 copy),
+                             matvec_prec FP64 and use_pcg 0 (refinement is
+                             stationary), else H2_ERR_ARG                     */
 } h2_params;
 
 typedef struct h2_ctx* h2_handle;

@@ -313,8 +313,11 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
   for (int t = 0; t < n_inst; ++t)
     if (kerns[t].id == 4 && kerns[t].beta != 0.0) lu = true;
   if (prm->factor_lu != 0 && prm->factor_lu != 1) return H2_ERR_ARG;
-  if (lu && (prm->gemm_prec != H2_PREC_FP64 || prm->solve_prec != H2_PREC_FP64 ||
-             prm->matvec_prec != H2_PREC_FP64 || prm->use_pcg))
+  // the LU variant: any transform precision, FP64 or FP32 substitution
+  // copies (the packed BF16 copies follow the symmetric path's storage),
+  // stationary refinement with the FP64 operator
+  if (lu && (prm->solve_prec == H2_PREC_BF16 || prm->matvec_prec != H2_PREC_FP64 ||
+             prm->use_pcg))
     return H2_ERR_ARG;
   if (fixed_ranks && n_inst != 1) return H2_ERR_ARG;
   if (prm->allocator && (!prm->allocator->alloc || !prm->allocator->free)) return H2_ERR_ARG;
@@ -1041,6 +1044,10 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       S.dF32 = c.alloc<float>(std::max<int64_t>(S.poff[np], 1));
       S.dP32 = c.alloc<float>(std::max<int64_t>(q, 1));
       ALLOCHK(S.dF32); ALLOCHK(S.dP32);
+      if (c.lu) {
+        S.dPr32 = c.alloc<float>(std::max<int64_t>(q, 1));
+        ALLOCHK(S.dPr32);
+      }
     }
     if (c.prm.solve_prec == H2_PREC_BF16) {
       int64_t nF = 0, nP = 0;
@@ -1214,8 +1221,9 @@ h2_status plan_factor(Ctx& c, hipStream_t st) {
       }
       const int mi = S.m[i], mj = S.m[j];
       if (f32pair) {
-        gp1.push_back(gd(asd(S.dD32 + S.poff[p]), mi, 0, asd(S.dP32 + S.qoff[j]), mj, 0, nullptr,
-                         1, asd(S.dT232 + S.poff[p]), mi, mi, mj, mj, 1.0, 0.0));
+        gp1.push_back(gd(asd(S.dD32 + S.poff[p]), mi, 0,
+                         asd((c.lu ? S.dPr32 : S.dP32) + S.qoff[j]), mj, 0, nullptr, 1,
+                         asd(S.dT232 + S.poff[p]), mi, mi, mj, mj, 1.0, 0.0));
         gp2.push_back(gd(asd(S.dP32 + S.qoff[i]), mi, 1, asd(S.dT232 + S.poff[p]), mi, 0, nullptr,
                          1, asd(S.dF32 + S.poff[p]), mi, mi, mj, mi, 1.0, 0.0));
       } else {

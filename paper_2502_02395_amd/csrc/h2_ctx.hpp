@@ -87,6 +87,7 @@ struct Step {
   double* dW = nullptr;                    // QR workspace at qoff
   double* dTau = nullptr;                  // Householder scalars at koff
   float *dF32 = nullptr, *dP32 = nullptr;  // FP32 copies of F and P for the substitution
+  float* dPr32 = nullptr;                  // LU variant: FP32 copy of the right basis P'
   unsigned short *dF16 = nullptr, *dP16 = nullptr;  // packed BF16 copies (solve_prec BF16)
   std::vector<CopyMap> cmF, cmP;           // their layout (sorted by source block)
   Batch<CvtBlk> cvF16, cvP16;              // their conversion blocks

@@ -423,6 +423,7 @@ h2_status plan_solve(Ctx& c, hipStream_t st) {
     } else if (c.prm.solve_prec == H2_PREC_FP32 || c.prm.gemm_prec != H2_PREC_FP64) {
       rb.push_back({S.dF, S.poff.back(), S.dF32, 4});
       rb.push_back({S.dP, S.qoff[S.nbox], S.dP32, 4});
+      if (c.lu) rb.push_back({S.dPr, S.qoff[S.nbox], S.dPr32, 4});
     }
     const int sg = h >= GATHER_SEG_TOP_FROM ? GATHER_SEG_TOP
                  : h >= GATHER_SEG_FROM     ? GATHER_SEG
@@ -651,6 +652,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     if (f32t) {  // FP32 pair transforms: operands and finished F_ii to FP32
       HIPCHK(mark(FP_F32));
       HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
+      if (c.lu) HIPCHK(launch_cvt_f32(S.dPr, S.dPr32, S.qoff[S.nbox], st));
       HIPCHK(launch_cvt_f32(S.dR, S.dR32, S.rkoff[S.nbox], st));
       HIPCHK(launch_cvt_list(S.cv_fii.d, S.cv_fii.count, st));
       HIPCHK(done());
@@ -690,6 +692,7 @@ h2_status do_factor(Ctx& c, hipStream_t st) {
     for (auto& S : c.steps) {
       HIPCHK(launch_cvt_f32(S.dF, S.dF32, S.poff.back(), st));
       HIPCHK(launch_cvt_f32(S.dP, S.dP32, S.qoff[S.nbox], st));
+      if (c.lu) HIPCHK(launch_cvt_f32(S.dPr, S.dPr32, S.qoff[S.nbox], st));
     }
     HIPCHK(done());
   }

@@ -56,12 +56,12 @@ def test_status_strings_and_argument_errors_without_gpu():
         prm = h2.make_params(3, 8, 1.0, 1e-6, **kw)
         assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
                           ctypes.byref(out)) == h2.ERR_ARG, kw
-    # the LU variant (a non-symmetric drift kernel, or factor_lu) needs FP64
-    # transforms, substitution and matvec and stationary refinement;
-    # factor_lu is 0 or 1; beta must be finite
+    # the LU variant (a non-symmetric drift kernel, or factor_lu) takes FP64
+    # or FP32 substitution copies, the FP64 matvec and stationary
+    # refinement; factor_lu is 0 or 1; beta must be finite
     kd = h2.Kernel(4, 1e-3, 1.0, 1.0, 0.0, 0.5)
-    for kw in ({"gemm_prec": h2.PREC_FP32}, {"gemm_prec": h2.PREC_BF16X3},
-               {"solve_prec": h2.PREC_FP32}, {"matvec_prec": h2.PREC_FP32}, {"use_pcg": True}):
+    for kw in ({"solve_prec": h2.PREC_BF16}, {"gemm_prec": h2.PREC_BF16X3, "solve_prec": h2.PREC_BF16},
+               {"matvec_prec": h2.PREC_FP32}, {"use_pcg": True}):
         prm = h2.make_params(3, 8, 1.0, 1e-6, **kw)
         assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(kd), ctypes.byref(prm), None, None,
                           ctypes.byref(out)) == h2.ERR_ARG, kw

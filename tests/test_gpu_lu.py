@@ -193,10 +193,10 @@ def test_free_lu_build_end_to_end(lib):
     H.close()
 
 
-def test_lu_rejects_reduced_precision_and_pcg(lib):
+def test_lu_rejects_bf16_copies_and_pcg(lib):
     p = W.yukawa_drift_cube(n=512, leaf=64, eps=1e-6, beta=0.5)
-    for kw in ({"gemm_prec": lib.PREC_FP32}, {"solve_prec": lib.PREC_BF16},
-               {"matvec_prec": lib.PREC_FP32}, {"use_pcg": True}):
+    for kw in ({"solve_prec": lib.PREC_BF16}, {"matvec_prec": lib.PREC_FP32},
+               {"use_pcg": True}):
         with pytest.raises(lib.H2Error) as ei:
             lib.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), **kw)
         assert ei.value.status == lib.ERR_ARG
@@ -204,6 +204,43 @@ def test_lu_rejects_reduced_precision_and_pcg(lib):
     q = dataclasses.replace(p, kernel=dataclasses.replace(p.kernel, beta=0.0))
     H = lib.build(q.points, q.kernel, q.leaf, q.eta, q.eps, q.perm())
     assert H.stats()["lu_variant"] == 0
+    H.close()
+
+
+@pytest.mark.parametrize("gp,sp", [("fp32", "fp64"), ("bf16x3", "fp32")])
+def test_lu_precision_split_against_oracle(lib, gp, sp):
+    """The LU variant with reduced-precision transforms (FP32, or split BF16
+    on the BF16 matrix cores) and FP64 or FP32 substitution copies, refined
+    by stationary iterations against the FP64 H^2 operator on the oracle's
+    H^2 matrix: the refined x meets 2 kappa(A~) max(res, res_o) of the
+    oracle's refined x (both residuals against A~ at most 1.1e-10), and the
+    iterations stay few (the preconditioner's error is that of its
+    precision)."""
+    import torch
+    P = {"fp64": lib.PREC_FP64, "fp32": lib.PREC_FP32, "bf16x3": lib.PREC_BF16X3}
+    p = W.yukawa_drift_cube(n=4096, leaf=128, eps=1e-8, beta=0.5, s=256)
+    h2o = _oracle(p)
+    sk, ranks, pos = _skeletons(h2o)
+    h2f = _oracle(p, skeletons=sk)
+    b = W.rhs(p.n, 2, 5)
+    xo, hist = ulv_lu.refine(ulv_lu.factor(h2f), b, 1e-10, 30)
+    At = h2matrix.assemble_dense(h2f)
+    kappa = np.linalg.cond(At)
+    res_o = np.linalg.norm(b - At @ xo, axis=0) / np.linalg.norm(b, axis=0)
+    H = lib.build_fixed(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), ranks, pos,
+                        s_far=p.s_far, s_near=p.s_near, gemm_prec=P[gp], solve_prec=P[sp],
+                        ir_max_iter=30, ir_tol=1e-10)
+    assert H.stats()["lu_variant"] == 1
+    H.factor()
+    x = H.solve(torch.from_numpy(b).cuda()).cpu().numpy()
+    st = H.stats()
+    res = np.linalg.norm(b - At @ x, axis=0) / np.linalg.norm(b, axis=0)
+    print(f"[lu {gp} transforms, {sp} copies] {st['ir_iters']} steps (oracle FP64 "
+          f"{len(hist) - 1}), residual {res.max():.2e}, x vs oracle {_rel(x, xo):.2e}", flush=True)
+    assert H.last_solve_status == lib.OK
+    assert st["ir_residual"] <= 1e-10 and res.max() <= 1.1e-10
+    assert _rel(x, xo) <= 2 * kappa * max(res.max(), res_o.max())
+    assert st["ir_iters"] <= 3 * max(len(hist) - 1, 1) + 4
     H.close()
 
 
