@@ -356,7 +356,10 @@ def main():
     if a.s_near <= 0:
         a.s_near = a.s
     if a.kernel == "yukawa_drift":
-        # the LU variant runs in FP64 with stationary refinement only
+        # the LU variant refines by stationary iterations and takes no BF16
+        # substitution copies: the target path's settings do not apply, so it
+        # defaults to the FP64 path (--path custom --prec bf16x3 --solve-prec
+        # fp32 for the precision split)
         if a.path == "target":
             a.path = "plain"
         a.stationary = True
