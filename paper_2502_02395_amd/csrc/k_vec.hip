@@ -150,19 +150,22 @@ __global__ __launch_bounds__(256) void cvt_bf16_blks_kernel(const TS* __restrict
   int sg = first[blockIdx.x];
   while (sg + 1 < count && blks[sg + 1].g0 <= e) ++sg;
   const CvtBlk g = blks[sg];
-  int64_t le = e - g.g0;
+  // the group's index inside its block: a block has fewer than 2^31 groups
+  // (its columns times its 8-row groups), so 32-bit quotients suffice
+  int le = (int)(e - g.g0);
   int col, r;
   bool top;
-  const int64_t lead = (int64_t)g.c_top * g.gb;  // columns with a bottom part only
+  const int lead = g.c_top * g.gb;  // columns with a bottom part only
   if (le < lead) {
-    col = (int)(le / g.gb);
-    r = (int)(le % g.gb);
+    col = le / g.gb;
+    r = le - col * g.gb;
     top = false;
   } else {
     le -= lead;
     const int per = g.gt + g.gb;
-    col = g.c_top + (int)(le / per);
-    r = (int)(le % per);
+    const int q = le / per;
+    col = g.c_top + q;
+    r = le - q * per;
     top = r < g.gt;
     if (!top) r -= g.gt;
   }
