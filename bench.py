@@ -307,6 +307,48 @@ def run_path(a, h2, prec: int, sprec: int, model, label: str, mvprec: int = 0) -
     }
 
 
+def run_graph(a, h2, model) -> dict:
+    """The target path's settings with the factorization and the solve's
+    substitutions and products captured in hipGraphs (use_graph) and no
+    per-launch timing: K steps of factor + solve after W warm-up steps
+    (the first of which captures)."""
+    import torch
+    p = workload(a.n, a.kernel, a.eps, a.leaf, a.s, 1)
+    H = h2.build(p.points, p.kernel, p.leaf, p.eta, p.eps, p.perm(), s_far=a.s, s_near=a.s_near,
+                 ir_max_iter=100, ir_tol=a.tol, gemm_prec=h2.PREC_BF16X3, rank_model=model,
+                 use_graph=True, use_pcg=True, solve_prec=h2.PREC_BF16,
+                 matvec_prec=h2.PREC_FP32)
+    b = torch.from_numpy(p.b()).cuda()
+    cols_b = b.t().contiguous()
+    cols_x = torch.empty_like(cols_b)
+    for _ in range(max(a.warmup, 1)):
+        H.factor()
+        if H.solve_into(cols_b, cols_x) != h2.OK:
+            raise h2.H2Error(h2.ERR_NOCONV, "h2_solve")
+    torch.cuda.synchronize()
+    K = a.steps
+    iters = 0
+    res = 0.0
+    t0 = time.perf_counter()
+    for _ in range(K):
+        H.factor()
+        s = H.solve_into(cols_b, cols_x)
+        if s != h2.OK:
+            raise h2.H2Error(s, "h2_solve")
+        st = H.stats()
+        iters += st["ir_iters"]
+        res = max(res, st["ir_residual"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = H.stats()
+    H.close()
+    torch.cuda.empty_cache()
+    flops_step = st["flops_factor"] + st["flops_solve"] * (1 + iters / K)
+    return {"value": flops_step * K / dt / 1e12, "unit": "TFLOP/s", "ms_per_step": 1e3 * dt / K,
+            "ir_iters": iters / K, "residual": res, "steps": K,
+            "graph": "factor and solve captured", "launch_timing": False}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,6 +480,13 @@ def main():
                              "roofline": plain["cands"][0] if plain["cands"] else None}
         out["speedup_vs_plain_fp64"] = plain["ms_per_step"] / r["ms_per_step"]
     if a.path == "target" and a.kernel == "yukawa" and a.n == 1 << 20 and not a.no_extras:
+        # the same path with captured factorization and solves, without
+        # per-launch timing (beside the timed headline)
+        print("[bench] target path, captured", file=sys.stderr, flush=True)
+        try:
+            out["target_graph"] = run_graph(a, h2, model)
+        except h2.H2Error as e:
+            out["target_graph"] = {"status": str(e)}
         # the batched configuration (64 independent 2-D Gaussian systems, one
         # handle, factorization captured in a hipGraph; FP64 transforms: these
         # covariance matrices break down under FP32 ones) and the status of

@@ -110,7 +110,14 @@ typedef struct {
   int32_t ir_max_iter;    /* 0 = plain direct solve                              */
   double ir_tol;          /* relative residual target of refinement              */
   int32_t use_pcg;        /* 1 = PCG instead of stationary refinement            */
-  int32_t use_graph;      /* 1 = capture factor launches in a hipGraph           */
+  int32_t use_graph;      /* 1 = capture the factorization's launches in a hipGraph
+                             (on the first h2_factor; replayed after), and in an
+                             untimed h2_solve the launches of each substitution
+                             and H^2 product (one graph per shape, captured on
+                             first use).  Captures and replays run on a stream
+                             of the handle, ordered after and before the
+                             caller's stream by events.  h2_solve_noalloc
+                             never captures                                   */
   const float* rank_model;/* host, 4801 MLP weights; NULL = plain pivoted QR    */
   double rank_margin;     /* predicted-rank buffer margin (fraction, e.g. 0.25) */
   int32_t timing;         /* 1 = time factor phases and solve gathers (events)   */

@@ -230,6 +230,8 @@ h2_status h2_build_fixed(const double* pts, int64_t n, const h2_kernel* kernel,
   return s;
 }
 
+static h2_status ensure_graph_stream(Ctx& c);
+
 h2_status h2_factor(h2_handle h, void* stream) {
   if (!h || !h->c) return H2_ERR_ARG;
   Ctx& c = *h->c;
@@ -240,11 +242,8 @@ h2_status h2_factor(h2_handle h, void* stream) {
     // The caller's stream may be the null stream, which cannot be captured:
     // capture and replay on a stream of our own (default priority), ordered
     // after and before the caller's work by events.
-    if (!c.graph_stream) {
-      HIPCHK(hipStreamCreateWithFlags(&c.graph_stream, hipStreamNonBlocking));
-      HIPCHK(hipEventCreateWithFlags(&c.ev_g0, hipEventDisableTiming));
-      HIPCHK(hipEventCreateWithFlags(&c.ev_g1, hipEventDisableTiming));
-    }
+    h2_status ge = ensure_graph_stream(c);
+    if (ge != H2_OK) return ge;
     hipStream_t gs = c.graph_stream;
     HIPCHK(hipEventRecord(c.ev_g0, st));
     HIPCHK(hipStreamWaitEvent(gs, c.ev_g0, 0));
@@ -300,6 +299,65 @@ static h2_status solve_plain(Ctx& c, const double* b, double* x, int nc, hipStre
   return do_solve_chunk(c, b, c.N, x, c.N, nc, st);
 }
 
+// The capture stream and the events that order it after and before the
+// caller's stream (created once per handle).
+static h2_status ensure_graph_stream(Ctx& c) {
+  if (c.graph_stream) return H2_OK;
+  HIPCHK(hipStreamCreateWithFlags(&c.graph_stream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c.ev_g0, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c.ev_g1, hipEventDisableTiming));
+  return H2_OK;
+}
+
+// A substitution (op 0: out = M^{-1} in) or an H^2 product (op 1: out = A in,
+// on the FP32 copies if lowp) of nc columns.  With `graphs`, the launch
+// sequence is captured once per (op, in, out, nc, lowp, partial buffer) on the
+// handle's own stream and replayed there, ordered after and before the
+// caller's work by events: a solve's hundreds of short launches then cost one
+// graph launch.  The sequences hold no memset and no host synchronization.
+static h2_status run_op(Ctx& c, int op, const double* in, double* out, int nc, bool lowp,
+                        bool graphs, hipStream_t st) {
+  auto direct = [&](hipStream_t s) -> h2_status {
+    return op == 0 ? solve_plain(c, in, out, nc, s)
+                   : do_matvec_chunk(c, in, c.N, out, c.N, nc, s, lowp);
+  };
+  if (!graphs) return direct(st);
+  h2_status e = ensure_graph_stream(c);
+  if (e != H2_OK) return e;
+  Ctx::SolveGraph* sg = nullptr;
+  for (auto& q : c.sgraphs)
+    if (q.op == op && q.in == in && q.out == out && q.nc == nc && q.lowp == lowp &&
+        q.part == c.part_cur) {
+      sg = &q;
+      break;
+    }
+  hipStream_t gs = c.graph_stream;
+  HIPCHK(hipEventRecord(c.ev_g0, st));
+  HIPCHK(hipStreamWaitEvent(gs, c.ev_g0, 0));
+  if (!sg) {
+    Ctx::SolveGraph ng;
+    ng.op = op; ng.in = in; ng.out = out; ng.nc = nc; ng.lowp = lowp; ng.part = c.part_cur;
+    HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    e = direct(gs);
+    const hipError_t ce = hipStreamEndCapture(gs, &ng.g);
+    if (e != H2_OK) {
+      if (ng.g) (void)hipGraphDestroy(ng.g);
+      return e;
+    }
+    HIPCHK(ce);
+    if (hipGraphInstantiate(&ng.exec, ng.g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(ng.g);
+      return H2_ERR_HIP;
+    }
+    c.sgraphs.push_back(ng);
+    sg = &c.sgraphs.back();
+  }
+  HIPCHK(hipGraphLaunch(sg->exec, gs));
+  HIPCHK(hipEventRecord(c.ev_g1, gs));
+  HIPCHK(hipStreamWaitEvent(st, c.ev_g1, 0));
+  return H2_OK;
+}
+
 static h2_status colnorms(Ctx& c, const double* a, int nc, double* out, hipStream_t st) {
   HIPCHK(launch_coldot(a, c.N, a, c.N, c.N, nc, c.dWs, out, st));
   return H2_OK;
@@ -310,8 +368,11 @@ static h2_status colnorms(Ctx& c, const double* a, int nc, double* out, hipStrea
 // for part_len x chunk doubles).  time_gathers: record gather events (the
 // event pool is created on first use).
 static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, int64_t ld,
-                            hipStream_t st, int chunk, bool time_gathers) {
+                            hipStream_t st, int chunk, bool time_gathers, bool graphs_ok) {
   const double t0 = now_seconds();
+  // captured substitutions and products: use_graph, untimed (a graph carries
+  // no per-launch events), and a caller that allows the graphs' allocations
+  const bool graphs = graphs_ok && c.prm.use_graph && !time_gathers;
   const int maxit = c.prm.ir_max_iter;
   if (time_gathers) {
     if (c.gev.empty()) {
@@ -334,7 +395,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
     // keep b (x may alias it)
     HIPCHK(launch_axpby(c.w_t, c.N, bb, ld, bb, ld, c.N, nc, nullptr, nullptr, 0.0, st));
     if (maxit <= 0) {
-      h2_status e = solve_plain(c, c.w_t, c.w_x, nc, st);
+      h2_status e = run_op(c, 0, c.w_t, c.w_x, nc, false, graphs, st);
       if (e != H2_OK) return e;
     } else {
       double* sc = c.dScal;  // [0,16): r.r  [16,32): b.b  [32,48): rz  [48,64): pq  [64,80): rz_new
@@ -342,9 +403,9 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
       h2_status e = colnorms(c, c.w_t, nc, sc + 16, st);
       if (e != H2_OK) return e;
       HIPCHK(hipMemcpyAsync(hb, sc + 16, nc * sizeof(double), hipMemcpyDeviceToHost, st));
-      if ((e = solve_plain(c, c.w_t, c.w_x, nc, st)) != H2_OK) return e;
+      if ((e = run_op(c, 0, c.w_t, c.w_x, nc, false, graphs, st)) != H2_OK) return e;
       // r = b - A x
-      if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+      if ((e = run_op(c, 1, c.w_x, c.w_q, nc, false, graphs, st)) != H2_OK) return e;
       HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
       const bool pcg = c.prm.use_pcg != 0;
       // PCG on FP32 copies of the near blocks and couplings: its own
@@ -353,7 +414,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
       int restarts = 0;
       ++fp64_mv;
       if (pcg) {
-        if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+        if ((e = run_op(c, 0, c.w_r, c.w_z, nc, false, graphs, st)) != H2_OK) return e;
         HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
         HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 32, st));
       }
@@ -372,7 +433,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
         if (res <= c.prm.ir_tol && lowp) {
           // the FP64 operator's residual r = b - A x; restart PCG from it
           // while it is above the target
-          if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          if ((e = run_op(c, 1, c.w_x, c.w_q, nc, false, graphs, st)) != H2_OK) return e;
           ++fp64_mv;
           HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
           if ((e = colnorms(c, c.w_r, nc, sc, st)) != H2_OK) return e;
@@ -387,7 +448,7 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
           if (res <= c.prm.ir_tol) break;
           if (restarts >= 8 || it >= maxit) { noconv = true; break; }
           ++restarts;
-          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          if ((e = run_op(c, 0, c.w_r, c.w_z, nc, false, graphs, st)) != H2_OK) return e;
           HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 0.0, st));
           HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 32, st));
           continue;
@@ -396,18 +457,18 @@ static h2_status solve_impl(Ctx& c, const double* b, double* x, int64_t nrhs, in
         if (it >= maxit) { noconv = true; break; }
         ++it;
         if (!pcg) {
-          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          if ((e = run_op(c, 0, c.w_r, c.w_z, nc, false, graphs, st)) != H2_OK) return e;
           HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_z, c.N, c.N, nc, nullptr, nullptr, 1.0, st));
-          if ((e = do_matvec_chunk(c, c.w_x, c.N, c.w_q, c.N, nc, st)) != H2_OK) return e;
+          if ((e = run_op(c, 1, c.w_x, c.w_q, nc, false, graphs, st)) != H2_OK) return e;
           ++fp64_mv;
           HIPCHK(launch_axpby(c.w_r, c.N, c.w_t, c.N, c.w_q, c.N, c.N, nc, nullptr, nullptr, -1.0, st));
         } else {
-          if ((e = do_matvec_chunk(c, c.w_p, c.N, c.w_q, c.N, nc, st, lowp)) != H2_OK) return e;
+          if ((e = run_op(c, 1, c.w_p, c.w_q, nc, lowp, graphs, st)) != H2_OK) return e;
           if (!lowp) ++fp64_mv;
           HIPCHK(launch_coldot(c.w_p, c.N, c.w_q, c.N, c.N, nc, c.dWs, sc + 48, st));
           HIPCHK(launch_axpby(c.w_x, c.N, c.w_x, c.N, c.w_p, c.N, c.N, nc, sc + 32, sc + 48, 1.0, st));
           HIPCHK(launch_axpby(c.w_r, c.N, c.w_r, c.N, c.w_q, c.N, c.N, nc, sc + 32, sc + 48, -1.0, st));
-          if ((e = solve_plain(c, c.w_r, c.w_z, nc, st)) != H2_OK) return e;
+          if ((e = run_op(c, 0, c.w_r, c.w_z, nc, false, graphs, st)) != H2_OK) return e;
           HIPCHK(launch_coldot(c.w_r, c.N, c.w_z, c.N, c.N, nc, c.dWs, sc + 64, st));
           HIPCHK(launch_axpby(c.w_p, c.N, c.w_z, c.N, c.w_p, c.N, c.N, nc, sc + 64, sc + 32, 1.0, st));
           HIPCHK(hipMemcpyAsync(sc + 32, sc + 64, nc * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -457,7 +518,7 @@ h2_status h2_solve(h2_handle h, const double* b, double* x, int64_t nrhs, int64_
     if (e != H2_OK) return e;
   }
   c.part_cur = c.dPart;
-  return solve_impl(c, b, x, nrhs, ld, S(stream), NRHS_MAX, c.prm.timing != 0);
+  return solve_impl(c, b, x, nrhs, ld, S(stream), NRHS_MAX, c.prm.timing != 0, true);
 }
 
 h2_status h2_solve_noalloc(h2_handle h, const double* b, double* x, int64_t nrhs, int64_t ld,
@@ -476,7 +537,7 @@ h2_status h2_solve_noalloc(h2_handle h, const double* b, double* x, int64_t nrhs
   const int64_t fit = c.part_len > 0 ? H2_NOALLOC_PARTIALS / c.part_len : NRHS_MAX;
   const int chunk = (int)std::min<int64_t>(NRHS_MAX, fit);
   c.part_cur = part;
-  return solve_impl(c, b, x, nrhs, ld, S(stream), chunk, false);
+  return solve_impl(c, b, x, nrhs, ld, S(stream), chunk, false, false);
 }
 
 h2_status h2_matvec(h2_handle h, const double* x, double* y, int64_t nrhs, int64_t ld, void* stream) {

@@ -27,6 +27,10 @@ Ctx::~Ctx() {
   if (ev_b) (void)hipEventDestroy(ev_b);
   if (graph) (void)hipGraphExecDestroy(graph);
   if (graph_def) (void)hipGraphDestroy(graph_def);
+  for (auto& sg : sgraphs) {
+    if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+    if (sg.g) (void)hipGraphDestroy(sg.g);
+  }
   for (hipEvent_t e : gev) (void)hipEventDestroy(e);
   for (hipEvent_t e : fev) (void)hipEventDestroy(e);
   if (ev_g0) (void)hipEventDestroy(ev_g0);

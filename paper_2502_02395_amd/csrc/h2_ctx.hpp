@@ -200,6 +200,20 @@ struct Ctx {
   int pair_launches = 0;
   hipGraphExec_t graph = nullptr;
   hipGraph_t graph_def = nullptr;
+  // captured substitutions and operator products of the solve (use_graph,
+  // untimed solves): one per (operation, input, output, columns, precision,
+  // partial buffer)
+  struct SolveGraph {
+    int op;                                // 0 substitution, 1 H^2 product
+    const double* in;
+    double* out;
+    int nc;
+    bool lowp;
+    const double* part;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<SolveGraph> sgraphs;
   hipStream_t graph_stream = nullptr;      // capture and replay (never the null stream)
   // gather timing (params.timing): per gather four events, the start and end
   // of its chunk launch and of its reduction launch (marked by the launches'
