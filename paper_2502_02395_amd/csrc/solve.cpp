@@ -12,6 +12,11 @@
 //   s_j   = t_j - sum_{i>j} (L(r)_ii^{-1} L(r)_ij)^T t_i,
 //   x_j   = P_j [x_j^S; s_j]                           (backward),
 // which is the transpose of Eq. 31 since Q_j^R L(r)_jj^{-T} s_j = Q_j^R x_j^R.
+// LU variant (every ordered pair stored): the left basis P_i as above, the
+// right basis P'_j = [Q_j^S | Q_j^R U(r)_jj^{-1}], F_ij = P_i^T A_ij P'_j with
+// L(s)_ij, U(s)_ij and L(r)_ii^{-1} RR_ij U(r)_jj^{-1}; the same recurrences
+// read every block directly (F_ij^SR, F_ji^RS, F_ji^RR where the symmetric
+// form reads transposes) and the backward sweep ends with x_j = P'_j [x^S; s].
 // Every step is a batched product or neighbour gather, the root solve
 // included (a product with the explicit root inverse).
 #include <algorithm>
