@@ -256,8 +256,8 @@ typedef struct {
  *  perm:  host, n int64, the sampling permutation pi of 0..n-1; S_F / S_C take
  *         the candidates that come first in pi.  NULL = identity.
  *  out:   receives the new handle.
- * Errors: H2_ERR_ARG for n < 1, leaf < 2, dim not 2/3, bad kernel id, eps < 0,
- *         an allocator without both callbacks;
+ * Errors: H2_ERR_ARG for n < 1, a non-finite coordinate, leaf < 2, dim not 2/3,
+ *         bad kernel id, eps < 0, an allocator without both callbacks;
  *         H2_ERR_ALLOC when a device allocation fails (everything allocated
  *         so far is freed);
  *         H2_ERR_NOT_SPD if a near-sample matrix G(S_C, S_C) is not SPD (LU

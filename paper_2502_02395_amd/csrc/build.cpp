@@ -305,6 +305,8 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     return H2_ERR_ARG;
   for (int t = 0; t < n_inst; ++t) {
     if (!pts[t] || ns[t] < 1) return H2_ERR_ARG;
+    for (int64_t q = 0; q < ns[t] * prm->dim; ++q)
+      if (!std::isfinite(pts[t][q])) return H2_ERR_ARG;
     const h2_kernel& k = kerns[t];
     if (k.id < 0 || k.id > 4) return H2_ERR_ARG;
     const bool reg = k.id <= 1 || k.id == 4;
@@ -370,14 +372,16 @@ h2_status build_impl(int n_inst, const double* const* pts, const int64_t* ns,
     }
   }
   c.N = N;
-  // trees in parallel over instances
+  // trees in parallel over instances, each on its share of the threads
   {
+    const unsigned tw = std::min<unsigned>(hw, n_inst);
+    const int per = (int)std::max(1u, hw / tw);
     std::vector<std::thread> th;
     std::atomic<int> next{0};
-    for (unsigned w = 0; w < std::min<unsigned>(hw, n_inst); ++w)
+    for (unsigned w = 0; w < tw; ++w)
       th.emplace_back([&]() {
         for (int t; (t = next.fetch_add(1)) < n_inst;)
-          build_tree(pts[t], c.ins[t].n, c.dim, prm->leaf, prm->eta, c.ins[t].tree);
+          build_tree(pts[t], c.ins[t].n, c.dim, prm->leaf, prm->eta, c.ins[t].tree, per);
       });
     for (auto& x : th) x.join();
   }

@@ -27,14 +27,18 @@ struct Tree {
 int num_levels(int64_t n, int leaf);
 
 // Far iff ||c_a - c_b||_2 > eta (rho_a + rho_b), evaluated in this order in
-// double precision; only children of near pairs are tested.
-void build_tree(const double* X, int64_t n, int dim, int leaf, double eta, Tree& t);
+// double precision; only children of near pairs are tested.  X must be finite
+// (dim <= 3).  nthreads: threads for the boxes of a level (the result does
+// not depend on it).
+void build_tree(const double* X, int64_t n, int dim, int leaf, double eta, Tree& t,
+                int nthreads = 1);
 
 // Sample selection of one level of one instance (Algorithm 1, Sample()):
 // for each box i, S_F = the s_far active points of non-near boxes that come
 // first in pi order, S_C = the s_near active points of near boxes j != i that
 // come first in pi order (negative size: all of them).  Active points are
-// given per box as ids; rank[id - id_base] is the position of a point in pi.
+// given per box as ids; rank[id - id_base] is the position of a point in pi
+// (distinct points, distinct positions).
 void sample_level(const std::vector<std::vector<int64_t>>& B,
                   const std::vector<std::vector<int>>& near_of,
                   const int64_t* rank, int64_t id_base, int s_far, int s_near,

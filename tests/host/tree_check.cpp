@@ -15,10 +15,11 @@ std::vector<std::vector<int64_t>> g_sf, g_sc;
 
 extern "C" {
 
-// Builds the tree of X (n x dim, row-major); returns its number of levels L.
-int tc_build(const double* X, int64_t n, int dim, int leaf, double eta) {
+// Builds the tree of X (n x dim, row-major) on nthreads threads; returns its
+// number of levels L.
+int tc_build(const double* X, int64_t n, int dim, int leaf, double eta, int nthreads) {
   g_tree = h2::Tree();
-  h2::build_tree(X, n, dim, leaf, eta, g_tree);
+  h2::build_tree(X, n, dim, leaf, eta, g_tree, nthreads);
   return g_tree.L;
 }
 

@@ -77,6 +77,12 @@ def test_status_strings_and_argument_errors_without_gpu():
                 h2.Kernel(5, 1e-3, 1.0, 1.0, 0.0, 0.0)):
         assert L.h2_build(pts.ctypes.data, 4, ctypes.byref(bad), ctypes.byref(prm), None, None,
                           ctypes.byref(out)) == h2.ERR_ARG
+    # non-finite coordinates
+    for v in (float("nan"), float("inf")):
+        bad_pts = np.zeros((4, 3))
+        bad_pts[2, 1] = v
+        assert L.h2_build(bad_pts.ctypes.data, 4, ctypes.byref(k), ctypes.byref(prm), None, None,
+                          ctypes.byref(out)) == h2.ERR_ARG
     assert L.h2_factor(None, None) == h2.ERR_ARG
     assert L.h2_solve(None, None, None, 1, 1, None) == h2.ERR_ARG
     assert L.h2_solve_noalloc(None, None, None, 1, 1, None) == h2.ERR_ARG

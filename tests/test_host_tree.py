@@ -5,7 +5,7 @@ bit: permutation, box ranges, box centres, extents and radii, the near and
 far lists of every level, and the far and near samples of every box.  Point
 sets: the workloads' cube and sphere, 1-D and 2-D sets, and degenerate ones
 (duplicated coordinates, a set of identical points, sizes at the leaf size),
-at admissibility 0 (HSS), 0.5, 1 and 2.  The tree source is compiled with the
+at admissibility 0 (HSS), 0.5, 1 and 2, built on one and on several threads.  The tree source is compiled with the
 flags the library uses for it, into a helper loaded through ctypes."""
 import ctypes
 import os
@@ -37,7 +37,8 @@ def tc(tmp_path_factory):
                         "-shared"] + SRC + ["-o", so], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-3000:]
     lib = ctypes.CDLL(so)
-    lib.tc_build.argtypes = [f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+    lib.tc_build.argtypes = [f64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                             ctypes.c_int]
     lib.tc_build.restype = ctypes.c_int
     lib.tc_perm.argtypes = [i64p]
     lib.tc_level.argtypes = [ctypes.c_int, i64p, f64p, f64p, f64p]
@@ -95,14 +96,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("threads", [1, 5])
 @pytest.mark.parametrize("kind,n,leaf,eta", CASES,
                          ids=[f"{c[0]}-{c[1]}-leaf{c[2]}-eta{c[3]}" for c in CASES])
-def test_tree_and_lists_equal_the_oracle(tc, kind, n, leaf, eta):
+def test_tree_and_lists_equal_the_oracle(tc, kind, n, leaf, eta, threads):
     rng = np.random.default_rng(n * 31 + leaf)
     X = np.ascontiguousarray(_points(kind, n, rng))
     dim = X.shape[1]
     o = ot.ClusterTree(X, leaf, eta)
-    L = tc.tc_build(_p(X, f64p), n, dim, leaf, eta)
+    L = tc.tc_build(_p(X, f64p), n, dim, leaf, eta, threads)
     assert L == o.L
     perm = np.empty(n, np.int64)
     tc.tc_perm(_p(perm, i64p))
