@@ -19,6 +19,8 @@ Kernel identifiers follow the C ABI (``include/h2.h``):
   1 = regularised Yukawa  exp(-kappa r)/(r+delta)
   2 = Gaussian            exp(-r^2/ell^2) + nugget [i==j]
   3 = Matern nu=3/2       (1+sqrt3 r/ell) exp(-sqrt3 r/ell) + nugget [i==j]
+  4 = Yukawa with drift   exp(-kappa r)/(r+delta) (1 + beta (x_0 - y_0)/(r+delta))
+                          (non-symmetric for beta != 0)
 """
 from __future__ import annotations
 
