@@ -17,7 +17,7 @@ int num_levels(int64_t n, int leaf) {
 
 namespace {
 
-// fn(i) for i in [0, count) on up to nthreads threads (w = the thread's index)
+// fn(i, w) for i in [0, count) on up to nthreads threads (w: the thread's index)
 template <class F>
 void parallel_for(int count, int nthreads, F fn) {
   const int nt = std::max(1, std::min(nthreads, count));
@@ -34,13 +34,35 @@ void parallel_for(int count, int nthreads, F fn) {
   for (auto& x : th) x.join();
 }
 
+// Sorts distinct keys on up to nthreads threads: runs sorted in parallel,
+// then merged pairwise (distinct keys have one sorted order).
+template <class K>
+void sort_distinct(std::vector<K>& k, int nthreads) {
+  const int T = std::max(1, std::min(nthreads, (int)(k.size() / 32768)));
+  if (T == 1) {
+    std::sort(k.begin(), k.end());
+    return;
+  }
+  std::vector<size_t> bnd(T + 1);
+  for (int i = 0; i <= T; ++i) bnd[i] = k.size() * i / T;
+  parallel_for(T, T, [&](int i, int) { std::sort(k.begin() + bnd[i], k.begin() + bnd[i + 1]); });
+  for (int w = 1; w < T; w *= 2) {
+    const int jobs = (T + 2 * w - 1) / (2 * w);
+    parallel_for(jobs, T, [&](int j, int) {
+      const int a = 2 * w * j, m = std::min(a + w, T), e = std::min(a + 2 * w, T);
+      if (m < e) std::inplace_merge(k.begin() + bnd[a], k.begin() + bnd[m], k.begin() + bnd[e]);
+    });
+  }
+}
+
 }  // namespace
 
 // Every level sorts each box's points along the longest axis of its bounding
 // box.  The points travel with their coordinates (a copy in tree order, so
 // every scan is contiguous); a box sorts (coordinate, position) keys, whose
 // order is the one a stable sort by coordinate gives, since positions are
-// unique; the boxes of a level are spread over threads.  Geometry: a leaf's
+// unique; the boxes of a level are spread over threads (a level with fewer
+// boxes than threads sorts each box on its share of them).  Geometry: a leaf's
 // bounding box from its points, a parent's from its children's (min and max
 // are exact, so each is the bounding box of the box's points).
 void build_tree(const double* X, int64_t n, int dim, int leaf, double eta, Tree& t,
@@ -63,6 +85,7 @@ void build_tree(const double* X, int64_t n, int dim, int leaf, double eta, Tree&
     const std::vector<int64_t>& st = t.start[l];
     const int nb = 1 << l;
     std::vector<int64_t> nx((size_t)2 * nb + 1, 0);
+    const int inner = std::max(1, nthreads / nb);  // threads per box for its sort
     parallel_for(nb, nthreads, [&](int b, int w) {
       Scratch& sc = scr[w];
       const int64_t s = st[b], e = st[b + 1], m = e - s;
@@ -79,7 +102,7 @@ void build_tree(const double* X, int64_t n, int dim, int leaf, double eta, Tree&
         if (mx[a] - mn[a] > best) { best = mx[a] - mn[a]; axis = a; }
       sc.key.resize(m);
       for (int64_t q = 0; q < m; ++q) sc.key[q] = {Xp[(s + q) * dim + axis], q};
-      std::sort(sc.key.begin(), sc.key.end());
+      sort_distinct(sc.key, inner);
       sc.x.resize(m * dim);
       sc.p.resize(m);
       for (int64_t q = 0; q < m; ++q) {

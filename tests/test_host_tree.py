@@ -5,8 +5,10 @@ bit: permutation, box ranges, box centres, extents and radii, the near and
 far lists of every level, and the far and near samples of every box.  Point
 sets: the workloads' cube and sphere, 1-D and 2-D sets, and degenerate ones
 (duplicated coordinates, a set of identical points, sizes at the leaf size),
-at admissibility 0 (HSS), 0.5, 1 and 2, built on one and on several threads.  The tree source is compiled with the
-flags the library uses for it, into a helper loaded through ctypes."""
+at admissibility 0 (HSS), 0.5, 1 and 2, built on one and on several threads
+(boxes of 2^16 points and more sort in parallel runs).  The tree source is
+compiled with the flags the library uses for it, into a helper loaded
+through ctypes."""
 import ctypes
 import os
 import shutil
@@ -93,10 +95,14 @@ CASES = [
     ("cube", 64, 64, 1.0),        # n = leaf: the root is the only box
     ("cube", 65, 64, 1.0),        # one split
     ("cube", 2, 2, 1.0),
+    # boxes of 2^16 points and more: their keys are sorted in parallel runs
+    # and merged (with ties in grid_dups)
+    ("cube", 131072, 2048, 1.0),
+    ("grid_dups", 131072, 4096, 1.0),
 ]
 
 
-@pytest.mark.parametrize("threads", [1, 5])
+@pytest.mark.parametrize("threads", [1, 3, 5])
 @pytest.mark.parametrize("kind,n,leaf,eta", CASES,
                          ids=[f"{c[0]}-{c[1]}-leaf{c[2]}-eta{c[3]}" for c in CASES])
 def test_tree_and_lists_equal_the_oracle(tc, kind, n, leaf, eta, threads):
@@ -130,7 +136,7 @@ def test_tree_and_lists_equal_the_oracle(tc, kind, n, leaf, eta, threads):
             assert [tuple(map(int, x)) for x in pr] == [tuple(x) for x in ref], (l, far)
     # every ordered pair of boxes is covered once at the finest level where
     # its ancestors were near (a partition of the matrix)
-    if L <= 6:
+    if L <= 6 and n <= 8192:
         cover = np.zeros((n, n), np.int32)
         pos = np.empty(n, np.int64)
         pos[o.perm] = np.arange(n)
