@@ -1,9 +1,16 @@
-"""The C ABI's structs (include/h2.h) against the ctypes structures of the
-Python binding (paper_2502_02395_amd/h2.py): the same members in the same
-order, at the same offsets, of the same sizes, and the same struct sizes.
-The header's member lists are read from its text.  The offsets and sizes
-come from a C program compiled against the header, so a member added,
-removed, reordered or retyped on one side only fails here, without a GPU."""
+"""The C ABI (include/h2.h) against the Python binding
+(paper_2502_02395_amd/h2.py), without a GPU.
+
+Structs: the same members in the same order, at the same offsets, of the
+same sizes, and the same struct sizes.  The header's member lists are read
+from its text; the offsets and sizes come from a C program compiled against
+the header.
+
+Functions: every prototype against the binding's argtypes and restype, the
+same number of arguments, each of the same class.
+
+A member or argument added, removed, reordered or retyped on one side only
+fails here."""
 import ctypes
 import os
 import re
@@ -76,3 +83,46 @@ def test_offsets_and_sizes_match(tmp_path):
             assert (fd.offset, fd.size) == (int(a), int(b)), (cname, f, fd.offset, fd.size, a, b)
         seen += 1
     assert seen == sum(len(c._fields_) + 1 for c in STRUCTS.values())
+
+
+def _cls_c(decl):
+    """Argument class of a C parameter or return type."""
+    d = " ".join(decl.split())
+    if "*" in d or d.split()[0] == "h2_handle":
+        return "ptr"
+    base = d.replace("const ", "").split()[0]
+    return {"int64_t": "i64", "int32_t": "i32", "int": "i32", "h2_status": "i32", "float": "f32",
+            "double": "f64", "void": "void"}[base]
+
+
+def _cls_ctypes(t):
+    if t is None:
+        return "void"
+    if t in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(t, ctypes._Pointer):
+        return "ptr"
+    if ctypes.sizeof(t) == 8 and t in (ctypes.c_int64, ctypes.c_long, ctypes.c_longlong):
+        return "i64"
+    if t in (ctypes.c_int32, ctypes.c_int):
+        return "i32"
+    return {ctypes.c_float: "f32", ctypes.c_double: "f64"}[t]
+
+
+def test_function_signatures_match():
+    """Every prototype of the header against the binding's argtypes and
+    restype: the same number of arguments, each of the same class (pointer,
+    32- or 64-bit integer, float, double)."""
+    if not os.path.exists(h2.LIB_PATH):
+        pytest.skip("libh2.so not built")
+    L = h2.load()
+    text = re.sub(r"/\*.*?\*/", " ", open(HEADER).read(), flags=re.S)
+    protos = re.findall(r"\b(h2_status|void|const char\s*\*)\s+(h2_\w+)\s*\(([^;{]*?)\)\s*;", text)
+    assert len(protos) >= 18
+    for ret, name, params in protos:
+        fn = getattr(L, name)
+        args = [p for p in (" ".join(params.split())).split(",") if p.strip()]
+        want = [_cls_c(p.rsplit(" ", 1)[0] if not p.strip().endswith("*") else p) for p in args]
+        got = [_cls_ctypes(t) for t in (fn.argtypes or [])]
+        assert got == want, (name, got, want)
+        rw = _cls_c(ret)
+        rg = _cls_ctypes(fn.restype) if fn.restype is not ctypes.c_int else "i32"
+        assert rg == rw or (rw == "ptr" and fn.restype is ctypes.c_char_p), (name, rg, rw)
