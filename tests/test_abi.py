@@ -94,3 +94,16 @@ def test_graft_entry_has_build_and_smoke():
     m = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(m)
     assert callable(m.build) and callable(m.smoke)
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: without libh2.so every entry of the binding raises."""
+    import numpy as np
+    from paper_2502_02395_amd import h2
+    import workloads as W
+    monkeypatch.setattr(h2, "_lib", None)
+    monkeypatch.setattr(h2, "LIB_PATH", str(tmp_path / "libh2.so"))
+    with pytest.raises(ImportError, match="missing"):
+        h2.load()
+    with pytest.raises(ImportError, match="missing"):
+        h2.build(np.random.default_rng(0).random((64, 3)), W.Kernel(W.LAPLACE), 16, 1.0, 1e-6)
